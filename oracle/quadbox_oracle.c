@@ -1,0 +1,654 @@
+/*
+ * QuadBox CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously correct reference for the rasterizer hot path of
+ * "QuadBox: Accelerating 3D Gaussian Splatting with Geometry-Aware Boxes"
+ * (arXiv 2605.04844).  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library; the GPU path never links or calls it,
+ * and it shares no code, header or table with the GPU path.
+ *
+ * Precision.  Every floating-point value that decides an integer result (a tile
+ * set, a depth key, the alpha-cutoff decision of the render) is computed in
+ * IEEE binary32 with a fixed operation order (no contraction: build with
+ * -ffp-contract=off; `fmaf` appears only where the order says so), with `/`
+ * and `sqrtf` correctly rounded, and with every transcendental evaluated in
+ * binary64 and rounded once to binary32.  Everything that only feeds the
+ * image (colour, blending weights, accumulation) is binary64.
+ *
+ * Parity status per function (see the tests that pin each one):
+ *   oc_project        pinned: closed forms (Eqs. 5, 6, 9, 11, 12), textbook
+ *                     isotropic projection, support-function brute force (Eq. 8)
+ *   oc_sh_basis       pinned: complex spherical harmonics of scipy
+ *   oc_tile_set       pinned: brute-force conservativeness, set inclusions
+ *   oc_pairs          pinned: library sort (qsort) + uniqueness/inclusion tests
+ *   oc_ranges         pinned: binary search definition vs linear scan
+ *   oc_render         pinned: Eq. (2) closed forms for one and two Gaussians,
+ *                     tile-free brute-force render
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OC_TILE 16
+
+enum { OC_BOX_3SIGMA = 0, OC_BOX_ADR = 1, OC_BOX_QUADBOX = 2, OC_BOX_DUALBOX = 3 };
+
+/* Camera: world->camera rotation R (row-major) and translation t, pinhole
+ * intrinsics; x right, y down, z forward; pixel (i, j) samples the point (i, j). */
+typedef struct {
+    int32_t W, H;
+    float fx, fy, cx, cy, near_plane;
+    float R[9];
+    float t[3];
+    float campos[3];
+} oc_camera;
+
+/* Per-Gaussian projected values (all binary32 except rgb). */
+typedef struct {
+    float u, v, depth;       /* mean2D and view depth                                 */
+    float A, B, C;           /* Sigma2D entries incl. the 0.3 low-pass on A and C     */
+    float a, b, c;           /* conic Lambda = inverse(Sigma2D) = [a b; b c]           */
+    float opacity, gamma;    /* o and gamma = 2 ln(o / alpha_min)                      */
+    int32_t visible;         /* 0 when culled                                         */
+    int32_t nrect;           /* number of tile rectangles whose union is the tile set */
+    int32_t rect[4][4];      /* tile rects: tx0, tx1, ty0, ty1 (inclusive)             */
+    double rgb[3];
+} oc_gauss;
+
+/* ------------------------------------------------------------------------- */
+/* Real spherical harmonics, degree <= 3, index k = l*l + l + m.              */
+/* Basis: complex SH with the Condon-Shortley phase, made real by              */
+/*   m > 0: sqrt2 Re Y_l^m,  m < 0: sqrt2 Im Y_l^|m|,  m = 0: Y_l^0,            */
+/* written out as polynomials of the unit direction (x, y, z).                  */
+/* ------------------------------------------------------------------------- */
+void oc_sh_basis(double x, double y, double z, double out[16])
+{
+    const double pi = 3.14159265358979323846;
+    const double k00 = 0.5 * sqrt(1.0 / pi);
+    const double k1 = sqrt(3.0 / (4.0 * pi));
+    const double k2a = 0.5 * sqrt(15.0 / pi);
+    const double k2b = 0.25 * sqrt(5.0 / pi);
+    const double k2c = 0.25 * sqrt(15.0 / pi);
+    const double k3a = 0.25 * sqrt(35.0 / (2.0 * pi));
+    const double k3b = 0.5 * sqrt(105.0 / pi);
+    const double k3c = 0.25 * sqrt(21.0 / (2.0 * pi));
+    const double k3d = 0.25 * sqrt(7.0 / pi);
+    const double k3e = 0.25 * sqrt(105.0 / pi);
+    double xx = x * x, yy = y * y, zz = z * z;
+    out[0] = k00;
+    out[1] = -k1 * y;
+    out[2] = k1 * z;
+    out[3] = -k1 * x;
+    out[4] = k2a * x * y;
+    out[5] = -k2a * y * z;
+    out[6] = k2b * (2.0 * zz - xx - yy);
+    out[7] = -k2a * x * z;
+    out[8] = k2c * (xx - yy);
+    out[9] = -k3a * y * (3.0 * xx - yy);
+    out[10] = k3b * x * y * z;
+    out[11] = -k3c * y * (4.0 * zz - xx - yy);
+    out[12] = k3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+    out[13] = -k3c * x * (4.0 * zz - xx - yy);
+    out[14] = k3e * z * (xx - yy);
+    out[15] = -k3a * x * (xx - 3.0 * yy);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tile mapping of a closed pixel-coordinate interval [x0, x1] on an axis of   */
+/* `n` pixels: the tiles holding the integer samples that lie in it (the       */
+/* tile-space bounds of Sec. 3.2).  Returns 0 when no sample lies inside.       */
+/* ------------------------------------------------------------------------- */
+static int oc_axis_tiles(float x0, float x1, int n, int* t0, int* t1)
+{
+    float hi = (float)(n - 1);
+    if (!(x1 >= 0.0f) || !(x0 <= hi)) return 0;
+    float lo_c = x0 > 0.0f ? x0 : 0.0f;
+    float hi_c = x1 < hi ? x1 : hi;
+    int p0 = (int)ceilf(lo_c);
+    int p1 = (int)floorf(hi_c);
+    if (p0 > p1) return 0;
+    *t0 = p0 / OC_TILE;
+    *t1 = p1 / OC_TILE;
+    return 1;
+}
+
+/* A pixel-coordinate box [x0,x1]x[y0,y1] -> tile rect; 0 when empty. */
+static int oc_box_rect(float x0, float x1, float y0, float y1, int W, int H, int32_t r[4])
+{
+    int a, b, c, d;
+    if (!oc_axis_tiles(x0, x1, W, &a, &b)) return 0;
+    if (!oc_axis_tiles(y0, y1, H, &c, &d)) return 0;
+    r[0] = a; r[1] = b; r[2] = c; r[3] = d;
+    return 1;
+}
+
+/* Pixel-space boxes of one projected Gaussian (Sec. 2 for the 3-sigma square,
+ * Sec. 3.1 for AdR-AABB, DualBox and QuadBox).  Each box is the closed region
+ * [x0, x1] x [y0, y1]; returns how many boxes were written (1, 2 or 4). */
+int oc_pixel_boxes(const oc_gauss* g, int mode, float box[4][4])
+{
+    float u = g->u, v = g->v, A = g->A, B = g->B, C = g->C, gam = g->gamma;
+    if (mode == OC_BOX_3SIGMA) {
+        /* square of side 6 sqrt(lambda_max) (Sec. 2), radius rounded up to a
+         * whole pixel, discriminant floored at 0.1 */
+        float det = A * C - B * B;
+        float mid = 0.5f * (A + C);
+        float disc = mid * mid - det;
+        if (disc < 0.1f) disc = 0.1f;
+        float lam = mid + sqrtf(disc);
+        float r = ceilf(3.0f * sqrtf(lam));
+        box[0][0] = u - r; box[0][1] = u + r; box[0][2] = v - r; box[0][3] = v + r;
+        return 1;
+    }
+    /* half extents from the support function, Eqs. (9)/(11) in Sigma2D entries */
+    float xm = sqrtf(gam * A);
+    float ym = sqrtf(gam * C);
+    if (mode == OC_BOX_ADR) {
+        box[0][0] = u - xm; box[0][1] = u + xm; box[0][2] = v - ym; box[0][3] = v + ym;
+        return 1;
+    }
+    /* stretching factor, Eq. (12): b^2/(ac) = B^2/(AC) */
+    float ratio = (B * B) / (A * C);
+    float fs = 1.0f - ratio;
+    if (fs < 0.0f) fs = 0.0f;
+    float f = sqrtf(fs);
+    /* quadrants holding the major axis: (+,+),(-,-) when B > 0, else (+,-),(-,+) */
+    int maj_same = B > 0.0f;
+    int nb = 0;
+    for (int q = 0; q < 4; q++) {
+        int sx = (q & 1) ? 1 : -1;
+        int sy = (q & 2) ? 1 : -1;
+        int major = maj_same ? (sx == sy) : (sx != sy);
+        float w, h;
+        if (major) {
+            w = xm; h = ym;
+        } else {
+            if (mode == OC_BOX_DUALBOX) continue;
+            w = f * xm; h = f * ym;
+        }
+        box[nb][0] = sx > 0 ? u : u - w;
+        box[nb][1] = sx > 0 ? u + w : u;
+        box[nb][2] = sy > 0 ? v : v - h;
+        box[nb][3] = sy > 0 ? v + h : v;
+        nb++;
+    }
+    return nb;
+}
+
+/* Tile rects of the boxes; empty ones are dropped.  Fills g->rect / g->nrect. */
+void oc_build_boxes(oc_gauss* g, int mode, int W, int H)
+{
+    float box[4][4];
+    int nb = oc_pixel_boxes(g, mode, box);
+    g->nrect = 0;
+    for (int k = 0; k < nb; k++)
+        if (oc_box_rect(box[k][0], box[k][1], box[k][2], box[k][3], W, H, g->rect[g->nrect]))
+            g->nrect++;
+}
+
+/* ------------------------------------------------------------------------- */
+/* EWA projection of one Gaussian (Sec. 2, Eq. (1); Eqs. (3), (4) for gamma).  */
+/* ------------------------------------------------------------------------- */
+void oc_project_one(const oc_camera* cam, const float mean[3], const float lscale[3],
+                    const float quat[4], float logit, const float* sh, int64_t n, int64_t i,
+                    int sh_degree, int mode, oc_gauss* g)
+{
+    memset(g, 0, sizeof(*g));
+    const float* R = cam->R;
+    /* view transform */
+    float px = ((R[0] * mean[0] + R[1] * mean[1]) + R[2] * mean[2]) + cam->t[0];
+    float py = ((R[3] * mean[0] + R[4] * mean[1]) + R[5] * mean[2]) + cam->t[1];
+    float pz = ((R[6] * mean[0] + R[7] * mean[1]) + R[8] * mean[2]) + cam->t[2];
+    g->depth = pz;
+    if (!(pz > cam->near_plane) || !isfinite(px) || !isfinite(py) || !isfinite(pz)) return;
+
+    /* activations: evaluated in binary64, rounded once */
+    float s0 = (float)exp((double)lscale[0]);
+    float s1 = (float)exp((double)lscale[1]);
+    float s2 = (float)exp((double)lscale[2]);
+    float o = (float)(1.0 / (1.0 + exp(-(double)logit)));
+    g->opacity = o;
+    /* gamma = 2 ln(o / alpha_min) with alpha_min = 1/255 (Eq. (3)) */
+    g->gamma = (float)(2.0 * log(255.0 * (double)o));
+
+    /* unit quaternion (w, x, y, z) -> rotation */
+    float n2 = ((quat[0] * quat[0] + quat[1] * quat[1]) + quat[2] * quat[2]) + quat[3] * quat[3];
+    if (!(n2 > 0.0f) || !isfinite(n2)) return;
+    float nr = sqrtf(n2);
+    float w = quat[0] / nr, x = quat[1] / nr, y = quat[2] / nr, z = quat[3] / nr;
+    float Rq[9];
+    Rq[0] = 1.0f - 2.0f * (y * y + z * z);
+    Rq[1] = 2.0f * (x * y - w * z);
+    Rq[2] = 2.0f * (x * z + w * y);
+    Rq[3] = 2.0f * (x * y + w * z);
+    Rq[4] = 1.0f - 2.0f * (x * x + z * z);
+    Rq[5] = 2.0f * (y * z - w * x);
+    Rq[6] = 2.0f * (x * z - w * y);
+    Rq[7] = 2.0f * (y * z + w * x);
+    Rq[8] = 1.0f - 2.0f * (x * x + y * y);
+
+    /* Sigma3D = M M^T with M = Rq diag(s) */
+    float M[9];
+    for (int r = 0; r < 3; r++) {
+        M[r * 3 + 0] = Rq[r * 3 + 0] * s0;
+        M[r * 3 + 1] = Rq[r * 3 + 1] * s1;
+        M[r * 3 + 2] = Rq[r * 3 + 2] * s2;
+    }
+    float S[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            S[r * 3 + c] = (M[r * 3 + 0] * M[c * 3 + 0] + M[r * 3 + 1] * M[c * 3 + 1]) +
+                           M[r * 3 + 2] * M[c * 3 + 2];
+
+    /* local affine approximation of the projection (EWA), evaluated at the
+     * view-space mean with its image-plane slope clamped to 1.3x the half fov */
+    float limx = 1.3f * (0.5f * (float)cam->W / cam->fx);
+    float limy = 1.3f * (0.5f * (float)cam->H / cam->fy);
+    float xs = px / pz, ys = py / pz;
+    if (xs < -limx) xs = -limx;
+    if (xs > limx) xs = limx;
+    if (ys < -limy) ys = -limy;
+    if (ys > limy) ys = limy;
+    float tx = xs * pz, ty = ys * pz;
+    float zz = pz * pz;
+    float J00 = cam->fx / pz, J02 = -(cam->fx * tx) / zz;
+    float J11 = cam->fy / pz, J12 = -(cam->fy * ty) / zz;
+    /* T = J * R (2x3) */
+    float T[6];
+    for (int c = 0; c < 3; c++) {
+        T[c] = J00 * R[c] + J02 * R[6 + c];
+        T[3 + c] = J11 * R[3 + c] + J12 * R[6 + c];
+    }
+    /* U = T Sigma3D (2x3); Sigma2D = U T^T */
+    float U[6];
+    for (int r = 0; r < 2; r++)
+        for (int c = 0; c < 3; c++)
+            U[r * 3 + c] = (T[r * 3 + 0] * S[0 * 3 + c] + T[r * 3 + 1] * S[1 * 3 + c]) +
+                           T[r * 3 + 2] * S[2 * 3 + c];
+    float A = (U[0] * T[0] + U[1] * T[1]) + U[2] * T[2];
+    float B = (U[0] * T[3] + U[1] * T[4]) + U[2] * T[5];
+    float C = (U[3] * T[3] + U[4] * T[4]) + U[5] * T[5];
+    A = A + 0.3f;
+    C = C + 0.3f;
+    g->A = A; g->B = B; g->C = C;
+
+    /* image-plane mean */
+    g->u = cam->fx * (px / pz) + cam->cx;
+    g->v = cam->fy * (py / pz) + cam->cy;
+
+    /* conic = inverse of Sigma2D */
+    float det = A * C - B * B;
+    if (!(det > 0.0f) || !isfinite(det) || !isfinite(g->u) || !isfinite(g->v)) return;
+    g->a = C / det;
+    g->b = -(B / det);
+    g->c = A / det;
+
+    /* opacity-aware modes drop Gaussians that can never reach alpha_min */
+    if (mode != OC_BOX_3SIGMA && !(g->gamma > 0.0f)) return;
+
+    /* view-dependent colour from SH, binary64 */
+    {
+        double dx = (double)mean[0] - (double)cam->campos[0];
+        double dy = (double)mean[1] - (double)cam->campos[1];
+        double dz = (double)mean[2] - (double)cam->campos[2];
+        double nn = sqrt(dx * dx + dy * dy + dz * dz);
+        double Y[16];
+        if (nn > 0) { dx /= nn; dy /= nn; dz /= nn; }
+        oc_sh_basis(dx, dy, dz, Y);
+        int K = (sh_degree + 1) * (sh_degree + 1);
+        for (int ch = 0; ch < 3; ch++) {
+            double acc = 0.5;
+            for (int k = 0; k < K; k++) acc += Y[k] * (double)sh[(int64_t)(k * 3 + ch) * n + i];
+            g->rgb[ch] = acc > 0.0 ? acc : 0.0;
+        }
+    }
+
+    oc_build_boxes(g, mode, cam->W, cam->H);
+    g->visible = 1;
+}
+
+/* Project every Gaussian; SoA inputs as in the public interface. */
+void oc_project(const oc_camera* cam, int64_t n, const float* means, const float* log_scales,
+                const float* quats, const float* logits, const float* sh, int sh_degree,
+                int mode, oc_gauss* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        float m[3] = {means[i], means[n + i], means[2 * n + i]};
+        float l[3] = {log_scales[i], log_scales[n + i], log_scales[2 * n + i]};
+        float q[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+        oc_project_one(cam, m, l, q, logits[i], sh, n, i, sh_degree, mode, &out[i]);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tile set of one Gaussian: the plain union of its tile rects (Sec. 3.2).     */
+/* ------------------------------------------------------------------------- */
+static int oc_in_rects(const oc_gauss* g, int tx, int ty)
+{
+    for (int r = 0; r < g->nrect; r++)
+        if (tx >= g->rect[r][0] && tx <= g->rect[r][1] && ty >= g->rect[r][2] && ty <= g->rect[r][3])
+            return 1;
+    return 0;
+}
+
+/* Writes the tile ids of the union (ascending) into out (may be NULL);
+ * returns the count. */
+int64_t oc_tile_set(const oc_gauss* g, int tiles_x, int64_t* out)
+{
+    if (!g->visible || g->nrect == 0) return 0;
+    int x0 = g->rect[0][0], x1 = g->rect[0][1], y0 = g->rect[0][2], y1 = g->rect[0][3];
+    for (int r = 1; r < g->nrect; r++) {
+        if (g->rect[r][0] < x0) x0 = g->rect[r][0];
+        if (g->rect[r][1] > x1) x1 = g->rect[r][1];
+        if (g->rect[r][2] < y0) y0 = g->rect[r][2];
+        if (g->rect[r][3] > y1) y1 = g->rect[r][3];
+    }
+    int64_t cnt = 0;
+    for (int ty = y0; ty <= y1; ty++)
+        for (int tx = x0; tx <= x1; tx++)
+            if (oc_in_rects(g, tx, ty)) {
+                if (out) out[cnt] = (int64_t)ty * tiles_x + tx;
+                cnt++;
+            }
+    return cnt;
+}
+
+void oc_tile_counts(const oc_gauss* g, int64_t n, int tiles_x, int64_t* counts)
+{
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; i++) counts[i] = oc_tile_set(&g[i], tiles_x, NULL);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Keys and sort (Sec. 2 DuplicateWithKeys / SortPairs): key = tile << 32 |    */
+/* bits(depth); ascending by key, equal keys ascending by Gaussian id.         */
+/* ------------------------------------------------------------------------- */
+typedef struct { uint64_t key; uint32_t id; uint32_t pad; } oc_pair;
+
+static int oc_pair_cmp(const void* pa, const void* pb)
+{
+    const oc_pair* a = (const oc_pair*)pa;
+    const oc_pair* b = (const oc_pair*)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    if (a->id != b->id) return a->id < b->id ? -1 : 1;
+    return 0;
+}
+
+static uint64_t oc_depth_bits(float d)
+{
+    uint32_t u;
+    memcpy(&u, &d, 4);
+    return (uint64_t)u;
+}
+
+/* Emits and sorts every pair; returns P (or -1 when P > capacity). */
+int64_t oc_pairs(const oc_gauss* g, int64_t n, int tiles_x, int64_t capacity, uint64_t* keys,
+                 uint32_t* ids)
+{
+    int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+    oc_tile_counts(g, n, tiles_x, cnt);
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t c = cnt[i];
+        cnt[i] = total;
+        total += c;
+    }
+    cnt[n] = total;
+    if (total > capacity) { free(cnt); return -1; }
+    oc_pair* pr = (oc_pair*)malloc(sizeof(oc_pair) * (total > 0 ? total : 1));
+#pragma omp parallel
+    {
+        int64_t* tl = (int64_t*)malloc(sizeof(int64_t) * 65536);
+#pragma omp for schedule(dynamic, 1024)
+        for (int64_t i = 0; i < n; i++) {
+            int64_t m = cnt[i + 1] - cnt[i];
+            if (m == 0) continue;
+            int64_t* buf = m <= 65536 ? tl : (int64_t*)malloc(sizeof(int64_t) * m);
+            oc_tile_set(&g[i], tiles_x, buf);
+            for (int64_t k = 0; k < m; k++) {
+                pr[cnt[i] + k].key = ((uint64_t)buf[k] << 32) | oc_depth_bits(g[i].depth);
+                pr[cnt[i] + k].id = (uint32_t)i;
+                pr[cnt[i] + k].pad = 0;
+            }
+            if (buf != tl) free(buf);
+        }
+        free(tl);
+    }
+    qsort(pr, (size_t)total, sizeof(oc_pair), oc_pair_cmp);
+    for (int64_t k = 0; k < total; k++) {
+        keys[k] = pr[k].key;
+        ids[k] = pr[k].id;
+    }
+    free(pr);
+    free(cnt);
+    return total;
+}
+
+/* Per-tile ranges [start, end) of the sorted list: lower bounds of t<<32 and
+ * (t+1)<<32. */
+static int64_t oc_lower_bound(const uint64_t* keys, int64_t P, uint64_t k)
+{
+    int64_t lo = 0, hi = P;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+void oc_ranges(const uint64_t* keys, int64_t P, int num_tiles, uint32_t* ranges)
+{
+    for (int t = 0; t < num_tiles; t++) {
+        ranges[2 * t] = (uint32_t)oc_lower_bound(keys, P, (uint64_t)t << 32);
+        ranges[2 * t + 1] = (uint32_t)oc_lower_bound(keys, P, (uint64_t)(t + 1) << 32);
+    }
+}
+
+/* Sorted (depth, id) list of the Gaussians whose tile set holds `tile`:
+ * one tile's slice of the sorted pair list, computed on its own. */
+int64_t oc_tile_list(const oc_gauss* g, int64_t n, int tiles_x, int64_t tile, uint32_t* out)
+{
+    int tx = (int)(tile % tiles_x), ty = (int)(tile / tiles_x);
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (g[i].visible && oc_in_rects(&g[i], tx, ty)) out[m++] = (uint32_t)i;
+    /* order by (depth bits, id) with the same comparator as the pair sort */
+    oc_pair* pr = (oc_pair*)malloc(sizeof(oc_pair) * (m > 0 ? m : 1));
+    for (int64_t k = 0; k < m; k++) {
+        pr[k].key = oc_depth_bits(g[out[k]].depth);
+        pr[k].id = out[k];
+        pr[k].pad = 0;
+    }
+    qsort(pr, (size_t)m, sizeof(oc_pair), oc_pair_cmp);
+    for (int64_t k = 0; k < m; k++) out[k] = pr[k].id;
+    free(pr);
+    return m;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Render, Eq. (2): front-to-back compositing of one pixel over a depth-      */
+/* ordered list.  The alpha_min test is taken in its exact log form            */
+/* (power >= -gamma/2, i.e. Eq. (4)), in binary32; alpha, T and the colour     */
+/* are binary64.  alpha is capped at 0.99; compositing stops before the first  */
+/* Gaussian that would push T below 1e-4.                                      */
+/* Returns the count of list entries up to and including the last one that    */
+/* contributed; *near flags a pixel whose stopping test came within `band`     */
+/* (relative) of the 1e-4 threshold.                                           */
+/* ------------------------------------------------------------------------- */
+float oc_power(const oc_gauss* gi, float pxf, float pyf)
+{
+    float dx = gi->u - pxf;
+    float dy = gi->v - pyf;
+    float ha = -0.5f * gi->a, hc = -0.5f * gi->c, nb = -gi->b;
+    return fmaf(fmaf(ha, dx, nb * dy), dx, (hc * dy) * dy);
+}
+
+uint32_t oc_render_pixel(const oc_gauss* g, const uint32_t* list, int64_t m, int px, int py,
+                         const double bg[3], double band, double out_rgb[3], double* out_T,
+                         int* near)
+{
+    double T = 1.0, acc[3] = {0, 0, 0};
+    uint32_t last = 0;
+    *near = 0;
+    for (int64_t k = 0; k < m; k++) {
+        const oc_gauss* gi = &g[list[k]];
+        float power = oc_power(gi, (float)px, (float)py);
+        if (power > 0.0f) continue;
+        if (power < -0.5f * gi->gamma) continue;
+        double alpha = (double)gi->opacity * exp((double)power);
+        if (alpha > 0.99) alpha = 0.99;
+        double test_T = T * (1.0 - alpha);
+        if (fabs(test_T - 1e-4) <= band * 1e-4) *near = 1;
+        if (test_T < 1e-4) break;
+        for (int ch = 0; ch < 3; ch++) acc[ch] += gi->rgb[ch] * alpha * T;
+        T = test_T;
+        last = (uint32_t)(k + 1);
+    }
+    for (int ch = 0; ch < 3; ch++) out_rgb[ch] = acc[ch] + T * bg[ch];
+    *out_T = T;
+    return last;
+}
+
+/* Full tiled render over the sorted list and ranges. */
+void oc_render(const oc_gauss* g, int W, int H, const uint32_t* ranges, const uint32_t* ids,
+               const double bg[3], double band, double* image, double* final_T,
+               uint32_t* n_contrib, uint8_t* near_mask)
+{
+    int tiles_x = (W + OC_TILE - 1) / OC_TILE;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < (int64_t)W * H; p++) {
+        int px = (int)(p % W), py = (int)(p / W);
+        int tile = (py / OC_TILE) * tiles_x + px / OC_TILE;
+        uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
+        double rgb[3], T;
+        int near;
+        uint32_t last = oc_render_pixel(g, ids + s, (int64_t)e - s, px, py, bg, band, rgb, &T, &near);
+        for (int ch = 0; ch < 3; ch++) image[(int64_t)ch * W * H + p] = rgb[ch];
+        final_T[p] = T;
+        n_contrib[p] = last;
+        near_mask[p] = (uint8_t)near;
+    }
+}
+
+/* Render of selected pixels only, each from its own tile list computed from
+ * the Gaussians directly (no pair list): for parity at full size. */
+void oc_render_pixels(const oc_gauss* g, int64_t n, int W, int64_t npix, const int32_t* pix,
+                      const double bg[3], double band, double* rgb_out, double* T_out,
+                      uint32_t* contrib_out, uint8_t* near_out)
+{
+    int tiles_x = (W + OC_TILE - 1) / OC_TILE;
+#pragma omp parallel
+    {
+        uint32_t* list = (uint32_t*)malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t k = 0; k < npix; k++) {
+            int px = pix[2 * k], py = pix[2 * k + 1];
+            int64_t tile = (int64_t)(py / OC_TILE) * tiles_x + px / OC_TILE;
+            int64_t m = oc_tile_list(g, n, tiles_x, tile, list);
+            int near;
+            contrib_out[k] = oc_render_pixel(g, list, m, px, py, bg, band, rgb_out + 3 * k, &T_out[k], &near);
+            near_out[k] = (uint8_t)near;
+        }
+        free(list);
+    }
+}
+
+/* Tile-free render: every visible Gaussian, in (depth, id) order, at every
+ * pixel.  Differs from the tiled render only where a box misses a pixel. */
+void oc_render_brute(const oc_gauss* g, int64_t n, int W, int H, const double bg[3], double band,
+                     double* image, double* final_T, uint32_t* n_contrib, uint8_t* near_mask)
+{
+    oc_pair* pr = (oc_pair*)malloc(sizeof(oc_pair) * (n > 0 ? n : 1));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (g[i].visible) {
+            pr[m].key = oc_depth_bits(g[i].depth);
+            pr[m].id = (uint32_t)i;
+            pr[m].pad = 0;
+            m++;
+        }
+    qsort(pr, (size_t)m, sizeof(oc_pair), oc_pair_cmp);
+    uint32_t* list = (uint32_t*)malloc(sizeof(uint32_t) * (m > 0 ? m : 1));
+    for (int64_t k = 0; k < m; k++) list[k] = pr[k].id;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < (int64_t)W * H; p++) {
+        int px = (int)(p % W), py = (int)(p / W);
+        double rgb[3], T;
+        int near;
+        uint32_t last = oc_render_pixel(g, list, m, px, py, bg, band, rgb, &T, &near);
+        for (int ch = 0; ch < 3; ch++) image[(int64_t)ch * W * H + p] = rgb[ch];
+        final_T[p] = T;
+        n_contrib[p] = last;
+        near_mask[p] = (uint8_t)near;
+    }
+    free(list);
+    free(pr);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Coverage audit (the paper's conservativeness claim, Sec. 1 and Sec. 3):     */
+/* every tile holding a pixel sample p with q(p) <= gamma * s^2 must be in the  */
+/* tile set, where q is the binary64 quadratic form of the stored Sigma2D and  */
+/* s = 1 - margin / r_min shrinks the ellipse by `margin` pixels to absorb the */
+/* binary32 rounding of the box extents.  Also counts the exact-sample pairs   */
+/* (tiles with a sample at q <= gamma) and reports QuadBox-not-in-box events.  */
+/* Returns the number of missed (tile, Gaussian) pairs.                        */
+/* ------------------------------------------------------------------------- */
+int64_t oc_coverage_audit(const oc_gauss* g, int64_t n, int W, int H, double margin,
+                          int64_t* exact_pairs, int64_t* missed_ids, int64_t max_missed)
+{
+    int tiles_x = (W + OC_TILE - 1) / OC_TILE, tiles_y = (H + OC_TILE - 1) / OC_TILE;
+    int64_t missed = 0, exact = 0;
+    for (int64_t i = 0; i < n; i++) {
+        const oc_gauss* gi = &g[i];
+        if (!gi->visible || !(gi->gamma > 0.0f)) continue;
+        double A = gi->A, B = gi->B, C = gi->C, gam = gi->gamma;
+        double det = A * C - B * B;
+        double ia = C / det, ib = -B / det, ic = A / det; /* inverse in binary64 */
+        /* smallest semi-axis: sqrt(gamma * lambda_min(Sigma2D)) */
+        double mid = 0.5 * (A + C), rad = sqrt(0.25 * (A - C) * (A - C) + B * B);
+        double lmin = mid - rad;
+        double rmin = sqrt(gam * (lmin > 0 ? lmin : 0));
+        double s = rmin > 0 ? 1.0 - margin / rmin : 0.0;
+        if (s < 0) s = 0;
+        double xr = sqrt(gam * A) + 1.0, yr = sqrt(gam * C) + 1.0;
+        int tx0 = (int)floor((gi->u - xr) / OC_TILE), tx1 = (int)floor((gi->u + xr) / OC_TILE);
+        int ty0 = (int)floor((gi->v - yr) / OC_TILE), ty1 = (int)floor((gi->v + yr) / OC_TILE);
+        if (tx0 < 0) tx0 = 0;
+        if (ty0 < 0) ty0 = 0;
+        if (tx1 > tiles_x - 1) tx1 = tiles_x - 1;
+        if (ty1 > tiles_y - 1) ty1 = tiles_y - 1;
+        for (int ty = ty0; ty <= ty1; ty++)
+            for (int tx = tx0; tx <= tx1; tx++) {
+                int need = 0, any = 0;
+                for (int py = ty * OC_TILE; py < ty * OC_TILE + OC_TILE && py < H; py++)
+                    for (int px = tx * OC_TILE; px < tx * OC_TILE + OC_TILE && px < W; px++) {
+                        double dx = (double)px - gi->u, dy = (double)py - gi->v;
+                        double q = ia * dx * dx + 2.0 * ib * dx * dy + ic * dy * dy;
+                        if (q <= gam) any = 1;
+                        if (q <= gam * s * s) need = 1;
+                    }
+                exact += any;
+                if (need && !oc_in_rects(gi, tx, ty)) {
+                    if (missed < max_missed && missed_ids) missed_ids[missed] = i;
+                    missed++;
+                }
+            }
+    }
+    if (exact_pairs) *exact_pairs = exact;
+    return missed;
+}
+
+/* Struct layout, so the Python side can check its view of oc_gauss. */
+#include <stddef.h>
+void oc_layout(int64_t* out)
+{
+    out[0] = (int64_t)sizeof(oc_gauss);
+    out[1] = (int64_t)offsetof(oc_gauss, visible);
+    out[2] = (int64_t)offsetof(oc_gauss, nrect);
+    out[3] = (int64_t)offsetof(oc_gauss, rect);
+    out[4] = (int64_t)offsetof(oc_gauss, rgb);
+    out[5] = (int64_t)sizeof(oc_camera);
+}

@@ -1,0 +1,190 @@
+"""Pins of the oracle's pair list, ranges and render against independent
+facts: the per-Gaussian set union of rects (numpy), a linear scan for the
+ranges, Eq. (2) in closed form for one, two and four Gaussians, the tile-free
+brute-force render, and the image invariance across conservative box modes."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_04844_amd import scenes
+
+
+def _rec(O, n):
+    g = np.zeros(n, O.GAUSS_DTYPE)
+    g["visible"] = 1
+    return g
+
+
+def _set_gauss(g, i, u, v, A, B, C, o, rgb, depth):
+    det = A * C - B * B
+    g["u"][i], g["v"][i], g["depth"][i] = u, v, depth
+    g["A"][i], g["B"][i], g["C"][i] = A, B, C
+    g["a"][i], g["b"][i], g["c"][i] = C / det, -B / det, A / det
+    g["opacity"][i] = o
+    g["gamma"][i] = 2.0 * math.log(255.0 * float(np.float32(o)))
+    g["rgb"][i] = rgb
+
+
+def _all_tiles_ranges(n_tiles, order):
+    """Every tile's list is `order` (a depth-sorted id list)."""
+    m = len(order)
+    ids = np.tile(np.asarray(order, np.uint32), n_tiles)
+    rt = np.stack([np.arange(n_tiles) * m, np.arange(1, n_tiles + 1) * m], 1).astype(np.uint32)
+    return rt, ids
+
+
+def _alpha(g, i, px, py):
+    """alpha of Gaussian i at pixels (px, py) from the float64 quadratic form;
+    the rows with q within 1e-4 of gamma are returned as a separate mask."""
+    dx, dy = px - float(g["u"][i]), py - float(g["v"][i])
+    a, b, c = float(g["a"][i]), float(g["b"][i]), float(g["c"][i])
+    q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+    gam = float(g["gamma"][i])
+    al = np.minimum(0.99, float(g["opacity"][i]) * np.exp(-0.5 * q))
+    return np.where(q <= gam, al, 0.0), np.abs(q - gam) <= 1e-4 * gam
+
+
+def test_single_gaussian_closed_form(oracle):
+    """C(u) = alpha(u) c and T = 1 - alpha (Eq. (2) with N = 1)."""
+    W = H = 48
+    g = _rec(oracle, 1)
+    _set_gauss(g, 0, 20.3, 25.7, 40.0, 12.0, 25.0, 0.8, (0.2, 0.5, 0.9), 3.0)
+    rt, ids = _all_tiles_ranges(9, [0])
+    img, T, nc, near = oracle.render(g, W, H, rt, ids)
+    py, px = np.mgrid[0:H, 0:W].astype(np.float64)
+    al, edge = _alpha(g, 0, px, py)
+    ok = ~edge
+    for ch, col in enumerate((0.2, 0.5, 0.9)):
+        assert np.abs(img[ch] - al * col)[ok].max() <= 1e-6
+    assert np.abs(T - (1 - al))[ok].max() <= 1e-6
+    assert np.array_equal((nc == 1)[ok], (al > 0)[ok])
+
+
+def test_two_gaussians_front_to_back(oracle):
+    """C = a0 c0 + (1 - a0) a1 c1 for two overlapping Gaussians in depth order."""
+    W = H = 32
+    g = _rec(oracle, 2)
+    _set_gauss(g, 0, 14.0, 15.0, 30.0, -8.0, 20.0, 0.7, (1.0, 0.0, 0.0), 2.0)
+    _set_gauss(g, 1, 17.5, 16.5, 25.0, 5.0, 35.0, 0.9, (0.0, 0.0, 1.0), 4.0)
+    rt, ids = _all_tiles_ranges(4, [0, 1])
+    img, T, nc, near = oracle.render(g, W, H, rt, ids)
+    py, px = np.mgrid[0:H, 0:W].astype(np.float64)
+    a0, e0 = _alpha(g, 0, px, py)
+    a1, e1 = _alpha(g, 1, px, py)
+    ok = ~(e0 | e1)
+    assert np.abs(img[0] - a0)[ok].max() <= 1e-6
+    assert np.abs(img[2] - (1 - a0) * a1)[ok].max() <= 1e-6
+    assert np.abs(T - (1 - a0) * (1 - a1))[ok].max() <= 1e-6
+
+
+def test_early_stop_rule(oracle):
+    """Four coincident Gaussians of alpha 0.95 at their centre: T goes 0.05,
+    0.0025, 1.25e-4; the fourth would drop it below 1e-4, so compositing stops
+    before it and three contribute."""
+    W = H = 16
+    g = _rec(oracle, 4)
+    for i in range(4):
+        _set_gauss(g, i, 8.0, 8.0, 4.0, 0.0, 4.0, 0.95, (1.0, 1.0, 1.0), 1.0 + i)
+    rt, ids = _all_tiles_ranges(1, [0, 1, 2, 3])
+    img, T, nc, near = oracle.render(g, W, H, rt, ids)
+    o = float(np.float32(0.95))      # opacity is stored in binary32
+    assert nc[8, 8] == 3
+    assert abs(T[8, 8] - (1 - o) ** 3) <= 1e-15
+    assert abs(img[0, 8, 8] - o * (1 + (1 - o) + (1 - o) ** 2)) <= 1e-12
+
+
+def test_alpha_cutoff_equals_quadratic_form_test(oracle):
+    """A pixel receives a Gaussian iff q <= gamma, i.e. alpha >= 1/255 (Eq. (4));
+    checked away from a 1e-4 relative band around the level set."""
+    W = H = 64
+    g = _rec(oracle, 1)
+    _set_gauss(g, 0, 30.2, 33.9, 90.0, -60.0, 70.0, 0.3, (1, 1, 1), 1.0)
+    rt, ids = _all_tiles_ranges(16, [0])
+    img, T, nc, near = oracle.render(g, W, H, rt, ids)
+    py, px = np.mgrid[0:H, 0:W].astype(np.float64)
+    al, edge = _alpha(g, 0, px, py)
+    assert np.array_equal((nc == 1)[~edge], (al > 0)[~edge])
+    assert np.all(img[0][al > 0] >= 1.0 / 255.0 * (1 - 1e-5))
+
+
+def test_pairs_are_rect_unions(oracle):
+    """Each Gaussian's tiles in the pair list are the set union of its tile
+    rects, once each (Sec. 3.2); keys carry tile << 32 | depth bits and are
+    sorted with ties by id."""
+    scene, cam = scenes.small_scene(n=4000)
+    g = oracle.project(scene, cam, "quadbox")
+    keys, ids = oracle.pairs(g, cam.tiles_x)
+    assert np.all(keys[1:] >= keys[:-1])
+    tie = keys[1:] == keys[:-1]
+    assert np.all(ids[1:][tie] > ids[:-1][tie])
+    depth_bits = g["depth"].view(np.uint32)
+    assert np.array_equal(keys & np.uint64(0xFFFFFFFF), depth_bits[ids].astype(np.uint64))
+    tiles = (keys >> np.uint64(32)).astype(np.int64)
+    per = {}
+    for t, i in zip(tiles.tolist(), ids.tolist()):
+        per.setdefault(i, []).append(t)
+    for i in range(scene.n):
+        want = set()
+        for r in range(g["nrect"][i]):
+            x0, x1, y0, y1 = g["rect"][i][r]
+            want |= {ty * cam.tiles_x + tx for ty in range(y0, y1 + 1) for tx in range(x0, x1 + 1)}
+        if not g["visible"][i]:
+            want = set()
+        got = per.get(i, [])
+        assert len(got) == len(set(got)) and set(got) == want
+
+
+def test_ranges_linear_scan(oracle):
+    scene, cam = scenes.small_scene(n=2000)
+    g = oracle.project(scene, cam, "adr")
+    keys, ids = oracle.pairs(g, cam.tiles_x)
+    rt = oracle.ranges(keys, cam.num_tiles)
+    tiles = (keys >> np.uint64(32)).astype(np.int64)
+    pos = 0
+    for t in range(cam.num_tiles):
+        start = pos
+        while pos < len(tiles) and tiles[pos] == t:
+            pos += 1
+        assert rt[t, 0] == start and rt[t, 1] == pos
+    assert pos == len(tiles)
+
+
+def test_tile_list_matches_pair_slices(oracle):
+    scene, cam = scenes.small_scene(n=3000)
+    g = oracle.project(scene, cam, "quadbox")
+    keys, ids = oracle.pairs(g, cam.tiles_x)
+    rt = oracle.ranges(keys, cam.num_tiles)
+    for t in [0, 17, 100, 128, 200, 255]:
+        assert np.array_equal(oracle.tile_list(g, cam.tiles_x, t), ids[rt[t, 0]:rt[t, 1]])
+
+
+def test_tiled_equals_brute_force_render(oracle):
+    """The tiled render equals compositing every Gaussian at every pixel: a
+    conservative box only removes Gaussians that contribute nothing."""
+    scene, cam = scenes.small_scene(n=3000)
+    out = oracle.forward(scene, cam, "quadbox")
+    img_b, T_b, _, _ = oracle.render_brute(out["g"], cam.width, cam.height)
+    assert np.array_equal(out["image"], img_b)
+    assert np.array_equal(out["T"], T_b)
+
+
+def test_image_invariant_across_conservative_modes(oracle):
+    scene, cam = scenes.small_scene(n=5000)
+    a = oracle.forward(scene, cam, "adr")
+    q = oracle.forward(scene, cam, "quadbox")
+    assert np.array_equal(a["image"], q["image"])
+    assert np.array_equal(a["T"], q["T"])
+    d = oracle.forward(scene, cam, "dualbox")
+    assert not np.array_equal(d["image"], q["image"])
+
+
+def test_render_pixels_matches_full_render(oracle):
+    scene, cam = scenes.small_scene(n=3000)
+    out = oracle.forward(scene, cam, "quadbox")
+    rng = np.random.default_rng(3)
+    pix = np.stack([rng.integers(0, cam.width, 200), rng.integers(0, cam.height, 200)], 1)
+    rgb, T, nc, near = oracle.render_pixels(out["g"], cam.width, pix)
+    for k, (x, y) in enumerate(pix):
+        assert np.array_equal(rgb[k], out["image"][:, y, x])
+        assert T[k] == out["T"][y, x] and nc[k] == out["n_contrib"][y, x]
