@@ -1,0 +1,191 @@
+/*
+ * quadbox.h -- C ABI of the MI355X (gfx950) QuadBox rasterizer hot path.
+ *
+ * Implements the forward rasterization of 3D Gaussian Splatting with the
+ * QuadBox tile culling and the QPass traversal of "QuadBox: Accelerating 3D
+ * Gaussian Splatting with Geometry-Aware Boxes" (arXiv 2605.04844):
+ *   qb_project    Sec. 2 (EWA projection, Eq. 1; Preprocess), Sec. 3.1 (boxes,
+ *                 Eqs. 3-12), Sec. 3.2 (tile-space bounds)
+ *   qb_intersect  Sec. 2 (DuplicateWithKeys), Sec. 3.2 (QPass)
+ *   qb_sort       Sec. 2 (SortPairs) and the per-tile ranges
+ *   qb_render     Sec. 2, Eq. (2) (front-to-back alpha compositing)
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers owned by the caller; the library never
+ *     allocates, frees or retains caller memory.  Scratch memory comes from a
+ *     caller-provided workspace of qb_*_workspace_size() bytes (256-byte aligned).
+ *   - Every call is asynchronous on the given HIP stream (0 = null stream) and
+ *     returns after enqueueing its kernels.
+ *   - Argument errors (null pointers, negative or oversized counts, bad modes,
+ *     bad image sizes) are detected on the host before anything is launched and
+ *     return QB_ERR_INVALID_ARG; a failed launch returns QB_ERR_HIP.  Nothing
+ *     aborts or throws across the ABI.
+ *   - Tiles are 16x16 pixels; tile id = ty * tiles_x + tx with
+ *     tiles_x = ceil(W/16), tiles_y = ceil(H/16).
+ *   - Floating point is IEEE binary32.  Values that decide tile sets, keys and
+ *     the render's 1/255 cutoff follow one fixed operation order (no
+ *     contraction, correctly rounded divide and sqrt, transcendentals evaluated
+ *     in binary64 and rounded once), so they are reproducible bit for bit.
+ */
+#ifndef QUADBOX_H
+#define QUADBOX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* qb_stream_t; /* a hipStream_t */
+
+typedef enum {
+    QB_OK = 0,
+    QB_ERR_INVALID_ARG = -1,
+    QB_ERR_CAPACITY = -2,   /* more pairs than the caller's capacity            */
+    QB_ERR_HIP = -3,        /* a HIP runtime call or kernel launch failed        */
+    QB_ERR_UNSUPPORTED = -4 /* no gfx950 device / feature not built              */
+} qb_status;
+
+/* Box that decides which tiles a Gaussian is listed in. */
+typedef enum {
+    QB_BOX_3SIGMA = 0,  /* square of side 6 sqrt(lambda_max) (Sec. 2)               */
+    QB_BOX_ADR = 1,     /* opacity-aware AABB, half extents sqrt(gamma*Sigma2D_ii)
+                           (Sec. 3.1, Eqs. 9, 11)                                   */
+    QB_BOX_QUADBOX = 2, /* four quadrant boxes: two full (major axis) and two
+                           scaled by f = sqrt(1 - b^2/(ac)) (Sec. 3.1, Eq. 12)      */
+    QB_BOX_DUALBOX = 3  /* the two major-axis quadrant boxes only (Sec. 3.1);
+                           not conservative, ablation only (Table 3)              */
+} qb_box_mode;
+
+/* Pinhole camera.  R (row-major) and t map world to camera coordinates:
+ * p = R mu + t, x right, y down, z forward; pixel (i, j) samples the image
+ * point (i, j); u = fx x/z + cx.  campos is the camera centre in world space
+ * (used for the view direction of the SH colour).  Gaussians with p.z <=
+ * near_plane are culled. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float near_plane;
+    float R[9];
+    float t[3];
+    float campos[3];
+} qb_camera;
+
+/* Projected record of one Gaussian, written by qb_project (48 bytes, 16-byte
+ * aligned, array of N):
+ *   u, v         image-plane mean (pixels)
+ *   depth        view-space z (only meaningful when the Gaussian is visible)
+ *   opacity      o = sigmoid(logit)
+ *   a, b, c      conic Lambda = inverse(Sigma2D) = [a b; b c]
+ *   gamma        2 ln(o / (1/255)): the 1/255 level of Eqs. (3), (4)
+ *   r, g, bl     view-dependent colour from the SH coefficients
+ *   visible      1.0f when the Gaussian survived culling, else 0.0f          */
+typedef struct {
+    float u, v, depth, opacity;
+    float a, b, c, gamma;
+    float r, g, bl, visible;
+} qb_splat;
+
+/* Per-Gaussian tile rects: four sub-boxes of (tx0, tx1, ty0, ty1), inclusive
+ * tile bounds, int16 each (32 bytes).  An empty sub-box has tx0 > tx1.  The
+ * Gaussian's tile set is the union of the four.  QB_BOX_3SIGMA and
+ * QB_BOX_ADR store their single rect in slot 0. */
+typedef struct {
+    int16_t r[4][4];
+} qb_rects;
+
+/* ------------------------------------------------------------------------- */
+
+/* qb_project -- Preprocess (Sec. 2) with the box of `mode` (Sec. 3.1) and
+ * the tile count of the union of its sub-boxes (Sec. 3.2).
+ *   n                number of Gaussians, 0 <= n < 2^31 (n = 0 is a no-op)
+ *   means            [3][n] float, structure of arrays (x plane, y plane, z)
+ *   log_scales       [3][n] float; scale s = exp(log_scale)
+ *   quats            [4][n] float (w, x, y, z); need not be unit length
+ *   opacity_logits   [n] float; opacity o = sigmoid(logit)
+ *   sh               [(sh_degree+1)^2 * 3][n] float; plane k*3+ch holds SH
+ *                    coefficient k = l*l + l + m of colour channel ch
+ *   sh_degree        0..3
+ *   cam              host pointer, read during the call only
+ *   out_splats       [n] qb_splat
+ *   out_rects        [n] qb_rects
+ *   out_counts       [n] int32: number of tiles in the Gaussian's tile set
+ *                    (0 when culled or off-screen)
+ * Culled: p.z <= near, non-finite values, zero quaternion, det(Sigma2D) <= 0,
+ * and (all modes but 3SIGMA) o <= 1/255. */
+qb_status qb_project(int64_t n, const float* means, const float* log_scales, const float* quats,
+                     const float* opacity_logits, const float* sh, int32_t sh_degree,
+                     const qb_camera* cam, int32_t mode, qb_splat* out_splats,
+                     qb_rects* out_rects, int32_t* out_counts, qb_stream_t stream);
+
+/* Workspace bytes qb_intersect needs for n Gaussians. */
+size_t qb_intersect_workspace_size(int64_t n);
+
+/* qb_intersect -- DuplicateWithKeys with the QPass traversal (Sec. 2, 3.2).
+ * Orders the Gaussians by (depth bits, id), takes the exclusive prefix sum of
+ * their counts in that order, then writes for every tile of every Gaussian's
+ * tile set exactly one pair
+ *     key = (uint64)tile << 32 | float_bits(depth),   id = Gaussian index.
+ * The pairs of one Gaussian are contiguous and the Gaussians appear in
+ * ascending (depth, id) order; qb_sort relies on that order.
+ *   splats, rects, counts   outputs of qb_project for the same n
+ *   pair_capacity           entries available in keys/ids
+ *   keys, ids               [pair_capacity] uint64 / uint32
+ *   num_pairs               device int64: receives the total pair count P,
+ *                           also when P > pair_capacity; then no pair is
+ *                           written, qb_sort writes empty ranges and the
+ *                           caller re-runs with a larger capacity
+ *   workspace               qb_intersect_workspace_size(n) bytes           */
+qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_rects* rects,
+                       const int32_t* counts, int32_t width, int32_t height,
+                       int64_t pair_capacity, uint64_t* keys, uint32_t* ids,
+                       int64_t* num_pairs, void* workspace, size_t workspace_bytes,
+                       qb_stream_t stream);
+
+/* Workspace bytes qb_sort needs for a pair capacity. */
+size_t qb_sort_workspace_size(int64_t pair_capacity, int32_t num_tiles);
+
+/* qb_sort -- SortPairs (Sec. 2): the P = *num_pairs pairs of keys_in/ids_in,
+ * produced by qb_intersect, in ascending (key, id) order into
+ * keys_out/ids_out, and per-tile ranges of the sorted list:
+ *   ranges[2t] = first index with tile >= t, ranges[2t+1] = first index with
+ *   tile > t (empty tiles get start == end).
+ * Only the tile bits are sorted (a stable LSD radix sort), since qb_intersect
+ * emits the pairs in (depth, id) order.  When P > pair_capacity nothing is
+ * sorted and every range is [0, 0).
+ *   num_tiles        tiles_x * tiles_y, 1 .. 2^24
+ *   keys_in, ids_in  [pair_capacity]; not modified
+ *   keys_out, ids_out [pair_capacity]
+ *   ranges           [num_tiles][2] uint32                                  */
+qb_status qb_sort(int64_t pair_capacity, const int64_t* num_pairs, int32_t num_tiles,
+                  const uint64_t* keys_in, const uint32_t* ids_in, uint64_t* keys_out,
+                  uint32_t* ids_out, uint32_t* ranges, void* workspace, size_t workspace_bytes,
+                  qb_stream_t stream);
+
+/* qb_render -- Eq. (2) per pixel over its tile's sorted list: front to back,
+ * skipping a Gaussian where its quadratic form exceeds gamma (alpha < 1/255,
+ * Eq. (4)), alpha = min(0.99, o exp(-q/2)), stopping before the first
+ * Gaussian that would take T below 1e-4; output C + T * bg.
+ *   ranges, ids      from qb_sort (ids = ids_out)
+ *   splats           from qb_project
+ *   bg               host pointer to 3 floats
+ *   image            [3][H][W] float
+ *   final_T          [H][W] float (may be NULL)
+ *   n_contrib        [H][W] uint32: 1 + list index of the last contributor,
+ *                    0 if none (may be NULL)                                */
+qb_status qb_render(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
+                    const qb_splat* splats, const float* bg, float* image, float* final_T,
+                    uint32_t* n_contrib, qb_stream_t stream);
+
+/* Human-readable name of a status code (static string). */
+const char* qb_status_string(qb_status s);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t qb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QUADBOX_H */

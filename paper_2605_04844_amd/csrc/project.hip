@@ -1,0 +1,294 @@
+// qb_project: Gaussian-parallel preprocess (Sec. 2: EWA projection of Eq. (1)
+// Gaussians; Sec. 3.1: box construction; Sec. 3.2: tile-space bounds and the
+// QPass tile count).
+//
+// One lane per Gaussian; inputs are structure-of-arrays so every plane is read
+// with coalesced 256-byte wave accesses, outputs are 48-byte records and
+// 32-byte rect sets written as 16-byte vectors.  The work is HBM-bound (236 B
+// read per SH3 Gaussian), so the arithmetic follows the fixed binary32
+// operation order that makes keys reproducible: no contraction (the library is
+// built with -ffp-contract=off), correctly rounded divide/sqrt, and the three
+// transcendentals in binary64 rounded once.
+#include "qb_common.h"
+
+namespace {
+
+struct ProjCam {
+    int W, H, tiles_x, tiles_y;
+    float fx, fy, cx, cy, near_plane;
+    float R[9], t[3], campos[3];
+    float limx, limy;
+};
+
+// Tile range of the integer pixel samples in the closed interval [x0, x1] of
+// an axis with n pixels; false when none lies inside.
+__device__ __forceinline__ bool axis_tiles(float x0, float x1, int n, int* t0, int* t1)
+{
+    float hi = (float)(n - 1);
+    if (!(x1 >= 0.0f) || !(x0 <= hi)) return false;
+    float lo_c = x0 > 0.0f ? x0 : 0.0f;
+    float hi_c = x1 < hi ? x1 : hi;
+    int p0 = (int)ceilf(lo_c);
+    int p1 = (int)floorf(hi_c);
+    if (p0 > p1) return false;
+    *t0 = p0 / QB_TILE;
+    *t1 = p1 / QB_TILE;
+    return true;
+}
+
+__device__ __forceinline__ QRect box_rect(float x0, float x1, float y0, float y1, int W, int H)
+{
+    QRect r{1, 0, 1, 0};
+    int a, b, c, d;
+    if (axis_tiles(x0, x1, W, &a, &b) && axis_tiles(y0, y1, H, &c, &d)) r = QRect{a, b, c, d};
+    return r;
+}
+
+// Real SH basis of degree <= 3 (Condon-Shortley phase, index l*l + l + m).
+__device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t n, int64_t i,
+                                          int deg, float x, float y, float z, float rgb[3])
+{
+    const float k00 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
+    const float k1 = 0.48860251190291992f;    // sqrt(3 / (4 pi))
+    const float k2a = 1.0925484305920792f;    // sqrt(15 / pi) / 2
+    const float k2b = 0.31539156525252005f;   // sqrt(5 / pi) / 4
+    const float k2c = 0.54627421529603959f;   // sqrt(15 / pi) / 4
+    const float k3a = 0.59004358992664352f;   // sqrt(35 / (2 pi)) / 4
+    const float k3b = 2.8906114426405538f;    // sqrt(105 / pi) / 2
+    const float k3c = 0.45704579946446572f;   // sqrt(21 / (2 pi)) / 4
+    const float k3d = 0.3731763325901154f;    // sqrt(7 / pi) / 4
+    const float k3e = 1.4453057213202769f;    // sqrt(105 / pi) / 4
+    float Y[16];
+    float xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = k00;
+    int K = (deg + 1) * (deg + 1);
+    if (deg >= 1) {
+        Y[1] = -k1 * y;
+        Y[2] = k1 * z;
+        Y[3] = -k1 * x;
+    }
+    if (deg >= 2) {
+        Y[4] = k2a * x * y;
+        Y[5] = -k2a * y * z;
+        Y[6] = k2b * (2.0f * zz - xx - yy);
+        Y[7] = -k2a * x * z;
+        Y[8] = k2c * (xx - yy);
+    }
+    if (deg >= 3) {
+        Y[9] = -k3a * y * (3.0f * xx - yy);
+        Y[10] = k3b * x * y * z;
+        Y[11] = -k3c * y * (4.0f * zz - xx - yy);
+        Y[12] = k3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+        Y[13] = -k3c * x * (4.0f * zz - xx - yy);
+        Y[14] = k3e * z * (xx - yy);
+        Y[15] = -k3a * x * (xx - 3.0f * yy);
+    }
+    float acc[3] = {0.5f, 0.5f, 0.5f};
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = fmaf(Y[k], __ldg(sh + (int64_t)(k * 3 + ch) * n + i), acc[ch]);
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) rgb[ch] = acc[ch] > 0.0f ? acc[ch] : 0.0f;
+}
+
+__global__ __launch_bounds__(QB_BLOCK) void k_project(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int sh_degree, ProjCam cam, int mode,
+    float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
+{
+    int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    float mx = means[i], my = means[n + i], mz = means[2 * n + i];
+    const float* R = cam.R;
+    float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + cam.t[0];
+    float py = ((R[3] * mx + R[4] * my) + R[5] * mz) + cam.t[1];
+    float pz = ((R[6] * mx + R[7] * my) + R[8] * mz) + cam.t[2];
+
+    float4 s0 = make_float4(0.f, 0.f, pz, 0.f), s1 = make_float4(0.f, 0.f, 0.f, 0.f),
+           s2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    QRect rr[4] = {{1, 0, 1, 0}, {1, 0, 1, 0}, {1, 0, 1, 0}, {1, 0, 1, 0}};
+    int count = 0;
+    bool vis = false;
+
+    do {
+        if (!(pz > cam.near_plane) || !isfinite(px) || !isfinite(py) || !isfinite(pz)) break;
+        float sx = (float)exp((double)log_scales[i]);
+        float sy = (float)exp((double)log_scales[n + i]);
+        float sz = (float)exp((double)log_scales[2 * n + i]);
+        float o = (float)(1.0 / (1.0 + exp(-(double)logits[i])));
+        float gam = (float)(2.0 * log(255.0 * (double)o));
+
+        float qw = quats[i], qx = quats[n + i], qy = quats[2 * n + i], qz = quats[3 * n + i];
+        float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+        if (!(n2 > 0.0f) || !isfinite(n2)) break;
+        float nr = sqrtf(n2);
+        float w = qw / nr, x = qx / nr, y = qy / nr, z = qz / nr;
+        float Rq[9];
+        Rq[0] = 1.0f - 2.0f * (y * y + z * z);
+        Rq[1] = 2.0f * (x * y - w * z);
+        Rq[2] = 2.0f * (x * z + w * y);
+        Rq[3] = 2.0f * (x * y + w * z);
+        Rq[4] = 1.0f - 2.0f * (x * x + z * z);
+        Rq[5] = 2.0f * (y * z - w * x);
+        Rq[6] = 2.0f * (x * z - w * y);
+        Rq[7] = 2.0f * (y * z + w * x);
+        Rq[8] = 1.0f - 2.0f * (x * x + y * y);
+        float M[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            M[r * 3 + 0] = Rq[r * 3 + 0] * sx;
+            M[r * 3 + 1] = Rq[r * 3 + 1] * sy;
+            M[r * 3 + 2] = Rq[r * 3 + 2] * sz;
+        }
+        float S[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                S[r * 3 + c] = (M[r * 3 + 0] * M[c * 3 + 0] + M[r * 3 + 1] * M[c * 3 + 1]) +
+                               M[r * 3 + 2] * M[c * 3 + 2];
+
+        float xs = px / pz, ys = py / pz;
+        xs = xs < -cam.limx ? -cam.limx : (xs > cam.limx ? cam.limx : xs);
+        ys = ys < -cam.limy ? -cam.limy : (ys > cam.limy ? cam.limy : ys);
+        float tx = xs * pz, ty = ys * pz;
+        float zz = pz * pz;
+        float J00 = cam.fx / pz, J02 = -(cam.fx * tx) / zz;
+        float J11 = cam.fy / pz, J12 = -(cam.fy * ty) / zz;
+        float T[6];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T[c] = J00 * R[c] + J02 * R[6 + c];
+            T[3 + c] = J11 * R[3 + c] + J12 * R[6 + c];
+        }
+        float U[6];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                U[r * 3 + c] = (T[r * 3 + 0] * S[0 * 3 + c] + T[r * 3 + 1] * S[1 * 3 + c]) +
+                               T[r * 3 + 2] * S[2 * 3 + c];
+        float A = (U[0] * T[0] + U[1] * T[1]) + U[2] * T[2];
+        float B = (U[0] * T[3] + U[1] * T[4]) + U[2] * T[5];
+        float C = (U[3] * T[3] + U[4] * T[4]) + U[5] * T[5];
+        A = A + 0.3f;
+        C = C + 0.3f;
+
+        float u = cam.fx * (px / pz) + cam.cx;
+        float v = cam.fy * (py / pz) + cam.cy;
+        float det = A * C - B * B;
+        if (!(det > 0.0f) || !isfinite(det) || !isfinite(u) || !isfinite(v)) break;
+        float ca = C / det, cb = -(B / det), cc = A / det;
+        if (mode != QB_BOX_3SIGMA && !(gam > 0.0f)) break;
+
+        float rgb[3];
+        {
+            float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
+            float nn = sqrtf(dx * dx + dy * dy + dz * dz);
+            if (nn > 0.0f) { dx /= nn; dy /= nn; dz /= nn; }
+            sh_colour(sh, n, i, sh_degree, dx, dy, dz, rgb);
+        }
+
+        if (mode == QB_BOX_3SIGMA) {
+            float mid = 0.5f * (A + C);
+            float disc = mid * mid - det;
+            if (disc < 0.1f) disc = 0.1f;
+            float lam = mid + sqrtf(disc);
+            float r = ceilf(3.0f * sqrtf(lam));
+            rr[0] = box_rect(u - r, u + r, v - r, v + r, cam.W, cam.H);
+        } else {
+            float xm = sqrtf(gam * A);
+            float ym = sqrtf(gam * C);
+            if (mode == QB_BOX_ADR) {
+                rr[0] = box_rect(u - xm, u + xm, v - ym, v + ym, cam.W, cam.H);
+            } else {
+                // stretching factor f = sqrt(1 - b^2/(ac)) = sqrt(1 - B^2/(AC)), Eq. (12)
+                float ratio = (B * B) / (A * C);
+                float fs = 1.0f - ratio;
+                if (fs < 0.0f) fs = 0.0f;
+                float f = sqrtf(fs);
+                float fw = f * xm, fh = f * ym;
+                bool maj_same = B > 0.0f;  // major axis through (+,+) and (-,-)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    int qsx = (q & 1) ? 1 : -1;
+                    int qsy = (q & 2) ? 1 : -1;
+                    bool major = maj_same ? (qsx == qsy) : (qsx != qsy);
+                    if (!major && mode == QB_BOX_DUALBOX) continue;
+                    float bw = major ? xm : fw;
+                    float bh = major ? ym : fh;
+                    float x0 = qsx > 0 ? u : u - bw;
+                    float x1 = qsx > 0 ? u + bw : u;
+                    float y0 = qsy > 0 ? v : v - bh;
+                    float y1 = qsy > 0 ? v + bh : v;
+                    rr[q] = box_rect(x0, x1, y0, y1, cam.W, cam.H);
+                }
+            }
+        }
+        QSeg seg[QB_MAX_SEG];
+        int axis;
+        qpass_segments(rr, seg, &axis, &count);
+        s0 = make_float4(u, v, pz, o);
+        s1 = make_float4(ca, cb, cc, gam);
+        s2 = make_float4(rgb[0], rgb[1], rgb[2], 1.0f);
+        vis = true;
+    } while (0);
+    (void)vis;
+
+    out_splat[3 * i + 0] = s0;
+    out_splat[3 * i + 1] = s1;
+    out_splat[3 * i + 2] = s2;
+    int4 p0, p1;
+    p0.x = (rr[0].x0 & 0xFFFF) | (rr[0].x1 << 16);
+    p0.y = (rr[0].y0 & 0xFFFF) | (rr[0].y1 << 16);
+    p0.z = (rr[1].x0 & 0xFFFF) | (rr[1].x1 << 16);
+    p0.w = (rr[1].y0 & 0xFFFF) | (rr[1].y1 << 16);
+    p1.x = (rr[2].x0 & 0xFFFF) | (rr[2].x1 << 16);
+    p1.y = (rr[2].y0 & 0xFFFF) | (rr[2].y1 << 16);
+    p1.z = (rr[3].x0 & 0xFFFF) | (rr[3].x1 << 16);
+    p1.w = (rr[3].y0 & 0xFFFF) | (rr[3].y1 << 16);
+    out_rects[2 * i + 0] = p0;
+    out_rects[2 * i + 1] = p1;
+    out_count[i] = count;
+}
+
+}  // namespace
+
+extern "C" qb_status qb_project(int64_t n, const float* means, const float* log_scales,
+                                const float* quats, const float* opacity_logits, const float* sh,
+                                int32_t sh_degree, const qb_camera* cam, int32_t mode,
+                                qb_splat* out_splats, qb_rects* out_rects, int32_t* out_counts,
+                                qb_stream_t stream)
+{
+    if (n < 0 || n >= (int64_t)1 << 31 || !cam || sh_degree < 0 || sh_degree > 3) return QB_ERR_INVALID_ARG;
+    if (mode < QB_BOX_3SIGMA || mode > QB_BOX_DUALBOX) return QB_ERR_INVALID_ARG;
+    if (cam->width <= 0 || cam->height <= 0 || cam->width > 32767 * QB_TILE ||
+        cam->height > 32767 * QB_TILE)
+        return QB_ERR_INVALID_ARG;
+    if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return QB_ERR_INVALID_ARG;
+    if (n == 0) return QB_OK;
+    if (!means || !log_scales || !quats || !opacity_logits || !sh || !out_splats || !out_rects ||
+        !out_counts)
+        return QB_ERR_INVALID_ARG;
+    ProjCam pc;
+    pc.W = cam->width;
+    pc.H = cam->height;
+    pc.tiles_x = (int)qb_div_up(cam->width, QB_TILE);
+    pc.tiles_y = (int)qb_div_up(cam->height, QB_TILE);
+    pc.fx = cam->fx; pc.fy = cam->fy; pc.cx = cam->cx; pc.cy = cam->cy;
+    pc.near_plane = cam->near_plane;
+    for (int k = 0; k < 9; ++k) pc.R[k] = cam->R[k];
+    for (int k = 0; k < 3; ++k) { pc.t[k] = cam->t[k]; pc.campos[k] = cam->campos[k]; }
+    // 1.3 x tan(half fov), in the same binary32 order as the oracle
+    volatile float hx = 0.5f * (float)cam->width;
+    volatile float hy = 0.5f * (float)cam->height;
+    pc.limx = 1.3f * (hx / cam->fx);
+    pc.limy = 1.3f * (hy / cam->fy);
+    int64_t grid = qb_div_up(n, QB_BLOCK);
+    QB_LAUNCH(k_project, grid, QB_BLOCK, 0, qb_hip_stream(stream), n, means, log_scales, quats,
+              opacity_logits, sh, (int)sh_degree, pc, (int)mode,
+              reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects), out_counts);
+    return QB_OK;
+}

@@ -1,0 +1,327 @@
+// Device-wide exclusive scan and a stable LSD radix sort for wave64 (gfx950).
+//
+// Both are reduce-then-scan: no workgroup ever waits on another, so there is
+// no inter-workgroup spin and no forward-progress assumption.
+//   scan:  per-block reduction -> recursive scan of block totals -> per-block scan
+//   radix pass (<= 8 bits):
+//     upsweep   per-block digit histogram in LDS, stored digit-major
+//     scan      exclusive scan of the digit-major histogram (global offsets)
+//     downsweep per-block stable ranks: each wave owns a contiguous run of the
+//               block's items and ranks 64 at a time by matching digits with
+//               one ballot per digit bit; per-wave digit counts are combined
+//               across the 4 waves in LDS; items scatter to offset + rank.
+#pragma once
+
+#include "qb_common.h"
+
+namespace qbr {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 2048 items per block
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortItems = 16;                           // per lane
+constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 items per block
+
+// Inclusive scan across one wave64 (Hillis-Steele over lane shuffles).
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v)
+{
+    int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan over the block (256 threads); returns the block total too.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* total, T* lds /*[4]*/)
+{
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T inc = wave_inclusive_scan(v);
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    T wbase = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        T x = lds[w];
+        if (w < wave) wbase += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return wbase + inc - v;
+}
+
+// ---- device-wide exclusive scan --------------------------------------------
+
+template <typename TIn, typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const TIn* __restrict__ in, int64_t n,
+                                                              T* __restrict__ block_sums)
+{
+    __shared__ T lds[4];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (idx < n) s += (T)in[idx];
+    }
+    T tot;
+    block_exclusive_scan<T>(s, &tot, lds);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// Block scan of kScanTile items: coalesced load to LDS, per-thread serial scan
+// of 8 consecutive items, block scan of the thread totals, coalesced store.
+template <typename TIn, typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const TIn* __restrict__ in, int64_t n,
+                                                             const T* __restrict__ block_base,
+                                                             T* __restrict__ out,
+                                                             T* __restrict__ total_out)
+{
+    __shared__ T tile[kScanTile];
+    __shared__ T lds[4];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
+        tile[k * kScanThreads + threadIdx.x] = idx < n ? (T)in[idx] : (T)0;
+    }
+    __syncthreads();
+    T loc[kScanItems];
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        loc[k] = s;
+        s += tile[threadIdx.x * kScanItems + k];
+    }
+    T tot;
+    T tb = block_exclusive_scan<T>(s, &tot, lds);
+    T bb = block_base ? block_base[blockIdx.x] : (T)0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = bb + tb + loc[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (idx < n) out[idx] = tile[k * kScanThreads + threadIdx.x];
+    }
+    if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = bb + tot;
+}
+
+// Scratch elements of type T the recursive scan of n items needs.
+inline int64_t scan_scratch(int64_t n)
+{
+    int64_t need = 0;
+    while (n > kScanTile) {
+        n = qb_div_up(n, kScanTile);
+        need += 2 * qb_div_up(n, 64) * 64;
+    }
+    return need + 64;
+}
+
+// out[i] = sum of in[0..i); *total_out (device, optional) = sum of all.
+template <typename TIn, typename T>
+qb_status exclusive_scan(const TIn* in, T* out, int64_t n, T* scratch, T* total_out, hipStream_t s)
+{
+    if (n <= 0) return QB_OK;
+    int64_t nb = qb_div_up(n, kScanTile);
+    if (nb == 1) {
+        QB_LAUNCH((k_scan_apply<TIn, T>), 1, kScanThreads, 0, s, in, n, (const T*)nullptr, out, total_out);
+        return QB_OK;
+    }
+    int64_t pad = qb_div_up(nb, 64) * 64;
+    T* sums = scratch;
+    T* sums_scan = scratch + pad;
+    QB_LAUNCH((k_scan_reduce<TIn, T>), nb, kScanThreads, 0, s, in, n, sums);
+    QB_CHECK((exclusive_scan<T, T>(sums, sums_scan, nb, scratch + 2 * pad, (T*)nullptr, s)));
+    QB_LAUNCH((k_scan_apply<TIn, T>), nb, kScanThreads, 0, s, in, n, (const T*)sums_scan, out, total_out);
+    return QB_OK;
+}
+
+// ---- radix sort --------------------------------------------------------------
+
+// Number of items the sort sees: *n_dev clamped to [0, cap]; a count above
+// the capacity means the producer overflowed, and nothing is sorted.
+__device__ __forceinline__ int64_t sort_count(const int64_t* n_dev, int64_t n_host, int64_t cap)
+{
+    int64_t n = n_dev ? *n_dev : n_host;
+    if (n < 0 || n > cap) n = 0;
+    return n;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask)
+{
+    return (uint32_t)(key >> shift) & mask;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(
+    const K* __restrict__ keys, const int64_t* n_dev, int64_t n_host, int64_t cap, int shift,
+    int bits, uint32_t* __restrict__ hist, int64_t nblocks)
+{
+    __shared__ uint32_t h[kSortWaves][kRadix];
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&h[0][0])[d] = 0;
+    __syncthreads();
+    int64_t n = sort_count(n_dev, n_host, cap);
+    uint32_t mask = (1u << bits) - 1u;
+    int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * 64 * kSortItems;
+#pragma unroll 4
+    for (int r = 0; r < kSortItems; ++r) {
+        int64_t idx = base + r * 64 + lane;
+        if (idx < n) atomicAdd(&h[wave][digit_of(keys[idx], shift, mask)], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) t += h[w][d];
+        if (d <= (int)mask) hist[(int64_t)d * nblocks + blockIdx.x] = t;
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(
+    const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, K* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, const int64_t* n_dev, int64_t n_host, int64_t cap, int shift,
+    int bits, const uint32_t* __restrict__ offs, int64_t nblocks)
+{
+    __shared__ uint32_t wcnt[kSortWaves][kRadix];
+    __shared__ uint32_t gbase[kRadix];
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int64_t n = sort_count(n_dev, n_host, cap);
+    int64_t blk0 = (int64_t)blockIdx.x * kSortTile;
+    if (blk0 >= n) return;
+    uint32_t mask = (1u << bits) - 1u;
+    for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&wcnt[0][0])[d] = 0;
+    for (int d = threadIdx.x; d <= (int)mask; d += kSortThreads) gbase[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+    __syncthreads();
+
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int64_t base = blk0 + (int64_t)wave * 64 * kSortItems;
+    K kv[kSortItems];
+    uint32_t vv[kSortItems];
+    uint32_t rank[kSortItems];
+    uint32_t dig[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        int64_t idx = base + r * 64 + lane;
+        bool valid = idx < n;
+        K k = valid ? keys_in[idx] : (K)0;
+        uint32_t v = valid ? vals_in[idx] : 0u;
+        uint32_t d = digit_of(k, shift, mask);
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        uint32_t below = (uint32_t)__popcll(peers & lt);
+        uint32_t cnt = (uint32_t)__popcll(peers);
+        uint32_t old = valid ? wcnt[wave][d] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && below + 1 == cnt) wcnt[wave][d] = old + cnt;
+        __builtin_amdgcn_wave_barrier();
+        kv[r] = k;
+        vv[r] = v;
+        dig[r] = valid ? d : 0xFFFFFFFFu;
+        rank[r] = old + below;
+    }
+    __syncthreads();
+    // exclusive prefix of the per-wave digit counts across waves
+    for (int d = threadIdx.x; d <= (int)mask; d += kSortThreads) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+            uint32_t t = wcnt[w][d];
+            wcnt[w][d] = s;
+            s += t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        if (dig[r] == 0xFFFFFFFFu) continue;
+        uint32_t pos = gbase[dig[r]] + wcnt[wave][dig[r]] + rank[r];
+        keys_out[pos] = kv[r];
+        vals_out[pos] = vv[r];
+    }
+}
+
+// Scratch bytes of one sort over `cap` items.
+inline size_t radix_scratch_bytes(int64_t cap)
+{
+    int64_t nb = qb_div_up(cap > 0 ? cap : 1, kSortTile);
+    int64_t hist = nb * kRadix;
+    return (size_t)(2 * hist + scan_scratch(hist) + 256) * sizeof(uint32_t);
+}
+
+template <typename K>
+__global__ __launch_bounds__(QB_BLOCK) void k_copy_items(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                         K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                         const int64_t* n_dev, int64_t n_host, int64_t cap)
+{
+    int64_t n = sort_count(n_dev, n_host, cap);
+    for (int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * QB_BLOCK) {
+        kout[i] = kin[i];
+        vout[i] = vin[i];
+    }
+}
+
+// Stable sort of (keys, vals) by key bits [lo_bit, hi_bit) in passes of at
+// most 8 bits (bits spread evenly over the passes).  Reads (kin, vin), ends in
+// (kout, vout), and uses (ktmp, vtmp) for the intermediate passes; kin may
+// alias kout only when the pass count is even.  The item count is *n_dev when
+// n_dev is given (clamped as in sort_count), else n_host; cap sizes the grid.
+template <typename K>
+qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, K* ktmp, uint32_t* vtmp,
+                     const int64_t* n_dev, int64_t n_host, int64_t cap, int lo_bit, int hi_bit,
+                     uint32_t* scratch, hipStream_t s)
+{
+    if (cap <= 0) return QB_OK;
+    int total_bits = hi_bit - lo_bit;
+    int np = total_bits > 0 ? (total_bits + kRadixBits - 1) / kRadixBits : 0;
+    if (np == 0) {
+        if ((const void*)kin != (const void*)kout) {
+            int64_t g = qb_div_up(cap, QB_BLOCK);
+            if (g > 4096) g = 4096;
+            QB_LAUNCH((k_copy_items<K>), g, QB_BLOCK, 0, s, kin, vin, kout, vout, n_dev, n_host, cap);
+        }
+        return QB_OK;
+    }
+    int64_t nb = qb_div_up(cap, kSortTile);
+    int64_t hn = nb * kRadix;
+    uint32_t* hist = scratch;
+    uint32_t* offs = scratch + hn;
+    uint32_t* sscr = scratch + 2 * hn;
+    int shift = lo_bit;
+    const K* src_k = kin;
+    const uint32_t* src_v = vin;
+    for (int p = 0; p < np; ++p) {
+        int bits = (total_bits - (shift - lo_bit) + (np - p) - 1) / (np - p);
+        bool to_out = ((np - 1 - p) & 1) == 0;
+        K* dk = to_out ? kout : ktmp;
+        uint32_t* dv = to_out ? vout : vtmp;
+        int64_t hn_used = (int64_t)(1 << bits) * nb;
+        QB_LAUNCH((k_radix_upsweep<K>), nb, kSortThreads, 0, s, src_k, n_dev, n_host, cap, shift, bits, hist, nb);
+        QB_CHECK((exclusive_scan<uint32_t, uint32_t>(hist, offs, hn_used, sscr, (uint32_t*)nullptr, s)));
+        QB_LAUNCH((k_radix_downsweep<K>), nb, kSortThreads, 0, s, src_k, src_v, dk, dv, n_dev, n_host, cap,
+                  shift, bits, (const uint32_t*)offs, nb);
+        src_k = dk;
+        src_v = dv;
+        shift += bits;
+    }
+    return QB_OK;
+}
+
+}  // namespace qbr

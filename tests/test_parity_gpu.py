@@ -1,0 +1,243 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element
+by element on the same seeded inputs.
+
+Bars: bit-exact for every value that decides an integer (mean2D, depth,
+conic, opacity, gamma), for the tile counts, the sorted (key, id) list and the
+ranges; colour within 1e-5; image and final transmittance within 1e-4 max-abs
+per channel outside the oracle's near-threshold mask (pixels whose stopping
+test came within a relative 1e-4 of T = 1e-4, where binary32 and binary64
+transmittances may legitimately stop at different Gaussians); n_contrib exact
+outside that mask."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2605_04844_amd import scenes  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["3sigma", "adr", "quadbox", "dualbox"]
+IMG_TOL = 1e-4
+RGB_TOL = 1e-5
+
+
+def say(*a):
+    print("[parity]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def qb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_04844_amd import quadbox
+    quadbox.lib()
+    return quadbox
+
+
+def gpu_forward(qb, scene, cam, mode, bg=(0.0, 0.0, 0.0), capacity=0):
+    g = qb.Gaussians(scene)
+    r = qb.Rasterizer(scene.n, cam, capacity=capacity)
+    r.forward(g, mode, bg)
+    torch.cuda.synchronize()
+    P = r.pairs()
+    out = dict(
+        splats=r.splats.cpu().numpy()[:scene.n],
+        rects=r.rects.cpu().numpy()[:scene.n],
+        counts=r.counts.cpu().numpy()[:scene.n],
+        P=P,
+        keys=r.keys_sorted[:P].cpu().numpy().view(np.uint64),
+        ids=r.ids_sorted[:P].cpu().numpy().view(np.uint32),
+        ranges=r.ranges.cpu().numpy().view(np.uint32),
+        image=r.image.cpu().numpy(),
+        T=r.final_T.cpu().numpy(),
+        n_contrib=r.n_contrib.cpu().numpy().view(np.uint32),
+    )
+    return out, r
+
+
+def bits(x):
+    return np.ascontiguousarray(x, np.float32).view(np.uint32)
+
+
+def check_project(oracle, gpu, g, label):
+    vis_o = g["visible"] == 1
+    vis_g = gpu["splats"][:, 11] == 1.0
+    assert np.array_equal(vis_o, vis_g), f"{label}: visibility differs at {np.nonzero(vis_o != vis_g)[0][:10]}"
+    sp = gpu["splats"][vis_o]
+    gv = g[vis_o]
+    for col, name in [(0, "u"), (1, "v"), (2, "depth"), (3, "opacity"), (4, "a"), (5, "b"), (6, "c"),
+                      (7, "gamma")]:
+        diff = np.nonzero(bits(sp[:, col]) != bits(gv[name]))[0]
+        assert diff.size == 0, f"{label}: {name} differs for {diff.size} Gaussians, e.g. {diff[:5]}"
+    rgb_err = np.abs(sp[:, 8:11] - gv["rgb"]).max() if sp.shape[0] else 0.0
+    assert rgb_err <= RGB_TOL, f"{label}: rgb err {rgb_err}"
+
+
+def check_counts(oracle, gpu, g, tiles_x, label):
+    want = oracle.tile_counts(g, tiles_x)
+    diff = np.nonzero(gpu["counts"].astype(np.int64) != want)[0]
+    assert diff.size == 0, f"{label}: counts differ for {diff.size}, e.g. {diff[:5]}"
+    assert gpu["P"] == int(want.sum())
+
+
+def check_image(oracle_img, oracle_T, oracle_nc, near, gpu, label, tiles=None):
+    ok = ~near
+    if tiles is not None:
+        ok = ok & tiles
+    err = np.abs(gpu["image"] - oracle_img).max(axis=0)
+    terr = np.abs(gpu["T"] - oracle_T)
+    worst = float(err[ok].max()) if ok.any() else 0.0
+    assert worst <= IMG_TOL, f"{label}: image err {worst} at {np.unravel_index(np.argmax(np.where(ok, err, 0)), err.shape)}"
+    assert float(terr[ok].max()) <= IMG_TOL if ok.any() else True
+    bad = np.nonzero((gpu["n_contrib"] != oracle_nc) & ok)
+    assert bad[0].size == 0, f"{label}: n_contrib differs at {bad[0].size} pixels"
+    say(f"{label}: max image err {worst:.2e}, masked pixels {int(near.sum())}")
+
+
+def full_check(oracle, qb, scene, cam, mode, bg=(0.0, 0.0, 0.0)):
+    label = f"{mode} N={scene.n} {cam.width}x{cam.height}"
+    say("running", label)
+    gpu, _ = gpu_forward(qb, scene, cam, mode, bg)
+    ref = oracle.forward(scene, cam, mode, bg)
+    check_project(oracle, gpu, ref["g"], label)
+    check_counts(oracle, gpu, ref["g"], cam.tiles_x, label)
+    assert np.array_equal(gpu["keys"], ref["keys"]), f"{label}: sorted keys differ"
+    assert np.array_equal(gpu["ids"], ref["ids"]), f"{label}: sorted ids differ"
+    assert np.array_equal(gpu["ranges"], ref["ranges"]), f"{label}: ranges differ"
+    check_image(ref["image"], ref["T"], ref["n_contrib"], ref["near"], gpu, label)
+    return gpu, ref
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_small_scene_all_modes(oracle, qb, mode):
+    """10k Gaussians, 256x256, SH degree 0 (the small workload), every box mode."""
+    scene, cam = scenes.small_scene()
+    full_check(oracle, qb, scene, cam, mode)
+
+
+@pytest.mark.parametrize("seed,n,w,h,deg", [(101, 3000, 200, 120, 3), (102, 700, 100, 37, 1),
+                                            (103, 5000, 333, 250, 2), (104, 1, 64, 64, 3)])
+def test_ragged_sizes(oracle, qb, seed, n, w, h, deg):
+    """Image sizes that are not tile multiples, all SH degrees, tiny N."""
+    scene, cam = scenes.random_scene(seed, n, w, h, 0.9 * w, sh_degree=deg, log_scale_mu=-3.5)
+    full_check(oracle, qb, scene, cam, "quadbox", bg=(0.1, 0.2, 0.3))
+
+
+def test_anisotropic_rotated_camera(oracle, qb):
+    """Highly anisotropic Gaussians (ratio up to 100), rotated camera, zoomed."""
+    scene, _ = scenes.aniso_scene(n=20_000)
+    from scipy.spatial.transform import Rotation
+    R = Rotation.from_euler("xyz", [0.1, -0.2, 0.3]).as_matrix().astype(np.float32)
+    cam = scenes.pinhole(320, 240, 900.0, R, np.array([0.1, -0.2, 0.5], np.float32))
+    for mode in ("quadbox", "adr"):
+        full_check(oracle, qb, scene, cam, mode)
+
+
+def test_edge_cases(oracle, qb):
+    """n = 0, everything culled, one Gaussian covering the whole image."""
+    cam = scenes.pinhole(80, 48, 80.0)
+    empty = scenes.random_scene(7, 0, 80, 48, 80.0)[0]
+    say("edge: empty scene")
+    gpu, _ = gpu_forward(qb, empty, cam, "quadbox", bg=(0.25, 0.5, 0.75))
+    assert gpu["P"] == 0
+    assert np.allclose(gpu["image"][0], 0.25) and np.allclose(gpu["image"][2], 0.75)
+    assert np.all(gpu["T"] == 1.0) and np.all(gpu["n_contrib"] == 0)
+    behind, _ = scenes.random_scene(8, 500, 80, 48, 80.0)
+    behind.means[2] = -behind.means[2]
+    say("edge: all behind the camera")
+    gpu, _ = gpu_forward(qb, behind, cam, "quadbox")
+    assert gpu["P"] == 0 and np.all(gpu["splats"][:, 11] == 0)
+    big, _ = scenes.random_scene(9, 3, 80, 48, 80.0)
+    big.means[:] = np.array([[0.0, 0.1, -0.05], [0.0, -0.1, 0.02], [3.0, 3.0, 3.0]], np.float32)
+    big.log_scales[:] = 0.5
+    full_check(oracle, qb, big, cam, "quadbox")
+
+
+def test_capacity_overflow(qb):
+    """With too small a pair capacity nothing is written and every range is empty."""
+    scene, cam = scenes.small_scene(n=2000)
+    g = qb.Gaussians(scene)
+    r = qb.Rasterizer(scene.n, cam, capacity=100)
+    say("capacity overflow")
+    r.project(g, "quadbox")
+    r.intersect()
+    r.sort()
+    r.render((0.0, 0.0, 0.0))
+    torch.cuda.synchronize()
+    assert r.pairs() > 100
+    assert np.all(r.ranges.cpu().numpy() == 0)
+    assert np.all(r.image.cpu().numpy() == 0.0)
+
+
+def test_deterministic(qb):
+    scene, cam = scenes.small_scene()
+    say("determinism")
+    a, _ = gpu_forward(qb, scene, cam, "quadbox")
+    b, _ = gpu_forward(qb, scene, cam, "quadbox")
+    for k in ("keys", "ids", "ranges", "image", "T", "n_contrib"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_quadbox_image_equals_adr_image(qb):
+    """A conservative culling changes tile lists, not pixels (bitwise)."""
+    scene, cam = scenes.small_scene()
+    say("image invariance")
+    a, _ = gpu_forward(qb, scene, cam, "adr")
+    q, _ = gpu_forward(qb, scene, cam, "quadbox")
+    assert q["P"] < a["P"]
+    assert np.array_equal(a["image"], q["image"]) and np.array_equal(a["T"], q["T"])
+
+
+def _sampled_tile_check(oracle, gpu, g, cam, tiles, label):
+    for t in tiles:
+        want = oracle.tile_list(g, cam.tiles_x, int(t))
+        s, e = gpu["ranges"][t]
+        got = gpu["ids"][s:e]
+        assert np.array_equal(got, want), f"{label}: tile {t} list differs ({len(got)} vs {len(want)})"
+
+
+def _sampled_render_check(oracle, gpu, g, cam, tiles, label):
+    """Oracle render of only the sampled tiles (their lists built by the oracle)."""
+    lists = [oracle.tile_list(g, cam.tiles_x, int(t)) for t in tiles]
+    rt = np.zeros((cam.num_tiles, 2), np.uint32)
+    pos = 0
+    for t, lst in zip(tiles, lists):
+        rt[t] = (pos, pos + len(lst))
+        pos += len(lst)
+    ids = np.concatenate(lists).astype(np.uint32) if pos else np.zeros(1, np.uint32)
+    img, T, nc, near = oracle.render(g, cam.width, cam.height, rt, ids)
+    mask = np.zeros((cam.height, cam.width), bool)
+    for t in tiles:
+        ty, tx = divmod(int(t), cam.tiles_x)
+        mask[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = True
+    check_image(img, T, nc, near, gpu, label, tiles=mask)
+
+
+@pytest.mark.parametrize("mode", ["quadbox", "3sigma"])
+def test_full_size_clusters(oracle, qb, mode):
+    """The 1M-Gaussian 1280x720 SH3 workload at full size: every projected
+    value and tile count bit-exact, keys globally sorted with consistent depth
+    bits, 160 sampled tile lists and 40 sampled tiles of pixels against the
+    oracle."""
+    scene, cam = scenes.cluster_scene()
+    label = f"clusters-1M {mode}"
+    say("running", label)
+    gpu, _ = gpu_forward(qb, scene, cam, mode)
+    g = oracle.project(scene, cam, mode)
+    check_project(oracle, gpu, g, label)
+    check_counts(oracle, gpu, g, cam.tiles_x, label)
+    keys, ids = gpu["keys"], gpu["ids"]
+    assert np.all(keys[1:] >= keys[:-1])
+    tie = keys[1:] == keys[:-1]
+    assert np.all(ids[1:][tie] > ids[:-1][tie])
+    assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), bits(g["depth"])[ids])
+    want_rt = oracle.ranges(keys, cam.num_tiles)
+    assert np.array_equal(gpu["ranges"], want_rt)
+    rng = np.random.default_rng(5)
+    busy = np.argsort(gpu["ranges"][:, 1] - gpu["ranges"][:, 0])[-20:]
+    tiles = np.unique(np.concatenate([rng.choice(cam.num_tiles, 140, replace=False), busy]))
+    _sampled_tile_check(oracle, gpu, g, cam, tiles, label)
+    _sampled_render_check(oracle, gpu, g, cam, tiles[:40], label)
