@@ -124,59 +124,65 @@ size_t qb_intersect_workspace_size(int64_t n);
 
 /* qb_intersect -- DuplicateWithKeys with the QPass traversal (Sec. 2, 3.2).
  * Orders the Gaussians by (depth bits, id), takes the exclusive prefix sum of
- * their counts in that order, then writes for every tile of every Gaussian's
- * tile set exactly one pair
- *     key = (uint64)tile << 32 | float_bits(depth),   id = Gaussian index.
+ * their tile counts in that order, then writes for every tile of every
+ * Gaussian's tile set, enumerated by QPass, exactly one pair
+ *     (tile, id):  the pair with key (uint64)tile << 32 | float_bits(depth).
  * The pairs of one Gaussian are contiguous and the Gaussians appear in
  * ascending (depth, id) order; qb_sort relies on that order.
- *   splats, rects, counts   outputs of qb_project for the same n
- *   pair_capacity           entries available in keys/ids
- *   keys, ids               [pair_capacity] uint64 / uint32
+ *   splats, rects, counts   outputs of qb_project for the same n and camera
+ *   width, height           image size; at most 65536 tiles
+ *   pair_capacity           entries available in pair_tiles / pair_ids
+ *   pair_tiles, pair_ids    [pair_capacity] uint16 tile id / uint32 Gaussian id
  *   num_pairs               device int64: receives the total pair count P,
  *                           also when P > pair_capacity; then no pair is
  *                           written, qb_sort writes empty ranges and the
  *                           caller re-runs with a larger capacity
- *   workspace               qb_intersect_workspace_size(n) bytes           */
+ *   workspace               qb_intersect_workspace_size(n) bytes
+ * Returns QB_ERR_UNSUPPORTED for more than 65536 tiles. */
 qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_rects* rects,
-                       const int32_t* counts, int32_t width, int32_t height,
-                       int64_t pair_capacity, uint64_t* keys, uint32_t* ids,
-                       int64_t* num_pairs, void* workspace, size_t workspace_bytes,
-                       qb_stream_t stream);
+                       const int32_t* counts, int32_t width, int32_t height, int64_t pair_capacity,
+                       uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs, void* workspace,
+                       size_t workspace_bytes, qb_stream_t stream);
 
 /* Workspace bytes qb_sort needs for a pair capacity. */
-size_t qb_sort_workspace_size(int64_t pair_capacity, int32_t num_tiles);
+size_t qb_sort_workspace_size(int64_t pair_capacity);
 
-/* qb_sort -- SortPairs (Sec. 2): the P = *num_pairs pairs of keys_in/ids_in,
- * produced by qb_intersect, in ascending (key, id) order into
- * keys_out/ids_out, and per-tile ranges of the sorted list:
+/* qb_sort -- SortPairs (Sec. 2): the P = *num_pairs pairs written by
+ * qb_intersect, in ascending (key, id) order, and per-tile ranges of the
+ * sorted list:
  *   ranges[2t] = first index with tile >= t, ranges[2t+1] = first index with
  *   tile > t (empty tiles get start == end).
  * Only the tile bits are sorted (a stable LSD radix sort), since qb_intersect
  * emits the pairs in (depth, id) order.  When P > pair_capacity nothing is
  * sorted and every range is [0, 0).
- *   num_tiles        tiles_x * tiles_y, 1 .. 2^24
- *   keys_in, ids_in  [pair_capacity]; not modified
- *   keys_out, ids_out [pair_capacity]
- *   ranges           [num_tiles][2] uint32                                  */
+ *   num_tiles              tiles_x * tiles_y, 1 .. 65536
+ *   pair_tiles, pair_ids   from qb_intersect; not modified
+ *   splats                 from qb_project; read only when keys != NULL
+ *   keys                   [pair_capacity] uint64 sorted keys, or NULL to skip
+ *   ids                    [pair_capacity] uint32 sorted Gaussian ids
+ *   ranges                 [num_tiles][2] uint32                              */
 qb_status qb_sort(int64_t pair_capacity, const int64_t* num_pairs, int32_t num_tiles,
-                  const uint64_t* keys_in, const uint32_t* ids_in, uint64_t* keys_out,
-                  uint32_t* ids_out, uint32_t* ranges, void* workspace, size_t workspace_bytes,
-                  qb_stream_t stream);
+                  const uint16_t* pair_tiles, const uint32_t* pair_ids, const qb_splat* splats,
+                  uint64_t* keys, uint32_t* ids, uint32_t* ranges, void* workspace,
+                  size_t workspace_bytes, qb_stream_t stream);
 
 /* qb_render -- Eq. (2) per pixel over its tile's sorted list: front to back,
  * skipping a Gaussian where its quadratic form exceeds gamma (alpha < 1/255,
  * Eq. (4)), alpha = min(0.99, o exp(-q/2)), stopping before the first
  * Gaussian that would take T below 1e-4; output C + T * bg.
- *   ranges, ids      from qb_sort (ids = ids_out)
+ *   ranges, ids      from qb_sort
  *   splats           from qb_project
  *   bg               host pointer to 3 floats
  *   image            [3][H][W] float
  *   final_T          [H][W] float (may be NULL)
  *   n_contrib        [H][W] uint32: 1 + list index of the last contributor,
- *                    0 if none (may be NULL)                                */
+ *                    0 if none (may be NULL)
+ *   n_touched        [H][W] uint32: list entries the pixel examined, i.e. its
+ *                    stop index, or the list length when it never stopped
+ *                    (may be NULL; the count of Eq. (2) evaluations)        */
 qb_status qb_render(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
                     const qb_splat* splats, const float* bg, float* image, float* final_T,
-                    uint32_t* n_contrib, qb_stream_t stream);
+                    uint32_t* n_contrib, uint32_t* n_touched, qb_stream_t stream);
 
 /* Human-readable name of a status code (static string). */
 const char* qb_status_string(qb_status s);

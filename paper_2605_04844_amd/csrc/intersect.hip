@@ -1,19 +1,26 @@
 // qb_intersect: DuplicateWithKeys with the QPass traversal (Sec. 2, Sec. 3.2).
 //
-//  1. key every Gaussian by its depth bits (0xFFFFFFFF when it covers no tile)
-//     and stable-radix-sort the ids: the (depth, id) order of the final list
-//  2. gather the tile counts in that order and scan them (pair offsets)
-//  3. emit: each 256-lane workgroup takes 256 consecutive Gaussians of that
-//     order, runs QPass for each (one lane per Gaussian) into run descriptors
-//     in LDS, then enumerates the workgroup's pairs pair-parallel: lane p finds
-//     its Gaussian by binary search over the LDS offsets and its tile by O(1)
-//     decoding of the runs, so every lane writes one pair per step and the
-//     stores of a wave are contiguous (coalesced 8-byte keys and 4-byte ids).
-#include "qb_radix.h"
+//  1. key every Gaussian by its depth bits (0xFFFFFFFF when it covers no
+//     tile) and stable-radix-sort the ids: the (depth, id) order that orders
+//     the Gaussians within every tile
+//  2. gather the tile counts in that order and scan them: the pair offsets
+//  3. emit: a 256-lane workgroup takes 256 consecutive Gaussians of that
+//     order and runs QPass for each (one lane per Gaussian); the non-empty
+//     runs (blocks of scanlines with one tile interval) go to a run list in
+//     LDS with the block-relative index of their first pair.  The workgroup
+//     then walks its pairs pair-parallel, 64 consecutive pairs per wave per
+//     step.  The run of each pair comes from a per-step owner table (every run
+//     that starts inside the step marks its first pair; a wave-wide running
+//     maximum carries it to the following pairs), its tile from one division
+//     of the pair's offset in the run; the stores of a wave are contiguous.
+// A pair is stored compactly as (uint16 tile, uint32 Gaussian id); its key
+// tile << 32 | bits(depth) is implied by the id.
+#include "qb_bin.h"
 
 namespace {
 
 constexpr int kEmitThreads = 256;
+constexpr int kDepthNT = 512, kDepthNI = 16;
 
 __global__ __launch_bounds__(QB_BLOCK) void k_depth_keys(int64_t n, const float4* __restrict__ splats,
                                                          const int32_t* __restrict__ counts,
@@ -36,107 +43,107 @@ __global__ __launch_bounds__(QB_BLOCK) void k_gather_counts(int64_t n, const uin
     out[i] = (uint32_t)counts[order[i]];
 }
 
-__device__ __forceinline__ QRect unpack_rect(int lohi_x, int lohi_y)
+__global__ void k_store_total(const uint64_t* __restrict__ tot, int64_t* __restrict__ num_pairs)
 {
-    QRect r;
-    r.x0 = (int)(int16_t)(lohi_x & 0xFFFF);
-    r.x1 = lohi_x >> 16;
-    r.y0 = (int)(int16_t)(lohi_y & 0xFFFF);
-    r.y1 = lohi_y >> 16;
-    return r;
+    *num_pairs = tot ? (int64_t)*tot : 0;
 }
 
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
-    int64_t n, const uint32_t* __restrict__ order, const uint64_t* __restrict__ offs,
-    const float4* __restrict__ splats, const int4* __restrict__ rects,
-    const int32_t* __restrict__ counts, int tiles_x, int64_t cap, const int64_t* __restrict__ num_pairs,
-    uint64_t* __restrict__ keys, uint32_t* __restrict__ ids)
+    int64_t n, const uint32_t* __restrict__ order, const uint64_t* __restrict__ goff,
+    const int4* __restrict__ rects, const int32_t* __restrict__ counts, int tiles_x, int64_t cap,
+    const int64_t* __restrict__ num_pairs, uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id)
 {
-    __shared__ int64_t s_off[kEmitThreads + 1];   // pair offsets relative to the block start
-    __shared__ QSeg s_seg[kEmitThreads][QB_MAX_SEG];
-    __shared__ int s_nseg[kEmitThreads];
-    __shared__ int s_axis[kEmitThreads];
-    __shared__ uint32_t s_id[kEmitThreads];
-    __shared__ uint32_t s_depth[kEmitThreads];
+    constexpr int kRuns = kEmitThreads * QB_MAX_SEG;
+    __shared__ uint32_t s_off[kRuns + 1];  // first pair of each run, block-relative
+    __shared__ uint32_t s_w0[kRuns];       // s0 | lo << 16
+    __shared__ uint32_t s_w1[kRuns];       // len | axis << 16
+    __shared__ uint32_t s_gid[kRuns];      // Gaussian id
+    __shared__ uint32_t s_scan[kEmitThreads / 64];
+    __shared__ int s_tab[kEmitThreads / 64][64];
 
     if (*num_pairs > cap) return;  // overflow: the caller re-runs with more capacity
+    int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int64_t k0 = (int64_t)blockIdx.x * kEmitThreads;
-    int t = threadIdx.x;
     int64_t k = k0 + t;
-    int64_t block_start = offs[k0];
-    int cnt = 0;
+    uint32_t gi = 0;
+    QRuns q;
+#pragma unroll
+    for (int i = 0; i < QB_MAX_SEG; ++i) q.n[i] = 0;
+    q.total = 0;
+    q.axis = 0;
     if (k < n) {
-        uint32_t gi = order[k];
-        cnt = counts[gi];
-        s_id[t] = gi;
-        s_off[t] = (int64_t)offs[k] - block_start;
-        if (cnt > 0) {
-            int4 p0 = rects[2 * (int64_t)gi], p1 = rects[2 * (int64_t)gi + 1];
-            QRect r[4] = {unpack_rect(p0.x, p0.y), unpack_rect(p0.z, p0.w), unpack_rect(p1.x, p1.y),
-                          unpack_rect(p1.z, p1.w)};
-            int axis, total;
-            QSeg seg[QB_MAX_SEG];
-            int ns = qpass_segments(r, seg, &axis, &total);
-            for (int s = 0; s < ns; ++s) s_seg[t][s] = seg[s];
-            s_nseg[t] = ns;
-            s_axis[t] = axis;
-            s_depth[t] = __float_as_uint(splats[3 * (int64_t)gi].z);
-            if (total != cnt) cnt = min(cnt, total);  // never write past the slot
-        } else {
-            s_nseg[t] = 0;
-        }
-    } else {
-        s_off[t] = 0x7FFFFFFFFFFFFFFFll;  // beyond every pair of the block
-        s_nseg[t] = 0;
+        gi = order[k];
+        if (counts[gi] > 0) qbb::gaussian_runs(rects, gi, q);
     }
-    // block pair total: offset of the last valid lane plus its count
-    __shared__ int64_t s_total;
-    int64_t last = min((int64_t)kEmitThreads, n - k0) - 1;
-    if (t == (int)last) s_total = s_off[t] + cnt;
+    uint32_t cnt = (uint32_t)q.total;
+    uint32_t nr = 0;
+#pragma unroll
+    for (int i = 0; i < QB_MAX_SEG; ++i) nr += (q.n[i] > 0 && q.len[i] > 0) ? 1u : 0u;
+    uint32_t total, nruns;
+    uint32_t off = qbr::block_exclusive_scan<uint32_t, kEmitThreads>(cnt, &total, s_scan);
+    uint32_t slot = qbr::block_exclusive_scan<uint32_t, kEmitThreads>(nr, &nruns, s_scan);
+#pragma unroll
+    for (int i = 0; i < QB_MAX_SEG; ++i) {
+        uint32_t sz = (uint32_t)(q.n[i] * q.len[i]);
+        if (sz > 0) {
+            s_off[slot] = off;
+            s_w0[slot] = (uint32_t)q.s0[i] | ((uint32_t)q.lo[i] << 16);
+            s_w1[slot] = (uint32_t)q.len[i] | ((uint32_t)q.axis << 16);
+            s_gid[slot] = gi;
+            ++slot;
+            off += sz;
+        }
+    }
+    if (t == 0) s_off[nruns] = total;  // sentinel
+    int64_t block_start = (int64_t)goff[k0];
     __syncthreads();
-    int64_t total = s_total;
-    int nvalid = (int)(last + 1);
-    for (int64_t p = t; p < total; p += kEmitThreads) {
-        // last Gaussian whose offset is <= p (zero-count ones share offsets
-        // with the next one and are skipped by taking the last match)
-        int lo = 0, hi = nvalid;  // invariant: s_off[lo] <= p < s_off[hi] (s_off[nvalid] = +inf)
+    for (uint32_t base = (uint32_t)wave * 64; base < total; base += kEmitThreads) {
+        // run of the step's first pair: last run with s_off <= base
+        int lo = 0, hi = (int)nruns;
         while (hi - lo > 1) {
             int mid = (lo + hi) >> 1;
-            if (s_off[mid] <= p) lo = mid; else hi = mid;
+            if (s_off[mid] <= base) lo = mid; else hi = mid;
         }
-        int j = lo;
-        int64_t local = p - s_off[j];
-        int ns = s_nseg[j];
-        int tx = -1, ty = -1;
-        for (int s = 0; s < ns; ++s) {
-            QSeg g = s_seg[j][s];
-            int64_t sz = (int64_t)g.n * g.len;
-            if (local < sz) {
-                int q = (int)(local / g.len);
-                int rem = (int)(local - (int64_t)q * g.len);
-                int sl = g.s0 + q, ot = g.lo + rem;
-                if (s_axis[j] == 0) { tx = sl; ty = ot; } else { tx = ot; ty = sl; }
-                break;
+        int j0 = lo;
+        // every later run that starts inside this step marks its first pair;
+        // a running maximum hands the run to the pairs that follow
+        s_tab[wave][lane] = -1;
+        __builtin_amdgcn_wave_barrier();
+        int jj = j0 + lane;
+        if (lane > 0 && jj < (int)nruns) {
+            uint32_t st = s_off[jj];
+            if (st < base + 64) s_tab[wave][st - base] = jj;
+        }
+        __builtin_amdgcn_wave_barrier();
+        int own = qbr::wave_inclusive_max(s_tab[wave][lane]);
+        if (own < 0) own = j0;
+        uint32_t p = base + lane;
+        if (p < total) {
+            uint32_t local = p - s_off[own];
+            uint32_t w0 = s_w0[own], w1 = s_w1[own];
+            uint32_t len = w1 & 0xFFFFu;
+            // local < 2^16, so the float quotient is off by at most one
+            uint32_t qq = (uint32_t)((float)local * __frcp_rn((float)len));
+            int32_t rem = (int32_t)local - (int32_t)(qq * len);
+            if (rem < 0) { --qq; rem += (int32_t)len; }
+            if (rem >= (int32_t)len) { ++qq; rem -= (int32_t)len; }
+            int sl = (int)(w0 & 0xFFFFu) + (int)qq;
+            int ot = (int)(w0 >> 16) + rem;
+            int tile = (w1 >> 16) ? sl * tiles_x + ot : ot * tiles_x + sl;
+            int64_t dst = block_start + p;
+            if (dst < cap) {
+                out_tile[dst] = (uint16_t)tile;
+                out_id[dst] = s_gid[own];
             }
-            local -= sz;
         }
-        if (tx < 0) continue;  // unreachable when counts match the runs
-        int64_t dst = block_start + p;
-        if (dst >= cap) break;
-        keys[dst] = ((uint64_t)(uint32_t)(ty * tiles_x + tx) << 32) | s_depth[j];
-        ids[dst] = s_id[j];
+        __builtin_amdgcn_wave_barrier();
     }
-}
-
-__global__ void k_store_total(const uint64_t* __restrict__ tot, int64_t* __restrict__ num_pairs)
-{
-    *num_pairs = (int64_t)*tot;
 }
 
 struct IsectWs {
-    uint32_t *dk0, *dv0, *dk1, *dv1;  // depth sort ping-pong
-    uint32_t* csorted;                // counts in sorted order
-    uint64_t* offs;                   // n + 1 offsets
+    uint32_t *dk0, *dv0, *dk1, *dv1;  // depth sort ping-pong; dv0 ends as the order
+    uint32_t* csorted;                // counts in that order
+    uint64_t* offs;                   // pair offsets
     uint64_t* total;
     uint64_t* scan64;
     uint32_t* radix;
@@ -153,7 +160,7 @@ IsectWs carve(QbArena& a, int64_t n)
     w.offs = a.take<uint64_t>(n + 1);
     w.total = a.take<uint64_t>(1);
     w.scan64 = a.take<uint64_t>(qbr::scan_scratch(n));
-    w.radix = a.take<uint32_t>((int64_t)(qbr::radix_scratch_bytes(n) / sizeof(uint32_t)));
+    w.radix = a.take<uint32_t>((int64_t)(qbr::radix_scratch_bytes<kDepthNT, kDepthNI>(n) / sizeof(uint32_t)));
     return w;
 }
 
@@ -168,39 +175,38 @@ extern "C" size_t qb_intersect_workspace_size(int64_t n)
 }
 
 extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_rects* rects,
-                                  const int32_t* counts, int32_t width, int32_t height,
-                                  int64_t pair_capacity, uint64_t* keys, uint32_t* ids,
-                                  int64_t* num_pairs, void* workspace, size_t workspace_bytes,
-                                  qb_stream_t stream)
+                                  const int32_t* counts, int32_t width, int32_t height, int64_t pair_capacity,
+                                  uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs, void* workspace,
+                                  size_t workspace_bytes, qb_stream_t stream)
 {
     if (n < 0 || n >= (int64_t)1 << 31 || width <= 0 || height <= 0 || pair_capacity < 0 ||
-        pair_capacity > (int64_t)0xFFFFFFFF || !num_pairs)
+        pair_capacity > (int64_t)0xFFFFFFFF || !num_pairs || !workspace)
         return QB_ERR_INVALID_ARG;
-    if (width > 32767 * QB_TILE || height > 32767 * QB_TILE) return QB_ERR_INVALID_ARG;
-    if (n > 0 && (!splats || !rects || !counts || !workspace)) return QB_ERR_INVALID_ARG;
-    if (pair_capacity > 0 && (!keys || !ids)) return QB_ERR_INVALID_ARG;
+    int tiles_x = (int)qb_div_up(width, QB_TILE);
+    int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
+    if (tiles > 65536) return QB_ERR_UNSUPPORTED;
+    if (n > 0 && (!splats || !rects || !counts)) return QB_ERR_INVALID_ARG;
+    if (pair_capacity > 0 && (!pair_tiles || !pair_ids)) return QB_ERR_INVALID_ARG;
     if (workspace_bytes < qb_intersect_workspace_size(n)) return QB_ERR_INVALID_ARG;
     hipStream_t s = qb_hip_stream(stream);
-    if (n == 0) {
-        if (hipMemsetAsync(num_pairs, 0, sizeof(int64_t), s) != hipSuccess) return QB_ERR_HIP;
-        return QB_OK;
-    }
     QbArena a{(char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255), workspace_bytes - 256, 0};
     IsectWs w = carve(a, n);
     if (!a.ok()) return QB_ERR_INVALID_ARG;
-    int tiles_x = (int)qb_div_up(width, QB_TILE);
+    if (n == 0) {
+        QB_LAUNCH(k_store_total, 1, 1, 0, s, (const uint64_t*)nullptr, num_pairs);  // no pairs
+        return QB_OK;
+    }
     int64_t grid = qb_div_up(n, QB_BLOCK);
-    const float4* sp = reinterpret_cast<const float4*>(splats);
-    QB_LAUNCH(k_depth_keys, grid, QB_BLOCK, 0, s, n, sp, counts, w.dk0, w.dv0);
-    // four 8-bit passes: ends back in (dk0, dv0)
-    QB_CHECK((qbr::radix_sort<uint32_t>(w.dk0, w.dv0, w.dk0, w.dv0, w.dk1, w.dv1, (const int64_t*)nullptr, n, n,
-                                        0, 32, w.radix, s)));
-    const uint32_t* order = w.dv0;
-    QB_LAUNCH(k_gather_counts, grid, QB_BLOCK, 0, s, n, order, counts, w.csorted);
+    QB_LAUNCH(k_depth_keys, grid, QB_BLOCK, 0, s, n, reinterpret_cast<const float4*>(splats), counts, w.dk0, w.dv0);
+    // four 8-bit passes: (dk0, dv0) -> (dk1, dv1) -> (dk0, dv0) -> ...
+    QB_CHECK((qbr::radix_sort<uint32_t, kDepthNT, kDepthNI>(w.dk0, w.dv0, w.dk0, w.dv0, w.dk1, w.dv1,
+                                                            (const int64_t*)nullptr, n, n, 0, 32, w.radix, s)));
+    QB_LAUNCH(k_gather_counts, grid, QB_BLOCK, 0, s, n, (const uint32_t*)w.dv0, counts, w.csorted);
     QB_CHECK((qbr::exclusive_scan<uint32_t, uint64_t>(w.csorted, w.offs, n, w.scan64, w.total, s)));
     QB_LAUNCH(k_store_total, 1, 1, 0, s, (const uint64_t*)w.total, num_pairs);
-    QB_LAUNCH(k_emit, qb_div_up(n, kEmitThreads), kEmitThreads, 0, s, n, order, (const uint64_t*)w.offs, sp,
-              reinterpret_cast<const int4*>(rects), counts, tiles_x, pair_capacity, (const int64_t*)num_pairs,
-              keys, ids);
+    if (pair_capacity > 0)
+        QB_LAUNCH(k_emit, qb_div_up(n, kEmitThreads), kEmitThreads, 0, s, n, (const uint32_t*)w.dv0,
+                  (const uint64_t*)w.offs, reinterpret_cast<const int4*>(rects), counts, tiles_x, pair_capacity,
+                  (const int64_t*)num_pairs, pair_tiles, pair_ids);
     return QB_OK;
 }

@@ -227,9 +227,9 @@ __global__ __launch_bounds__(QB_BLOCK) void k_project(
                 }
             }
         }
-        QSeg seg[QB_MAX_SEG];
-        int axis;
-        qpass_segments(rr, seg, &axis, &count);
+        QRuns runs;
+        qpass_runs(rr, runs);
+        count = runs.total;
         s0 = make_float4(u, v, pz, o);
         s1 = make_float4(ca, cb, cc, gam);
         s2 = make_float4(rgb[0], rgb[1], rgb[2], 1.0f);

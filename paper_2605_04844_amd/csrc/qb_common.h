@@ -46,78 +46,82 @@ struct QRect {
     int x0, x1, y0, y1;
 };
 
-// Run of scanlines with one tile span (the QPass per-scanline result is
-// constant between two consecutive sub-box ends along the scan axis).
-struct QSeg {
-    int s0;   // first scanline
-    int n;    // number of scanlines
-    int lo;   // first tile along the other axis
-    int len;  // tiles per scanline
+// QPass runs of one Gaussian (Sec. 3.2).  A run is a block of consecutive
+// scanlines whose QPass interval is the same: n scanlines from s0, each with
+// the len tiles from lo on the other axis.  Every run slot is filled (empty
+// ones have n = 0 or len = 0), so the arrays stay in registers.
+#define QB_MAX_SEG 7
+#define QB_BIG (1 << 30)
+
+struct QRuns {
+    int s0[QB_MAX_SEG], n[QB_MAX_SEG], lo[QB_MAX_SEG], len[QB_MAX_SEG];
+    int axis;   // 0: scanlines are tile columns, 1: tile rows
+    int total;  // tiles in the set
 };
 
-#define QB_MAX_SEG 7
-
-// QPass (Sec. 3.2): global tile range of the non-empty sub-boxes, scan along
-// its shorter axis; per scanline, the sub-boxes whose range on the scan axis
-// holds it (interval overlap test) give the span [min lo, max hi] on the other
-// axis.  Scanlines are grouped into runs whose active set is the same, which
-// makes each pair addressable in O(1).  Returns the number of runs; *axis = 0
-// scans columns (scanline = tx), 1 rows; *total = tiles in the set.
-__host__ __device__ __forceinline__ int qpass_segments(const QRect r[4], QSeg seg[QB_MAX_SEG], int* axis,
-                                              int* total)
+__host__ __device__ __forceinline__ void qb_cswap(int& x, int& y)
 {
-    int a[4], b[4], c[4], d[4];
-    int m = 0;
-    int gx0 = 1 << 30, gx1 = -(1 << 30), gy0 = 1 << 30, gy1 = -(1 << 30);
+    int lo = x < y ? x : y, hi = x < y ? y : x;
+    x = lo;
+    y = hi;
+}
+
+// QPass: the global tile range of the non-empty sub-boxes, scanned along its
+// shorter axis; on each scanline, the sub-boxes whose range on the scan axis
+// holds it (interval overlap test) give the span [min lo, max hi] on the other
+// axis.  The active set only changes at a sub-box start or end + 1, so the
+// scanlines between two consecutive such breakpoints form one run.
+__host__ __device__ __forceinline__ void qpass_runs(const QRect r[4], QRuns& q)
+{
+    bool act[4];
+    int gx0 = QB_BIG, gx1 = -QB_BIG, gy0 = QB_BIG, gy1 = -QB_BIG;
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (r[k].x0 > r[k].x1 || r[k].y0 > r[k].y1) continue;
-        gx0 = r[k].x0 < gx0 ? r[k].x0 : gx0;
-        gx1 = r[k].x1 > gx1 ? r[k].x1 : gx1;
-        gy0 = r[k].y0 < gy0 ? r[k].y0 : gy0;
-        gy1 = r[k].y1 > gy1 ? r[k].y1 : gy1;
-        a[m] = r[k].x0; b[m] = r[k].x1; c[m] = r[k].y0; d[m] = r[k].y1;
-        ++m;
-    }
-    *total = 0;
-    *axis = 0;
-    if (m == 0) return 0;
-    if (gx1 - gx0 > gy1 - gy0) {  // rows are the shorter axis: swap roles
-        *axis = 1;
-        for (int k = 0; k < m; ++k) {
-            int t0 = a[k], t1 = b[k];
-            a[k] = c[k]; b[k] = d[k]; c[k] = t0; d[k] = t1;
+        act[k] = r[k].x0 <= r[k].x1 && r[k].y0 <= r[k].y1;
+        if (act[k]) {
+            gx0 = r[k].x0 < gx0 ? r[k].x0 : gx0;
+            gx1 = r[k].x1 > gx1 ? r[k].x1 : gx1;
+            gy0 = r[k].y0 < gy0 ? r[k].y0 : gy0;
+            gy1 = r[k].y1 > gy1 ? r[k].y1 : gy1;
         }
     }
-    // breakpoints along the scan axis: every start and every end + 1
-    int e[8];
-    int ne = 0;
-    for (int k = 0; k < m; ++k) {
-        e[ne++] = a[k];
-        e[ne++] = b[k] + 1;
+    q.axis = (gx1 - gx0 > gy1 - gy0) ? 1 : 0;  // scan the shorter axis
+    int a[4], b[4], c[4], d[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int sa = q.axis ? r[k].y0 : r[k].x0, sb = q.axis ? r[k].y1 : r[k].x1;
+        int oa = q.axis ? r[k].x0 : r[k].y0, ob = q.axis ? r[k].x1 : r[k].y1;
+        a[k] = act[k] ? sa : QB_BIG;
+        b[k] = act[k] ? sb : QB_BIG - 1;
+        c[k] = oa;
+        d[k] = ob;
     }
-    for (int i = 1; i < ne; ++i) {  // insertion sort, at most 8 values
-        int v = e[i], j = i - 1;
-        while (j >= 0 && e[j] > v) { e[j + 1] = e[j]; --j; }
-        e[j + 1] = v;
-    }
-    int ns = 0, tot = 0;
-    for (int i = 0; i + 1 < ne; ++i) {
+    int e[8] = {a[0], b[0] + 1, a[1], b[1] + 1, a[2], b[2] + 1, a[3], b[3] + 1};
+    // Batcher's odd-even merge network for 8 keys (19 comparators)
+    qb_cswap(e[0], e[1]); qb_cswap(e[2], e[3]); qb_cswap(e[4], e[5]); qb_cswap(e[6], e[7]);
+    qb_cswap(e[0], e[2]); qb_cswap(e[1], e[3]); qb_cswap(e[4], e[6]); qb_cswap(e[5], e[7]);
+    qb_cswap(e[1], e[2]); qb_cswap(e[5], e[6]); qb_cswap(e[0], e[4]); qb_cswap(e[3], e[7]);
+    qb_cswap(e[1], e[5]); qb_cswap(e[2], e[6]);
+    qb_cswap(e[1], e[4]); qb_cswap(e[3], e[6]);
+    qb_cswap(e[2], e[4]); qb_cswap(e[3], e[5]);
+    qb_cswap(e[3], e[4]);
+    int tot = 0;
+#pragma unroll
+    for (int i = 0; i < QB_MAX_SEG; ++i) {
         int s0 = e[i], s1 = e[i + 1];
-        if (s1 <= s0) continue;
-        int lo = 1 << 30, hi = -(1 << 30);
-        for (int k = 0; k < m; ++k)
+        int lo = QB_BIG, hi = -QB_BIG;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
             if (a[k] <= s0 && b[k] >= s0) {  // interval overlap with this run
                 lo = c[k] < lo ? c[k] : lo;
                 hi = d[k] > hi ? d[k] : hi;
             }
-        if (hi < lo) continue;
-        seg[ns].s0 = s0;
-        seg[ns].n = s1 - s0;
-        seg[ns].lo = lo;
-        seg[ns].len = hi - lo + 1;
-        tot += seg[ns].n * seg[ns].len;
-        ++ns;
+        bool valid = s1 > s0 && s0 < QB_BIG && hi >= lo;
+        q.s0[i] = s0;
+        q.n[i] = valid ? s1 - s0 : 0;
+        q.lo[i] = lo;
+        q.len[i] = valid ? hi - lo + 1 : 0;
+        tot += q.n[i] * q.len[i];
     }
-    *total = tot;
-    return ns;
+    q.total = tot;
 }

@@ -2,14 +2,16 @@
 //
 // Both are reduce-then-scan: no workgroup ever waits on another, so there is
 // no inter-workgroup spin and no forward-progress assumption.
-//   scan:  per-block reduction -> recursive scan of block totals -> per-block scan
+//   scan:  up to 32768 items in one 1024-lane workgroup; beyond that a
+//          per-block reduction -> recursive scan of block totals -> per-block scan
 //   radix pass (<= 8 bits):
 //     upsweep   per-block digit histogram in LDS, stored digit-major
 //     scan      exclusive scan of the digit-major histogram (global offsets)
 //     downsweep per-block stable ranks: each wave owns a contiguous run of the
 //               block's items and ranks 64 at a time by matching digits with
 //               one ballot per digit bit; per-wave digit counts are combined
-//               across the 4 waves in LDS; items scatter to offset + rank.
+//               across waves in LDS; items are reordered by digit in LDS and
+//               then written out as contiguous runs (coalesced stores).
 #pragma once
 
 #include "qb_common.h"
@@ -19,13 +21,12 @@ namespace qbr {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;  // 2048 items per block
+constexpr int kBigScanThreads = 1024;
+constexpr int kBigScanItems = 32;
+constexpr int kBigScanTile = kBigScanThreads * kBigScanItems;  // 32768 items, one workgroup
 
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kSortThreads = 256;
-constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortItems = 16;                           // per lane
-constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 items per block
 
 // Inclusive scan across one wave64 (Hillis-Steele over lane shuffles).
 template <typename T>
@@ -40,9 +41,22 @@ __device__ __forceinline__ T wave_inclusive_scan(T v)
     return v;
 }
 
-// Exclusive scan over the block (256 threads); returns the block total too.
-template <typename T>
-__device__ __forceinline__ T block_exclusive_scan(T v, T* total, T* lds /*[4]*/)
+// Inclusive running maximum across one wave64.
+__device__ __forceinline__ int wave_inclusive_max(int v)
+{
+    int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int o = __shfl_up(v, off, 64);
+        if (lane >= off) v = max(v, o);
+    }
+    return v;
+}
+
+// Exclusive scan over a block of NT threads; returns the block total too.
+// lds must hold NT/64 elements.
+template <typename T, int NT>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* total, T* lds)
 {
     int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     T inc = wave_inclusive_scan(v);
@@ -50,7 +64,7 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* total, T* lds /*[4]*/)
     __syncthreads();
     T wbase = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kScanThreads / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         T x = lds[w];
         if (w < wave) wbase += x;
         tot += x;
@@ -66,7 +80,7 @@ template <typename TIn, typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const TIn* __restrict__ in, int64_t n,
                                                               T* __restrict__ block_sums)
 {
-    __shared__ T lds[4];
+    __shared__ T lds[kScanThreads / 64];
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     T s = 0;
 #pragma unroll
@@ -75,44 +89,51 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const TIn* __restr
         if (idx < n) s += (T)in[idx];
     }
     T tot;
-    block_exclusive_scan<T>(s, &tot, lds);
+    block_exclusive_scan<T, kScanThreads>(s, &tot, lds);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-// Block scan of kScanTile items: coalesced load to LDS, per-thread serial scan
-// of 8 consecutive items, block scan of the thread totals, coalesced store.
-template <typename TIn, typename T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const TIn* __restrict__ in, int64_t n,
-                                                             const T* __restrict__ block_base,
-                                                             T* __restrict__ out,
-                                                             T* __restrict__ total_out)
+// LDS index with one pad word per 32, so that lane t touching item t*NI + k
+// (the per-thread serial scan) hits distinct banks.
+__device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
+
+// Block scan of NT*NI items: coalesced load to LDS, per-thread serial scan of
+// NI consecutive items, block scan of the thread totals, coalesced store.
+template <typename TIn, typename T, int NT, int NI>
+__global__ __launch_bounds__(NT) void k_scan_apply(const TIn* __restrict__ in, int64_t n,
+                                                   const T* __restrict__ block_base, T* __restrict__ out,
+                                                   T* __restrict__ total_out)
 {
-    __shared__ T tile[kScanTile];
-    __shared__ T lds[4];
-    int64_t base = (int64_t)blockIdx.x * kScanTile;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
-        tile[k * kScanThreads + threadIdx.x] = idx < n ? (T)in[idx] : (T)0;
+    __shared__ T tile[NT * NI + NT * NI / 32];
+    __shared__ T lds[NT / 64];
+    int64_t base = (int64_t)blockIdx.x * (NT * NI);
+    const TIn* src = in + base;
+    int lim = (int)min((int64_t)(NT * NI), n - base);
+#pragma unroll 8
+    for (int k = 0; k < NI; ++k) {
+        int idx = k * NT + threadIdx.x;
+        tile[pad32(idx)] = idx < lim ? (T)src[idx] : (T)0;
     }
     __syncthreads();
-    T loc[kScanItems];
     T s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        loc[k] = s;
-        s += tile[threadIdx.x * kScanItems + k];
-    }
+    for (int k = 0; k < NI; ++k) s += tile[pad32(threadIdx.x * NI + k)];
     T tot;
-    T tb = block_exclusive_scan<T>(s, &tot, lds);
-    T bb = block_base ? block_base[blockIdx.x] : (T)0;
+    T tb = block_exclusive_scan<T, NT>(s, &tot, lds);
+    T run = (block_base ? block_base[blockIdx.x] : (T)0) + tb;
+    T bb = run - tb;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = bb + tb + loc[k];
+    for (int k = 0; k < NI; ++k) {
+        T v = tile[pad32(threadIdx.x * NI + k)];
+        tile[pad32(threadIdx.x * NI + k)] = run;
+        run += v;
+    }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
-        if (idx < n) out[idx] = tile[k * kScanThreads + threadIdx.x];
+    T* dst = out + base;
+#pragma unroll 8
+    for (int k = 0; k < NI; ++k) {
+        int idx = k * NT + threadIdx.x;
+        if (idx < lim) dst[idx] = tile[pad32(idx)];
     }
     if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = bb + tot;
 }
@@ -133,17 +154,26 @@ template <typename TIn, typename T>
 qb_status exclusive_scan(const TIn* in, T* out, int64_t n, T* scratch, T* total_out, hipStream_t s)
 {
     if (n <= 0) return QB_OK;
-    int64_t nb = qb_div_up(n, kScanTile);
-    if (nb == 1) {
-        QB_LAUNCH((k_scan_apply<TIn, T>), 1, kScanThreads, 0, s, in, n, (const T*)nullptr, out, total_out);
+    if (n <= kScanTile) {
+        QB_LAUNCH((k_scan_apply<TIn, T, kScanThreads, kScanItems>), 1, kScanThreads, 0, s, in, n,
+                  (const T*)nullptr, out, total_out);
         return QB_OK;
     }
+    if constexpr (sizeof(T) == 4) {
+        if (n <= kBigScanTile) {
+            QB_LAUNCH((k_scan_apply<TIn, T, kBigScanThreads, kBigScanItems>), 1, kBigScanThreads, 0, s, in, n,
+                      (const T*)nullptr, out, total_out);
+            return QB_OK;
+        }
+    }
+    int64_t nb = qb_div_up(n, kScanTile);
     int64_t pad = qb_div_up(nb, 64) * 64;
     T* sums = scratch;
     T* sums_scan = scratch + pad;
     QB_LAUNCH((k_scan_reduce<TIn, T>), nb, kScanThreads, 0, s, in, n, sums);
     QB_CHECK((exclusive_scan<T, T>(sums, sums_scan, nb, scratch + 2 * pad, (T*)nullptr, s)));
-    QB_LAUNCH((k_scan_apply<TIn, T>), nb, kScanThreads, 0, s, in, n, (const T*)sums_scan, out, total_out);
+    QB_LAUNCH((k_scan_apply<TIn, T, kScanThreads, kScanItems>), nb, kScanThreads, 0, s, in, n,
+              (const T*)sums_scan, out, total_out);
     return QB_OK;
 }
 
@@ -164,62 +194,75 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask)
     return (uint32_t)(key >> shift) & mask;
 }
 
-template <typename K>
-__global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(
-    const K* __restrict__ keys, const int64_t* n_dev, int64_t n_host, int64_t cap, int shift,
-    int bits, uint32_t* __restrict__ hist, int64_t nblocks)
+template <typename K, int NT, int NI>
+__global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys, const int64_t* n_dev,
+                                                      int64_t n_host, int64_t cap, int shift, int bits,
+                                                      uint32_t* __restrict__ hist, int64_t nblocks)
 {
-    __shared__ uint32_t h[kSortWaves][kRadix];
+    constexpr int NW = NT / 64;
+    __shared__ uint32_t h[NW][kRadix];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&h[0][0])[d] = 0;
+    for (int d = threadIdx.x; d < NW * kRadix; d += NT) (&h[0][0])[d] = 0;
     __syncthreads();
     int64_t n = sort_count(n_dev, n_host, cap);
     uint32_t mask = (1u << bits) - 1u;
-    int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * 64 * kSortItems;
+    int64_t base = (int64_t)blockIdx.x * (NT * NI) + (int64_t)wave * 64 * NI;
 #pragma unroll 4
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < NI; ++r) {
         int64_t idx = base + r * 64 + lane;
         if (idx < n) atomicAdd(&h[wave][digit_of(keys[idx], shift, mask)], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
+    for (int d = threadIdx.x; d <= (int)mask; d += NT) {
         uint32_t t = 0;
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) t += h[w][d];
-        if (d <= (int)mask) hist[(int64_t)d * nblocks + blockIdx.x] = t;
+        for (int w = 0; w < NW; ++w) t += h[w][d];
+        hist[(int64_t)d * nblocks + blockIdx.x] = t;
     }
 }
 
-template <typename K>
-__global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(
+template <typename K, int NT, int NI>
+__global__ __launch_bounds__(NT) void k_radix_downsweep(
     const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, K* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, const int64_t* n_dev, int64_t n_host, int64_t cap, int shift,
-    int bits, const uint32_t* __restrict__ offs, int64_t nblocks)
+    uint32_t* __restrict__ vals_out, const int64_t* n_dev, int64_t n_host, int64_t cap, int shift, int bits,
+    const uint32_t* __restrict__ offs, int64_t nblocks)
 {
-    __shared__ uint32_t wcnt[kSortWaves][kRadix];
-    __shared__ uint32_t gbase[kRadix];
+    constexpr int NW = NT / 64;
+    constexpr int TILE = NT * NI;
+    __shared__ uint32_t wcnt[NW][kRadix];   // per-wave counts, then per-wave starts
+    __shared__ uint32_t gbase[kRadix];      // global start of each digit for this block
+    __shared__ uint32_t lstart[kRadix];     // block-local start of each digit
+    __shared__ uint32_t scan_lds[NW];
+    __shared__ K s_key[TILE];
+    __shared__ uint32_t s_val[TILE];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int64_t n = sort_count(n_dev, n_host, cap);
-    int64_t blk0 = (int64_t)blockIdx.x * kSortTile;
+    int64_t blk0 = (int64_t)blockIdx.x * TILE;
     if (blk0 >= n) return;
+    int cnt_blk = (int)min((int64_t)TILE, n - blk0);
     uint32_t mask = (1u << bits) - 1u;
-    for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&wcnt[0][0])[d] = 0;
-    for (int d = threadIdx.x; d <= (int)mask; d += kSortThreads) gbase[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+    for (int d = threadIdx.x; d < NW * kRadix; d += NT) (&wcnt[0][0])[d] = 0;
+    for (int d = threadIdx.x; d <= (int)mask; d += NT) gbase[d] = offs[(int64_t)d * nblocks + blockIdx.x];
     __syncthreads();
 
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    int64_t base = blk0 + (int64_t)wave * 64 * kSortItems;
-    K kv[kSortItems];
-    uint32_t vv[kSortItems];
-    uint32_t rank[kSortItems];
-    uint32_t dig[kSortItems];
+    int64_t base = blk0 + (int64_t)wave * 64 * NI;
+    K kv[NI];
+    uint32_t vv[NI];
+    uint32_t rank[NI];
+    uint32_t dig[NI];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < NI; ++r) {
         int64_t idx = base + r * 64 + lane;
         bool valid = idx < n;
-        K k = valid ? keys_in[idx] : (K)0;
-        uint32_t v = valid ? vals_in[idx] : 0u;
-        uint32_t d = digit_of(k, shift, mask);
+        kv[r] = valid ? keys_in[idx] : (K)0;
+        vv[r] = valid ? vals_in[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        int64_t idx = base + r * 64 + lane;
+        bool valid = idx < n;
+        uint32_t d = digit_of(kv[r], shift, mask);
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
             bool bit = (d >> b) & 1u;
@@ -232,41 +275,54 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(
         __builtin_amdgcn_wave_barrier();
         if (valid && below + 1 == cnt) wcnt[wave][d] = old + cnt;
         __builtin_amdgcn_wave_barrier();
-        kv[r] = k;
-        vv[r] = v;
         dig[r] = valid ? d : 0xFFFFFFFFu;
         rank[r] = old + below;
     }
     __syncthreads();
-    // exclusive prefix of the per-wave digit counts across waves
-    for (int d = threadIdx.x; d <= (int)mask; d += kSortThreads) {
-        uint32_t s = 0;
+    // per digit: starts of each wave's items, block total, then block-local
+    // digit starts (exclusive scan over digits)
+    uint32_t tot_d = 0;
+    int d_own = threadIdx.x;
+    if (d_own < kRadix && d_own <= (int)mask) {
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) {
-            uint32_t t = wcnt[w][d];
-            wcnt[w][d] = s;
-            s += t;
+        for (int w = 0; w < NW; ++w) {
+            uint32_t t = wcnt[w][d_own];
+            wcnt[w][d_own] = tot_d;
+            tot_d += t;
         }
     }
+    static_assert(NT >= kRadix, "one lane per digit");
+    uint32_t dummy;
+    uint32_t ls = block_exclusive_scan<uint32_t, NT>(d_own < kRadix ? tot_d : 0u, &dummy, scan_lds);
+    if (d_own < kRadix) lstart[d_own] = ls;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < NI; ++r) {
         if (dig[r] == 0xFFFFFFFFu) continue;
-        uint32_t pos = gbase[dig[r]] + wcnt[wave][dig[r]] + rank[r];
-        keys_out[pos] = kv[r];
-        vals_out[pos] = vv[r];
+        uint32_t lp = lstart[dig[r]] + wcnt[wave][dig[r]] + rank[r];
+        s_key[lp] = kv[r];
+        s_val[lp] = vv[r];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt_blk; i += NT) {
+        K k = s_key[i];
+        uint32_t d = digit_of(k, shift, mask);
+        uint32_t pos = gbase[d] + (uint32_t)i - lstart[d];
+        keys_out[pos] = k;
+        vals_out[pos] = s_val[i];
     }
 }
 
-// Scratch bytes of one sort over `cap` items.
+// Scratch bytes of one sort over `cap` items with NT*NI items per block.
+template <int NT, int NI>
 inline size_t radix_scratch_bytes(int64_t cap)
 {
-    int64_t nb = qb_div_up(cap > 0 ? cap : 1, kSortTile);
+    int64_t nb = qb_div_up(cap > 0 ? cap : 1, NT * NI);
     int64_t hist = nb * kRadix;
     return (size_t)(2 * hist + scan_scratch(hist) + 256) * sizeof(uint32_t);
 }
 
-template <typename K>
+template <typename K, int NT, int NI>
 __global__ __launch_bounds__(QB_BLOCK) void k_copy_items(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                          K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const int64_t* n_dev, int64_t n_host, int64_t cap)
@@ -283,7 +339,7 @@ __global__ __launch_bounds__(QB_BLOCK) void k_copy_items(const K* __restrict__ k
 // (kout, vout), and uses (ktmp, vtmp) for the intermediate passes; kin may
 // alias kout only when the pass count is even.  The item count is *n_dev when
 // n_dev is given (clamped as in sort_count), else n_host; cap sizes the grid.
-template <typename K>
+template <typename K, int NT, int NI>
 qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, K* ktmp, uint32_t* vtmp,
                      const int64_t* n_dev, int64_t n_host, int64_t cap, int lo_bit, int hi_bit,
                      uint32_t* scratch, hipStream_t s)
@@ -295,11 +351,11 @@ qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout,
         if ((const void*)kin != (const void*)kout) {
             int64_t g = qb_div_up(cap, QB_BLOCK);
             if (g > 4096) g = 4096;
-            QB_LAUNCH((k_copy_items<K>), g, QB_BLOCK, 0, s, kin, vin, kout, vout, n_dev, n_host, cap);
+            QB_LAUNCH((k_copy_items<K, NT, NI>), g, QB_BLOCK, 0, s, kin, vin, kout, vout, n_dev, n_host, cap);
         }
         return QB_OK;
     }
-    int64_t nb = qb_div_up(cap, kSortTile);
+    int64_t nb = qb_div_up(cap, NT * NI);
     int64_t hn = nb * kRadix;
     uint32_t* hist = scratch;
     uint32_t* offs = scratch + hn;
@@ -313,10 +369,10 @@ qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout,
         K* dk = to_out ? kout : ktmp;
         uint32_t* dv = to_out ? vout : vtmp;
         int64_t hn_used = (int64_t)(1 << bits) * nb;
-        QB_LAUNCH((k_radix_upsweep<K>), nb, kSortThreads, 0, s, src_k, n_dev, n_host, cap, shift, bits, hist, nb);
+        QB_LAUNCH((k_radix_upsweep<K, NT, NI>), nb, NT, 0, s, src_k, n_dev, n_host, cap, shift, bits, hist, nb);
         QB_CHECK((exclusive_scan<uint32_t, uint32_t>(hist, offs, hn_used, sscr, (uint32_t*)nullptr, s)));
-        QB_LAUNCH((k_radix_downsweep<K>), nb, kSortThreads, 0, s, src_k, src_v, dk, dv, n_dev, n_host, cap,
-                  shift, bits, (const uint32_t*)offs, nb);
+        QB_LAUNCH((k_radix_downsweep<K, NT, NI>), nb, NT, 0, s, src_k, src_v, dk, dv, n_dev, n_host, cap, shift,
+                  bits, (const uint32_t*)offs, nb);
         src_k = dk;
         src_v = dv;
         shift += bits;

@@ -37,8 +37,6 @@ class CCamera(C.Structure):
 
 
 _lib = None
-_EXPORTS = ["qb_project", "qb_intersect_workspace_size", "qb_intersect", "qb_sort_workspace_size",
-            "qb_sort", "qb_render", "qb_status_string", "qb_version"]
 
 
 def lib():
@@ -56,11 +54,11 @@ def lib():
     L.qb_intersect_workspace_size.restype = sz
     L.qb_intersect.argtypes = [i64, vp, vp, vp, i32, i32, i64, vp, vp, vp, vp, sz, vp]
     L.qb_intersect.restype = i32
-    L.qb_sort_workspace_size.argtypes = [i64, i32]
+    L.qb_sort_workspace_size.argtypes = [i64]
     L.qb_sort_workspace_size.restype = sz
-    L.qb_sort.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.qb_sort.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.qb_sort.restype = i32
-    L.qb_render.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.qb_render.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.qb_render.restype = i32
     L.qb_status_string.argtypes = [i32]
     L.qb_status_string.restype = C.c_char_p
@@ -138,42 +136,47 @@ def intersect_workspace_size(n: int) -> int:
     return int(lib().qb_intersect_workspace_size(n))
 
 
-def intersect(n, splats, rects, counts, width, height, capacity, keys, ids, num_pairs, ws):
+def intersect(n, splats, rects, counts, width, height, capacity, pair_tiles, pair_ids, num_pairs, ws):
     _check("qb_intersect", lib().qb_intersect(
-        n, _ptr(splats), _ptr(rects), _ptr(counts), width, height, capacity, _ptr(keys), _ptr(ids),
+        n, _ptr(splats), _ptr(rects), _ptr(counts), width, height, capacity, _ptr(pair_tiles), _ptr(pair_ids),
         _ptr(num_pairs), _ptr(ws), ws.numel() * ws.element_size(), _stream()))
 
 
-def sort_workspace_size(capacity: int, num_tiles: int) -> int:
-    return int(lib().qb_sort_workspace_size(capacity, num_tiles))
+def sort_workspace_size(capacity: int) -> int:
+    return int(lib().qb_sort_workspace_size(capacity))
 
 
-def sort(capacity, num_pairs, num_tiles, keys_in, ids_in, keys_out, ids_out, ranges, ws):
+def sort(capacity, num_pairs, num_tiles, pair_tiles, pair_ids, splats, keys, ids, ranges, ws):
     _check("qb_sort", lib().qb_sort(
-        capacity, _ptr(num_pairs), num_tiles, _ptr(keys_in), _ptr(ids_in), _ptr(keys_out), _ptr(ids_out),
-        _ptr(ranges), _ptr(ws), ws.numel() * ws.element_size(), _stream()))
+        capacity, _ptr(num_pairs), num_tiles, _ptr(pair_tiles), _ptr(pair_ids), _ptr(splats), _ptr(keys),
+        _ptr(ids), _ptr(ranges), _ptr(ws), ws.numel() * ws.element_size(), _stream()))
 
 
-def render(width, height, ranges, ids, splats, bg, image, final_T=None, n_contrib=None):
+def render(width, height, ranges, ids, splats, bg, image, final_T=None, n_contrib=None, n_touched=None):
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
     _check("qb_render", lib().qb_render(
         width, height, _ptr(ranges), _ptr(ids), _ptr(splats), C.cast(bgv, C.c_void_p), _ptr(image),
-        _ptr(final_T), _ptr(n_contrib), _stream()))
+        _ptr(final_T), _ptr(n_contrib), _ptr(n_touched), _stream()))
 
 
 # ---- whole forward with persistent buffers -------------------------------------
 
 class Rasterizer:
     """Runs project -> intersect -> sort -> render for one camera size,
-    keeping device buffers between frames.  Pair buffers grow when a frame
-    needs more than the current capacity (one host read of the pair count per
-    frame unless ``sync_count=False``, which assumes the capacity suffices and
-    checks it after the fact)."""
+    keeping device buffers between frames.  The pair buffers grow when a frame
+    needs more than the current capacity: with ``sync_count=True`` the pair
+    count is read back after qb_intersect (one host synchronisation) and the
+    frame's qb_intersect is re-run with enough room; with ``sync_count=False``
+    nothing is read back and a frame that overflowed renders empty tiles
+    (check ``pairs() <= capacity`` afterwards).  ``write_keys`` selects
+    whether the sorted 64-bit keys are materialised (the render needs only
+    the sorted ids)."""
 
-    def __init__(self, n: int, cam, device="cuda", capacity: int = 0):
+    def __init__(self, n: int, cam, device="cuda", capacity: int = 0, write_keys: bool = True):
         self.n, self.cam, self.device = n, cam, device
         self.W, self.H = int(cam.width), int(cam.height)
         self.num_tiles = cam.tiles_x * cam.tiles_y
+        self.write_keys = write_keys
         d = device
         self.splats = torch.empty((max(n, 1), SPLAT_FLOATS), dtype=torch.float32, device=d)
         self.rects = torch.empty((max(n, 1), RECT_SHORTS), dtype=torch.int16, device=d)
@@ -184,34 +187,35 @@ class Rasterizer:
         self.image = torch.empty((3, self.H, self.W), dtype=torch.float32, device=d)
         self.final_T = torch.empty((self.H, self.W), dtype=torch.float32, device=d)
         self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=d)
+        self.n_touched = None   # set to an int32 [H, W] tensor to count evaluations
         self.capacity = 0
         self._alloc_pairs(capacity)
 
     def _alloc_pairs(self, cap):
         cap = int(cap)
-        d = self.device
         c1 = max(cap, 1)
-        self.keys = torch.empty(c1, dtype=torch.int64, device=d)
-        self.ids = torch.empty(c1, dtype=torch.int32, device=d)
-        self.keys_sorted = torch.empty(c1, dtype=torch.int64, device=d)
+        d = self.device
+        self.pair_tiles = torch.empty(c1, dtype=torch.int16, device=d)
+        self.pair_ids = torch.empty(c1, dtype=torch.int32, device=d)
+        self.keys_sorted = torch.empty(c1, dtype=torch.int64, device=d) if self.write_keys else None
         self.ids_sorted = torch.empty(c1, dtype=torch.int32, device=d)
-        self.ws_sort = torch.empty(sort_workspace_size(cap, self.num_tiles), dtype=torch.uint8, device=d)
+        self.ws_sort = torch.empty(sort_workspace_size(cap), dtype=torch.uint8, device=d)
         self.capacity = cap
 
     def project(self, g: Gaussians, mode):
         project(g, self.cam, mode, self.splats, self.rects, self.counts)
 
     def intersect(self):
-        intersect(self.n, self.splats, self.rects, self.counts, self.W, self.H, self.capacity, self.keys,
-                  self.ids, self.num_pairs, self.ws_isect)
+        intersect(self.n, self.splats, self.rects, self.counts, self.W, self.H, self.capacity, self.pair_tiles,
+                  self.pair_ids, self.num_pairs, self.ws_isect)
 
     def sort(self):
-        sort(self.capacity, self.num_pairs, self.num_tiles, self.keys, self.ids, self.keys_sorted,
-             self.ids_sorted, self.ranges, self.ws_sort)
+        sort(self.capacity, self.num_pairs, self.num_tiles, self.pair_tiles, self.pair_ids, self.splats,
+             self.keys_sorted, self.ids_sorted, self.ranges, self.ws_sort)
 
     def render(self, bg=(0.0, 0.0, 0.0)):
         render(self.W, self.H, self.ranges, self.ids_sorted, self.splats, bg, self.image, self.final_T,
-               self.n_contrib)
+               self.n_contrib, self.n_touched)
 
     def forward(self, g: Gaussians, mode="quadbox", bg=(0.0, 0.0, 0.0), sync_count=True):
         self.project(g, mode)

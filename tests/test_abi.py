@@ -69,11 +69,17 @@ def test_intersect_sort_render_reject_bad_arguments():
     assert ws > 0
     assert L.qb_intersect(10, d, d, d, 64, 48, 100, d, d, d, d, ws - 1, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_intersect(10, d, d, d, 0, 48, 100, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(-1, d, d, d, 64, 48, 100, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_intersect(10, d, d, d, 64, 48, -1, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_intersect(10, d, d, d, 64, 48, 100, d, d, None, d, ws, None) == qb.QB_ERR_INVALID_ARG
-    sws = qb.sort_workspace_size(100, 12)
-    assert L.qb_sort(100, d, 12, d, d, d, d, d, d, sws - 1, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_sort(100, d, 0, d, d, d, d, d, d, sws, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_sort(100, d, 12, d, d, d, C.c_void_p(512), d, d, sws, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_render(0, 48, d, d, d, d, d, None, None, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_render(64, 48, None, d, d, d, d, None, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(10, d, d, d, 64, 48, 100, None, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(10, d, d, d, 16 * 300, 16 * 300, 100, d, d, d, d, 1 << 40, None) == \
+        qb.QB_ERR_UNSUPPORTED
+    sws = qb.sort_workspace_size(100)
+    assert L.qb_sort(100, d, 12, d, d, d, d, C.c_void_p(512), d, d, sws - 1, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_sort(100, d, 0, d, d, d, d, C.c_void_p(512), d, d, sws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_sort(100, d, 12, d, d, d, d, d, d, d, sws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_sort(100, d, 12, d, d, None, d, C.c_void_p(512), d, d, sws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_sort(100, None, 12, d, d, d, d, C.c_void_p(512), d, d, sws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render(0, 48, d, d, d, d, d, None, None, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render(64, 48, None, d, d, d, d, None, None, None, None) == qb.QB_ERR_INVALID_ARG

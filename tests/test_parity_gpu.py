@@ -163,6 +163,8 @@ def test_capacity_overflow(qb):
     r = qb.Rasterizer(scene.n, cam, capacity=100)
     say("capacity overflow")
     r.project(g, "quadbox")
+    r.pair_ids.fill_(-7)
+    r.ids_sorted.fill_(-7)
     r.intersect()
     r.sort()
     r.render((0.0, 0.0, 0.0))
@@ -170,6 +172,14 @@ def test_capacity_overflow(qb):
     assert r.pairs() > 100
     assert np.all(r.ranges.cpu().numpy() == 0)
     assert np.all(r.image.cpu().numpy() == 0.0)
+    assert np.all(r.pair_ids.cpu().numpy() == -7) and np.all(r.ids_sorted.cpu().numpy() == -7)
+    # re-running qb_intersect with enough room completes the same frame
+    r._alloc_pairs(r.pairs())
+    r.intersect()
+    r.sort()
+    r.render((0.0, 0.0, 0.0))
+    torch.cuda.synchronize()
+    assert int(r.ranges[-1, 1]) == r.pairs()
 
 
 def test_deterministic(qb):
