@@ -12,6 +12,7 @@ boxes, per-stage times from HIP events, the roofline of the dominant kernel,
 and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,12 +23,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FPS & tile pairs/frame (QuadBox vs AABB); fwd+bwd ms/view, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-# Render roofline: one (pixel, list entry) evaluation of Eq. (2) needs
-# 2 sub (offsets) + 2 mul + 2 fma (quadratic form) + 2 cmp (cutoff) + 1 mul +
-# 1 exp + 1 min (alpha) + 1 sub + 1 mul + 1 cmp (transmittance) + 1 mul +
-# 3 fma (colour) = 18 VALU lane operations, exp counted once.
-RENDER_OPS_PER_EVAL = 18
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s of 256 CUs x 4 SIMD16 at 2.4 GHz
+# Render roofline.  One evaluation of Eq. (2) at a (pixel, list entry) that
+# composites: 2 sub (offsets), 5 mul/fma (quadratic form), 2 compares (1/255
+# cutoff and the sign test), exp, scale by o, cap at 0.99, 1 - alpha, times T,
+# compare with 1e-4, alpha * T, 3 fma (colour) = 21 VALU lane operations.
+RENDER_OPS_PER_EVAL = 21
+# VALU issue peak without packed math: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -44,6 +46,8 @@ def parse():
     ap.add_argument("--trials", type=int, default=3)
     ap.add_argument("--modes", default="quadbox,adr,3sigma",
                     help="box modes to time; the first one is the headline value")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -136,10 +140,9 @@ def render_evaluations(torch, r):
 
 
 def cpu_baseline(scene, cam):
-    """The oracle (as it stands) on a bounded sample of the same frame:
-    project + pair list + sort for all Gaussians, render of every 8th tile
-    row-major, extrapolated to the whole frame."""
-    import numpy as np
+    """The oracle (as it stands) on one whole frame of the same workload:
+    project, all pairs with qsort, ranges, and the per-pixel render; timed
+    wall-clock on every host core the process may use."""
     from oracle import oracle as O
     threads = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
@@ -148,16 +151,37 @@ def cpu_baseline(scene, cam):
     keys, ids = O.pairs(g, cam.tiles_x)
     rt = O.ranges(keys, cam.num_tiles)
     t2 = time.perf_counter()
-    keep = np.zeros(cam.num_tiles, bool)
-    keep[::8] = True
-    sub = rt.copy()
-    sub[~keep] = 0
-    O.render(g, cam.width, cam.height, sub, ids)
+    O.render(g, cam.width, cam.height, rt, ids)
     t3 = time.perf_counter()
-    frame_s = (t1 - t0) + (t2 - t1) + (t3 - t2) * cam.num_tiles / keep.sum()
+    frame_s = t3 - t0
     return {"value": round(1.0 / frame_s, 4), "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": f"project+pairs+sort of all {scene.n} Gaussians ({t2 - t0:.1f} s), render of "
-                      f"{int(keep.sum())}/{cam.num_tiles} tiles ({t3 - t2:.1f} s) scaled to the frame"}
+            "sample": f"one full frame of the same workload: project {t1 - t0:.2f} s, pairs+sort+ranges "
+                      f"{t2 - t1:.2f} s, render {t3 - t2:.2f} s"}
+
+
+def render_traffic(workload, mode):
+    """HBM bytes per k_render launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed counter summary, or None when that summary was taken on
+    another workload or on a different render source."""
+    path = os.path.join(ROOT, "profiles", "k_render_clusters_1M_counters.json")
+    if workload != "clusters" or mode != "quadbox" or not os.path.exists(path):
+        return None
+    meta = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2605_04844_amd", "csrc", "render.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != meta["render_source_sha256"]:
+        return None
+    return int(meta["fetch_bytes_per_launch"] + meta["write_bytes_per_launch"])
+
+
+def calibrate_copy(torch, mib=1024):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": mib << 20}), flush=True)
 
 
 def main():
@@ -170,6 +194,9 @@ def main():
     from paper_2605_04844_amd import quadbox as qb
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
     qb.lib()
     scene, cam, cfg = build_workload(args.workload)
     g = qb.Gaussians(scene)
@@ -185,18 +212,14 @@ def main():
     q = results[modes[0]]
     stage = q["stage_ms"]
     dominant = max(stage, key=stage.get)
-    roof = None
-    if dominant == "render" and q["evals"] is not None:
-        achieved = q["evals"] * RENDER_OPS_PER_EVAL / (stage["render"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                "kernel": "k_render"}
-    elif dominant == "sort":
-        # algorithmic floor of the pair sort: read and write 12 bytes per pair
-        byts = q["pairs"] * 24
-        achieved = byts / (stage["sort"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "qb_sort"}
+    # roofline of the render kernel (qb_render launches k_render alone, so the
+    # events around the call time that kernel)
+    render_ms = stage["render"]
+    achieved = q["evals"] * RENDER_OPS_PER_EVAL / (render_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
+            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": render_traffic(args.workload, modes[0]),
+            "kernel": "k_render", "evaluations_per_launch": q["evals"], "ops_per_evaluation": RENDER_OPS_PER_EVAL,
+            "launch_ms": round(render_ms, 4)}
     out = {
         "metric": METRIC,
         "value": round(1000.0 / q["ms"], 2),
