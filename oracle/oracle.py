@@ -60,6 +60,8 @@ def lib():
         L.oc_power.argtypes = [vp, C.c_float, C.c_float]
         L.oc_power.restype = C.c_float
         L.oc_layout.argtypes = [vp]
+        L.oc_forward64.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, i64, i32, dbl, vp]
+        L.oc_backward64.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, vp, vp]
         L.oc_pixel_boxes.argtypes = [vp, i32, vp]
         L.oc_pixel_boxes.restype = i32
         lay = np.zeros(6, np.int64)
@@ -218,3 +220,37 @@ def pixel_boxes(rec, mode) -> np.ndarray:
     out = np.zeros((4, 4), np.float32)
     nb = lib().oc_pixel_boxes(_p(r), mode, _p(out))
     return out[:nb]
+
+
+PARAMS_PER_GAUSSIAN = 59   # mean 3, log_scale 3, quat 4, logit 1, sh 48 (coefficient k*3 + ch)
+GROUPS = {"means": slice(0, 3), "log_scales": slice(3, 6), "quats": slice(6, 10), "logits": slice(10, 11),
+          "sh": slice(11, 59)}
+
+
+def _scene_arrays(scene):
+    return [np.ascontiguousarray(x, np.float32) for x in
+            (scene.means, scene.log_scales, scene.quats, scene.logits, scene.sh)]
+
+
+def forward64(scene, cam, bg=(0.0, 0.0, 0.0), pert=None) -> np.ndarray:
+    """Binary64 image [3, H, W]; pert = (gaussian, parameter index, step)."""
+    L = lib()
+    arrs = _scene_arrays(scene)
+    cs = camera_struct(cam)
+    bgv = np.asarray(bg, np.float64)
+    img = np.zeros((3, cam.height, cam.width), np.float64)
+    pi, pp, ph = pert if pert is not None else (-1, 0, 0.0)
+    L.oc_forward64(C.byref(cs), scene.n, *[_p(a) for a in arrs], scene.sh_degree, _p(bgv), pi, pp, ph, _p(img))
+    return img
+
+
+def backward64(scene, cam, dl_dimg, bg=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Gradient [N, 59] of sum(dl_dimg * forward64(...)) by reverse mode."""
+    L = lib()
+    arrs = _scene_arrays(scene)
+    cs = camera_struct(cam)
+    bgv = np.asarray(bg, np.float64)
+    dl = np.ascontiguousarray(dl_dimg, np.float64)
+    out = np.zeros((scene.n, PARAMS_PER_GAUSSIAN), np.float64)
+    L.oc_backward64(C.byref(cs), scene.n, *[_p(a) for a in arrs], scene.sh_degree, _p(bgv), _p(dl), _p(out))
+    return out

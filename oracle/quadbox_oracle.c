@@ -652,3 +652,363 @@ void oc_layout(int64_t* out)
     out[4] = (int64_t)offsetof(oc_gauss, rgb);
     out[5] = (int64_t)sizeof(oc_camera);
 }
+
+/* ========================================================================= */
+/* Binary64 forward and its gradient (the rasterizer is differentiable: the  */
+/* paper trains through it, Sec. 4.1).  This is a plain binary64 evaluation  */
+/* of the same function -- projection (Sec. 2, Eq. 1), the 1/255 cutoff     */
+/* (Eq. 4) and Eq. (2) over every visible Gaussian in (depth, id) order, no  */
+/* tiles -- and its reverse-mode derivative, written out by hand.            */
+/* ========================================================================= */
+
+typedef struct {
+    int visible;
+    double p[3], s[3], o, qn[4], qnorm, Rq[9], M[9], S[9];
+    double limx, limy, xs, ys, clampx, clampy;  /* clamp flags: 0 free, +-1 clamped */
+    double J00, J02, J11, J12, T[6];
+    double A, B, C, det, a, b, c, u, v, gamma;
+    double dir[3], dnorm, rgb_raw[3], rgb[3];
+} oc_g64;
+
+static void oc_project64_one(const oc_camera* cam, const double mean[3], const double ls[3],
+                             const double q[4], double logit, const double* shc, int K, oc_g64* g)
+{
+    memset(g, 0, sizeof(*g));
+    const float* Rc = cam->R;
+    for (int r = 0; r < 3; r++)
+        g->p[r] = (double)Rc[3 * r] * mean[0] + (double)Rc[3 * r + 1] * mean[1] + (double)Rc[3 * r + 2] * mean[2] +
+                  (double)cam->t[r];
+    double pz = g->p[2];
+    if (!(pz > (double)cam->near_plane)) return;
+    for (int k = 0; k < 3; k++) g->s[k] = exp(ls[k]);
+    g->o = 1.0 / (1.0 + exp(-logit));
+    g->gamma = 2.0 * log(255.0 * g->o);
+    double n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    if (!(n2 > 0)) return;
+    g->qnorm = sqrt(n2);
+    for (int k = 0; k < 4; k++) g->qn[k] = q[k] / g->qnorm;
+    double w = g->qn[0], x = g->qn[1], y = g->qn[2], z = g->qn[3];
+    double* R = g->Rq;
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) g->M[3 * r + c] = R[3 * r + c] * g->s[c];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            g->S[3 * r + c] = g->M[3 * r] * g->M[3 * c] + g->M[3 * r + 1] * g->M[3 * c + 1] + g->M[3 * r + 2] * g->M[3 * c + 2];
+    g->limx = 1.3 * (0.5 * cam->W / (double)cam->fx);
+    g->limy = 1.3 * (0.5 * cam->H / (double)cam->fy);
+    double xs = g->p[0] / pz, ys = g->p[1] / pz;
+    g->clampx = xs < -g->limx ? -1 : (xs > g->limx ? 1 : 0);
+    g->clampy = ys < -g->limy ? -1 : (ys > g->limy ? 1 : 0);
+    if (g->clampx) xs = g->clampx * g->limx;
+    if (g->clampy) ys = g->clampy * g->limy;
+    g->xs = xs; g->ys = ys;
+    double tx = xs * pz, ty = ys * pz;
+    g->J00 = cam->fx / pz; g->J02 = -cam->fx * tx / (pz * pz);
+    g->J11 = cam->fy / pz; g->J12 = -cam->fy * ty / (pz * pz);
+    for (int c = 0; c < 3; c++) {
+        g->T[c] = g->J00 * Rc[c] + g->J02 * Rc[6 + c];
+        g->T[3 + c] = g->J11 * Rc[3 + c] + g->J12 * Rc[6 + c];
+    }
+    double U[6];
+    for (int r = 0; r < 2; r++)
+        for (int c = 0; c < 3; c++)
+            U[3 * r + c] = g->T[3 * r] * g->S[c] + g->T[3 * r + 1] * g->S[3 + c] + g->T[3 * r + 2] * g->S[6 + c];
+    g->A = U[0] * g->T[0] + U[1] * g->T[1] + U[2] * g->T[2] + 0.3;
+    g->B = U[0] * g->T[3] + U[1] * g->T[4] + U[2] * g->T[5];
+    g->C = U[3] * g->T[3] + U[4] * g->T[4] + U[5] * g->T[5] + 0.3;
+    g->u = cam->fx * (g->p[0] / pz) + cam->cx;
+    g->v = cam->fy * (g->p[1] / pz) + cam->cy;
+    g->det = g->A * g->C - g->B * g->B;
+    if (!(g->det > 0)) return;
+    g->a = g->C / g->det; g->b = -g->B / g->det; g->c = g->A / g->det;
+    if (!(g->gamma > 0)) return;
+    double d[3];
+    for (int k = 0; k < 3; k++) d[k] = mean[k] - (double)cam->campos[k];
+    g->dnorm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int k = 0; k < 3; k++) g->dir[k] = d[k] / g->dnorm;
+    double Y[16];
+    oc_sh_basis(g->dir[0], g->dir[1], g->dir[2], Y);
+    for (int ch = 0; ch < 3; ch++) {
+        double acc = 0.5;
+        for (int k = 0; k < K; k++) acc += Y[k] * shc[k * 3 + ch];
+        g->rgb_raw[ch] = acc;
+        g->rgb[ch] = acc > 0 ? acc : 0;
+    }
+    g->visible = 1;
+}
+
+/* Gradient of the SH basis polynomials with respect to (x, y, z). */
+static void oc_sh_basis_grad(double x, double y, double z, double G[16][3])
+{
+    const double pi = 3.14159265358979323846;
+    const double k1 = sqrt(3.0 / (4.0 * pi));
+    const double k2a = 0.5 * sqrt(15.0 / pi), k2b = 0.25 * sqrt(5.0 / pi), k2c = 0.25 * sqrt(15.0 / pi);
+    const double k3a = 0.25 * sqrt(35.0 / (2.0 * pi)), k3b = 0.5 * sqrt(105.0 / pi);
+    const double k3c = 0.25 * sqrt(21.0 / (2.0 * pi)), k3d = 0.25 * sqrt(7.0 / pi), k3e = 0.25 * sqrt(105.0 / pi);
+    double xx = x * x, yy = y * y, zz = z * z;
+    double t[16][3] = {
+        {0, 0, 0},
+        {0, -k1, 0},
+        {0, 0, k1},
+        {-k1, 0, 0},
+        {k2a * y, k2a * x, 0},
+        {0, -k2a * z, -k2a * y},
+        {-2 * k2b * x, -2 * k2b * y, 4 * k2b * z},
+        {-k2a * z, 0, -k2a * x},
+        {2 * k2c * x, -2 * k2c * y, 0},
+        {-6 * k3a * x * y, -k3a * (3 * xx - 3 * yy), 0},
+        {k3b * y * z, k3b * x * z, k3b * x * y},
+        {2 * k3c * x * y, -k3c * (4 * zz - xx - 3 * yy), -8 * k3c * y * z},
+        {-6 * k3d * x * z, -6 * k3d * y * z, k3d * (6 * zz - 3 * xx - 3 * yy)},
+        {-k3c * (4 * zz - 3 * xx - yy), 2 * k3c * x * y, -8 * k3c * x * z},
+        {2 * k3e * x * z, -2 * k3e * y * z, k3e * (xx - yy)},
+        {-k3a * (3 * xx - 3 * yy), 6 * k3a * x * y, 0},
+    };
+    memcpy(G, t, sizeof(t));
+}
+
+typedef struct { uint64_t key; uint32_t id; uint32_t pad; } oc_dpair;
+
+static int oc_dpair_cmp(const void* pa, const void* pb)
+{
+    const oc_dpair* a = (const oc_dpair*)pa;
+    const oc_dpair* b = (const oc_dpair*)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    return a->id < b->id ? -1 : (a->id > b->id);
+}
+
+/* Order of the visible Gaussians by binary64 depth (ties by id). */
+static int64_t oc_order64(const oc_g64* g, int64_t n, uint32_t* order)
+{
+    oc_dpair* pr = (oc_dpair*)malloc(sizeof(oc_dpair) * (n > 0 ? n : 1));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (g[i].visible) {
+            uint64_t bits;
+            memcpy(&bits, &g[i].p[2], 8);
+            pr[m].key = bits; pr[m].id = (uint32_t)i; pr[m].pad = 0; m++;
+        }
+    qsort(pr, (size_t)m, sizeof(oc_dpair), oc_dpair_cmp);
+    for (int64_t k = 0; k < m; k++) order[k] = pr[k].id;
+    free(pr);
+    return m;
+}
+
+static void oc_unpack(const float* means, const float* ls, const float* quats, const float* logits,
+                      const float* sh, int64_t n, int64_t i, int K, const double* delta, double m[3],
+                      double l[3], double q[4], double* x, double shc[48])
+{
+    /* parameter vector of Gaussian i: mean(3) lscale(3) quat(4) logit(1) sh(K*3) */
+    const double* dd = delta;
+    for (int k = 0; k < 3; k++) m[k] = means[k * n + i] + (dd ? dd[k] : 0);
+    for (int k = 0; k < 3; k++) l[k] = ls[k * n + i] + (dd ? dd[3 + k] : 0);
+    for (int k = 0; k < 4; k++) q[k] = quats[k * n + i] + (dd ? dd[6 + k] : 0);
+    *x = logits[i] + (dd ? dd[10] : 0);
+    for (int k = 0; k < K * 3; k++) shc[k] = sh[(int64_t)k * n + i] + (dd ? dd[11 + k] : 0);
+}
+
+/* Binary64 render of all pixels; optional perturbation of one parameter of
+ * one Gaussian (for finite differences).  Returns the image [3][H][W]. */
+void oc_forward64(const oc_camera* cam, int64_t n, const float* means, const float* ls, const float* quats,
+                  const float* logits, const float* sh, int sh_degree, const double bg[3], int64_t pert_id,
+                  int pert_param, double pert_h, double* image)
+{
+    int K = (sh_degree + 1) * (sh_degree + 1);
+    oc_g64* g = (oc_g64*)malloc(sizeof(oc_g64) * (n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; i++) {
+        double delta[59] = {0};
+        if (i == pert_id) delta[pert_param] = pert_h;
+        double m[3], l[3], q[4], x, shc[48];
+        oc_unpack(means, ls, quats, logits, sh, n, i, K, delta, m, l, q, &x, shc);
+        oc_project64_one(cam, m, l, q, x, shc, K, &g[i]);
+    }
+    uint32_t* order = (uint32_t*)malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
+    int64_t m = oc_order64(g, n, order);
+    int W = cam->W, H = cam->H;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t pidx = 0; pidx < (int64_t)W * H; pidx++) {
+        double px = (double)(pidx % W), py = (double)(pidx / W);
+        double T = 1, acc[3] = {0, 0, 0};
+        for (int64_t k = 0; k < m; k++) {
+            const oc_g64* gi = &g[order[k]];
+            double dx = gi->u - px, dy = gi->v - py;
+            double power = -0.5 * (gi->a * dx * dx + gi->c * dy * dy) - gi->b * dx * dy;
+            if (power > 0 || power < -0.5 * gi->gamma) continue;
+            double alpha = gi->o * exp(power);
+            if (alpha > 0.99) alpha = 0.99;
+            double tT = T * (1 - alpha);
+            if (tT < 1e-4) break;
+            for (int ch = 0; ch < 3; ch++) acc[ch] += gi->rgb[ch] * alpha * T;
+            T = tT;
+        }
+        for (int ch = 0; ch < 3; ch++) image[(int64_t)ch * W * H + pidx] = acc[ch] + T * bg[ch];
+    }
+    free(order);
+    free(g);
+}
+
+/* Reverse mode of oc_forward64: given dL/dimage [3][H][W], the gradient with
+ * respect to every parameter, written per Gaussian as 59 doubles:
+ * mean(3) log_scale(3) quat(4) logit(1) sh(48, coefficient k*3+ch). */
+void oc_backward64(const oc_camera* cam, int64_t n, const float* means, const float* ls, const float* quats,
+                   const float* logits, const float* sh, int sh_degree, const double bg[3], const double* dL_dimg,
+                   double* grad)
+{
+    int K = (sh_degree + 1) * (sh_degree + 1);
+    int W = cam->W, H = cam->H;
+    oc_g64* g = (oc_g64*)malloc(sizeof(oc_g64) * (n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; i++) {
+        double m[3], l[3], q[4], x, shc[48];
+        oc_unpack(means, ls, quats, logits, sh, n, i, K, NULL, m, l, q, &x, shc);
+        oc_project64_one(cam, m, l, q, x, shc, K, &g[i]);
+    }
+    uint32_t* order = (uint32_t*)malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
+    int64_t m = oc_order64(g, n, order);
+    /* per-Gaussian 2D gradients: u v a b c o r g b */
+    double* g2 = (double*)calloc((size_t)(n > 0 ? n : 1) * 9, sizeof(double));
+    int64_t* list = (int64_t*)malloc(sizeof(int64_t) * (m > 0 ? m : 1));
+    double* al = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
+    double* Ts = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
+    for (int64_t pidx = 0; pidx < (int64_t)W * H; pidx++) {
+        double px = (double)(pidx % W), py = (double)(pidx / W);
+        double T = 1;
+        int64_t cnt = 0;
+        for (int64_t k = 0; k < m; k++) {
+            const oc_g64* gi = &g[order[k]];
+            double dx = gi->u - px, dy = gi->v - py;
+            double power = -0.5 * (gi->a * dx * dx + gi->c * dy * dy) - gi->b * dx * dy;
+            if (power > 0 || power < -0.5 * gi->gamma) continue;
+            double alpha = gi->o * exp(power);
+            if (alpha > 0.99) alpha = 0.99;
+            double tT = T * (1 - alpha);
+            if (tT < 1e-4) break;
+            list[cnt] = order[k]; al[cnt] = alpha; Ts[cnt] = T; cnt++;
+            T = tT;
+        }
+        double dC[3], rest[3];
+        for (int ch = 0; ch < 3; ch++) {
+            dC[ch] = dL_dimg[(int64_t)ch * W * H + pidx];
+            rest[ch] = T * bg[ch];   /* what lies behind the current Gaussian */
+        }
+        for (int64_t k = cnt - 1; k >= 0; k--) {
+            int64_t i = list[k];
+            const oc_g64* gi = &g[i];
+            double alpha = al[k], Ti = Ts[k];
+            double dalpha = 0;
+            for (int ch = 0; ch < 3; ch++) {
+                g2[9 * i + 6 + ch] += alpha * Ti * dC[ch];
+                dalpha += dC[ch] * (gi->rgb[ch] * Ti - rest[ch] / (1 - alpha));
+                rest[ch] += gi->rgb[ch] * alpha * Ti;
+            }
+            double dx = gi->u - px, dy = gi->v - py;
+            double power = -0.5 * (gi->a * dx * dx + gi->c * dy * dy) - gi->b * dx * dy;
+            double e = exp(power);
+            if (gi->o * e > 0.99) continue;    /* capped: alpha is constant */
+            double dpower = dalpha * alpha;
+            g2[9 * i + 5] += dalpha * e;
+            g2[9 * i + 0] += dpower * -(gi->a * dx + gi->b * dy);
+            g2[9 * i + 1] += dpower * -(gi->c * dy + gi->b * dx);
+            g2[9 * i + 2] += dpower * -0.5 * dx * dx;
+            g2[9 * i + 3] += dpower * -dx * dy;
+            g2[9 * i + 4] += dpower * -0.5 * dy * dy;
+        }
+    }
+    memset(grad, 0, sizeof(double) * 59 * (size_t)n);
+    const float* Rc = cam->R;
+    for (int64_t i = 0; i < n; i++) {
+        const oc_g64* gi = &g[i];
+        if (!gi->visible) continue;
+        double* out = grad + 59 * i;
+        const double* d2 = g2 + 9 * i;
+        /* colour: clamp, SH coefficients, view direction */
+        double Y[16], GY[16][3], drgb[3];
+        oc_sh_basis(gi->dir[0], gi->dir[1], gi->dir[2], Y);
+        oc_sh_basis_grad(gi->dir[0], gi->dir[1], gi->dir[2], GY);
+        double ddir[3] = {0, 0, 0};
+        double m_[3], l_[3], q_[4], x_, shc[48];
+        oc_unpack(means, ls, quats, logits, sh, n, i, K, NULL, m_, l_, q_, &x_, shc);
+        for (int ch = 0; ch < 3; ch++) {
+            drgb[ch] = gi->rgb_raw[ch] > 0 ? d2[6 + ch] : 0;
+            for (int k = 0; k < K; k++) {
+                out[11 + k * 3 + ch] = Y[k] * drgb[ch];
+                for (int c = 0; c < 3; c++) ddir[c] += GY[k][c] * shc[k * 3 + ch] * drgb[ch];
+            }
+        }
+        double dd = ddir[0] * gi->dir[0] + ddir[1] * gi->dir[1] + ddir[2] * gi->dir[2];
+        for (int c = 0; c < 3; c++) out[c] += (ddir[c] - gi->dir[c] * dd) / gi->dnorm;
+        /* opacity */
+        out[10] = d2[5] * gi->o * (1 - gi->o);
+        /* conic (a, b, c) -> Sigma2D (A, B, C) */
+        double det2 = gi->det * gi->det, A = gi->A, B = gi->B, C = gi->C;
+        double da = d2[2], db = d2[3], dc = d2[4];
+        double dA = da * (-C * C / det2) + db * (B * C / det2) + dc * (-B * B / det2);
+        double dB = da * (2 * B * C / det2) + db * (-1 / gi->det - 2 * B * B / det2) + dc * (2 * A * B / det2);
+        double dCc = da * (-B * B / det2) + db * (B * A / det2) + dc * (-A * A / det2);
+        /* Sigma2D = T Sigma T^T: symmetric cotangent G */
+        double G[2][2] = {{dA, 0.5 * dB}, {0.5 * dB, dCc}};
+        const double* T = gi->T;
+        double dS[9];  /* T^T G T */
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) {
+                double acc = 0;
+                for (int p = 0; p < 2; p++)
+                    for (int q2 = 0; q2 < 2; q2++) acc += T[3 * p + r] * G[p][q2] * T[3 * q2 + c];
+                dS[3 * r + c] = acc;
+            }
+        double dT[6];  /* 2 G T S */
+        for (int p = 0; p < 2; p++)
+            for (int c = 0; c < 3; c++) {
+                double acc = 0;
+                for (int q2 = 0; q2 < 2; q2++)
+                    for (int k = 0; k < 3; k++) acc += G[p][q2] * T[3 * q2 + k] * gi->S[3 * k + c];
+                dT[3 * p + c] = 2 * acc;
+            }
+        /* T = J R: J00, J02 act on rows 0 and 2 of R; J11, J12 on rows 1 and 2 */
+        double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
+        for (int c = 0; c < 3; c++) {
+            dJ00 += dT[c] * Rc[c];
+            dJ02 += dT[c] * Rc[6 + c];
+            dJ11 += dT[3 + c] * Rc[3 + c];
+            dJ12 += dT[3 + c] * Rc[6 + c];
+        }
+        double pz = gi->p[2], fx = cam->fx, fy = cam->fy;
+        double tx = gi->xs * pz, ty = gi->ys * pz;
+        double dp[3] = {0, 0, 0};
+        /* J00 = fx/pz, J11 = fy/pz, J02 = -fx tx/pz^2, J12 = -fy ty/pz^2 */
+        dp[2] += dJ00 * (-fx / (pz * pz)) + dJ11 * (-fy / (pz * pz));
+        double dtx = dJ02 * (-fx / (pz * pz)), dty = dJ12 * (-fy / (pz * pz));
+        dp[2] += dJ02 * (2 * fx * tx / (pz * pz * pz)) + dJ12 * (2 * fy * ty / (pz * pz * pz));
+        if (gi->clampx == 0) dp[0] += dtx; else dp[2] += dtx * gi->clampx * gi->limx;
+        if (gi->clampy == 0) dp[1] += dty; else dp[2] += dty * gi->clampy * gi->limy;
+        /* mean2D */
+        dp[0] += d2[0] * fx / pz;
+        dp[2] += d2[0] * (-fx * gi->p[0] / (pz * pz));
+        dp[1] += d2[1] * fy / pz;
+        dp[2] += d2[1] * (-fy * gi->p[1] / (pz * pz));
+        for (int c = 0; c < 3; c++) out[c] += Rc[c] * dp[0] + Rc[3 + c] * dp[1] + Rc[6 + c] * dp[2];
+        /* Sigma = M M^T, M = R diag(s) */
+        double dM[9];
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++)
+                dM[3 * r + c] = 2 * (dS[3 * r] * gi->M[c] + dS[3 * r + 1] * gi->M[3 + c] + dS[3 * r + 2] * gi->M[6 + c]);
+        double dR[9];
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) dR[3 * r + c] = dM[3 * r + c] * gi->s[c];
+        for (int c = 0; c < 3; c++) {
+            double dsc = dM[c] * gi->Rq[c] + dM[3 + c] * gi->Rq[3 + c] + dM[6 + c] * gi->Rq[6 + c];
+            out[3 + c] = dsc * gi->s[c];
+        }
+        double w = gi->qn[0], x = gi->qn[1], y = gi->qn[2], z = gi->qn[3];
+        double dq[4];
+        dq[0] = 2 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+        dq[1] = 2 * (y * dR[1] + z * dR[2] + y * dR[3] - 2 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] - 2 * x * dR[8]);
+        dq[2] = 2 * (-2 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] - 2 * y * dR[8]);
+        dq[3] = 2 * (-2 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2 * z * dR[4] + y * dR[5] + x * dR[6] + y * dR[7]);
+        double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+        for (int k = 0; k < 4; k++) out[6 + k] = (dq[k] - gi->qn[k] * qd) / gi->qnorm;
+    }
+    free(Ts); free(al); free(list); free(g2); free(order); free(g);
+}

@@ -27,6 +27,7 @@ constexpr int kBigScanTile = kBigScanThreads * kBigScanItems;  // 32768 items, o
 
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+constexpr int kFusedBlocks = 320;
 
 // Inclusive scan across one wave64 (Hillis-Steele over lane shuffles).
 template <typename T>
@@ -194,7 +195,10 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask)
     return (uint32_t)(key >> shift) & mask;
 }
 
-template <typename K, int NT, int NI>
+// Per-block digit histogram.  Digit-major layout (hist[d * nblocks + b]) feeds
+// the flat scan; block-major (hist[b * 256 + d], every digit written) feeds a
+// downsweep that derives its own offsets.
+template <typename K, int NT, int NI, bool BLOCK_MAJOR>
 __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys, const int64_t* n_dev,
                                                       int64_t n_host, int64_t cap, int shift, int bits,
                                                       uint32_t* __restrict__ hist, int64_t nblocks)
@@ -213,15 +217,22 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
         if (idx < n) atomicAdd(&h[wave][digit_of(keys[idx], shift, mask)], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d <= (int)mask; d += NT) {
+    for (int d = threadIdx.x; d < kRadix; d += NT) {
         uint32_t t = 0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) t += h[w][d];
-        hist[(int64_t)d * nblocks + blockIdx.x] = t;
+        if (BLOCK_MAJOR)
+            hist[(int64_t)blockIdx.x * kRadix + d] = t;
+        else if (d <= (int)mask)
+            hist[(int64_t)d * nblocks + blockIdx.x] = t;
     }
 }
 
-template <typename K, int NT, int NI>
+// FUSED: `offs` holds the raw block-major histograms of every block, and the
+// workgroup derives its global digit offsets from them (digit totals scanned
+// over digits, plus the counts of the earlier blocks); otherwise `offs` is the
+// scanned digit-major histogram.
+template <typename K, int NT, int NI, bool FUSED>
 __global__ __launch_bounds__(NT) void k_radix_downsweep(
     const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, K* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const int64_t* n_dev, int64_t n_host, int64_t cap, int shift, int bits,
@@ -242,7 +253,34 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
     int cnt_blk = (int)min((int64_t)TILE, n - blk0);
     uint32_t mask = (1u << bits) - 1u;
     for (int d = threadIdx.x; d < NW * kRadix; d += NT) (&wcnt[0][0])[d] = 0;
-    for (int d = threadIdx.x; d <= (int)mask; d += NT) gbase[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+    if (FUSED) {
+        static_assert(!FUSED || NT >= kRadix, "one lane per digit");
+        uint32_t tot = 0, pre = 0;
+        int d = threadIdx.x;
+        if (d < kRadix) {
+            int b = 0;
+            for (; b + 8 <= (int)nblocks; b += 8) {
+                uint32_t v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = offs[(int64_t)(b + u) * kRadix + d];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    tot += v[u];
+                    pre += (b + u < (int)blockIdx.x) ? v[u] : 0u;
+                }
+            }
+            for (; b < (int)nblocks; ++b) {
+                uint32_t v = offs[(int64_t)b * kRadix + d];
+                tot += v;
+                pre += (b < (int)blockIdx.x) ? v : 0u;
+            }
+        }
+        uint32_t all;
+        uint32_t start = block_exclusive_scan<uint32_t, NT>(d < kRadix ? tot : 0u, &all, gbase);
+        if (d < kRadix) gbase[d] = start + pre;  // scan scratch reused after its last read
+    } else {
+        for (int d = threadIdx.x; d <= (int)mask; d += NT) gbase[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+    }
     __syncthreads();
 
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -360,6 +398,9 @@ qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout,
     uint32_t* hist = scratch;
     uint32_t* offs = scratch + hn;
     uint32_t* sscr = scratch + 2 * hn;
+    // few blocks: every downsweep workgroup reads all histograms itself
+    // (at most kFusedBlocks * 1 KB), which saves the scan launches
+    bool fused = nb <= kFusedBlocks && NT >= kRadix;
     int shift = lo_bit;
     const K* src_k = kin;
     const uint32_t* src_v = vin;
@@ -369,10 +410,18 @@ qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout,
         K* dk = to_out ? kout : ktmp;
         uint32_t* dv = to_out ? vout : vtmp;
         int64_t hn_used = (int64_t)(1 << bits) * nb;
-        QB_LAUNCH((k_radix_upsweep<K, NT, NI>), nb, NT, 0, s, src_k, n_dev, n_host, cap, shift, bits, hist, nb);
-        QB_CHECK((exclusive_scan<uint32_t, uint32_t>(hist, offs, hn_used, sscr, (uint32_t*)nullptr, s)));
-        QB_LAUNCH((k_radix_downsweep<K, NT, NI>), nb, NT, 0, s, src_k, src_v, dk, dv, n_dev, n_host, cap, shift,
-                  bits, (const uint32_t*)offs, nb);
+        if (fused) {
+            QB_LAUNCH((k_radix_upsweep<K, NT, NI, true>), nb, NT, 0, s, src_k, n_dev, n_host, cap, shift, bits,
+                      hist, nb);
+            QB_LAUNCH((k_radix_downsweep<K, NT, NI, true>), nb, NT, 0, s, src_k, src_v, dk, dv, n_dev, n_host, cap,
+                      shift, bits, (const uint32_t*)hist, nb);
+        } else {
+            QB_LAUNCH((k_radix_upsweep<K, NT, NI, false>), nb, NT, 0, s, src_k, n_dev, n_host, cap, shift, bits,
+                      hist, nb);
+            QB_CHECK((exclusive_scan<uint32_t, uint32_t>(hist, offs, hn_used, sscr, (uint32_t*)nullptr, s)));
+            QB_LAUNCH((k_radix_downsweep<K, NT, NI, false>), nb, NT, 0, s, src_k, src_v, dk, dv, n_dev, n_host,
+                      cap, shift, bits, (const uint32_t*)offs, nb);
+        }
         src_k = dk;
         src_v = dv;
         shift += bits;
