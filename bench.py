@@ -8,12 +8,15 @@ from a warm-up frame, so a step issues no host synchronisation.
 
 Prints one JSON line: FPS of the QuadBox forward (`value`), tile pairs per
 frame, the same forward with the 3-sigma AABB and the opacity-aware AABB
-boxes, per-stage times from HIP events, the roofline of the dominant kernel,
-and the CPU oracle timed on a bounded sample.
+boxes, the ablation modes of Table 3 (DualBox, and QuadBox enumerated without
+QPass) with each mode's image compared with the QuadBox image, per-stage
+times from HIP events, forward+backward ms per view, the roofline of the
+dominant kernel, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -44,8 +47,10 @@ def parse():
     ap.add_argument("--workload", default="clusters", choices=["clusters", "small"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--trials", type=int, default=3)
-    ap.add_argument("--modes", default="quadbox,adr,3sigma",
+    ap.add_argument("--modes", default="quadbox,adr,3sigma,dualbox,quadbox_naive",
                     help="box modes to time; the first one is the headline value")
+    ap.add_argument("--no-backward", action="store_true", help="skip the forward+backward timing")
+    ap.add_argument("--no-multiview", action="store_true", help="skip the 32-view forward+backward timing")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -127,6 +132,130 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials):
     return dict(ms=dev, wall_ms=wall, pairs=pairs, stage_ms=stage, evals=evals, rast=r)
 
 
+def run_fwd_bwd(torch, qb, g, cam, steps, warmup, trials):
+    """Forward + backward of an L1 loss against a U(0,1) target (the
+    1M-Gaussian 1280x720 SH3 training step of one view): the four forward
+    calls, dL/dimage, qb_render_backward and qb_project_backward."""
+    from paper_2605_04844_amd import scenes
+    r = qb.Rasterizer(g.n, cam, write_keys=False)
+    r.forward(g, "quadbox")
+    torch.cuda.synchronize()
+    r._alloc_pairs(r.pairs())
+    target = torch.tensor(scenes.target_image(4, cam.width, cam.height), device="cuda")
+    grad2d = torch.empty((g.n, 9), dtype=torch.float32, device="cuda")
+    grads = [torch.empty_like(t) for t in g.tensors()]
+    inv = 1.0 / float(target.numel())
+
+    def step():
+        r.forward(g, "quadbox", sync_count=False)
+        dl = torch.sign(r.image - target) * inv
+        qb.render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, (0.0, 0.0, 0.0), r.final_T, r.n_contrib,
+                           dl, g.n, grad2d)
+        qb.project_backward(g, cam, r.splats, grad2d, *grads)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(trials):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / steps)
+    assert r.pairs() <= r.capacity
+    return sorted(times)[len(times) // 2]
+
+
+def _time(torch, fn, steps, warmup, trials):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(trials):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / steps)
+    return sorted(times)[len(times) // 2]
+
+
+def run_multiview(torch, qb, steps, warmup, trials):
+    """Forward + backward of an L1 loss over 32 views of 2M Gaussians
+    (640x360 / 1280x720 / 1920x1080 by view index), three ways: the
+    single-view entry points view after view (gradients summed by torch),
+    the batched entry points (quadbox.MultiView), and the batched step
+    captured once in a HIP graph and replayed.  Returns ms per view."""
+    from paper_2605_04844_amd import scenes
+    scene, cams = scenes.multiview_scene()
+    g = qb.Gaussians(scene)
+    V = len(cams)
+    targets = [torch.tensor(scenes.target_image(500 + v, c.width, c.height), device="cuda")
+               for v, c in enumerate(cams)]
+    mv = qb.MultiView(scene.n, cams)
+    pairs = mv.size_pairs(g, "quadbox")
+
+    def batched():
+        imgs = mv.forward(g)
+        for v in range(V):
+            torch.sign(imgs[v] - targets[v], out=mv.dl[v])
+            mv.dl[v].mul_(1.0 / imgs[v].numel())
+        mv.backward(g)
+
+    batched_ms = _time(torch, batched, steps, warmup, trials)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batched()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batched()
+    graph_ms = _time(torch, graph.replay, steps, warmup, trials)
+    assert not mv.overflowed()
+    del graph
+
+    rasts = []
+    for c in cams:
+        r = qb.Rasterizer(g.n, c, write_keys=False)
+        r.forward(g, "quadbox")
+        torch.cuda.synchronize()
+        r._alloc_pairs(int(r.pairs() * 1.1) + 1024)
+        rasts.append(r)
+    grad2d = torch.empty((g.n, 9), dtype=torch.float32, device="cuda")
+    part = [torch.empty_like(t) for t in g.tensors()]
+    total = [torch.empty_like(t) for t in g.tensors()]
+
+    def per_view():
+        for t in total:
+            t.zero_()
+        for v, r in enumerate(rasts):
+            r.forward(g, "quadbox", sync_count=False)
+            dl = torch.sign(r.image - targets[v]) * (1.0 / r.image.numel())
+            qb.render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, (0.0, 0.0, 0.0), r.final_T,
+                               r.n_contrib, dl, g.n, grad2d)
+            qb.project_backward(g, cams[v], r.splats, grad2d, *part)
+            for t, p in zip(total, part):
+                t.add_(p)
+
+    per_view_ms = _time(torch, per_view, max(1, steps // 4), 1, trials)
+    assert all(r.pairs() <= r.capacity for r in rasts)
+    return {"workload": "2M Gaussians (64 clusters in [-1,1]^3), 32 views at 640x360 / 1280x720 / 1920x1080, "
+                        "SH3, forward + L1 loss gradient + backward",
+            "views": V, "gaussians": g.n, "pairs_per_step": int(sum(pairs)),
+            "per_view_path_ms_per_view": round(per_view_ms / V, 4),
+            "batched_ms_per_view": round(batched_ms / V, 4),
+            "batched_graph_ms_per_view": round(graph_ms / V, 4),
+            "graph_speedup_vs_per_view": round(per_view_ms / graph_ms, 3)}
+
+
 def render_evaluations(torch, r):
     """(pixel, list entry) evaluations of Eq. (2) the render performs: every
     list entry up to the pixel's stop (qb_render's n_touched output), taken
@@ -137,6 +266,15 @@ def render_evaluations(torch, r):
     ev = int(r.n_touched.to(torch.int64).sum().item())
     r.n_touched = None
     return ev
+
+
+def image_delta(torch, img, ref):
+    """Max abs difference and PSNR (peak 1) of a mode's image against the
+    headline mode's image; DualBox drops real contributions (Table 3)."""
+    d = (img - ref).double()
+    mse = float((d * d).mean())
+    return {"image_max_abs_vs_headline": float(d.abs().max()),
+            "psnr_vs_headline": None if mse == 0.0 else round(10.0 * math.log10(1.0 / mse), 2)}
 
 
 def cpu_baseline(scene, cam):
@@ -209,6 +347,16 @@ def main():
         res = results[mode]
         log(mode, f"{res['ms']:.3f} ms/frame, {res['pairs']} pairs, stages",
             {k: round(v, 4) for k, v in res["stage_ms"].items()})
+    fwd_bwd = None
+    if args.workload == "clusters" and not args.no_backward:
+        log("forward + backward")
+        fwd_bwd = run_fwd_bwd(torch, qb, g, cam, args.steps, args.warmup, args.trials)
+        log(f"fwd+bwd {fwd_bwd:.3f} ms/view")
+    multiview = None
+    if args.workload == "clusters" and not args.no_multiview:
+        log("multi-view forward + backward")
+        multiview = run_multiview(torch, qb, args.steps, args.warmup, args.trials)
+        log("multi-view", multiview)
     q = results[modes[0]]
     stage = q["stage_ms"]
     dominant = max(stage, key=stage.get)
@@ -236,8 +384,11 @@ def main():
         "config": cfg,
         "pairs_per_frame": q["pairs"],
         "modes": {m: {"fps": round(1000.0 / r["ms"], 2), "ms": round(r["ms"], 4), "pairs": r["pairs"],
-                      "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()}}
+                      "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
+                      **image_delta(torch, r["rast"].image, q["rast"].image)}
                   for m, r in results.items()},
+        "fwd_bwd_ms_per_view": round(fwd_bwd, 4) if fwd_bwd is not None else None,
+        "multiview": multiview,
         "quadbox_vs_3sigma": round(results["3sigma"]["ms"] / q["ms"], 3) if "3sigma" in results else None,
         "quadbox_vs_adr": round(results["adr"]["ms"] / q["ms"], 3) if "adr" in results else None,
         "dominant_stage": dominant,

@@ -9,6 +9,9 @@
  *   qb_intersect  Sec. 2 (DuplicateWithKeys), Sec. 3.2 (QPass)
  *   qb_sort       Sec. 2 (SortPairs) and the per-tile ranges
  *   qb_render     Sec. 2, Eq. (2) (front-to-back alpha compositing)
+ *   qb_render_backward, qb_project_backward
+ *                 gradients (the rasterizer is trained through, Sec. 4.1)
+ *   qb_*_views    the same stages over several views per launch
  *
  * Conventions shared by every entry point
  *   - Array arguments are DEVICE pointers owned by the caller; the library never
@@ -54,8 +57,13 @@ typedef enum {
                            (Sec. 3.1, Eqs. 9, 11)                                   */
     QB_BOX_QUADBOX = 2, /* four quadrant boxes: two full (major axis) and two
                            scaled by f = sqrt(1 - b^2/(ac)) (Sec. 3.1, Eq. 12)      */
-    QB_BOX_DUALBOX = 3  /* the two major-axis quadrant boxes only (Sec. 3.1);
+    QB_BOX_DUALBOX = 3, /* the two major-axis quadrant boxes only (Sec. 3.1);
                            not conservative, ablation only (Table 3)              */
+    QB_BOX_QUADBOX_NAIVE = 4 /* the QuadBox tile set enumerated without QPass: each
+                           sub-box's tile rect walked with nested loops, tiles
+                           of earlier sub-boxes skipped by rect tests (Sec. 3.2;
+                           the dagger row of Table 3).  Same sets, counts, pairs
+                           after sorting and image as QB_BOX_QUADBOX.            */
 } qb_box_mode;
 
 /* Pinhole camera.  R (row-major) and t map world to camera coordinates:
@@ -131,6 +139,9 @@ size_t qb_intersect_workspace_size(int64_t n);
  * ascending (depth, id) order; qb_sort relies on that order.
  *   splats, rects, counts   outputs of qb_project for the same n and camera
  *   width, height           image size; at most 65536 tiles
+ *   mode                    the qb_box_mode given to qb_project; only
+ *                           QB_BOX_QUADBOX_NAIVE changes the traversal (one
+ *                           lane per Gaussian walks its sub-box rects)
  *   pair_capacity           entries available in pair_tiles / pair_ids
  *   pair_tiles, pair_ids    [pair_capacity] uint16 tile id / uint32 Gaussian id
  *   num_pairs               device int64: receives the total pair count P,
@@ -138,9 +149,11 @@ size_t qb_intersect_workspace_size(int64_t n);
  *                           written, qb_sort writes empty ranges and the
  *                           caller re-runs with a larger capacity
  *   workspace               qb_intersect_workspace_size(n) bytes
- * Returns QB_ERR_UNSUPPORTED for more than 65536 tiles. */
+ * Returns QB_ERR_UNSUPPORTED for more than 65536 tiles, QB_ERR_INVALID_ARG
+ * for an unknown mode. */
 qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_rects* rects,
-                       const int32_t* counts, int32_t width, int32_t height, int64_t pair_capacity,
+                       const int32_t* counts, int32_t width, int32_t height, int32_t mode,
+                       int64_t pair_capacity,
                        uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs, void* workspace,
                        size_t workspace_bytes, qb_stream_t stream);
 
@@ -184,7 +197,98 @@ qb_status qb_render(int32_t width, int32_t height, const uint32_t* ranges, const
                     const qb_splat* splats, const float* bg, float* image, float* final_T,
                     uint32_t* n_contrib, uint32_t* n_touched, qb_stream_t stream);
 
+/* qb_render_backward -- gradient of Eq. (2) (the rasterizer is trained
+ * through; Sec. 4.1) with respect to each Gaussian's 2D parameters.  For
+ * every pixel, walks its tile's list back to front from its last contributor,
+ * re-evaluating the forward's alpha decisions, and accumulates
+ *   grad2d[i] = dL/d(u, v, a, b, c, opacity, r, g, b)   (9 floats per Gaussian)
+ * where (a, b, c) is the conic.  grad2d is cleared first, then summed with
+ * float atomics (order-dependent rounding).
+ *   ranges, ids, splats, bg   as given to qb_render for this frame
+ *   final_T, n_contrib        qb_render's outputs for this frame
+ *   dL_dimage                 [3][H][W] float
+ *   n                         number of Gaussians (rows of grad2d)
+ *   grad2d                    [n][9] float                                   */
+qb_status qb_render_backward(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
+                             const qb_splat* splats, const float* bg, const float* final_T,
+                             const uint32_t* n_contrib, const float* dL_dimage, int64_t n, float* grad2d,
+                             qb_stream_t stream);
+
+/* qb_project_backward -- chain rule from grad2d (qb_render_backward) to the
+ * inputs of qb_project (Sec. 2, Eq. 1; the projection of Sec. 2): through the
+ * conic inverse, the EWA covariance with its clamped Jacobian, the mean
+ * projection, Sigma3D = R S S^T R^T, the quaternion normalisation, the
+ * exp / sigmoid activations and the SH colour (no gradient where the colour
+ * was clamped at 0).  The 1/255 cutoff, the 0.99 cap and the tile sets are
+ * piecewise constant and contribute nothing.
+ *   n .. cam          as given to qb_project; splats its output
+ *   grad2d            [n][9] from qb_render_backward
+ *   d_means .. d_sh   gradients in the input layouts ([3][n], [3][n], [4][n],
+ *                     [n], [(sh_degree+1)^2 * 3][n]); culled Gaussians get 0 */
+qb_status qb_project_backward(int64_t n, const float* means, const float* log_scales, const float* quats,
+                              const float* opacity_logits, const float* sh, int32_t sh_degree,
+                              const qb_camera* cam, const qb_splat* splats, const float* grad2d,
+                              float* d_means, float* d_log_scales, float* d_quats, float* d_opacity_logits,
+                              float* d_sh, qb_stream_t stream);
+
 /* Human-readable name of a status code (static string). */
+/* ---- Several views of one Gaussian set in one launch per stage ------------
+ * For multi-view training (many cameras of one scene per step).  Each view
+ * keeps its own projected splats, pairs, ranges and image; the preprocessing
+ * of a view (qb_intersect, qb_sort) stays per view, while the stages below
+ * treat all views at once: projection over (view, Gaussian), the render and
+ * its backward over every (view, tile), and the projection backward over
+ * Gaussians with the sum over views taken in registers.  At most
+ * QB_MAX_VIEWS views per call; the per-view tables travel as kernel
+ * arguments, so a call holds no device memory of its own and can be
+ * captured in a HIP graph as long as the buffers stay put. */
+#define QB_MAX_VIEWS 32
+
+/* Per-view buffers of a batched forward/backward (device pointers). */
+typedef struct {
+    int32_t width, height;
+    const uint32_t* ranges;  /* qb_sort ranges of this view                     */
+    const uint32_t* ids;     /* qb_sort sorted Gaussian ids of this view         */
+    const qb_splat* splats;  /* qb_project(_views) splats of this view, [n]      */
+    float* image;            /* [3][height][width], written by qb_render_views   */
+    float* final_T;          /* [height][width], written by qb_render_views      */
+    uint32_t* n_contrib;     /* [height][width], written by qb_render_views      */
+    const float* dL_dimage;  /* [3][height][width], read by the backward         */
+    float* grad2d;           /* [n][9], cleared and written by the backward      */
+} qb_view;
+
+/* qb_project_views -- qb_project for num_views cameras in one launch.
+ *   cams          host array of num_views cameras
+ *   out_splats    [num_views][n] qb_splat;  out_rects [num_views][n];
+ *   out_counts    [num_views][n] int32 (view v's block starts at v*n)
+ * Same results per view as qb_project with that camera. */
+qb_status qb_project_views(int64_t n, const float* means, const float* log_scales, const float* quats,
+                           const float* opacity_logits, const float* sh, int32_t sh_degree,
+                           const qb_camera* cams, int32_t num_views, int32_t mode, qb_splat* out_splats,
+                           qb_rects* out_rects, int32_t* out_counts, qb_stream_t stream);
+
+/* qb_render_views -- qb_render of every view in one launch (one workgroup
+ * per tile of every view).  views: host array; uses width, height, ranges,
+ * ids, splats, image, final_T, n_contrib (final_T and n_contrib required).
+ * Same image, T and contributor counts per view as qb_render. */
+qb_status qb_render_views(int32_t num_views, const qb_view* views, const float* bg, qb_stream_t stream);
+
+/* qb_render_backward_views -- qb_render_backward of every view in one
+ * launch; each view's grad2d ([n][9]) is cleared first.  Uses every field of
+ * each view except image. */
+qb_status qb_render_backward_views(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
+                                   qb_stream_t stream);
+
+/* qb_project_backward_views -- gradients of the loss summed over views:
+ * one lane per Gaussian runs the chain rule of qb_project_backward for each
+ * view (camera cams[v], splats[v][n], grad2d[v][n][9]) and writes the sums
+ * once (no atomics).  d_* as in qb_project_backward. */
+qb_status qb_project_backward_views(int64_t n, const float* means, const float* log_scales, const float* quats,
+                                    const float* opacity_logits, const float* sh, int32_t sh_degree,
+                                    const qb_camera* cams, int32_t num_views, const qb_splat* splats,
+                                    const float* grad2d, float* d_means, float* d_log_scales, float* d_quats,
+                                    float* d_opacity_logits, float* d_sh, qb_stream_t stream);
+
 const char* qb_status_string(qb_status s);
 
 /* Library version, major*10000 + minor*100 + patch. */

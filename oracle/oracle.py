@@ -12,7 +12,10 @@ import numpy as np
 from . import build as _build
 
 BOX_3SIGMA, BOX_ADR, BOX_QUADBOX, BOX_DUALBOX = 0, 1, 2, 3
-MODES = {"3sigma": BOX_3SIGMA, "adr": BOX_ADR, "quadbox": BOX_QUADBOX, "dualbox": BOX_DUALBOX}
+# "quadbox_naive" (the ablation without QPass, Sec. 3.2) only changes how the
+# tiles are enumerated; its tile set is the QuadBox union by definition.
+MODES = {"3sigma": BOX_3SIGMA, "adr": BOX_ADR, "quadbox": BOX_QUADBOX, "dualbox": BOX_DUALBOX,
+         "quadbox_naive": BOX_QUADBOX}
 TILE = 16
 
 GAUSS_DTYPE = np.dtype({
@@ -61,7 +64,7 @@ def lib():
         L.oc_power.restype = C.c_float
         L.oc_layout.argtypes = [vp]
         L.oc_forward64.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, i64, i32, dbl, vp]
-        L.oc_backward64.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, vp, vp]
+        L.oc_backward64.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, vp, dbl, vp, vp, vp]
         L.oc_pixel_boxes.argtypes = [vp, i32, vp]
         L.oc_pixel_boxes.restype = i32
         lay = np.zeros(6, np.int64)
@@ -244,13 +247,25 @@ def forward64(scene, cam, bg=(0.0, 0.0, 0.0), pert=None) -> np.ndarray:
     return img
 
 
-def backward64(scene, cam, dl_dimg, bg=(0.0, 0.0, 0.0)) -> np.ndarray:
-    """Gradient [N, 59] of sum(dl_dimg * forward64(...)) by reverse mode."""
+def backward64(scene, cam, dl_dimg, bg=(0.0, 0.0, 0.0), band=1e-4, with_near=False, with_2d=False):
+    """Gradient [N, 59] of sum(dl_dimg * forward64(...)) by reverse mode.
+    with_near: also return the [H, W] mask of pixels (among those with a
+    non-zero dl_dimg) whose stop test or 0.99 cap came within `band`
+    (relative) of its threshold.  with_2d: also return the gradient [N, 9]
+    with respect to the projected quantities (u v a b c o r g b)."""
     L = lib()
     arrs = _scene_arrays(scene)
     cs = camera_struct(cam)
     bgv = np.asarray(bg, np.float64)
     dl = np.ascontiguousarray(dl_dimg, np.float64)
     out = np.zeros((scene.n, PARAMS_PER_GAUSSIAN), np.float64)
-    L.oc_backward64(C.byref(cs), scene.n, *[_p(a) for a in arrs], scene.sh_degree, _p(bgv), _p(dl), _p(out))
-    return out
+    near = np.zeros((cam.height, cam.width), np.uint8)
+    g2 = np.zeros((scene.n, 9), np.float64)
+    L.oc_backward64(C.byref(cs), scene.n, *[_p(a) for a in arrs], scene.sh_degree, _p(bgv), _p(dl), band,
+                    _p(near), _p(out), _p(g2))
+    res = (out,)
+    if with_near:
+        res += (near.astype(bool),)
+    if with_2d:
+        res += (g2,)
+    return res if len(res) > 1 else out

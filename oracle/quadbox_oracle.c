@@ -12,8 +12,12 @@
  * IEEE binary32 with a fixed operation order (no contraction: build with
  * -ffp-contract=off; `fmaf` appears only where the order says so), with `/`
  * and `sqrtf` correctly rounded, and with every transcendental evaluated in
- * binary64 and rounded once to binary32.  Everything that only feeds the
- * image (colour, blending weights, accumulation) is binary64.
+ * binary64 and rounded once to binary32.  The one exception is the chain
+ * Sigma3D -> Sigma2D -> conic, formed with binary64 +, -, *, / from the
+ * binary32 scales, unit quaternion and projected mean, each result rounded
+ * once to binary32 (a nearly singular Sigma2D loses its conic to cancellation
+ * in binary32).  Everything that only feeds the image (colour, blending
+ * weights, accumulation) is binary64.
  *
  * Parity status per function (see the tests that pin each one):
  *   oc_project        pinned: closed forms (Eqs. 5, 6, 9, 11, 12), textbook
@@ -217,32 +221,36 @@ void oc_project_one(const oc_camera* cam, const float mean[3], const float lscal
     if (!(n2 > 0.0f) || !isfinite(n2)) return;
     float nr = sqrtf(n2);
     float w = quat[0] / nr, x = quat[1] / nr, y = quat[2] / nr, z = quat[3] / nr;
-    float Rq[9];
-    Rq[0] = 1.0f - 2.0f * (y * y + z * z);
-    Rq[1] = 2.0f * (x * y - w * z);
-    Rq[2] = 2.0f * (x * z + w * y);
-    Rq[3] = 2.0f * (x * y + w * z);
-    Rq[4] = 1.0f - 2.0f * (x * x + z * z);
-    Rq[5] = 2.0f * (y * z - w * x);
-    Rq[6] = 2.0f * (x * z - w * y);
-    Rq[7] = 2.0f * (y * z + w * x);
-    Rq[8] = 1.0f - 2.0f * (x * x + y * y);
+    /* From here to the conic the arithmetic is binary64 on the binary32
+     * values above, and each result is rounded once to binary32: Sigma2D of
+     * a needle-like Gaussian is nearly singular, and binary32 entries would
+     * lose a large part of A C - B^2 to cancellation. */
+    double dw = w, dx = x, dy = y, dz = z;
+    double Rq[9];
+    Rq[0] = 1.0 - 2.0 * (dy * dy + dz * dz);
+    Rq[1] = 2.0 * (dx * dy - dw * dz);
+    Rq[2] = 2.0 * (dx * dz + dw * dy);
+    Rq[3] = 2.0 * (dx * dy + dw * dz);
+    Rq[4] = 1.0 - 2.0 * (dx * dx + dz * dz);
+    Rq[5] = 2.0 * (dy * dz - dw * dx);
+    Rq[6] = 2.0 * (dx * dz - dw * dy);
+    Rq[7] = 2.0 * (dy * dz + dw * dx);
+    Rq[8] = 1.0 - 2.0 * (dx * dx + dy * dy);
 
     /* Sigma3D = M M^T with M = Rq diag(s) */
-    float M[9];
-    for (int r = 0; r < 3; r++) {
-        M[r * 3 + 0] = Rq[r * 3 + 0] * s0;
-        M[r * 3 + 1] = Rq[r * 3 + 1] * s1;
-        M[r * 3 + 2] = Rq[r * 3 + 2] * s2;
-    }
-    float S[9];
+    double sc[3] = {s0, s1, s2};
+    double M[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) M[r * 3 + c] = Rq[r * 3 + c] * sc[c];
+    double S[9];
     for (int r = 0; r < 3; r++)
         for (int c = 0; c < 3; c++)
             S[r * 3 + c] = (M[r * 3 + 0] * M[c * 3 + 0] + M[r * 3 + 1] * M[c * 3 + 1]) +
                            M[r * 3 + 2] * M[c * 3 + 2];
 
     /* local affine approximation of the projection (EWA), evaluated at the
-     * view-space mean with its image-plane slope clamped to 1.3x the half fov */
+     * view-space mean with its image-plane slope clamped to 1.3x the half fov
+     * (slope in binary32, Jacobian in binary64) */
     float limx = 1.3f * (0.5f * (float)cam->W / cam->fx);
     float limy = 1.3f * (0.5f * (float)cam->H / cam->fy);
     float xs = px / pz, ys = py / pz;
@@ -251,38 +259,39 @@ void oc_project_one(const oc_camera* cam, const float mean[3], const float lscal
     if (ys < -limy) ys = -limy;
     if (ys > limy) ys = limy;
     float tx = xs * pz, ty = ys * pz;
-    float zz = pz * pz;
-    float J00 = cam->fx / pz, J02 = -(cam->fx * tx) / zz;
-    float J11 = cam->fy / pz, J12 = -(cam->fy * ty) / zz;
+    double z64 = pz, zz = z64 * z64;
+    double J00 = (double)cam->fx / z64, J02 = -((double)cam->fx * (double)tx) / zz;
+    double J11 = (double)cam->fy / z64, J12 = -((double)cam->fy * (double)ty) / zz;
     /* T = J * R (2x3) */
-    float T[6];
+    double T[6];
     for (int c = 0; c < 3; c++) {
-        T[c] = J00 * R[c] + J02 * R[6 + c];
-        T[3 + c] = J11 * R[3 + c] + J12 * R[6 + c];
+        T[c] = J00 * (double)R[c] + J02 * (double)R[6 + c];
+        T[3 + c] = J11 * (double)R[3 + c] + J12 * (double)R[6 + c];
     }
-    /* U = T Sigma3D (2x3); Sigma2D = U T^T */
-    float U[6];
+    /* U = T Sigma3D (2x3); Sigma2D = U T^T plus the 0.3 low-pass */
+    double U[6];
     for (int r = 0; r < 2; r++)
         for (int c = 0; c < 3; c++)
             U[r * 3 + c] = (T[r * 3 + 0] * S[0 * 3 + c] + T[r * 3 + 1] * S[1 * 3 + c]) +
                            T[r * 3 + 2] * S[2 * 3 + c];
-    float A = (U[0] * T[0] + U[1] * T[1]) + U[2] * T[2];
-    float B = (U[0] * T[3] + U[1] * T[4]) + U[2] * T[5];
-    float C = (U[3] * T[3] + U[4] * T[4]) + U[5] * T[5];
-    A = A + 0.3f;
-    C = C + 0.3f;
-    g->A = A; g->B = B; g->C = C;
+    double A = ((U[0] * T[0] + U[1] * T[1]) + U[2] * T[2]) + 0.3;
+    double B = (U[0] * T[3] + U[1] * T[4]) + U[2] * T[5];
+    double C = ((U[3] * T[3] + U[4] * T[4]) + U[5] * T[5]) + 0.3;
 
     /* image-plane mean */
     g->u = cam->fx * (px / pz) + cam->cx;
     g->v = cam->fy * (py / pz) + cam->cy;
 
     /* conic = inverse of Sigma2D */
-    float det = A * C - B * B;
-    if (!(det > 0.0f) || !isfinite(det) || !isfinite(g->u) || !isfinite(g->v)) return;
-    g->a = C / det;
-    g->b = -(B / det);
-    g->c = A / det;
+    double det = A * C - B * B;
+    if (!(det > 0.0)) return;
+    g->A = (float)A; g->B = (float)B; g->C = (float)C;
+    g->a = (float)(C / det);
+    g->b = (float)(-(B / det));
+    g->c = (float)(A / det);
+    if (!isfinite(g->A) || !isfinite(g->B) || !isfinite(g->C) || !isfinite(g->a) || !isfinite(g->b) ||
+        !isfinite(g->c) || !isfinite(g->u) || !isfinite(g->v))
+        return;
 
     /* opacity-aware modes drop Gaussians that can never reach alpha_min */
     if (mode != OC_BOX_3SIGMA && !(g->gamma > 0.0f)) return;
@@ -658,7 +667,9 @@ void oc_layout(int64_t* out)
 /* paper trains through it, Sec. 4.1).  This is a plain binary64 evaluation  */
 /* of the same function -- projection (Sec. 2, Eq. 1), the 1/255 cutoff     */
 /* (Eq. 4) and Eq. (2) over every visible Gaussian in (depth, id) order, no  */
-/* tiles -- and its reverse-mode derivative, written out by hand.            */
+/* tiles -- and its reverse-mode derivative, written out by hand.  Order,   */
+/* visibility and the cutoff are the rasterizer's binary32 decisions         */
+/* (oc_decide32); the rest is binary64.                                      */
 /* ========================================================================= */
 
 typedef struct {
@@ -780,21 +791,43 @@ static int oc_dpair_cmp(const void* pa, const void* pb)
     return a->id < b->id ? -1 : (a->id > b->id);
 }
 
-/* Order of the visible Gaussians by binary64 depth (ties by id). */
-static int64_t oc_order64(const oc_g64* g, int64_t n, uint32_t* order)
+/* The decisions of the rasterized image, taken in binary32 exactly as the
+ * rasterizer takes them (the depth sort key and the alpha cutoff of Eq. (4)
+ * are binary32 quantities), once, from the unperturbed parameters:
+ *   - which Gaussians are visible, from the binary32 projection;
+ *   - their order: binary32 depth bits, ties by id (the depth part of the
+ *     sort key);
+ *   - per pixel, whether an entry passes the cutoff: its binary32 power lies
+ *     in [-gamma/2, 0] (oc_power).
+ * On that fixed decision set the image is a smooth function of the parameters
+ * (up to the 0.99 cap and the stop at T < 1e-4, taken in binary64), which
+ * oc_forward64 evaluates and oc_backward64 differentiates. */
+static oc_gauss* oc_decide32(const oc_camera* cam, int64_t n, const float* means, const float* ls,
+                             const float* quats, const float* logits, const float* sh, int sh_degree,
+                             uint32_t* order, int64_t* m_out)
 {
+    oc_gauss* d = (oc_gauss*)malloc(sizeof(oc_gauss) * (n > 0 ? n : 1));
+    oc_project(cam, n, means, ls, quats, logits, sh, sh_degree, OC_BOX_QUADBOX, d);
     oc_dpair* pr = (oc_dpair*)malloc(sizeof(oc_dpair) * (n > 0 ? n : 1));
     int64_t m = 0;
     for (int64_t i = 0; i < n; i++)
-        if (g[i].visible) {
-            uint64_t bits;
-            memcpy(&bits, &g[i].p[2], 8);
+        if (d[i].visible) {
+            uint32_t bits;
+            memcpy(&bits, &d[i].depth, 4);
             pr[m].key = bits; pr[m].id = (uint32_t)i; pr[m].pad = 0; m++;
         }
     qsort(pr, (size_t)m, sizeof(oc_dpair), oc_dpair_cmp);
     for (int64_t k = 0; k < m; k++) order[k] = pr[k].id;
     free(pr);
-    return m;
+    *m_out = m;
+    return d;
+}
+
+/* Cutoff decision of one entry at pixel (px, py), Eq. (4) in binary32. */
+static int oc_passes32(const oc_gauss* d, int px, int py)
+{
+    float power = oc_power(d, (float)px, (float)py);
+    return !(power > 0.0f) && !(power < -0.5f * d->gamma);
 }
 
 static void oc_unpack(const float* means, const float* ls, const float* quats, const float* logits,
@@ -826,7 +859,8 @@ void oc_forward64(const oc_camera* cam, int64_t n, const float* means, const flo
         oc_project64_one(cam, m, l, q, x, shc, K, &g[i]);
     }
     uint32_t* order = (uint32_t*)malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
-    int64_t m = oc_order64(g, n, order);
+    int64_t m;
+    oc_gauss* d = oc_decide32(cam, n, means, ls, quats, logits, sh, sh_degree, order, &m);
     int W = cam->W, H = cam->H;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t pidx = 0; pidx < (int64_t)W * H; pidx++) {
@@ -834,9 +868,9 @@ void oc_forward64(const oc_camera* cam, int64_t n, const float* means, const flo
         double T = 1, acc[3] = {0, 0, 0};
         for (int64_t k = 0; k < m; k++) {
             const oc_g64* gi = &g[order[k]];
+            if (!gi->visible || !oc_passes32(&d[order[k]], (int)px, (int)py)) continue;
             double dx = gi->u - px, dy = gi->v - py;
             double power = -0.5 * (gi->a * dx * dx + gi->c * dy * dy) - gi->b * dx * dy;
-            if (power > 0 || power < -0.5 * gi->gamma) continue;
             double alpha = gi->o * exp(power);
             if (alpha > 0.99) alpha = 0.99;
             double tT = T * (1 - alpha);
@@ -846,6 +880,7 @@ void oc_forward64(const oc_camera* cam, int64_t n, const float* means, const flo
         }
         for (int ch = 0; ch < 3; ch++) image[(int64_t)ch * W * H + pidx] = acc[ch] + T * bg[ch];
     }
+    free(d);
     free(order);
     free(g);
 }
@@ -855,69 +890,83 @@ void oc_forward64(const oc_camera* cam, int64_t n, const float* means, const flo
  * mean(3) log_scale(3) quat(4) logit(1) sh(48, coefficient k*3+ch). */
 void oc_backward64(const oc_camera* cam, int64_t n, const float* means, const float* ls, const float* quats,
                    const float* logits, const float* sh, int sh_degree, const double bg[3], const double* dL_dimg,
-                   double* grad)
+                   double band, uint8_t* near, double* grad, double* grad2d)
 {
     int K = (sh_degree + 1) * (sh_degree + 1);
     int W = cam->W, H = cam->H;
     oc_g64* g = (oc_g64*)malloc(sizeof(oc_g64) * (n > 0 ? n : 1));
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
         double m[3], l[3], q[4], x, shc[48];
         oc_unpack(means, ls, quats, logits, sh, n, i, K, NULL, m, l, q, &x, shc);
         oc_project64_one(cam, m, l, q, x, shc, K, &g[i]);
     }
     uint32_t* order = (uint32_t*)malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
-    int64_t m = oc_order64(g, n, order);
+    int64_t m;
+    oc_gauss* d = oc_decide32(cam, n, means, ls, quats, logits, sh, sh_degree, order, &m);
+    if (near) memset(near, 0, (size_t)W * H);
     /* per-Gaussian 2D gradients: u v a b c o r g b */
     double* g2 = (double*)calloc((size_t)(n > 0 ? n : 1) * 9, sizeof(double));
-    int64_t* list = (int64_t*)malloc(sizeof(int64_t) * (m > 0 ? m : 1));
-    double* al = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
-    double* Ts = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
-    for (int64_t pidx = 0; pidx < (int64_t)W * H; pidx++) {
-        double px = (double)(pidx % W), py = (double)(pidx / W);
-        double T = 1;
-        int64_t cnt = 0;
-        for (int64_t k = 0; k < m; k++) {
-            const oc_g64* gi = &g[order[k]];
-            double dx = gi->u - px, dy = gi->v - py;
-            double power = -0.5 * (gi->a * dx * dx + gi->c * dy * dy) - gi->b * dx * dy;
-            if (power > 0 || power < -0.5 * gi->gamma) continue;
-            double alpha = gi->o * exp(power);
-            if (alpha > 0.99) alpha = 0.99;
-            double tT = T * (1 - alpha);
-            if (tT < 1e-4) break;
-            list[cnt] = order[k]; al[cnt] = alpha; Ts[cnt] = T; cnt++;
-            T = tT;
-        }
-        double dC[3], rest[3];
-        for (int ch = 0; ch < 3; ch++) {
-            dC[ch] = dL_dimg[(int64_t)ch * W * H + pidx];
-            rest[ch] = T * bg[ch];   /* what lies behind the current Gaussian */
-        }
-        for (int64_t k = cnt - 1; k >= 0; k--) {
-            int64_t i = list[k];
-            const oc_g64* gi = &g[i];
-            double alpha = al[k], Ti = Ts[k];
-            double dalpha = 0;
-            for (int ch = 0; ch < 3; ch++) {
-                g2[9 * i + 6 + ch] += alpha * Ti * dC[ch];
-                dalpha += dC[ch] * (gi->rgb[ch] * Ti - rest[ch] / (1 - alpha));
-                rest[ch] += gi->rgb[ch] * alpha * Ti;
+#pragma omp parallel
+    {
+        int64_t* list = (int64_t*)malloc(sizeof(int64_t) * (m > 0 ? m : 1));
+        double* al = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
+        double* Ts = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t pidx = 0; pidx < (int64_t)W * H; pidx++) {
+            double dC[3], rest[3];
+            for (int ch = 0; ch < 3; ch++) dC[ch] = dL_dimg[(int64_t)ch * W * H + pidx];
+            if (dC[0] == 0 && dC[1] == 0 && dC[2] == 0) continue;   /* contributes nothing */
+            double px = (double)(pidx % W), py = (double)(pidx / W);
+            double T = 1;
+            int64_t cnt = 0;
+            int close = 0;
+            for (int64_t k = 0; k < m; k++) {
+                const oc_g64* gi = &g[order[k]];
+                if (!gi->visible || !oc_passes32(&d[order[k]], (int)px, (int)py)) continue;
+                double dx = gi->u - px, dy = gi->v - py;
+                double power = -0.5 * (gi->a * dx * dx + gi->c * dy * dy) - gi->b * dx * dy;
+                double alpha = gi->o * exp(power);
+                if (fabs(alpha - 0.99) <= band * 0.99) close = 1;
+                if (alpha > 0.99) alpha = 0.99;
+                double tT = T * (1 - alpha);
+                if (fabs(tT - 1e-4) <= band * 1e-4) close = 1;
+                if (tT < 1e-4) break;
+                list[cnt] = order[k]; al[cnt] = alpha; Ts[cnt] = T; cnt++;
+                T = tT;
             }
-            double dx = gi->u - px, dy = gi->v - py;
-            double power = -0.5 * (gi->a * dx * dx + gi->c * dy * dy) - gi->b * dx * dy;
-            double e = exp(power);
-            if (gi->o * e > 0.99) continue;    /* capped: alpha is constant */
-            double dpower = dalpha * alpha;
-            g2[9 * i + 5] += dalpha * e;
-            g2[9 * i + 0] += dpower * -(gi->a * dx + gi->b * dy);
-            g2[9 * i + 1] += dpower * -(gi->c * dy + gi->b * dx);
-            g2[9 * i + 2] += dpower * -0.5 * dx * dx;
-            g2[9 * i + 3] += dpower * -dx * dy;
-            g2[9 * i + 4] += dpower * -0.5 * dy * dy;
+            if (near) near[pidx] = (uint8_t)close;
+            for (int ch = 0; ch < 3; ch++) rest[ch] = T * bg[ch];   /* what lies behind */
+            for (int64_t k = cnt - 1; k >= 0; k--) {
+                int64_t i = list[k];
+                const oc_g64* gi = &g[i];
+                double alpha = al[k], Ti = Ts[k];
+                double dalpha = 0;
+                for (int ch = 0; ch < 3; ch++) {
+                    double v = alpha * Ti * dC[ch];
+#pragma omp atomic
+                    g2[9 * i + 6 + ch] += v;
+                    dalpha += dC[ch] * (gi->rgb[ch] * Ti - rest[ch] / (1 - alpha));
+                    rest[ch] += gi->rgb[ch] * alpha * Ti;
+                }
+                double dx = gi->u - px, dy = gi->v - py;
+                double power = -0.5 * (gi->a * dx * dx + gi->c * dy * dy) - gi->b * dx * dy;
+                double e = exp(power);
+                if (gi->o * e > 0.99) continue;    /* capped: alpha is constant */
+                double dpower = dalpha * alpha;
+                double v[6] = {dpower * -(gi->a * dx + gi->b * dy), dpower * -(gi->c * dy + gi->b * dx),
+                               dpower * -0.5 * dx * dx, dpower * -dx * dy, dpower * -0.5 * dy * dy, dalpha * e};
+                for (int c = 0; c < 6; c++) {
+#pragma omp atomic
+                    g2[9 * i + c] += v[c];
+                }
+            }
         }
+        free(Ts); free(al); free(list);
     }
     memset(grad, 0, sizeof(double) * 59 * (size_t)n);
     const float* Rc = cam->R;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
         const oc_g64* gi = &g[i];
         if (!gi->visible) continue;
@@ -1010,5 +1059,6 @@ void oc_backward64(const oc_camera* cam, int64_t n, const float* means, const fl
         double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
         for (int k = 0; k < 4; k++) out[6 + k] = (dq[k] - gi->qn[k] * qd) / gi->qnorm;
     }
-    free(Ts); free(al); free(list); free(g2); free(order); free(g);
+    if (grad2d) memcpy(grad2d, g2, sizeof(double) * 9 * (size_t)n);
+    free(g2); free(d); free(order); free(g);
 }

@@ -1,0 +1,631 @@
+// Gradients of the forward rasterizer (the paper trains through it, Sec. 4.1).
+//
+// qb_render_backward: per 16x16 tile, one 256-lane workgroup (one pixel per
+//   lane) walks the tile's list back to front, starting at each pixel's last
+//   contributor.  Each step re-evaluates the forward's binary32 power, 1/255
+//   cutoff and alpha exactly, recovers the transmittance in front of the
+//   Gaussian by dividing out (1 - alpha), and forms the pixel's share of
+//   dL/d(u, v, conic, opacity, rgb) of Eq. (2).  The shares are summed across
+//   each wave64 (butterfly shuffles, skipped when no lane of the wave takes
+//   part) and one lane per wave adds them to the Gaussian's 2D gradient with
+//   global float atomics; the order of those additions is not fixed, so the
+//   result is deterministic only up to float reassociation.
+//
+// qb_project_backward: one lane per Gaussian; recomputes the projection's
+//   intermediates and applies the chain rule through the conic inverse, the
+//   EWA covariance J W Sigma W^T J^T (with the clamped Jacobian), the mean
+//   projection, Sigma = R S S^T R^T, the quaternion normalisation, the scale
+//   and opacity activations and the SH colour.
+#include "qb_common.h"
+
+namespace {
+
+constexpr int kBwdThreads = QB_TILE * QB_TILE;
+
+__device__ __forceinline__ int xcd_tile(int b, int tiles)
+{
+    int q = tiles >> 3, r = tiles & 7;
+    int x = b & 7, idx = b >> 3;
+    return x * q + min(x, r) + idx;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Backward of one tile of one image (the workgroup's 256 lanes).
+__device__ __forceinline__ void render_backward_tile(
+    int tile, int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ splats, float bg0, float bg1, float bg2, const float* __restrict__ final_T,
+    const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimg, float* __restrict__ grad2d)
+{
+    __shared__ float4 s_geo[kBwdThreads];   // u, v, -a/2, -b
+    __shared__ float4 s_opa[kBwdThreads];   // -c/2, o, -gamma/2, (a)
+    __shared__ float4 s_col[kBwdThreads];   // r, g, b, (b)
+    __shared__ float s_c[kBwdThreads];      // c
+    __shared__ uint32_t s_id[kBwdThreads];
+    __shared__ uint32_t s_maxlast;
+
+    int tx = tile % tiles_x, ty = tile / tiles_x;
+    int lx = threadIdx.x & (QB_TILE - 1), ly = threadIdx.x >> 4;
+    int px = tx * QB_TILE + lx, py = ty * QB_TILE + ly;
+    bool inside = px < W && py < H;
+    float fx = (float)px, fy = (float)py;
+    int lane = threadIdx.x & 63;
+
+    uint2 rg = ranges[tile];
+    int64_t start = rg.x;
+    int64_t p = (int64_t)py * W + px;
+    int64_t plane = (int64_t)W * H;
+    uint32_t last = inside ? n_contrib[p] : 0u;
+    float T = inside ? final_T[p] : 1.0f;
+    float dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
+    if (inside) {
+        dC0 = dL_dimg[p];
+        dC1 = dL_dimg[plane + p];
+        dC2 = dL_dimg[2 * plane + p];
+    }
+    float rest0 = T * bg0, rest1 = T * bg1, rest2 = T * bg2;
+
+    if (threadIdx.x == 0) s_maxlast = 0;
+    __syncthreads();
+    if (last) atomicMax(&s_maxlast, last);
+    __syncthreads();
+    int64_t hi = (int64_t)s_maxlast;  // entries [0, hi) of the tile list matter
+
+    for (int64_t b1 = hi; b1 > 0; b1 -= kBwdThreads) {
+        int64_t b0 = b1 - kBwdThreads > 0 ? b1 - kBwdThreads : 0;
+        int64_t j = b0 + threadIdx.x;
+        __syncthreads();
+        if (j < b1) {
+            uint32_t id = ids[start + j];
+            float4 a = splats[3 * (int64_t)id + 0];
+            float4 b = splats[3 * (int64_t)id + 1];
+            float4 c = splats[3 * (int64_t)id + 2];
+            s_geo[threadIdx.x] = make_float4(a.x, a.y, -0.5f * b.x, -b.y);
+            s_opa[threadIdx.x] = make_float4(-0.5f * b.z, a.w, -0.5f * b.w, b.x);
+            s_col[threadIdx.x] = make_float4(c.x, c.y, c.z, b.y);
+            s_c[threadIdx.x] = b.z;
+            s_id[threadIdx.x] = id;
+        }
+        __syncthreads();
+        for (int k = (int)(b1 - b0) - 1; k >= 0; --k) {
+            uint32_t idx = (uint32_t)(b0 + k);  // list index of this entry
+            float4 g = s_geo[k];
+            float4 o = s_opa[k];
+            float dx = g.x - fx, dy = g.y - fy;
+            float power = fmaf(fmaf(g.z, dx, g.w * dy), dx, (o.x * dy) * dy);
+            bool act = idx < last && !(power > 0.0f || power < o.z);
+            if (!__any(act)) continue;
+            float4 col = s_col[k];
+            float cc = s_c[k];
+            float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+            if (act) {
+                float e = __expf(power);
+                float raw = o.y * e;
+                float alpha = fminf(0.99f, raw);
+                float Ti = T / (1.0f - alpha);           // transmittance in front of this Gaussian
+                float w = alpha * Ti;
+                gr = w * dC0;
+                gg = w * dC1;
+                gbl = w * dC2;
+                float inv = 1.0f / (1.0f - alpha);
+                float dalpha = dC0 * (col.x * Ti - rest0 * inv) + dC1 * (col.y * Ti - rest1 * inv) +
+                               dC2 * (col.z * Ti - rest2 * inv);
+                rest0 = fmaf(col.x, w, rest0);
+                rest1 = fmaf(col.y, w, rest1);
+                rest2 = fmaf(col.z, w, rest2);
+                T = Ti;
+                if (raw <= 0.99f) {
+                    float dpow = dalpha * alpha;
+                    go = dalpha * e;
+                    float a = o.w, b = col.w;
+                    gu = -dpow * (a * dx + b * dy);
+                    gv = -dpow * (cc * dy + b * dx);
+                    ga = -0.5f * dpow * dx * dx;
+                    gb = -dpow * dx * dy;
+                    gc = -0.5f * dpow * dy * dy;
+                }
+            }
+            gu = wave_sum(gu);
+            gv = wave_sum(gv);
+            ga = wave_sum(ga);
+            gb = wave_sum(gb);
+            gc = wave_sum(gc);
+            go = wave_sum(go);
+            gr = wave_sum(gr);
+            gg = wave_sum(gg);
+            gbl = wave_sum(gbl);
+            if (lane == 0) {
+                float* d = grad2d + 9 * (int64_t)s_id[k];
+                atomicAdd(d + 0, gu);
+                atomicAdd(d + 1, gv);
+                atomicAdd(d + 2, ga);
+                atomicAdd(d + 3, gb);
+                atomicAdd(d + 4, gc);
+                atomicAdd(d + 5, go);
+                atomicAdd(d + 6, gr);
+                atomicAdd(d + 7, gg);
+                atomicAdd(d + 8, gbl);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBwdThreads) void k_render_backward(
+    int W, int H, int tiles_x, int tiles, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ splats, float bg0, float bg1, float bg2, const float* __restrict__ final_T,
+    const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimg, float* __restrict__ grad2d)
+{
+    render_backward_tile(xcd_tile((int)blockIdx.x, tiles), W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2,
+                         final_T, n_contrib, dL_dimg, grad2d);
+}
+
+// Every tile of every view in one launch (global tile b = blockIdx.x).
+__global__ __launch_bounds__(kBwdThreads) void k_render_backward_views(QbViewTable vt, float bg0, float bg1,
+                                                                       float bg2)
+{
+    int b = (int)blockIdx.x;
+    int v = qb_view_of(vt, b);
+    const qb_view& w = vt.view[v];
+    render_backward_tile(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v],
+                         reinterpret_cast<const uint2*>(w.ranges), w.ids, reinterpret_cast<const float4*>(w.splats),
+                         bg0, bg1, bg2, w.final_T, w.n_contrib, w.dL_dimage, w.grad2d);
+}
+
+// Clears grad2d of every view: blockIdx.y is the view.
+__global__ void k_zero_views(QbViewTable vt, int64_t count)
+{
+    float* p = vt.view[blockIdx.y].grad2d;
+    for (int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x; i < count; i += (int64_t)gridDim.x * QB_BLOCK)
+        p[i] = 0.0f;
+}
+
+struct BwdCam {
+    int W, H;
+    float fx, fy, cx, cy, near_plane;
+    float R[9], t[3], campos[3];
+    float limx, limy;
+};
+
+// Cameras of a batched call, by value as a kernel argument (3 KB at
+// QB_MAX_VIEWS).
+struct BwdCamTable {
+    BwdCam cam[QB_MAX_VIEWS];
+};
+
+// Real SH basis Y_k of degree <= 3 at the unit direction (x, y, z) and its
+// gradient, dY_k = G[k][0] dx + G[k][1] dy + G[k][2] dz.
+__device__ __forceinline__ void sh_basis_and_grad(float x, float y, float z, float Y[16], float G[16][3])
+{
+    const float k00 = 0.28209479177387814f, k1 = 0.48860251190291992f;
+    const float k2a = 1.0925484305920792f, k2b = 0.31539156525252005f, k2c = 0.54627421529603959f;
+    const float k3a = 0.59004358992664352f, k3b = 2.8906114426405538f, k3c = 0.45704579946446572f;
+    const float k3d = 0.3731763325901154f, k3e = 1.4453057213202769f;
+    float xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = k00; G[0][0] = 0.f; G[0][1] = 0.f; G[0][2] = 0.f;
+    Y[1] = -k1 * y; G[1][0] = 0.f; G[1][1] = -k1; G[1][2] = 0.f;
+    Y[2] = k1 * z; G[2][0] = 0.f; G[2][1] = 0.f; G[2][2] = k1;
+    Y[3] = -k1 * x; G[3][0] = -k1; G[3][1] = 0.f; G[3][2] = 0.f;
+    Y[4] = k2a * x * y; G[4][0] = k2a * y; G[4][1] = k2a * x; G[4][2] = 0.f;
+    Y[5] = -k2a * y * z; G[5][0] = 0.f; G[5][1] = -k2a * z; G[5][2] = -k2a * y;
+    Y[6] = k2b * (2.f * zz - xx - yy); G[6][0] = -2.f * k2b * x; G[6][1] = -2.f * k2b * y; G[6][2] = 4.f * k2b * z;
+    Y[7] = -k2a * x * z; G[7][0] = -k2a * z; G[7][1] = 0.f; G[7][2] = -k2a * x;
+    Y[8] = k2c * (xx - yy); G[8][0] = 2.f * k2c * x; G[8][1] = -2.f * k2c * y; G[8][2] = 0.f;
+    Y[9] = -k3a * y * (3.f * xx - yy); G[9][0] = -6.f * k3a * x * y; G[9][1] = -k3a * (3.f * xx - 3.f * yy); G[9][2] = 0.f;
+    Y[10] = k3b * x * y * z; G[10][0] = k3b * y * z; G[10][1] = k3b * x * z; G[10][2] = k3b * x * y;
+    Y[11] = -k3c * y * (4.f * zz - xx - yy); G[11][0] = 2.f * k3c * x * y; G[11][1] = -k3c * (4.f * zz - xx - 3.f * yy);
+    G[11][2] = -8.f * k3c * y * z;
+    Y[12] = k3d * z * (2.f * zz - 3.f * xx - 3.f * yy); G[12][0] = -6.f * k3d * x * z; G[12][1] = -6.f * k3d * y * z;
+    G[12][2] = k3d * (6.f * zz - 3.f * xx - 3.f * yy);
+    Y[13] = -k3c * x * (4.f * zz - xx - yy); G[13][0] = -k3c * (4.f * zz - 3.f * xx - yy); G[13][1] = 2.f * k3c * x * y;
+    G[13][2] = -8.f * k3c * x * z;
+    Y[14] = k3e * z * (xx - yy); G[14][0] = 2.f * k3e * x * z; G[14][1] = -2.f * k3e * y * z; G[14][2] = k3e * (xx - yy);
+    Y[15] = -k3a * x * (xx - 3.f * yy); G[15][0] = -k3a * (3.f * xx - 3.f * yy); G[15][1] = 6.f * k3a * x * y; G[15][2] = 0.f;
+}
+
+// Single view: writes d_sh of Gaussian i and returns dL/d(direction).
+__device__ __forceinline__ void sh_colour_backward(const float* __restrict__ sh, int64_t n, int64_t i, int deg,
+                                                   float x, float y, float z, const float drgb[3],
+                                                   float* __restrict__ d_sh, float ddir[3])
+{
+    float Y[16], G[16][3];
+    sh_basis_and_grad(x, y, z, Y, G);
+    int K = (deg + 1) * (deg + 1);
+    ddir[0] = ddir[1] = ddir[2] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k < K) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                int64_t off = (int64_t)(k * 3 + ch) * n + i;
+                d_sh[off] = Y[k] * drgb[ch];
+                float cw = sh[off] * drgb[ch];
+                ddir[0] = fmaf(G[k][0], cw, ddir[0]);
+                ddir[1] = fmaf(G[k][1], cw, ddir[1]);
+                ddir[2] = fmaf(G[k][2], cw, ddir[2]);
+            }
+        }
+    }
+}
+
+// Chain rule of one Gaussian for one camera from its grad2d row g2 to the
+// mean (through the projection), log-scales, quaternion and opacity logit;
+// ADDS to the accumulators.  The forward forms Sigma3D, Sigma2D and the conic
+// in binary64 from its binary32 inputs; their derivatives are taken the same
+// way.  The colour's share of the mean gradient is left to the SH part.
+__device__ __forceinline__ void geometry_backward(int64_t i, int64_t n, const float* __restrict__ means,
+                                                  const float* __restrict__ log_scales,
+                                                  const float* __restrict__ quats, const float* __restrict__ logits,
+                                                  const BwdCam& cam, const float* __restrict__ g2, double dm[3],
+                                                  double dls[3], double dq[4], float& dlogit)
+{
+    double du = g2[0], dv = g2[1], da = g2[2], db = g2[3], dc = g2[4];
+    float dop = g2[5];
+    float mx = means[i], my = means[n + i], mz = means[2 * n + i];
+    const float* R = cam.R;
+    float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + cam.t[0];
+    float py = ((R[3] * mx + R[4] * my) + R[5] * mz) + cam.t[1];
+    float pz = ((R[6] * mx + R[7] * my) + R[8] * mz) + cam.t[2];
+    double s[3];
+    for (int k = 0; k < 3; ++k) s[k] = (double)(float)exp((double)log_scales[k * n + i]);
+    float o = (float)(1.0 / (1.0 + exp(-(double)logits[i])));
+    float q4[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+    float n2 = ((q4[0] * q4[0] + q4[1] * q4[1]) + q4[2] * q4[2]) + q4[3] * q4[3];
+    float nrf = sqrtf(n2);
+    double nr = nrf;
+    double w = q4[0] / nrf, x = q4[1] / nrf, y = q4[2] / nrf, z = q4[3] / nrf;
+    double Rq[9];
+    Rq[0] = 1.0 - 2.0 * (y * y + z * z); Rq[1] = 2.0 * (x * y - w * z); Rq[2] = 2.0 * (x * z + w * y);
+    Rq[3] = 2.0 * (x * y + w * z); Rq[4] = 1.0 - 2.0 * (x * x + z * z); Rq[5] = 2.0 * (y * z - w * x);
+    Rq[6] = 2.0 * (x * z - w * y); Rq[7] = 2.0 * (y * z + w * x); Rq[8] = 1.0 - 2.0 * (x * x + y * y);
+    double M[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[r * 3 + c] = Rq[r * 3 + c] * s[c];
+    double S[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            S[r * 3 + c] = (M[r * 3 + 0] * M[c * 3 + 0] + M[r * 3 + 1] * M[c * 3 + 1]) + M[r * 3 + 2] * M[c * 3 + 2];
+    float xs = px / pz, ys = py / pz;
+    float clx = xs < -cam.limx ? -1.f : (xs > cam.limx ? 1.f : 0.f);
+    float cly = ys < -cam.limy ? -1.f : (ys > cam.limy ? 1.f : 0.f);
+    if (clx != 0.f) xs = clx * cam.limx;
+    if (cly != 0.f) ys = cly * cam.limy;
+    float txf = xs * pz, tyf = ys * pz;
+    double fx = cam.fx, fy = cam.fy, tx = txf, ty = tyf, z1 = pz, z2 = z1 * z1, z3 = z2 * z1;
+    double J00 = fx / z1, J02 = -(fx * tx) / z2;
+    double J11 = fy / z1, J12 = -(fy * ty) / z2;
+    double T[6];
+    for (int c = 0; c < 3; ++c) {
+        T[c] = J00 * (double)R[c] + J02 * (double)R[6 + c];
+        T[3 + c] = J11 * (double)R[3 + c] + J12 * (double)R[6 + c];
+    }
+    double U[6];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c)
+            U[r * 3 + c] = (T[r * 3 + 0] * S[c] + T[r * 3 + 1] * S[3 + c]) + T[r * 3 + 2] * S[6 + c];
+    double A = ((U[0] * T[0] + U[1] * T[1]) + U[2] * T[2]) + 0.3;
+    double B = (U[0] * T[3] + U[1] * T[4]) + U[2] * T[5];
+    double C = ((U[3] * T[3] + U[4] * T[4]) + U[5] * T[5]) + 0.3;
+    double det = A * C - B * B;
+    double id2 = 1.0 / (det * det);
+    // conic (a, b, c) = (C, -B, A) / det
+    double dA = (da * (-C * C) + db * (B * C) + dc * (-B * B)) * id2;
+    double dB = da * (2.0 * B * C) * id2 + db * (-1.0 / det - 2.0 * B * B * id2) + dc * (2.0 * A * B) * id2;
+    double dCc = (da * (-B * B) + db * (B * A) + dc * (-A * A)) * id2;
+    // Sigma2D = T Sigma T^T with symmetric cotangent G
+    double G00 = dA, G01 = 0.5 * dB, G11 = dCc;
+    double GT[6];  // G T (2x3)
+    for (int c = 0; c < 3; ++c) {
+        GT[c] = G00 * T[c] + G01 * T[3 + c];
+        GT[3 + c] = G01 * T[c] + G11 * T[3 + c];
+    }
+    double dS[9];  // T^T G T
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) dS[r * 3 + c] = T[r] * GT[c] + T[3 + r] * GT[3 + c];
+    double dT[6];  // 2 G T S
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c)
+            dT[r * 3 + c] = 2.0 * (GT[r * 3 + 0] * S[c] + GT[r * 3 + 1] * S[3 + c] + GT[r * 3 + 2] * S[6 + c]);
+    double dJ00 = 0.0, dJ02 = 0.0, dJ11 = 0.0, dJ12 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        dJ00 += dT[c] * (double)R[c];
+        dJ02 += dT[c] * (double)R[6 + c];
+        dJ11 += dT[3 + c] * (double)R[3 + c];
+        dJ12 += dT[3 + c] * (double)R[6 + c];
+    }
+    double dp[3] = {0.0, 0.0, 0.0};
+    dp[2] += dJ00 * (-fx / z2) + dJ11 * (-fy / z2);
+    double dtx = dJ02 * (-fx / z2), dty = dJ12 * (-fy / z2);
+    dp[2] += dJ02 * (2.0 * fx * tx / z3) + dJ12 * (2.0 * fy * ty / z3);
+    if (clx == 0.f) dp[0] += dtx; else dp[2] += dtx * clx * cam.limx;
+    if (cly == 0.f) dp[1] += dty; else dp[2] += dty * cly * cam.limy;
+    double dpx = px, dpy = py;
+    dp[0] += du * fx / z1;
+    dp[2] += du * (-fx * dpx / z2);
+    dp[1] += dv * fy / z1;
+    dp[2] += dv * (-fy * dpy / z2);
+    for (int c = 0; c < 3; ++c)
+        dm[c] += (double)R[c] * dp[0] + (double)R[3 + c] * dp[1] + (double)R[6 + c] * dp[2];
+    // Sigma = M M^T, M = R diag(s)
+    double dM[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            dM[r * 3 + c] = 2.0 * (dS[r * 3 + 0] * M[c] + dS[r * 3 + 1] * M[3 + c] + dS[r * 3 + 2] * M[6 + c]);
+    double dR[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) dR[r * 3 + c] = dM[r * 3 + c] * s[c];
+    for (int c = 0; c < 3; ++c)
+        dls[c] += (dM[c] * Rq[c] + dM[3 + c] * Rq[3 + c] + dM[6 + c] * Rq[6 + c]) * s[c];
+    double gq[4];
+    gq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    gq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                   2.0 * x * dR[8]);
+    gq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                   2.0 * y * dR[8]);
+    gq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
+                   y * dR[7]);
+    double qd = w * gq[0] + x * gq[1] + y * gq[2] + z * gq[3];
+    double qn[4] = {w, x, y, z};
+    for (int k = 0; k < 4; ++k) dq[k] += (gq[k] - qn[k] * qd) / nr;
+    dlogit += dop * o * (1.0f - o);
+}
+
+// dL/drgb of one view: the forward clamps rgb at 0, so no gradient where the
+// clamp was active (s2 = the splat's colour record).
+__device__ __forceinline__ void colour_grad(const float4& s2, const float* __restrict__ g2, float drgb[3])
+{
+    drgb[0] = s2.x > 0.0f ? g2[6] : 0.0f;
+    drgb[1] = s2.y > 0.0f ? g2[7] : 0.0f;
+    drgb[2] = s2.z > 0.0f ? g2[8] : 0.0f;
+}
+
+// Unit view direction from a camera centre to the mean; returns its length.
+__device__ __forceinline__ float view_dir(float mx, float my, float mz, const float campos[3], float dir[3])
+{
+    float dxw = mx - campos[0], dyw = my - campos[1], dzw = mz - campos[2];
+    float dn = sqrtf(dxw * dxw + dyw * dyw + dzw * dzw);
+    dir[0] = dxw; dir[1] = dyw; dir[2] = dzw;
+    if (dn > 0.0f) { dir[0] /= dn; dir[1] /= dn; dir[2] /= dn; }
+    return dn;
+}
+
+__global__ __launch_bounds__(QB_BLOCK) void k_project_backward(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits, const float* __restrict__ sh, int sh_degree,
+    BwdCam cam, const float4* __restrict__ splats, const float* __restrict__ grad2d, float* __restrict__ d_means,
+    float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_logits,
+    float* __restrict__ d_sh)
+{
+    int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    int K = (sh_degree + 1) * (sh_degree + 1);
+    float4 s2 = splats[3 * i + 2];
+    double dm[3] = {0.0, 0.0, 0.0}, dls[3] = {0.0, 0.0, 0.0}, dq[4] = {0.0, 0.0, 0.0, 0.0};
+    float dlogit = 0.f;
+    if (s2.w != 1.0f) {
+        for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = 0.f;
+    } else {
+        const float* g2 = grad2d + 9 * i;
+        geometry_backward(i, n, means, log_scales, quats, logits, cam, g2, dm, dls, dq, dlogit);
+        float dir[3], drgb[3], ddir[3];
+        float dn = view_dir(means[i], means[n + i], means[2 * n + i], cam.campos, dir);
+        colour_grad(s2, g2, drgb);
+        sh_colour_backward(sh, n, i, sh_degree, dir[0], dir[1], dir[2], drgb, d_sh, ddir);
+        if (dn > 0.0f) {
+            float dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
+            for (int c = 0; c < 3; ++c) dm[c] += (double)((ddir[c] - dir[c] * dd) / dn);
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        d_means[c * n + i] = (float)dm[c];
+        d_log_scales[c * n + i] = (float)dls[c];
+    }
+    for (int c = 0; c < 4; ++c) d_quats[c * n + i] = (float)dq[c];
+    d_logits[i] = dlogit;
+}
+
+// Views: the geometry part summed over views (the colour's share of the
+// mean gradient follows in k_sh_backward_views).
+__global__ __launch_bounds__(QB_BLOCK) void k_geometry_backward_views(
+    int64_t n, int nv, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits, BwdCamTable cams,
+    const float4* __restrict__ splats, const float* __restrict__ grad2d, float* __restrict__ d_means,
+    float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_logits)
+{
+    int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double dm[3] = {0.0, 0.0, 0.0}, dls[3] = {0.0, 0.0, 0.0}, dq[4] = {0.0, 0.0, 0.0, 0.0};
+    float dlogit = 0.f;
+    for (int v = 0; v < nv; ++v) {
+        int64_t vi = (int64_t)v * n + i;
+        if (splats[3 * vi + 2].w != 1.0f) continue;
+        geometry_backward(i, n, means, log_scales, quats, logits, cams.cam[v], grad2d + 9 * vi, dm, dls, dq, dlogit);
+    }
+    for (int c = 0; c < 3; ++c) {
+        d_means[c * n + i] = (float)dm[c];
+        d_log_scales[c * n + i] = (float)dls[c];
+    }
+    for (int c = 0; c < 4; ++c) d_quats[c * n + i] = (float)dq[c];
+    d_logits[i] = dlogit;
+}
+
+// Views: SH coefficients and the colour's share of the mean gradient, summed
+// over views in registers; adds to d_means (after k_geometry_backward_views).
+template <int DEG>
+__global__ __launch_bounds__(QB_BLOCK) void k_sh_backward_views(
+    int64_t n, int nv, const float* __restrict__ means, const float* __restrict__ sh, BwdCamTable cams,
+    const float4* __restrict__ splats, const float* __restrict__ grad2d, float* __restrict__ d_means,
+    float* __restrict__ d_sh)
+{
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    float coef[K * 3], acc[K * 3];
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) {
+        coef[k] = sh[(int64_t)k * n + i];
+        acc[k] = 0.0f;
+    }
+    float mx = means[i], my = means[n + i], mz = means[2 * n + i];
+    float dmx = 0.f, dmy = 0.f, dmz = 0.f;
+    for (int v = 0; v < nv; ++v) {
+        int64_t vi = (int64_t)v * n + i;
+        float4 s2 = splats[3 * vi + 2];
+        if (s2.w != 1.0f) continue;
+        float dir[3], drgb[3];
+        float dn = view_dir(mx, my, mz, cams.cam[v].campos, dir);
+        colour_grad(s2, grad2d + 9 * vi, drgb);
+        float Y[16], G[16][3];
+        sh_basis_and_grad(dir[0], dir[1], dir[2], Y, G);
+        float ddir[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                acc[k * 3 + ch] = fmaf(Y[k], drgb[ch], acc[k * 3 + ch]);
+                float cw = coef[k * 3 + ch] * drgb[ch];
+                ddir[0] = fmaf(G[k][0], cw, ddir[0]);
+                ddir[1] = fmaf(G[k][1], cw, ddir[1]);
+                ddir[2] = fmaf(G[k][2], cw, ddir[2]);
+            }
+        if (dn > 0.0f) {
+            float dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
+            dmx += (ddir[0] - dir[0] * dd) / dn;
+            dmy += (ddir[1] - dir[1] * dd) / dn;
+            dmz += (ddir[2] - dir[2] * dd) / dn;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = acc[k];
+    d_means[i] += dmx;
+    d_means[n + i] += dmy;
+    d_means[2 * n + i] += dmz;
+}
+
+__global__ void k_zero(float* __restrict__ p, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x; i < count; i += (int64_t)gridDim.x * QB_BLOCK)
+        p[i] = 0.0f;
+}
+
+}  // namespace
+
+namespace {
+
+// Camera constants of the backward; lim = 1.3 * (0.5 W / fx) as the forward.
+void make_bwd_cam(const qb_camera& cam, BwdCam* bc)
+{
+    bc->W = cam.width;
+    bc->H = cam.height;
+    bc->fx = cam.fx; bc->fy = cam.fy; bc->cx = cam.cx; bc->cy = cam.cy;
+    bc->near_plane = cam.near_plane;
+    for (int k = 0; k < 9; ++k) bc->R[k] = cam.R[k];
+    for (int k = 0; k < 3; ++k) { bc->t[k] = cam.t[k]; bc->campos[k] = cam.campos[k]; }
+    volatile float hx = 0.5f * (float)cam.width;
+    volatile float hy = 0.5f * (float)cam.height;
+    bc->limx = 1.3f * (hx / cam.fx);
+    bc->limy = 1.3f * (hy / cam.fy);
+}
+
+}  // namespace
+
+extern "C" qb_status qb_render_backward(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
+                                        const qb_splat* splats, const float* bg, const float* final_T,
+                                        const uint32_t* n_contrib, const float* dL_dimage, int64_t n,
+                                        float* grad2d, qb_stream_t stream)
+{
+    if (width <= 0 || height <= 0 || width > 32767 * QB_TILE || height > 32767 * QB_TILE || !ranges || !bg ||
+        !final_T || !n_contrib || !dL_dimage || n < 0 || (n > 0 && (!grad2d || !splats)))
+        return QB_ERR_INVALID_ARG;
+    int tiles_x = (int)qb_div_up(width, QB_TILE);
+    int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
+    if (tiles > (1 << 24)) return QB_ERR_INVALID_ARG;
+    hipStream_t s = qb_hip_stream(stream);
+    if (n > 0) {
+        int64_t g = qb_div_up(9 * n, QB_BLOCK);
+        QB_LAUNCH(k_zero, g > 4096 ? 4096 : g, QB_BLOCK, 0, s, grad2d, 9 * n);
+    }
+    QB_LAUNCH(k_render_backward, tiles, kBwdThreads, 0, s, (int)width, (int)height, tiles_x, (int)tiles,
+              reinterpret_cast<const uint2*>(ranges), ids, reinterpret_cast<const float4*>(splats), bg[0], bg[1],
+              bg[2], final_T, n_contrib, dL_dimage, grad2d);
+    return QB_OK;
+}
+
+extern "C" qb_status qb_project_backward(int64_t n, const float* means, const float* log_scales,
+                                         const float* quats, const float* opacity_logits, const float* sh,
+                                         int32_t sh_degree, const qb_camera* cam, const qb_splat* splats,
+                                         const float* grad2d, float* d_means, float* d_log_scales, float* d_quats,
+                                         float* d_opacity_logits, float* d_sh, qb_stream_t stream)
+{
+    if (n < 0 || n >= (int64_t)1 << 31 || !cam || sh_degree < 0 || sh_degree > 3) return QB_ERR_INVALID_ARG;
+    if (cam->width <= 0 || cam->height <= 0 || !(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return QB_ERR_INVALID_ARG;
+    if (n == 0) return QB_OK;
+    if (!means || !log_scales || !quats || !opacity_logits || !sh || !splats || !grad2d || !d_means ||
+        !d_log_scales || !d_quats || !d_opacity_logits || !d_sh)
+        return QB_ERR_INVALID_ARG;
+    BwdCam bc;
+    make_bwd_cam(*cam, &bc);
+    QB_LAUNCH(k_project_backward, qb_div_up(n, QB_BLOCK), QB_BLOCK, 0, qb_hip_stream(stream), n, means, log_scales,
+              quats, opacity_logits, sh, (int)sh_degree, bc, reinterpret_cast<const float4*>(splats), grad2d, d_means,
+              d_log_scales, d_quats, d_opacity_logits, d_sh);
+    return QB_OK;
+}
+
+extern "C" qb_status qb_render_backward_views(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
+                                              qb_stream_t stream)
+{
+    if (!bg || n < 0) return QB_ERR_INVALID_ARG;
+    QbViewTable vt;
+    qb_status st = qb_make_view_table(num_views, views, true, &vt);
+    if (st != QB_OK) return st;
+    hipStream_t s = qb_hip_stream(stream);
+    if (n > 0) {
+        int64_t g = qb_div_up(9 * n, QB_BLOCK);
+        QB_LAUNCH(k_zero_views, dim3(g > 1024 ? 1024 : (unsigned)g, num_views), QB_BLOCK, 0, s, vt, 9 * n);
+    }
+    if (vt.tile_start[num_views] > 0)
+        QB_LAUNCH(k_render_backward_views, vt.tile_start[num_views], kBwdThreads, 0, s, vt, bg[0], bg[1], bg[2]);
+    return QB_OK;
+}
+
+extern "C" qb_status qb_project_backward_views(int64_t n, const float* means, const float* log_scales,
+                                               const float* quats, const float* opacity_logits, const float* sh,
+                                               int32_t sh_degree, const qb_camera* cams, int32_t num_views,
+                                               const qb_splat* splats, const float* grad2d, float* d_means,
+                                               float* d_log_scales, float* d_quats, float* d_opacity_logits,
+                                               float* d_sh, qb_stream_t stream)
+{
+    if (n < 0 || n >= (int64_t)1 << 31 || !cams || sh_degree < 0 || sh_degree > 3 || num_views < 1 ||
+        num_views > QB_MAX_VIEWS)
+        return QB_ERR_INVALID_ARG;
+    BwdCamTable ct;
+    for (int v = 0; v < num_views; ++v) {
+        const qb_camera& c = cams[v];
+        if (c.width <= 0 || c.height <= 0 || !(c.fx > 0.0f) || !(c.fy > 0.0f)) return QB_ERR_INVALID_ARG;
+        make_bwd_cam(c, &ct.cam[v]);
+    }
+    if (n == 0) return QB_OK;
+    if (!means || !log_scales || !quats || !opacity_logits || !sh || !splats || !grad2d || !d_means ||
+        !d_log_scales || !d_quats || !d_opacity_logits || !d_sh)
+        return QB_ERR_INVALID_ARG;
+    hipStream_t s = qb_hip_stream(stream);
+    int64_t grid = qb_div_up(n, QB_BLOCK);
+    const float4* sp = reinterpret_cast<const float4*>(splats);
+    QB_LAUNCH(k_geometry_backward_views, grid, QB_BLOCK, 0, s, n, (int)num_views, means, log_scales, quats,
+              opacity_logits, ct, sp, grad2d, d_means, d_log_scales, d_quats, d_opacity_logits);
+    switch (sh_degree) {
+    case 0: QB_LAUNCH(k_sh_backward_views<0>, grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, grad2d,
+                      d_means, d_sh); break;
+    case 1: QB_LAUNCH(k_sh_backward_views<1>, grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, grad2d,
+                      d_means, d_sh); break;
+    case 2: QB_LAUNCH(k_sh_backward_views<2>, grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, grad2d,
+                      d_means, d_sh); break;
+    default: QB_LAUNCH(k_sh_backward_views<3>, grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, grad2d,
+                       d_means, d_sh); break;
+    }
+    return QB_OK;
+}

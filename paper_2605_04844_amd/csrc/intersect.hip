@@ -15,6 +15,9 @@
 //     of the pair's offset in the run; the stores of a wave are contiguous.
 // A pair is stored compactly as (uint16 tile, uint32 Gaussian id); its key
 // tile << 32 | bits(depth) is implied by the id.
+// The naive traversal (QB_BOX_QUADBOX_NAIVE, the ablation without QPass)
+// replaces step 3 by one lane per Gaussian that walks its sub-box rects with
+// nested loops and writes its pairs one by one, as DuplicateWithKeys does.
 #include "qb_bin.h"
 
 namespace {
@@ -140,6 +143,29 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     }
 }
 
+__global__ __launch_bounds__(QB_BLOCK) void k_emit_naive(
+    int64_t n, const uint32_t* __restrict__ order, const uint64_t* __restrict__ goff,
+    const int4* __restrict__ rects, const int32_t* __restrict__ counts, int tiles_x, int64_t cap,
+    const int64_t* __restrict__ num_pairs, uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id)
+{
+    if (*num_pairs > cap) return;  // overflow: the caller re-runs with more capacity
+    int64_t k = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
+    if (k >= n) return;
+    uint32_t gi = order[k];
+    if (counts[gi] <= 0) return;
+    int4 p0 = rects[2 * (int64_t)gi], p1 = rects[2 * (int64_t)gi + 1];
+    QRect r[4] = {qbb::unpack_rect(p0.x, p0.y), qbb::unpack_rect(p0.z, p0.w), qbb::unpack_rect(p1.x, p1.y),
+                  qbb::unpack_rect(p1.z, p1.w)};
+    int64_t base = (int64_t)goff[k];
+    naive_walk(r, [&](int tx, int ty, int c) {
+        int64_t dst = base + c;
+        if (dst < cap) {
+            out_tile[dst] = (uint16_t)(ty * tiles_x + tx);
+            out_id[dst] = gi;
+        }
+    });
+}
+
 struct IsectWs {
     uint32_t *dk0, *dv0, *dk1, *dv1;  // depth sort ping-pong; dv0 ends as the order
     uint32_t* csorted;                // counts in that order
@@ -175,11 +201,13 @@ extern "C" size_t qb_intersect_workspace_size(int64_t n)
 }
 
 extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_rects* rects,
-                                  const int32_t* counts, int32_t width, int32_t height, int64_t pair_capacity,
+                                  const int32_t* counts, int32_t width, int32_t height, int32_t mode,
+                                  int64_t pair_capacity,
                                   uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs, void* workspace,
                                   size_t workspace_bytes, qb_stream_t stream)
 {
-    if (n < 0 || n >= (int64_t)1 << 31 || width <= 0 || height <= 0 || pair_capacity < 0 ||
+    if (n < 0 || n >= (int64_t)1 << 31 || width <= 0 || height <= 0 || mode < QB_BOX_3SIGMA ||
+        mode > QB_BOX_QUADBOX_NAIVE || pair_capacity < 0 ||
         pair_capacity > (int64_t)0xFFFFFFFF || !num_pairs || !workspace)
         return QB_ERR_INVALID_ARG;
     int tiles_x = (int)qb_div_up(width, QB_TILE);
@@ -204,7 +232,11 @@ extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_re
     QB_LAUNCH(k_gather_counts, grid, QB_BLOCK, 0, s, n, (const uint32_t*)w.dv0, counts, w.csorted);
     QB_CHECK((qbr::exclusive_scan<uint32_t, uint64_t>(w.csorted, w.offs, n, w.scan64, w.total, s)));
     QB_LAUNCH(k_store_total, 1, 1, 0, s, (const uint64_t*)w.total, num_pairs);
-    if (pair_capacity > 0)
+    if (pair_capacity > 0 && mode == QB_BOX_QUADBOX_NAIVE)
+        QB_LAUNCH(k_emit_naive, grid, QB_BLOCK, 0, s, n, (const uint32_t*)w.dv0, (const uint64_t*)w.offs,
+                  reinterpret_cast<const int4*>(rects), counts, tiles_x, pair_capacity, (const int64_t*)num_pairs,
+                  pair_tiles, pair_ids);
+    else if (pair_capacity > 0)
         QB_LAUNCH(k_emit, qb_div_up(n, kEmitThreads), kEmitThreads, 0, s, n, (const uint32_t*)w.dv0,
                   (const uint64_t*)w.offs, reinterpret_cast<const int4*>(rects), counts, tiles_x, pair_capacity,
                   (const int64_t*)num_pairs, pair_tiles, pair_ids);

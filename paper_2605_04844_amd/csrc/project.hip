@@ -92,14 +92,14 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t 
     for (int ch = 0; ch < 3; ++ch) rgb[ch] = acc[ch] > 0.0f ? acc[ch] : 0.0f;
 }
 
-__global__ __launch_bounds__(QB_BLOCK) void k_project(
-    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
-    const float* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, int sh_degree, ProjCam cam, int mode,
-    float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
+// Projects Gaussian i for one camera and writes its splat, rects and count.
+__device__ __forceinline__ void project_one(int64_t i, int64_t n, const float* __restrict__ means,
+                                            const float* __restrict__ log_scales, const float* __restrict__ quats,
+                                            const float* __restrict__ logits, const float* __restrict__ sh,
+                                            int sh_degree, const ProjCam& cam, int mode,
+                                            float4* __restrict__ out_splat, int4* __restrict__ out_rects,
+                                            int32_t* __restrict__ out_count)
 {
-    int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
-    if (i >= n) return;
     float mx = means[i], my = means[n + i], mz = means[2 * n + i];
     const float* R = cam.R;
     float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + cam.t[0];
@@ -125,24 +125,29 @@ __global__ __launch_bounds__(QB_BLOCK) void k_project(
         if (!(n2 > 0.0f) || !isfinite(n2)) break;
         float nr = sqrtf(n2);
         float w = qw / nr, x = qx / nr, y = qy / nr, z = qz / nr;
-        float Rq[9];
-        Rq[0] = 1.0f - 2.0f * (y * y + z * z);
-        Rq[1] = 2.0f * (x * y - w * z);
-        Rq[2] = 2.0f * (x * z + w * y);
-        Rq[3] = 2.0f * (x * y + w * z);
-        Rq[4] = 1.0f - 2.0f * (x * x + z * z);
-        Rq[5] = 2.0f * (y * z - w * x);
-        Rq[6] = 2.0f * (x * z - w * y);
-        Rq[7] = 2.0f * (y * z + w * x);
-        Rq[8] = 1.0f - 2.0f * (x * x + y * y);
-        float M[9];
+        // Sigma3D, the EWA projection and the conic in binary64, each result
+        // rounded once to binary32: for needle-like Gaussians Sigma2D is
+        // nearly singular (condition up to ~1e6), and binary32 entries would
+        // lose up to a percent of the conic to cancellation in A C - B^2.
+        double dw = w, dxq = x, dyq = y, dzq = z;
+        double Rq[9];
+        Rq[0] = 1.0 - 2.0 * (dyq * dyq + dzq * dzq);
+        Rq[1] = 2.0 * (dxq * dyq - dw * dzq);
+        Rq[2] = 2.0 * (dxq * dzq + dw * dyq);
+        Rq[3] = 2.0 * (dxq * dyq + dw * dzq);
+        Rq[4] = 1.0 - 2.0 * (dxq * dxq + dzq * dzq);
+        Rq[5] = 2.0 * (dyq * dzq - dw * dxq);
+        Rq[6] = 2.0 * (dxq * dzq - dw * dyq);
+        Rq[7] = 2.0 * (dyq * dzq + dw * dxq);
+        Rq[8] = 1.0 - 2.0 * (dxq * dxq + dyq * dyq);
+        double M[9];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-            M[r * 3 + 0] = Rq[r * 3 + 0] * sx;
-            M[r * 3 + 1] = Rq[r * 3 + 1] * sy;
-            M[r * 3 + 2] = Rq[r * 3 + 2] * sz;
+            M[r * 3 + 0] = Rq[r * 3 + 0] * (double)sx;
+            M[r * 3 + 1] = Rq[r * 3 + 1] * (double)sy;
+            M[r * 3 + 2] = Rq[r * 3 + 2] * (double)sz;
         }
-        float S[9];
+        double S[9];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -150,37 +155,42 @@ __global__ __launch_bounds__(QB_BLOCK) void k_project(
                 S[r * 3 + c] = (M[r * 3 + 0] * M[c * 3 + 0] + M[r * 3 + 1] * M[c * 3 + 1]) +
                                M[r * 3 + 2] * M[c * 3 + 2];
 
+        // Jacobian at the view-space mean with its image-plane slope clamped
+        // to 1.3x the half field of view (binary32 slope, binary64 Jacobian)
         float xs = px / pz, ys = py / pz;
         xs = xs < -cam.limx ? -cam.limx : (xs > cam.limx ? cam.limx : xs);
         ys = ys < -cam.limy ? -cam.limy : (ys > cam.limy ? cam.limy : ys);
         float tx = xs * pz, ty = ys * pz;
-        float zz = pz * pz;
-        float J00 = cam.fx / pz, J02 = -(cam.fx * tx) / zz;
-        float J11 = cam.fy / pz, J12 = -(cam.fy * ty) / zz;
-        float T[6];
+        double dpz = pz, zz = dpz * dpz;
+        double J00 = (double)cam.fx / dpz, J02 = -((double)cam.fx * (double)tx) / zz;
+        double J11 = (double)cam.fy / dpz, J12 = -((double)cam.fy * (double)ty) / zz;
+        double T[6];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            T[c] = J00 * R[c] + J02 * R[6 + c];
-            T[3 + c] = J11 * R[3 + c] + J12 * R[6 + c];
+            T[c] = J00 * (double)R[c] + J02 * (double)R[6 + c];
+            T[3 + c] = J11 * (double)R[3 + c] + J12 * (double)R[6 + c];
         }
-        float U[6];
+        double U[6];
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 U[r * 3 + c] = (T[r * 3 + 0] * S[0 * 3 + c] + T[r * 3 + 1] * S[1 * 3 + c]) +
                                T[r * 3 + 2] * S[2 * 3 + c];
-        float A = (U[0] * T[0] + U[1] * T[1]) + U[2] * T[2];
-        float B = (U[0] * T[3] + U[1] * T[4]) + U[2] * T[5];
-        float C = (U[3] * T[3] + U[4] * T[4]) + U[5] * T[5];
-        A = A + 0.3f;
-        C = C + 0.3f;
+        double A64 = ((U[0] * T[0] + U[1] * T[1]) + U[2] * T[2]) + 0.3;
+        double B64 = (U[0] * T[3] + U[1] * T[4]) + U[2] * T[5];
+        double C64 = ((U[3] * T[3] + U[4] * T[4]) + U[5] * T[5]) + 0.3;
+        double det64 = A64 * C64 - B64 * B64;
+        if (!(det64 > 0.0)) break;
+        float A = (float)A64, B = (float)B64, C = (float)C64;
+        float ca = (float)(C64 / det64), cb = (float)(-(B64 / det64)), cc = (float)(A64 / det64);
+        float det = A * C - B * B;  // binary32, for the 3-sigma radius only
 
         float u = cam.fx * (px / pz) + cam.cx;
         float v = cam.fy * (py / pz) + cam.cy;
-        float det = A * C - B * B;
-        if (!(det > 0.0f) || !isfinite(det) || !isfinite(u) || !isfinite(v)) break;
-        float ca = C / det, cb = -(B / det), cc = A / det;
+        if (!isfinite(A) || !isfinite(B) || !isfinite(C) || !isfinite(ca) || !isfinite(cb) || !isfinite(cc) ||
+            !isfinite(u) || !isfinite(v))
+            break;
         if (mode != QB_BOX_3SIGMA && !(gam > 0.0f)) break;
 
         float rgb[3];
@@ -227,9 +237,13 @@ __global__ __launch_bounds__(QB_BLOCK) void k_project(
                 }
             }
         }
-        QRuns runs;
-        qpass_runs(rr, runs);
-        count = runs.total;
+        if (mode == QB_BOX_QUADBOX_NAIVE) {
+            count = naive_walk(rr, [](int, int, int) {});
+        } else {
+            QRuns runs;
+            qpass_runs(rr, runs);
+            count = runs.total;
+        }
         s0 = make_float4(u, v, pz, o);
         s1 = make_float4(ca, cb, cc, gam);
         s2 = make_float4(rgb[0], rgb[1], rgb[2], 1.0f);
@@ -254,6 +268,64 @@ __global__ __launch_bounds__(QB_BLOCK) void k_project(
     out_count[i] = count;
 }
 
+__global__ __launch_bounds__(QB_BLOCK) void k_project(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int sh_degree, ProjCam cam, int mode,
+    float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
+{
+    int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    project_one(i, n, means, log_scales, quats, logits, sh, sh_degree, cam, mode, out_splat, out_rects, out_count);
+}
+
+// Cameras of a batched call, by value as a kernel argument (3.3 KB at
+// QB_MAX_VIEWS).
+struct ProjCamTable {
+    ProjCam cam[QB_MAX_VIEWS];
+};
+
+// blockIdx.y is the view; view v writes the block of records starting at v*n.
+__global__ __launch_bounds__(QB_BLOCK) void k_project_views(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int sh_degree, ProjCamTable cams, int mode,
+    float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
+{
+    int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    int64_t v = blockIdx.y;
+    project_one(i, n, means, log_scales, quats, logits, sh, sh_degree, cams.cam[v], mode, out_splat + 3 * v * n,
+                out_rects + 2 * v * n, out_count + v * n);
+}
+
+}  // namespace
+
+namespace {
+
+bool valid_camera(const qb_camera& c)
+{
+    return c.width > 0 && c.height > 0 && c.width <= 32767 * QB_TILE && c.height <= 32767 * QB_TILE &&
+           c.fx > 0.0f && c.fy > 0.0f;
+}
+
+void make_proj_cam(const qb_camera& cam, ProjCam* pc)
+{
+    pc->W = cam.width;
+    pc->H = cam.height;
+    pc->tiles_x = (int)qb_div_up(cam.width, QB_TILE);
+    pc->tiles_y = (int)qb_div_up(cam.height, QB_TILE);
+    pc->fx = cam.fx; pc->fy = cam.fy; pc->cx = cam.cx; pc->cy = cam.cy;
+    pc->near_plane = cam.near_plane;
+    for (int k = 0; k < 9; ++k) pc->R[k] = cam.R[k];
+    for (int k = 0; k < 3; ++k) { pc->t[k] = cam.t[k]; pc->campos[k] = cam.campos[k]; }
+    // 1.3 x tan(half fov), in the same binary32 order as the oracle
+    volatile float hx = 0.5f * (float)cam.width;
+    volatile float hy = 0.5f * (float)cam.height;
+    pc->limx = 1.3f * (hx / cam.fx);
+    pc->limy = 1.3f * (hy / cam.fy);
+}
+
 }  // namespace
 
 extern "C" qb_status qb_project(int64_t n, const float* means, const float* log_scales,
@@ -263,32 +335,42 @@ extern "C" qb_status qb_project(int64_t n, const float* means, const float* log_
                                 qb_stream_t stream)
 {
     if (n < 0 || n >= (int64_t)1 << 31 || !cam || sh_degree < 0 || sh_degree > 3) return QB_ERR_INVALID_ARG;
-    if (mode < QB_BOX_3SIGMA || mode > QB_BOX_DUALBOX) return QB_ERR_INVALID_ARG;
-    if (cam->width <= 0 || cam->height <= 0 || cam->width > 32767 * QB_TILE ||
-        cam->height > 32767 * QB_TILE)
-        return QB_ERR_INVALID_ARG;
-    if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return QB_ERR_INVALID_ARG;
+    if (mode < QB_BOX_3SIGMA || mode > QB_BOX_QUADBOX_NAIVE) return QB_ERR_INVALID_ARG;
+    if (!valid_camera(*cam)) return QB_ERR_INVALID_ARG;
     if (n == 0) return QB_OK;
     if (!means || !log_scales || !quats || !opacity_logits || !sh || !out_splats || !out_rects ||
         !out_counts)
         return QB_ERR_INVALID_ARG;
     ProjCam pc;
-    pc.W = cam->width;
-    pc.H = cam->height;
-    pc.tiles_x = (int)qb_div_up(cam->width, QB_TILE);
-    pc.tiles_y = (int)qb_div_up(cam->height, QB_TILE);
-    pc.fx = cam->fx; pc.fy = cam->fy; pc.cx = cam->cx; pc.cy = cam->cy;
-    pc.near_plane = cam->near_plane;
-    for (int k = 0; k < 9; ++k) pc.R[k] = cam->R[k];
-    for (int k = 0; k < 3; ++k) { pc.t[k] = cam->t[k]; pc.campos[k] = cam->campos[k]; }
-    // 1.3 x tan(half fov), in the same binary32 order as the oracle
-    volatile float hx = 0.5f * (float)cam->width;
-    volatile float hy = 0.5f * (float)cam->height;
-    pc.limx = 1.3f * (hx / cam->fx);
-    pc.limy = 1.3f * (hy / cam->fy);
+    make_proj_cam(*cam, &pc);
     int64_t grid = qb_div_up(n, QB_BLOCK);
     QB_LAUNCH(k_project, grid, QB_BLOCK, 0, qb_hip_stream(stream), n, means, log_scales, quats,
               opacity_logits, sh, (int)sh_degree, pc, (int)mode,
+              reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects), out_counts);
+    return QB_OK;
+}
+
+extern "C" qb_status qb_project_views(int64_t n, const float* means, const float* log_scales,
+                                      const float* quats, const float* opacity_logits, const float* sh,
+                                      int32_t sh_degree, const qb_camera* cams, int32_t num_views, int32_t mode,
+                                      qb_splat* out_splats, qb_rects* out_rects, int32_t* out_counts,
+                                      qb_stream_t stream)
+{
+    if (n < 0 || n >= (int64_t)1 << 31 || !cams || sh_degree < 0 || sh_degree > 3 || num_views < 1 ||
+        num_views > QB_MAX_VIEWS)
+        return QB_ERR_INVALID_ARG;
+    if (mode < QB_BOX_3SIGMA || mode > QB_BOX_QUADBOX_NAIVE) return QB_ERR_INVALID_ARG;
+    ProjCamTable ct;
+    for (int v = 0; v < num_views; ++v) {
+        if (!valid_camera(cams[v])) return QB_ERR_INVALID_ARG;
+        make_proj_cam(cams[v], &ct.cam[v]);
+    }
+    if (n == 0) return QB_OK;
+    if (!means || !log_scales || !quats || !opacity_logits || !sh || !out_splats || !out_rects ||
+        !out_counts)
+        return QB_ERR_INVALID_ARG;
+    QB_LAUNCH(k_project_views, dim3((unsigned)qb_div_up(n, QB_BLOCK), (unsigned)num_views), QB_BLOCK, 0,
+              qb_hip_stream(stream), n, means, log_scales, quats, opacity_logits, sh, (int)sh_degree, ct, (int)mode,
               reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects), out_counts);
     return QB_OK;
 }

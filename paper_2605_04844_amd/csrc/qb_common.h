@@ -46,6 +46,78 @@ struct QRect {
     int x0, x1, y0, y1;
 };
 
+// Per-view table of a batched call, passed by value as a kernel argument
+// (about 2.6 KB at QB_MAX_VIEWS views).  tile_start[v] is the first global
+// tile of view v; tile_start[num] is the total.
+struct QbViewTable {
+    int num;
+    int tile_start[QB_MAX_VIEWS + 1];
+    int tiles_x[QB_MAX_VIEWS];
+    qb_view view[QB_MAX_VIEWS];
+};
+
+// View of global tile b (b < tile_start[num]).
+__device__ __forceinline__ int qb_view_of(const QbViewTable& vt, int b)
+{
+    int v = 0;
+    while (v + 1 < vt.num && b >= vt.tile_start[v + 1]) ++v;
+    return v;
+}
+
+// Validates the views of a batched render (backward: also the gradient
+// buffers) and fills the table.
+static inline qb_status qb_make_view_table(int32_t num_views, const qb_view* views, bool backward,
+                                           QbViewTable* vt)
+{
+    if (num_views < 1 || num_views > QB_MAX_VIEWS || !views) return QB_ERR_INVALID_ARG;
+    vt->num = num_views;
+    int64_t total = 0;
+    for (int v = 0; v < num_views; ++v) {
+        const qb_view& w = views[v];
+        if (w.width <= 0 || w.height <= 0 || w.width > 32767 * QB_TILE || w.height > 32767 * QB_TILE ||
+            !w.ranges || !w.ids || !w.splats || !w.final_T || !w.n_contrib)
+            return QB_ERR_INVALID_ARG;
+        if (!backward && !w.image) return QB_ERR_INVALID_ARG;
+        if (backward && (!w.dL_dimage || !w.grad2d)) return QB_ERR_INVALID_ARG;
+        int64_t tx = qb_div_up(w.width, QB_TILE);
+        vt->tile_start[v] = (int)total;
+        vt->tiles_x[v] = (int)tx;
+        vt->view[v] = w;
+        total += tx * qb_div_up(w.height, QB_TILE);
+        if (total > (1 << 30)) return QB_ERR_INVALID_ARG;
+    }
+    vt->tile_start[num_views] = (int)total;
+    return QB_OK;
+}
+
+__host__ __device__ __forceinline__ bool qrect_holds(const QRect& r, int tx, int ty)
+{
+    return tx >= r.x0 && tx <= r.x1 && ty >= r.y0 && ty <= r.y1;
+}
+
+// Naive QuadBox traversal, the ablation without QPass (Sec. 3.2): each
+// sub-box's tile rect is walked with nested loops, and a tile that an earlier
+// sub-box's rect holds was visited already and is skipped.  visit(tx, ty, c)
+// sees the c-th new tile; returns the number of tiles.
+template <class Visit>
+__host__ __device__ __forceinline__ int naive_walk(const QRect r[4], Visit visit)
+{
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int ty = r[k].y0; ty <= r[k].y1; ++ty)
+            for (int tx = r[k].x0; tx <= r[k].x1; ++tx) {
+                bool seen = false;
+#pragma unroll
+                for (int j = 0; j < k; ++j) seen = seen || qrect_holds(r[j], tx, ty);
+                if (!seen) {
+                    visit(tx, ty, cnt);
+                    ++cnt;
+                }
+            }
+    return cnt;
+}
+
 // QPass runs of one Gaussian (Sec. 3.2).  A run is a block of consecutive
 // scanlines whose QPass interval is the same: n scanlines from s0, each with
 // the len tiles from lo on the other axis.  Every run slot is filled (empty

@@ -20,26 +20,22 @@ namespace {
 
 constexpr int kRenderThreads = 128;  // two wave64; each lane owns two pixels of one row
 
-// XCD-aware tile of a workgroup: workgroups go round-robin to the 8 XCDs, so
-// XCD x receives workgroups x, x+8, ...; mapping them to a contiguous band of
-// tiles keeps the Gaussians that neighbouring tiles share in one L2.
-__device__ __forceinline__ int xcd_tile(int b, int tiles)
-{
-    int q = tiles >> 3, r = tiles & 7;
-    int x = b & 7, idx = b >> 3;
-    return x * q + min(x, r) + idx;
-}
-
-__global__ __launch_bounds__(kRenderThreads) void k_render(
-    int W, int H, int tiles_x, int tiles, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ splats, float bg0, float bg1, float bg2, float* __restrict__ image,
-    float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_touched)
+// Tiles go to workgroups in row-major order.  The dispatcher deals
+// workgroups round-robin to the 8 XCDs, so each XCD receives every 8th tile of
+// every row band: the heavy tiles of a dense region are spread over all XCDs
+// (measured faster than giving each XCD a contiguous band of tiles, which
+// keeps shared Gaussians in one L2 but leaves the XCDs unevenly loaded).
+// Composites one tile of one image (the workgroup's 128 lanes).
+__device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x, const uint2* __restrict__ ranges,
+                                            const uint32_t* __restrict__ ids, const float4* __restrict__ splats,
+                                            float bg0, float bg1, float bg2, float* __restrict__ image,
+                                            float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
+                                            uint32_t* __restrict__ n_touched)
 {
     __shared__ float4 s_geo[kRenderThreads];   // u, v, -a/2, -b
     __shared__ float4 s_opa[kRenderThreads];   // -c/2, o, -gamma/2, unused
     __shared__ float4 s_col[kRenderThreads];   // r, g, b, unused
 
-    int tile = xcd_tile(blockIdx.x, tiles);
     int tx = tile % tiles_x, ty = tile / tiles_x;
     int lx = threadIdx.x & 7, ly = threadIdx.x >> 3;
     int px0 = tx * QB_TILE + lx, px1 = px0 + 8, py = ty * QB_TILE + ly;
@@ -138,6 +134,27 @@ __global__ __launch_bounds__(kRenderThreads) void k_render(
     }
 }
 
+__global__ __launch_bounds__(kRenderThreads) void k_render(
+    int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ splats, float bg0, float bg1, float bg2, float* __restrict__ image,
+    float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_touched)
+{
+    render_tile((int)blockIdx.x, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T, n_contrib,
+                n_touched);
+}
+
+// Every tile of every view in one launch: workgroup b takes global tile b,
+// whose view is found in the (at most QB_MAX_VIEWS) tile offsets.
+__global__ __launch_bounds__(kRenderThreads) void k_render_views(QbViewTable vt, float bg0, float bg1, float bg2)
+{
+    int b = (int)blockIdx.x;
+    int v = qb_view_of(vt, b);
+    const qb_view& w = vt.view[v];
+    render_tile(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
+                w.ids, reinterpret_cast<const float4*>(w.splats), bg0, bg1, bg2, w.image, w.final_T, w.n_contrib,
+                nullptr);
+}
+
 }  // namespace
 
 extern "C" qb_status qb_render(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
@@ -151,7 +168,19 @@ extern "C" qb_status qb_render(int32_t width, int32_t height, const uint32_t* ra
     int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
     if (tiles > (1 << 24)) return QB_ERR_INVALID_ARG;
     QB_LAUNCH(k_render, tiles, kRenderThreads, 0, qb_hip_stream(stream), (int)width, (int)height, tiles_x,
-              (int)tiles, reinterpret_cast<const uint2*>(ranges), ids, reinterpret_cast<const float4*>(splats), bg[0], bg[1],
+              reinterpret_cast<const uint2*>(ranges), ids, reinterpret_cast<const float4*>(splats), bg[0], bg[1],
               bg[2], image, final_T, n_contrib, n_touched);
+    return QB_OK;
+}
+
+extern "C" qb_status qb_render_views(int32_t num_views, const qb_view* views, const float* bg, qb_stream_t stream)
+{
+    if (!bg) return QB_ERR_INVALID_ARG;
+    QbViewTable vt;
+    qb_status st = qb_make_view_table(num_views, views, false, &vt);
+    if (st != QB_OK) return st;
+    if (vt.tile_start[num_views] == 0) return QB_OK;
+    QB_LAUNCH(k_render_views, vt.tile_start[num_views], kRenderThreads, 0, qb_hip_stream(stream), vt, bg[0], bg[1],
+              bg[2]);
     return QB_OK;
 }

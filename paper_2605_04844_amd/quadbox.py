@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libquadbox.so")
 
-BOX_MODES = {"3sigma": 0, "adr": 1, "quadbox": 2, "dualbox": 3}
+BOX_MODES = {"3sigma": 0, "adr": 1, "quadbox": 2, "dualbox": 3, "quadbox_naive": 4}
 TILE = 16
 SPLAT_FLOATS = 12   # qb_splat: u v depth o | a b c gamma | r g b visible
 RECT_SHORTS = 16    # qb_rects: 4 x (tx0, tx1, ty0, ty1)
@@ -36,6 +36,15 @@ class CCamera(C.Structure):
                 ("R", C.c_float * 9), ("t", C.c_float * 3), ("campos", C.c_float * 3)]
 
 
+class CView(C.Structure):
+    """qb_view: per-view buffers of a batched call."""
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("ranges", C.c_void_p), ("ids", C.c_void_p),
+                ("splats", C.c_void_p), ("image", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
+                ("dL_dimage", C.c_void_p), ("grad2d", C.c_void_p)]
+
+
+MAX_VIEWS = 32
+
 _lib = None
 
 
@@ -52,7 +61,7 @@ def lib():
     L.qb_project.restype = i32
     L.qb_intersect_workspace_size.argtypes = [i64]
     L.qb_intersect_workspace_size.restype = sz
-    L.qb_intersect.argtypes = [i64, vp, vp, vp, i32, i32, i64, vp, vp, vp, vp, sz, vp]
+    L.qb_intersect.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz, vp]
     L.qb_intersect.restype = i32
     L.qb_sort_workspace_size.argtypes = [i64]
     L.qb_sort_workspace_size.restype = sz
@@ -60,6 +69,20 @@ def lib():
     L.qb_sort.restype = i32
     L.qb_render.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.qb_render.restype = i32
+    L.qb_render_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp]
+    L.qb_render_backward.restype = i32
+    L.qb_project_backward.argtypes = [i64, vp, vp, vp, vp, vp, i32, C.POINTER(CCamera), vp, vp, vp, vp, vp, vp, vp,
+                                      vp]
+    L.qb_project_backward.restype = i32
+    pc = C.POINTER(CCamera)
+    L.qb_project_views.argtypes = [i64, vp, vp, vp, vp, vp, i32, pc, i32, i32, vp, vp, vp, vp]
+    L.qb_project_views.restype = i32
+    L.qb_render_views.argtypes = [i32, C.POINTER(CView), vp, vp]
+    L.qb_render_views.restype = i32
+    L.qb_render_backward_views.argtypes = [i32, C.POINTER(CView), vp, i64, vp]
+    L.qb_render_backward_views.restype = i32
+    L.qb_project_backward_views.argtypes = [i64, vp, vp, vp, vp, vp, i32, pc, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.qb_project_backward_views.restype = i32
     L.qb_status_string.argtypes = [i32]
     L.qb_status_string.restype = C.c_char_p
     L.qb_version.argtypes = []
@@ -111,17 +134,26 @@ def _dev_f32(x, device):
 class Gaussians:
     """Device-resident SoA parameters (see scenes.Scene for the layouts)."""
 
-    def __init__(self, scene, device="cuda"):
-        self.means = _dev_f32(scene.means, device)
-        self.log_scales = _dev_f32(scene.log_scales, device)
-        self.quats = _dev_f32(scene.quats, device)
-        self.logits = _dev_f32(scene.logits, device)
-        self.sh = _dev_f32(scene.sh, device)
-        self.sh_degree = int(scene.sh_degree)
+    def __init__(self, scene=None, device="cuda", tensors=None):
+        if tensors is not None:
+            self.means, self.log_scales, self.quats, self.logits, self.sh = [t.contiguous() for t in tensors]
+            self.sh_degree = int(round((self.sh.shape[0] // 3) ** 0.5)) - 1
+        else:
+            self.means = _dev_f32(scene.means, device)
+            self.log_scales = _dev_f32(scene.log_scales, device)
+            self.quats = _dev_f32(scene.quats, device)
+            self.logits = _dev_f32(scene.logits, device)
+            self.sh = _dev_f32(scene.sh, device)
+            self.sh_degree = int(scene.sh_degree)
         self.n = int(self.means.shape[1])
         for name in ("means", "log_scales", "quats", "sh"):
             assert getattr(self, name).shape[-1] == self.n, name
         assert self.sh.shape[0] == 3 * (self.sh_degree + 1) ** 2
+        for t in (self.means, self.log_scales, self.quats, self.logits, self.sh):
+            assert t.dtype == torch.float32 and t.is_contiguous()
+
+    def tensors(self):
+        return self.means, self.log_scales, self.quats, self.logits, self.sh
 
 
 # ---- one call per ABI entry point --------------------------------------------
@@ -136,9 +168,11 @@ def intersect_workspace_size(n: int) -> int:
     return int(lib().qb_intersect_workspace_size(n))
 
 
-def intersect(n, splats, rects, counts, width, height, capacity, pair_tiles, pair_ids, num_pairs, ws):
+def intersect(n, splats, rects, counts, width, height, capacity, pair_tiles, pair_ids, num_pairs, ws,
+              mode="quadbox"):
     _check("qb_intersect", lib().qb_intersect(
-        n, _ptr(splats), _ptr(rects), _ptr(counts), width, height, capacity, _ptr(pair_tiles), _ptr(pair_ids),
+        n, _ptr(splats), _ptr(rects), _ptr(counts), width, height, _mode(mode), capacity, _ptr(pair_tiles),
+        _ptr(pair_ids),
         _ptr(num_pairs), _ptr(ws), ws.numel() * ws.element_size(), _stream()))
 
 
@@ -159,6 +193,20 @@ def render(width, height, ranges, ids, splats, bg, image, final_T=None, n_contri
         _ptr(final_T), _ptr(n_contrib), _ptr(n_touched), _stream()))
 
 
+def render_backward(width, height, ranges, ids, splats, bg, final_T, n_contrib, dl_dimage, n, grad2d):
+    bgv = (C.c_float * 3)(*[float(x) for x in bg])
+    _check("qb_render_backward", lib().qb_render_backward(
+        width, height, _ptr(ranges), _ptr(ids), _ptr(splats), C.cast(bgv, C.c_void_p), _ptr(final_T),
+        _ptr(n_contrib), _ptr(dl_dimage), n, _ptr(grad2d), _stream()))
+
+
+def project_backward(g: Gaussians, cam, splats, grad2d, d_means, d_log_scales, d_quats, d_logits, d_sh):
+    _check("qb_project_backward", lib().qb_project_backward(
+        g.n, _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats), _ptr(g.logits), _ptr(g.sh), g.sh_degree,
+        C.byref(camera_struct(cam)), _ptr(splats), _ptr(grad2d), _ptr(d_means), _ptr(d_log_scales), _ptr(d_quats),
+        _ptr(d_logits), _ptr(d_sh), _stream()))
+
+
 # ---- whole forward with persistent buffers -------------------------------------
 
 class Rasterizer:
@@ -177,6 +225,7 @@ class Rasterizer:
         self.W, self.H = int(cam.width), int(cam.height)
         self.num_tiles = cam.tiles_x * cam.tiles_y
         self.write_keys = write_keys
+        self.mode = "quadbox"
         d = device
         self.splats = torch.empty((max(n, 1), SPLAT_FLOATS), dtype=torch.float32, device=d)
         self.rects = torch.empty((max(n, 1), RECT_SHORTS), dtype=torch.int16, device=d)
@@ -204,10 +253,11 @@ class Rasterizer:
 
     def project(self, g: Gaussians, mode):
         project(g, self.cam, mode, self.splats, self.rects, self.counts)
+        self.mode = mode
 
     def intersect(self):
         intersect(self.n, self.splats, self.rects, self.counts, self.W, self.H, self.capacity, self.pair_tiles,
-                  self.pair_ids, self.num_pairs, self.ws_isect)
+                  self.pair_ids, self.num_pairs, self.ws_isect, self.mode)
 
     def sort(self):
         sort(self.capacity, self.num_pairs, self.num_tiles, self.pair_tiles, self.pair_ids, self.splats,
@@ -231,3 +281,173 @@ class Rasterizer:
 
     def pairs(self) -> int:
         return int(self.num_pairs.item())
+
+
+# ---- autograd ------------------------------------------------------------------
+
+class _Rasterize(torch.autograd.Function):
+    """Forward: qb_project -> qb_intersect -> qb_sort -> qb_render.
+    Backward: qb_render_backward -> qb_project_backward."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, logits, sh, cam, mode, bg, rast):
+        g = Gaussians(tensors=(means.detach(), log_scales.detach(), quats.detach(), logits.detach(), sh.detach()))
+        rast.forward(g, mode, bg)
+        ctx.rast, ctx.cam, ctx.bg, ctx.g = rast, cam, bg, g
+        return rast.image.clone()
+
+    @staticmethod
+    def backward(ctx, dl_dimage):
+        r, g = ctx.rast, ctx.g
+        dl = dl_dimage.contiguous().float()
+        grad2d = torch.empty((max(g.n, 1), 9), dtype=torch.float32, device=dl.device)
+        render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, ctx.bg, r.final_T, r.n_contrib, dl, g.n, grad2d)
+        d = [torch.empty_like(t) for t in g.tensors()]
+        project_backward(g, ctx.cam, r.splats, grad2d, *d)
+        ctx.grad2d = grad2d
+        return d[0], d[1], d[2], d[3], d[4], None, None, None, None
+
+
+def rasterize(means, log_scales, quats, logits, sh, cam, mode="quadbox", bg=(0.0, 0.0, 0.0), rasterizer=None):
+    """Differentiable render of one camera: image [3, H, W].  The parameter
+    tensors are float32 CUDA tensors in the structure-of-arrays layouts of
+    Gaussians; pass a persistent Rasterizer to reuse its buffers."""
+    n = int(means.shape[1])
+    if rasterizer is None:
+        rasterizer = Rasterizer(n, cam, device=means.device, write_keys=False)
+    return _Rasterize.apply(means, log_scales, quats, logits, sh, cam, mode, tuple(bg), rasterizer)
+
+
+# ---- several views of one Gaussian set -----------------------------------------
+
+def project_views(g: Gaussians, cam_array, num_views, mode, splats, rects, counts):
+    _check("qb_project_views", lib().qb_project_views(
+        g.n, _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats), _ptr(g.logits), _ptr(g.sh), g.sh_degree, cam_array,
+        num_views, _mode(mode), _ptr(splats), _ptr(rects), _ptr(counts), _stream()))
+
+
+def render_views(view_array, num_views, bg):
+    bgv = (C.c_float * 3)(*[float(x) for x in bg])
+    _check("qb_render_views", lib().qb_render_views(num_views, view_array, C.cast(bgv, C.c_void_p), _stream()))
+
+
+def render_backward_views(view_array, num_views, bg, n):
+    bgv = (C.c_float * 3)(*[float(x) for x in bg])
+    _check("qb_render_backward_views", lib().qb_render_backward_views(
+        num_views, view_array, C.cast(bgv, C.c_void_p), n, _stream()))
+
+
+def project_backward_views(g: Gaussians, cam_array, num_views, splats, grad2d, d_means, d_log_scales, d_quats,
+                           d_logits, d_sh):
+    _check("qb_project_backward_views", lib().qb_project_backward_views(
+        g.n, _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats), _ptr(g.logits), _ptr(g.sh), g.sh_degree, cam_array,
+        num_views, _ptr(splats), _ptr(grad2d), _ptr(d_means), _ptr(d_log_scales), _ptr(d_quats), _ptr(d_logits),
+        _ptr(d_sh), _stream()))
+
+
+class MultiView:
+    """Forward and backward of one Gaussian set seen by up to MAX_VIEWS
+    cameras.  Forward: qb_project_views (one launch for all views), then
+    qb_intersect and qb_sort per view, then qb_render_views (one launch over
+    every tile of every view).  Backward: qb_render_backward_views and
+    qb_project_backward_views (gradients summed over views).  The buffers
+    persist, so a whole step can be captured in a HIP graph once the pair
+    buffers are sized (size_pairs); a frame whose pair count exceeds its
+    view's capacity renders that view empty (check overflowed())."""
+
+    def __init__(self, n: int, cams, device="cuda"):
+        self.V = len(cams)
+        if not 1 <= self.V <= MAX_VIEWS:
+            raise ValueError(f"1..{MAX_VIEWS} views per MultiView")
+        self.n, self.cams, self.device = n, list(cams), device
+        self.cam_array = (CCamera * self.V)(*[camera_struct(c) for c in cams])
+        d, V, n1 = device, self.V, max(n, 1)
+        self.splats = torch.empty((V, n1, SPLAT_FLOATS), dtype=torch.float32, device=d)
+        self.rects = torch.empty((V, n1, RECT_SHORTS), dtype=torch.int16, device=d)
+        self.counts = torch.empty((V, n1), dtype=torch.int32, device=d)
+        self.num_pairs = torch.zeros(V, dtype=torch.int64, device=d)
+        self.ws_isect = torch.empty(intersect_workspace_size(n), dtype=torch.uint8, device=d)
+        self.sizes = [(int(c.width), int(c.height)) for c in cams]
+        self.num_tiles = [int(c.tiles_x * c.tiles_y) for c in cams]
+        self.ranges = [torch.zeros(2 * t, dtype=torch.int32, device=d) for t in self.num_tiles]
+        self.images = [torch.zeros((3, h, w), dtype=torch.float32, device=d) for w, h in self.sizes]
+        self.final_T = [torch.zeros((h, w), dtype=torch.float32, device=d) for w, h in self.sizes]
+        self.n_contrib = [torch.zeros((h, w), dtype=torch.int32, device=d) for w, h in self.sizes]
+        self.dl = [torch.zeros((3, h, w), dtype=torch.float32, device=d) for w, h in self.sizes]
+        self.grad2d = torch.empty((V, n1, 9), dtype=torch.float32, device=d)
+        self.capacity = [0] * V
+        self.mode = "quadbox"
+        self.grads = None
+        self._table = None
+
+    def _slice(self, v):
+        return self.splats[v], self.rects[v], self.counts[v], self.num_pairs[v:v + 1]
+
+    def _intersect(self, v):
+        s, r, c, npairs = self._slice(v)
+        w, h = self.sizes[v]
+        cap = self.capacity[v]
+        intersect(self.n, s, r, c, w, h, cap, self.pair_tiles[v] if cap else None,
+                  self.pair_ids[v] if cap else None, npairs, self.ws_isect, self.mode)
+
+    def size_pairs(self, g: Gaussians, mode="quadbox", slack=1.1):
+        """Runs the projection and counting once (one host synchronisation)
+        and sizes every view's pair buffers with `slack`."""
+        self.mode = mode
+        self.capacity = [0] * self.V
+        project_views(g, self.cam_array, self.V, mode, self.splats, self.rects, self.counts)
+        for v in range(self.V):
+            self._intersect(v)
+        counts = self.num_pairs.cpu().tolist()
+        self.capacity = [int(p * slack) + 1024 for p in counts]
+        total = sum(self.capacity)
+        d = self.device
+        flat_t = torch.empty(total, dtype=torch.int16, device=d)
+        flat_i = torch.empty(total, dtype=torch.int32, device=d)
+        flat_s = torch.empty(total, dtype=torch.int32, device=d)
+        self.pair_tiles, self.pair_ids, self.ids_sorted = [], [], []
+        o = 0
+        for cap in self.capacity:
+            self.pair_tiles.append(flat_t[o:o + cap])
+            self.pair_ids.append(flat_i[o:o + cap])
+            self.ids_sorted.append(flat_s[o:o + cap])
+            o += cap
+        self._flat = (flat_t, flat_i, flat_s)
+        self.ws_sort = torch.empty(max(sort_workspace_size(c) for c in self.capacity), dtype=torch.uint8, device=d)
+        views = (CView * self.V)()
+        for v in range(self.V):
+            w, h = self.sizes[v]
+            views[v].width, views[v].height = w, h
+            views[v].ranges = self.ranges[v].data_ptr()
+            views[v].ids = self.ids_sorted[v].data_ptr()
+            views[v].splats = self.splats[v].data_ptr()
+            views[v].image = self.images[v].data_ptr()
+            views[v].final_T = self.final_T[v].data_ptr()
+            views[v].n_contrib = self.n_contrib[v].data_ptr()
+            views[v].dL_dimage = self.dl[v].data_ptr()
+            views[v].grad2d = self.grad2d[v].data_ptr()
+        self._table = views
+        return counts
+
+    def forward(self, g: Gaussians, bg=(0.0, 0.0, 0.0)):
+        if self._table is None:
+            raise RuntimeError("call size_pairs() first")
+        project_views(g, self.cam_array, self.V, self.mode, self.splats, self.rects, self.counts)
+        for v in range(self.V):
+            self._intersect(v)
+            sort(self.capacity[v], self.num_pairs[v:v + 1], self.num_tiles[v], self.pair_tiles[v], self.pair_ids[v],
+                 self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort)
+        render_views(self._table, self.V, bg)
+        return self.images
+
+    def backward(self, g: Gaussians, bg=(0.0, 0.0, 0.0)):
+        """Gradients of sum over views of <dl[v], image[v]> (fill self.dl
+        first); returns (d_means, d_log_scales, d_quats, d_logits, d_sh)."""
+        if self.grads is None:
+            self.grads = [torch.empty_like(t) for t in g.tensors()]
+        render_backward_views(self._table, self.V, bg, self.n)
+        project_backward_views(g, self.cam_array, self.V, self.splats, self.grad2d, *self.grads)
+        return self.grads
+
+    def overflowed(self) -> bool:
+        return any(p > c for p, c in zip(self.num_pairs.cpu().tolist(), self.capacity))

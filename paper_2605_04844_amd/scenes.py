@@ -113,6 +113,21 @@ def look_at(eye, target=(0.0, 0.0, 0.0), width=640, height=360, focal=None) -> C
     return pinhole(width, height, width if focal is None else focal, R, t)
 
 
+def multiview_scene(seed: int = 5, n: int = 2_000_000, views: int = 32,
+                    sizes=((640, 360), (1280, 720), (1920, 1080))):
+    """The clustered generator with centres U([-1,1]^3) seen by `views`
+    cameras at 5 * normalize(N(0, I3)) looking at the origin; camera j has
+    resolution sizes[j % len(sizes)] and focal length = its width."""
+    scene, _ = cluster_scene(seed, n, cube_centres=True)
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    cams = []
+    for j in range(views):
+        d = rng.normal(size=3)
+        w, h = sizes[j % len(sizes)]
+        cams.append(look_at(5.0 * d / np.linalg.norm(d), width=w, height=h))
+    return scene, cams
+
+
 def small_scene(seed: int = 1, n: int = 10_000):
     """10k Gaussians, x,y ~ U(-1,1), z ~ U(2,6), log-scales N(-3, 0.5^2),
     opacity logits N(0,1), SH degree 0 from RGB U(0,1); 256x256, f = 256."""

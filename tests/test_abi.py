@@ -67,13 +67,15 @@ def test_intersect_sort_render_reject_bad_arguments():
     d = C.c_void_p(256)
     ws = qb.intersect_workspace_size(10)
     assert ws > 0
-    assert L.qb_intersect(10, d, d, d, 64, 48, 100, d, d, d, d, ws - 1, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_intersect(10, d, d, d, 0, 48, 100, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_intersect(-1, d, d, d, 64, 48, 100, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_intersect(10, d, d, d, 64, 48, -1, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_intersect(10, d, d, d, 64, 48, 100, d, d, None, d, ws, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_intersect(10, d, d, d, 64, 48, 100, None, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_intersect(10, d, d, d, 16 * 300, 16 * 300, 100, d, d, d, d, 1 << 40, None) == \
+    assert L.qb_intersect(10, d, d, d, 64, 48, 2, 100, d, d, d, d, ws - 1, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(10, d, d, d, 0, 48, 2, 100, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(-1, d, d, d, 64, 48, 2, 100, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(10, d, d, d, 64, 48, 2, -1, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(10, d, d, d, 64, 48, 2, 100, d, d, None, d, ws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(10, d, d, d, 64, 48, 2, 100, None, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(10, d, d, d, 64, 48, 5, 100, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(10, d, d, d, 64, 48, -1, 100, d, d, d, d, ws, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect(10, d, d, d, 16 * 300, 16 * 300, 2, 100, d, d, d, d, 1 << 40, None) == \
         qb.QB_ERR_UNSUPPORTED
     sws = qb.sort_workspace_size(100)
     assert L.qb_sort(100, d, 12, d, d, d, d, C.c_void_p(512), d, d, sws - 1, None) == qb.QB_ERR_INVALID_ARG

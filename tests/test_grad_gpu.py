@@ -1,0 +1,130 @@
+"""GPU gradients (qb_render_backward + qb_project_backward, through the torch
+autograd wrapper) against the oracle's binary64 reverse-mode gradient, which
+the finite-difference tests pin.  Loss: mean |image - target| with a U(0,1)
+target.  Bar: relative L2 error per parameter group <= 1e-3, plus an
+elementwise check with an absolute floor of 1e-3 x the group's RMS (the GPU
+sums with float atomics).  Both sides take the order, visibility and cutoff
+decisions in binary32; the stop at T < 1e-4 and the 0.99 cap are taken in
+binary32 on the GPU and in binary64 by the oracle, so pixels where either
+came within 1e-4 (relative) of its threshold are left out of the loss."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2605_04844_amd import scenes  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = {"means": (0, 3), "log_scales": (3, 6), "quats": (6, 10), "logits": (10, 11), "sh": (11, 59)}
+
+
+def say(*a):
+    print("[grad]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def qb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_04844_amd import quadbox
+    quadbox.lib()
+    return quadbox
+
+
+def gpu_grads(qb, scene, cam, target, bg=(0.0, 0.0, 0.0), mask=None):
+    params = [torch.tensor(x, device="cuda", requires_grad=True)
+              for x in (scene.means, scene.log_scales, scene.quats, scene.logits, scene.sh)]
+    img = qb.rasterize(*params, cam, "quadbox", bg)
+    t = torch.tensor(target, device="cuda", dtype=torch.float32)
+    diff = (img - t).abs()
+    if mask is not None:
+        diff = diff * torch.tensor(mask, device="cuda", dtype=torch.float32)
+    loss = diff.sum() / img.numel()
+    loss.backward()
+    torch.cuda.synchronize()
+    img_np = img.detach().cpu().numpy().astype(np.float64)
+    dl = np.sign(img_np - target) / img_np.size
+    if mask is not None:
+        dl = dl * mask
+    n = scene.n
+    k = scene.sh.shape[0]
+    G = np.zeros((n, 59))
+    G[:, 0:3] = params[0].grad.cpu().numpy().T
+    G[:, 3:6] = params[1].grad.cpu().numpy().T
+    G[:, 6:10] = params[2].grad.cpu().numpy().T
+    G[:, 10] = params[3].grad.cpu().numpy()
+    G[:, 11:11 + k] = params[4].grad.cpu().numpy().T
+    return G, dl
+
+
+def decided_mask(oracle, scene, cam, mask=None, bg=(0.0, 0.0, 0.0)):
+    """Loss mask [3, H, W]: `mask` (default: every pixel) minus the pixels
+    whose stop or cap decision is within rounding of its threshold."""
+    if mask is None:
+        mask = np.ones((3, cam.height, cam.width))
+    _, near = oracle.backward64(scene, cam, mask, bg, with_near=True)
+    say(f"pixels left out near a threshold: {int(near.sum())} of {int((mask[0] > 0).sum())}")
+    return mask * (~near)[None]
+
+
+def compare(G_gpu, G_ref, label, tol=1e-3):
+    for name, (a, b) in GROUPS.items():
+        x, y = G_gpu[:, a:b].ravel(), G_ref[:, a:b].ravel()
+        ref = np.linalg.norm(y)
+        if ref == 0:
+            assert np.abs(x).max() == 0, (label, name)
+            continue
+        rel = np.linalg.norm(x - y) / ref
+        floor = 1e-3 * np.sqrt((y ** 2).mean())
+        bad = np.abs(x - y) > floor + 1e-2 * np.abs(y)
+        say(f"{label} {name}: rel-L2 {rel:.2e}, elementwise outliers {int(bad.sum())}/{bad.size}")
+        assert rel <= tol, (label, name, rel)
+        assert bad.mean() <= 1e-3, (label, name, int(bad.sum()))
+
+
+def test_tiny_scene_against_oracle(oracle, qb):
+    """200 Gaussians, 32x32, SH degree 3 (the finite-difference case)."""
+    scene, cam = scenes.tiny_grad_scene()
+    target = scenes.target_image(41, cam.width, cam.height).astype(np.float64)
+    say("tiny")
+    mask = decided_mask(oracle, scene, cam)
+    G, dl = gpu_grads(qb, scene, cam, target, mask=mask)
+    G_ref = oracle.backward64(scene, cam, dl)
+    compare(G, G_ref, "tiny")
+
+
+def test_rotated_camera_background(oracle, qb):
+    """5000 Gaussians, 160x96 with a rotated, offset camera and a background."""
+    from scipy.spatial.transform import Rotation
+    scene, _ = scenes.random_scene(46, 5000, 160, 96, 150.0, sh_degree=3, log_scale_mu=-3.0, log_scale_sd=0.6)
+    R = Rotation.from_euler("xyz", [0.05, 0.1, -0.08]).as_matrix().astype(np.float32)
+    cam = scenes.pinhole(160, 96, 150.0, R, np.array([0.1, 0.05, 0.2], np.float32))
+    target = scenes.target_image(47, cam.width, cam.height).astype(np.float64)
+    bg = (0.3, 0.2, 0.1)
+    say("rotated")
+    mask = decided_mask(oracle, scene, cam, bg=bg)
+    G, dl = gpu_grads(qb, scene, cam, target, bg, mask=mask)
+    G_ref = oracle.backward64(scene, cam, dl, bg)
+    compare(G, G_ref, "rotated")
+
+
+def test_full_size_clusters_sampled_tiles(oracle, qb):
+    """The 1M-Gaussian 1280x720 SH3 workload with an L1 loss restricted to 24
+    sampled tiles (the oracle's binary64 gradient is computed for those
+    pixels only); compared over the Gaussians that receive a gradient."""
+    scene, cam = scenes.cluster_scene()
+    target = scenes.target_image(4, cam.width, cam.height).astype(np.float64)
+    rng = np.random.default_rng(7)
+    mask = np.zeros((3, cam.height, cam.width))
+    for t in rng.choice(cam.num_tiles, 24, replace=False):
+        ty, tx = divmod(int(t), cam.tiles_x)
+        mask[:, ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = 1.0
+    say("clusters-1M sampled tiles")
+    mask = decided_mask(oracle, scene, cam, mask)
+    G, dl = gpu_grads(qb, scene, cam, target, mask=mask)
+    G_ref = oracle.backward64(scene, cam, dl)
+    touched = np.abs(G_ref).sum(axis=1) > 0
+    say(f"Gaussians with a gradient: {int(touched.sum())}")
+    assert touched.sum() > 1000
+    compare(G[touched], G_ref[touched], "clusters")

@@ -19,7 +19,7 @@ from paper_2605_04844_amd import scenes  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["3sigma", "adr", "quadbox", "dualbox"]
+MODES = ["3sigma", "adr", "quadbox", "dualbox", "quadbox_naive"]
 IMG_TOL = 1e-4
 RGB_TOL = 1e-5
 
@@ -226,7 +226,7 @@ def _sampled_render_check(oracle, gpu, g, cam, tiles, label):
     check_image(img, T, nc, near, gpu, label, tiles=mask)
 
 
-@pytest.mark.parametrize("mode", ["quadbox", "3sigma"])
+@pytest.mark.parametrize("mode", ["quadbox", "3sigma", "quadbox_naive"])
 def test_full_size_clusters(oracle, qb, mode):
     """The 1M-Gaussian 1280x720 SH3 workload at full size: every projected
     value and tile count bit-exact, keys globally sorted with consistent depth
