@@ -100,28 +100,35 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     if (t == 0) s_off[nruns] = total;  // sentinel
     int64_t block_start = (int64_t)goff[k0];
     __syncthreads();
-    for (uint32_t base = (uint32_t)wave * 64; base < total; base += kEmitThreads) {
-        // run of the step's first pair: last run with s_off <= base
+    // each wave takes a contiguous quarter of the block's pairs, 64 per step;
+    // the run holding a step's first pair is the run of the previous step's
+    // last pair, so only the wave's first step searches for it
+    uint32_t per = (total + (kEmitThreads / 64) - 1) / (kEmitThreads / 64);
+    uint32_t w_lo = min(total, (uint32_t)wave * per), w_hi = min(total, w_lo + per);
+    int cur = 0;
+    {
         int lo = 0, hi = (int)nruns;
         while (hi - lo > 1) {
             int mid = (lo + hi) >> 1;
-            if (s_off[mid] <= base) lo = mid; else hi = mid;
+            if (s_off[mid] <= w_lo) lo = mid; else hi = mid;
         }
-        int j0 = lo;
+        cur = lo;
+    }
+    for (uint32_t base = w_lo; base < w_hi; base += 64) {
         // every later run that starts inside this step marks its first pair;
         // a running maximum hands the run to the pairs that follow
         s_tab[wave][lane] = -1;
         __builtin_amdgcn_wave_barrier();
-        int jj = j0 + lane;
-        if (lane > 0 && jj < (int)nruns) {
+        int jj = cur + 1 + lane;
+        if (jj < (int)nruns) {
             uint32_t st = s_off[jj];
-            if (st < base + 64) s_tab[wave][st - base] = jj;
+            if (st >= base && st < base + 64) s_tab[wave][st - base] = jj;
         }
         __builtin_amdgcn_wave_barrier();
         int own = qbr::wave_inclusive_max(s_tab[wave][lane]);
-        if (own < 0) own = j0;
+        if (own < 0) own = cur;
         uint32_t p = base + lane;
-        if (p < total) {
+        if (p < w_hi) {
             uint32_t local = p - s_off[own];
             uint32_t w0 = s_w0[own], w1 = s_w1[own];
             uint32_t len = w1 & 0xFFFFu;
@@ -139,6 +146,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
                 out_id[dst] = s_gid[own];
             }
         }
+        cur = __shfl(own, 63, 64);
         __builtin_amdgcn_wave_barrier();
     }
 }

@@ -211,10 +211,27 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
     int64_t n = sort_count(n_dev, n_host, cap);
     uint32_t mask = (1u << bits) - 1u;
     int64_t base = (int64_t)blockIdx.x * (NT * NI) + (int64_t)wave * 64 * NI;
+    // the histogram ignores order: when the wave's 64*NI keys are all valid
+    // and 16-byte aligned, each lane reads NI consecutive keys as 16-byte
+    // vectors; otherwise one key per lane per step
+    constexpr int kPerVec = 16 / sizeof(K);
+    const K* wk = keys + base;
+    bool vec = (NI * sizeof(K)) % 16 == 0 && base + 64 * NI <= n && ((uintptr_t)wk & 15u) == 0;
+    if (vec) {
+        const uint4* src = reinterpret_cast<const uint4*>(wk + (int64_t)lane * NI);
+#pragma unroll
+        for (int q = 0; q < (int)(NI * sizeof(K) / 16); ++q) {
+            uint4 x = src[q];
+            const K* e = reinterpret_cast<const K*>(&x);
+#pragma unroll
+            for (int u = 0; u < kPerVec; ++u) atomicAdd(&h[wave][digit_of(e[u], shift, mask)], 1u);
+        }
+    } else {
 #pragma unroll 4
-    for (int r = 0; r < NI; ++r) {
-        int64_t idx = base + r * 64 + lane;
-        if (idx < n) atomicAdd(&h[wave][digit_of(keys[idx], shift, mask)], 1u);
+        for (int r = 0; r < NI; ++r) {
+            int64_t idx = base + r * 64 + lane;
+            if (idx < n) atomicAdd(&h[wave][digit_of(keys[idx], shift, mask)], 1u);
+        }
     }
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += NT) {

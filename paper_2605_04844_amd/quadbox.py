@@ -399,7 +399,9 @@ class MultiView:
         for v in range(self.V):
             self._intersect(v)
         counts = self.num_pairs.cpu().tolist()
-        self.capacity = [int(p * slack) + 1024 for p in counts]
+        # capacities in multiples of 256 pairs keep every view's slice of the
+        # flat pair buffers 512-byte aligned
+        self.capacity = [(int(p * slack) + 1024 + 255) // 256 * 256 for p in counts]
         total = sum(self.capacity)
         d = self.device
         flat_t = torch.empty(total, dtype=torch.int16, device=d)

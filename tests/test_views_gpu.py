@@ -92,7 +92,7 @@ def test_views_forward_backward_against_oracle_and_single_view(oracle, qb):
         P = int(mv.num_pairs[v].item())
         assert P == len(ref["ids"]), label
         assert np.array_equal(mv.ids_sorted[v][:P].cpu().numpy().view(np.uint32), ref["ids"]), label
-        assert np.array_equal(mv.ranges[v].cpu().numpy().view(np.uint32), ref["ranges"]), label
+        assert np.array_equal(mv.ranges[v].cpu().numpy().view(np.uint32).ravel(), ref["ranges"].ravel()), label
         img = imgs[v].cpu().numpy()
         ok = ~ref["near"]
         err = float(np.abs(img - ref["image"]).max(axis=0)[ok].max())
