@@ -51,6 +51,7 @@ def parse():
                     help="box modes to time; the first one is the headline value")
     ap.add_argument("--no-backward", action="store_true", help="skip the forward+backward timing")
     ap.add_argument("--no-multiview", action="store_true", help="skip the 32-view forward+backward timing")
+    ap.add_argument("--no-zoom", action="store_true", help="skip the 3M anisotropic zoom sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -145,12 +146,14 @@ def run_fwd_bwd(torch, qb, g, cam, steps, warmup, trials):
     grad2d = torch.empty((g.n, 9), dtype=torch.float32, device="cuda")
     grads = [torch.empty_like(t) for t in g.tensors()]
     inv = 1.0 / float(target.numel())
+    r.forward(g, "quadbox", sync_count=False)
+    qb.autotune_backward(r, dl=torch.sign(r.image - target) * inv, grad2d=grad2d, reps=3, trials=2)
 
     def step():
         r.forward(g, "quadbox", sync_count=False)
         dl = torch.sign(r.image - target) * inv
         qb.render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, (0.0, 0.0, 0.0), r.final_T, r.n_contrib,
-                           dl, g.n, grad2d)
+                           dl, g.n, grad2d, r.backward_variant)
         qb.project_backward(g, cam, r.splats, grad2d, *grads)
 
     for _ in range(warmup):
@@ -201,6 +204,16 @@ def run_multiview(torch, qb, steps, warmup, trials):
                for v, c in enumerate(cams)]
     mv = qb.MultiView(scene.n, cams)
     pairs = mv.size_pairs(g, "quadbox")
+    mv.forward(g)
+    for v in range(V):
+        torch.sign(mv.images[v] - targets[v], out=mv.dl[v])
+        mv.dl[v].mul_(1.0 / mv.images[v].numel())
+    tuned = {"render_ms": qb.autotune_render(mv, reps=3, trials=2),
+             "render_backward_ms": qb.autotune_backward(mv, reps=2, trials=2)}
+    tuned = {k: {s: round(x, 4) for s, x in v.items()} for k, v in tuned.items()}
+    names = {v: k for k, v in qb.RENDER_VARIANTS.items()}
+    tuned["picked"] = {"render": names[mv.render_variant], "render_backward": names[mv.backward_variant]}
+    log("autotune", tuned)
 
     def batched():
         imgs = mv.forward(g)
@@ -253,7 +266,29 @@ def run_multiview(torch, qb, steps, warmup, trials):
             "per_view_path_ms_per_view": round(per_view_ms / V, 4),
             "batched_ms_per_view": round(batched_ms / V, 4),
             "batched_graph_ms_per_view": round(graph_ms / V, 4),
-            "graph_speedup_vs_per_view": round(per_view_ms / graph_ms, 3)}
+            "graph_speedup_vs_per_view": round(per_view_ms / graph_ms, 3),
+            "autotune": tuned}
+
+
+def run_zoom_sweep(torch, qb, steps, trials):
+    """Forward of the 3M highly anisotropic Gaussians at 1920x1080 with focal
+    1920*k, k = 1..8 (the zoom-in sweep): tile pairs per frame and FPS for
+    QuadBox, the opacity-aware AABB and the 3-sigma AABB."""
+    from paper_2605_04844_amd import scenes
+    scene, cams = scenes.aniso_scene()
+    g = qb.Gaussians(scene)
+    rows = []
+    for k, cam in enumerate(cams, start=1):
+        row = {"zoom": k}
+        for mode in ("quadbox", "adr", "3sigma"):
+            res = run_mode(torch, qb, g, cam, mode, steps, 2, trials)
+            row[mode] = {"pairs": res["pairs"], "fps": round(1000.0 / res["ms"], 2), "ms": round(res["ms"], 4)}
+            del res
+        row["quadbox_vs_3sigma"] = round(row["3sigma"]["ms"] / row["quadbox"]["ms"], 3)
+        log("zoom", row)
+        rows.append(row)
+    return {"workload": "3M anisotropic Gaussians (major/minor ratio log-uniform in [1,100]), 1920x1080, SH3, "
+                        "focal 1920*k, forward", "rows": rows}
 
 
 def render_evaluations(torch, r):
@@ -357,6 +392,10 @@ def main():
         log("multi-view forward + backward")
         multiview = run_multiview(torch, qb, args.steps, args.warmup, args.trials)
         log("multi-view", multiview)
+    zoom = None
+    if args.workload == "clusters" and not args.no_zoom:
+        log("zoom sweep")
+        zoom = run_zoom_sweep(torch, qb, max(2, args.steps // 5), 1)
     q = results[modes[0]]
     stage = q["stage_ms"]
     dominant = max(stage, key=stage.get)
@@ -389,6 +428,7 @@ def main():
                   for m, r in results.items()},
         "fwd_bwd_ms_per_view": round(fwd_bwd, 4) if fwd_bwd is not None else None,
         "multiview": multiview,
+        "zoom_sweep": zoom,
         "quadbox_vs_3sigma": round(results["3sigma"]["ms"] / q["ms"], 3) if "3sigma" in results else None,
         "quadbox_vs_adr": round(results["adr"]["ms"] / q["ms"], 3) if "adr" in results else None,
         "dominant_stage": dominant,

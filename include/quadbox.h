@@ -197,6 +197,22 @@ qb_status qb_render(int32_t width, int32_t height, const uint32_t* ranges, const
                     const qb_splat* splats, const float* bg, float* image, float* final_T,
                     uint32_t* n_contrib, uint32_t* n_touched, qb_stream_t stream);
 
+/* Launch shapes of the render (the same image, T and counts from each):
+ * pixels per lane of a tile row; 256 / pixels lanes per 16x16 tile. */
+typedef enum {
+    QB_RENDER_2PX = 0,   /* 128 lanes, 2 pixels each (qb_render's shape)       */
+    QB_RENDER_1PX = 1,   /* 256 lanes, 1 pixel each                            */
+    QB_RENDER_4PX = 2,   /* 64 lanes, 4 pixels each                            */
+    QB_RENDER_VARIANTS = 3
+} qb_render_variant;
+
+/* qb_render_ex -- qb_render with an explicit launch shape (chosen, for
+ * example, by timing each on the workload).  Same arguments as qb_render
+ * plus `variant` (a qb_render_variant); results identical for every variant. */
+qb_status qb_render_ex(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
+                       const qb_splat* splats, const float* bg, float* image, float* final_T,
+                       uint32_t* n_contrib, uint32_t* n_touched, int32_t variant, qb_stream_t stream);
+
 /* qb_render_backward -- gradient of Eq. (2) (the rasterizer is trained
  * through; Sec. 4.1) with respect to each Gaussian's 2D parameters.  For
  * every pixel, walks its tile's list back to front from its last contributor,
@@ -213,6 +229,14 @@ qb_status qb_render_backward(int32_t width, int32_t height, const uint32_t* rang
                              const qb_splat* splats, const float* bg, const float* final_T,
                              const uint32_t* n_contrib, const float* dL_dimage, int64_t n, float* grad2d,
                              qb_stream_t stream);
+
+/* qb_render_backward_ex -- qb_render_backward with an explicit launch shape
+ * (a qb_render_variant: pixels per lane); the same gradients up to the order
+ * of the float atomic additions. */
+qb_status qb_render_backward_ex(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
+                                const qb_splat* splats, const float* bg, const float* final_T,
+                                const uint32_t* n_contrib, const float* dL_dimage, int64_t n, float* grad2d,
+                                int32_t variant, qb_stream_t stream);
 
 /* qb_project_backward -- chain rule from grad2d (qb_render_backward) to the
  * inputs of qb_project (Sec. 2, Eq. 1; the projection of Sec. 2): through the
@@ -273,11 +297,19 @@ qb_status qb_project_views(int64_t n, const float* means, const float* log_scale
  * Same image, T and contributor counts per view as qb_render. */
 qb_status qb_render_views(int32_t num_views, const qb_view* views, const float* bg, qb_stream_t stream);
 
+/* qb_render_views_ex -- qb_render_views with a launch shape (qb_render_variant). */
+qb_status qb_render_views_ex(int32_t num_views, const qb_view* views, const float* bg, int32_t variant,
+                             qb_stream_t stream);
+
 /* qb_render_backward_views -- qb_render_backward of every view in one
  * launch; each view's grad2d ([n][9]) is cleared first.  Uses every field of
  * each view except image. */
 qb_status qb_render_backward_views(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
                                    qb_stream_t stream);
+
+/* qb_render_backward_views_ex -- with a launch shape (qb_render_variant). */
+qb_status qb_render_backward_views_ex(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
+                                      int32_t variant, qb_stream_t stream);
 
 /* qb_project_backward_views -- gradients of the loss summed over views:
  * one lane per Gaussian runs the chain rule of qb_project_backward for each

@@ -1,15 +1,15 @@
 // Gradients of the forward rasterizer (the paper trains through it, Sec. 4.1).
 //
-// qb_render_backward: per 16x16 tile, one 256-lane workgroup (one pixel per
+// qb_render_backward: per 16x16 tile, one workgroup (1, 2 or 4 pixels per
 //   lane) walks the tile's list back to front, starting at each pixel's last
 //   contributor.  Each step re-evaluates the forward's binary32 power, 1/255
 //   cutoff and alpha exactly, recovers the transmittance in front of the
 //   Gaussian by dividing out (1 - alpha), and forms the pixel's share of
-//   dL/d(u, v, conic, opacity, rgb) of Eq. (2).  The shares are summed across
-//   each wave64 (butterfly shuffles, skipped when no lane of the wave takes
-//   part) and one lane per wave adds them to the Gaussian's 2D gradient with
-//   global float atomics; the order of those additions is not fixed, so the
-//   result is deterministic only up to float reassociation.
+//   dL/d(u, v, conic, opacity, rgb) of Eq. (2).  The shares are summed over a
+//   lane's pixels, then across each wave64 (DPP, skipped when no lane of the
+//   wave takes part), and one lane per wave adds them to the Gaussian's 2D
+//   gradient with global float atomics; the order of those additions is not
+//   fixed, so the result is deterministic only up to float reassociation.
 //
 // qb_project_backward: one lane per Gaussian; recomputes the projection's
 //   intermediates and applies the chain rule through the conic inverse, the
@@ -20,64 +20,95 @@
 
 namespace {
 
-constexpr int kBwdThreads = QB_TILE * QB_TILE;
-
-__device__ __forceinline__ int xcd_tile(int b, int tiles)
+// Sum over the 64 lanes of a wave, returned to every lane.  Rows of 16 are
+// reduced with four DPP adds (neighbour, pair of neighbours, half-row mirror,
+// row mirror), then the four row sums are read with v_readlane.  Every lane
+// of the wave must be active.
+__device__ __forceinline__ float dpp_add(float v, int ctrl_sel)
 {
-    int q = tiles >> 3, r = tiles & 7;
-    int x = b & 7, idx = b >> 3;
-    return x * q + min(x, r) + idx;
+    int x = __float_as_int(v);
+    int y;
+    switch (ctrl_sel) {
+    case 0: y = __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
+    case 1: y = __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
+    case 2: y = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
+    default: y = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false); break; // row_mirror
+    }
+    return v + __int_as_float(y);
 }
 
 __device__ __forceinline__ float wave_sum(float v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = dpp_add(v, 0);
+    v = dpp_add(v, 1);
+    v = dpp_add(v, 2);
+    v = dpp_add(v, 3);
+    int x = __float_as_int(v);
+    float r0 = __int_as_float(__builtin_amdgcn_readlane(x, 0));
+    float r1 = __int_as_float(__builtin_amdgcn_readlane(x, 16));
+    float r2 = __int_as_float(__builtin_amdgcn_readlane(x, 32));
+    float r3 = __int_as_float(__builtin_amdgcn_readlane(x, 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
-// Backward of one tile of one image (the workgroup's 256 lanes).
+// Backward of one tile of one image: 256 / PPL lanes, each owning PPL pixels
+// of one tile row, 16 / PPL apart.  The list is walked back to front from the
+// furthest last contributor of the tile, in batches of one record per lane
+// staged in LDS.  Per entry, a lane sums its pixels' shares, the wave sums
+// its lanes (DPP), and one lane adds the nine totals to grad2d (float
+// atomics: order-dependent rounding).
+template <int PPL>
 __device__ __forceinline__ void render_backward_tile(
     int tile, int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splats, float bg0, float bg1, float bg2, const float* __restrict__ final_T,
     const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimg, float* __restrict__ grad2d)
 {
-    __shared__ float4 s_geo[kBwdThreads];   // u, v, -a/2, -b
-    __shared__ float4 s_opa[kBwdThreads];   // -c/2, o, -gamma/2, (a)
-    __shared__ float4 s_col[kBwdThreads];   // r, g, b, (b)
-    __shared__ float s_c[kBwdThreads];      // c
-    __shared__ uint32_t s_id[kBwdThreads];
+    constexpr int NT = 256 / PPL;
+    constexpr int LX = QB_TILE / PPL;
+    __shared__ float4 s_geo[NT];   // u, v, -a/2, -b
+    __shared__ float4 s_opa[NT];   // -c/2, o, -gamma/2, a
+    __shared__ float4 s_col[NT];   // r, g, b, b
+    __shared__ float s_c[NT];      // c
+    __shared__ uint32_t s_id[NT];
     __shared__ uint32_t s_maxlast;
 
     int tx = tile % tiles_x, ty = tile / tiles_x;
-    int lx = threadIdx.x & (QB_TILE - 1), ly = threadIdx.x >> 4;
-    int px = tx * QB_TILE + lx, py = ty * QB_TILE + ly;
-    bool inside = px < W && py < H;
-    float fx = (float)px, fy = (float)py;
+    int lx = threadIdx.x % LX, ly = threadIdx.x / LX;
+    int py = ty * QB_TILE + ly;
+    float fy = (float)py;
     int lane = threadIdx.x & 63;
+    int64_t plane = (int64_t)W * H;
+
+    float fxp[PPL], T[PPL], dC[PPL][3], rest[PPL][3];
+    uint32_t last[PPL];
+    uint32_t lmax = 0;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        int px = tx * QB_TILE + lx + q * LX;
+        bool inside = px < W && py < H;
+        int64_t pix = (int64_t)py * W + px;
+        fxp[q] = (float)px;
+        last[q] = inside ? n_contrib[pix] : 0u;
+        T[q] = inside ? final_T[pix] : 1.0f;
+        dC[q][0] = inside ? dL_dimg[pix] : 0.f;
+        dC[q][1] = inside ? dL_dimg[plane + pix] : 0.f;
+        dC[q][2] = inside ? dL_dimg[2 * plane + pix] : 0.f;
+        rest[q][0] = T[q] * bg0;
+        rest[q][1] = T[q] * bg1;
+        rest[q][2] = T[q] * bg2;
+        lmax = max(lmax, last[q]);
+    }
 
     uint2 rg = ranges[tile];
     int64_t start = rg.x;
-    int64_t p = (int64_t)py * W + px;
-    int64_t plane = (int64_t)W * H;
-    uint32_t last = inside ? n_contrib[p] : 0u;
-    float T = inside ? final_T[p] : 1.0f;
-    float dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
-    if (inside) {
-        dC0 = dL_dimg[p];
-        dC1 = dL_dimg[plane + p];
-        dC2 = dL_dimg[2 * plane + p];
-    }
-    float rest0 = T * bg0, rest1 = T * bg1, rest2 = T * bg2;
-
     if (threadIdx.x == 0) s_maxlast = 0;
     __syncthreads();
-    if (last) atomicMax(&s_maxlast, last);
+    if (lmax) atomicMax(&s_maxlast, lmax);
     __syncthreads();
     int64_t hi = (int64_t)s_maxlast;  // entries [0, hi) of the tile list matter
 
-    for (int64_t b1 = hi; b1 > 0; b1 -= kBwdThreads) {
-        int64_t b0 = b1 - kBwdThreads > 0 ? b1 - kBwdThreads : 0;
+    for (int64_t b1 = hi; b1 > 0; b1 -= NT) {
+        int64_t b0 = b1 - NT > 0 ? b1 - NT : 0;
         int64_t j = b0 + threadIdx.x;
         __syncthreads();
         if (j < b1) {
@@ -96,38 +127,52 @@ __device__ __forceinline__ void render_backward_tile(
             uint32_t idx = (uint32_t)(b0 + k);  // list index of this entry
             float4 g = s_geo[k];
             float4 o = s_opa[k];
-            float dx = g.x - fx, dy = g.y - fy;
-            float power = fmaf(fmaf(g.z, dx, g.w * dy), dx, (o.x * dy) * dy);
-            bool act = idx < last && !(power > 0.0f || power < o.z);
-            if (!__any(act)) continue;
+            float dy = g.y - fy;
+            float nbdy = g.w * dy;
+            float hcdy2 = (o.x * dy) * dy;
+            float dx[PPL], power[PPL];
+            bool act[PPL];
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                dx[q] = g.x - fxp[q];
+                power[q] = fmaf(fmaf(g.z, dx[q], nbdy), dx[q], hcdy2);
+                act[q] = idx < last[q] && !(power[q] > 0.0f || power[q] < o.z);
+                any = any || act[q];
+            }
+            if (!__any(any)) continue;
             float4 col = s_col[k];
             float cc = s_c[k];
             float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
-            if (act) {
-                float e = __expf(power);
-                float raw = o.y * e;
-                float alpha = fminf(0.99f, raw);
-                float Ti = T / (1.0f - alpha);           // transmittance in front of this Gaussian
-                float w = alpha * Ti;
-                gr = w * dC0;
-                gg = w * dC1;
-                gbl = w * dC2;
-                float inv = 1.0f / (1.0f - alpha);
-                float dalpha = dC0 * (col.x * Ti - rest0 * inv) + dC1 * (col.y * Ti - rest1 * inv) +
-                               dC2 * (col.z * Ti - rest2 * inv);
-                rest0 = fmaf(col.x, w, rest0);
-                rest1 = fmaf(col.y, w, rest1);
-                rest2 = fmaf(col.z, w, rest2);
-                T = Ti;
-                if (raw <= 0.99f) {
-                    float dpow = dalpha * alpha;
-                    go = dalpha * e;
-                    float a = o.w, b = col.w;
-                    gu = -dpow * (a * dx + b * dy);
-                    gv = -dpow * (cc * dy + b * dx);
-                    ga = -0.5f * dpow * dx * dx;
-                    gb = -dpow * dx * dy;
-                    gc = -0.5f * dpow * dy * dy;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                if (act[q]) {
+                    float e = __expf(power[q]);
+                    float raw = o.y * e;
+                    float alpha = fminf(0.99f, raw);
+                    float Ti = T[q] / (1.0f - alpha);           // transmittance in front of this Gaussian
+                    float w = alpha * Ti;
+                    gr = fmaf(w, dC[q][0], gr);
+                    gg = fmaf(w, dC[q][1], gg);
+                    gbl = fmaf(w, dC[q][2], gbl);
+                    float inv = 1.0f / (1.0f - alpha);
+                    float dalpha = dC[q][0] * (col.x * Ti - rest[q][0] * inv) +
+                                   dC[q][1] * (col.y * Ti - rest[q][1] * inv) +
+                                   dC[q][2] * (col.z * Ti - rest[q][2] * inv);
+                    rest[q][0] = fmaf(col.x, w, rest[q][0]);
+                    rest[q][1] = fmaf(col.y, w, rest[q][1]);
+                    rest[q][2] = fmaf(col.z, w, rest[q][2]);
+                    T[q] = Ti;
+                    if (raw <= 0.99f) {
+                        float dpow = dalpha * alpha;
+                        go += dalpha * e;
+                        float a = o.w, b = col.w, ddx = dx[q];
+                        gu -= dpow * (a * ddx + b * dy);
+                        gv -= dpow * (cc * dy + b * ddx);
+                        ga -= 0.5f * dpow * ddx * ddx;
+                        gb -= dpow * ddx * dy;
+                        gc -= 0.5f * dpow * dy * dy;
+                    }
                 }
             }
             gu = wave_sum(gu);
@@ -155,25 +200,28 @@ __device__ __forceinline__ void render_backward_tile(
     }
 }
 
-__global__ __launch_bounds__(kBwdThreads) void k_render_backward(
-    int W, int H, int tiles_x, int tiles, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
+template <int PPL>
+__global__ __launch_bounds__(256 / PPL) void k_render_backward(
+    int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splats, float bg0, float bg1, float bg2, const float* __restrict__ final_T,
     const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimg, float* __restrict__ grad2d)
 {
-    render_backward_tile(xcd_tile((int)blockIdx.x, tiles), W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2,
-                         final_T, n_contrib, dL_dimg, grad2d);
+    render_backward_tile<PPL>((int)blockIdx.x, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, final_T,
+                              n_contrib, dL_dimg, grad2d);
 }
 
 // Every tile of every view in one launch (global tile b = blockIdx.x).
-__global__ __launch_bounds__(kBwdThreads) void k_render_backward_views(QbViewTable vt, float bg0, float bg1,
-                                                                       float bg2)
+template <int PPL>
+__global__ __launch_bounds__(256 / PPL) void k_render_backward_views(QbViewTable vt, float bg0, float bg1,
+                                                                     float bg2)
 {
     int b = (int)blockIdx.x;
     int v = qb_view_of(vt, b);
     const qb_view& w = vt.view[v];
-    render_backward_tile(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v],
-                         reinterpret_cast<const uint2*>(w.ranges), w.ids, reinterpret_cast<const float4*>(w.splats),
-                         bg0, bg1, bg2, w.final_T, w.n_contrib, w.dL_dimage, w.grad2d);
+    render_backward_tile<PPL>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v],
+                              reinterpret_cast<const uint2*>(w.ranges), w.ids,
+                              reinterpret_cast<const float4*>(w.splats), bg0, bg1, bg2, w.final_T, w.n_contrib,
+                              w.dL_dimage, w.grad2d);
 }
 
 // Clears grad2d of every view: blockIdx.y is the view.
@@ -533,13 +581,14 @@ void make_bwd_cam(const qb_camera& cam, BwdCam* bc)
 
 }  // namespace
 
-extern "C" qb_status qb_render_backward(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
-                                        const qb_splat* splats, const float* bg, const float* final_T,
-                                        const uint32_t* n_contrib, const float* dL_dimage, int64_t n,
-                                        float* grad2d, qb_stream_t stream)
+extern "C" qb_status qb_render_backward_ex(int32_t width, int32_t height, const uint32_t* ranges,
+                                           const uint32_t* ids, const qb_splat* splats, const float* bg,
+                                           const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
+                                           int64_t n, float* grad2d, int32_t variant, qb_stream_t stream)
 {
     if (width <= 0 || height <= 0 || width > 32767 * QB_TILE || height > 32767 * QB_TILE || !ranges || !bg ||
-        !final_T || !n_contrib || !dL_dimage || n < 0 || (n > 0 && (!grad2d || !splats)))
+        !final_T || !n_contrib || !dL_dimage || n < 0 || (n > 0 && (!grad2d || !splats)) || variant < 0 ||
+        variant >= QB_RENDER_VARIANTS)
         return QB_ERR_INVALID_ARG;
     int tiles_x = (int)qb_div_up(width, QB_TILE);
     int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
@@ -549,10 +598,32 @@ extern "C" qb_status qb_render_backward(int32_t width, int32_t height, const uin
         int64_t g = qb_div_up(9 * n, QB_BLOCK);
         QB_LAUNCH(k_zero, g > 4096 ? 4096 : g, QB_BLOCK, 0, s, grad2d, 9 * n);
     }
-    QB_LAUNCH(k_render_backward, tiles, kBwdThreads, 0, s, (int)width, (int)height, tiles_x, (int)tiles,
-              reinterpret_cast<const uint2*>(ranges), ids, reinterpret_cast<const float4*>(splats), bg[0], bg[1],
-              bg[2], final_T, n_contrib, dL_dimage, grad2d);
+    const uint2* rg = reinterpret_cast<const uint2*>(ranges);
+    const float4* sp = reinterpret_cast<const float4*>(splats);
+    switch (variant) {
+    case QB_RENDER_2PX:
+        QB_LAUNCH(k_render_backward<2>, tiles, 128, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0],
+                  bg[1], bg[2], final_T, n_contrib, dL_dimage, grad2d);
+        break;
+    case QB_RENDER_1PX:
+        QB_LAUNCH(k_render_backward<1>, tiles, 256, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0],
+                  bg[1], bg[2], final_T, n_contrib, dL_dimage, grad2d);
+        break;
+    default:
+        QB_LAUNCH(k_render_backward<4>, tiles, 64, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0],
+                  bg[1], bg[2], final_T, n_contrib, dL_dimage, grad2d);
+        break;
+    }
     return QB_OK;
+}
+
+extern "C" qb_status qb_render_backward(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
+                                        const qb_splat* splats, const float* bg, const float* final_T,
+                                        const uint32_t* n_contrib, const float* dL_dimage, int64_t n,
+                                        float* grad2d, qb_stream_t stream)
+{
+    return qb_render_backward_ex(width, height, ranges, ids, splats, bg, final_T, n_contrib, dL_dimage, n, grad2d,
+                                 QB_RENDER_2PX, stream);
 }
 
 extern "C" qb_status qb_project_backward(int64_t n, const float* means, const float* log_scales,
@@ -575,10 +646,10 @@ extern "C" qb_status qb_project_backward(int64_t n, const float* means, const fl
     return QB_OK;
 }
 
-extern "C" qb_status qb_render_backward_views(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
-                                              qb_stream_t stream)
+extern "C" qb_status qb_render_backward_views_ex(int32_t num_views, const qb_view* views, const float* bg,
+                                                 int64_t n, int32_t variant, qb_stream_t stream)
 {
-    if (!bg || n < 0) return QB_ERR_INVALID_ARG;
+    if (!bg || n < 0 || variant < 0 || variant >= QB_RENDER_VARIANTS) return QB_ERR_INVALID_ARG;
     QbViewTable vt;
     qb_status st = qb_make_view_table(num_views, views, true, &vt);
     if (st != QB_OK) return st;
@@ -587,9 +658,20 @@ extern "C" qb_status qb_render_backward_views(int32_t num_views, const qb_view* 
         int64_t g = qb_div_up(9 * n, QB_BLOCK);
         QB_LAUNCH(k_zero_views, dim3(g > 1024 ? 1024 : (unsigned)g, num_views), QB_BLOCK, 0, s, vt, 9 * n);
     }
-    if (vt.tile_start[num_views] > 0)
-        QB_LAUNCH(k_render_backward_views, vt.tile_start[num_views], kBwdThreads, 0, s, vt, bg[0], bg[1], bg[2]);
+    int tiles = vt.tile_start[num_views];
+    if (tiles == 0) return QB_OK;
+    switch (variant) {
+    case QB_RENDER_2PX: QB_LAUNCH(k_render_backward_views<2>, tiles, 128, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_1PX: QB_LAUNCH(k_render_backward_views<1>, tiles, 256, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    default: QB_LAUNCH(k_render_backward_views<4>, tiles, 64, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    }
     return QB_OK;
+}
+
+extern "C" qb_status qb_render_backward_views(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
+                                              qb_stream_t stream)
+{
+    return qb_render_backward_views_ex(num_views, views, bg, n, QB_RENDER_2PX, stream);
 }
 
 extern "C" qb_status qb_project_backward_views(int64_t n, const float* means, const float* log_scales,

@@ -1,9 +1,10 @@
 // qb_render: per-tile front-to-back alpha compositing, Eq. (2).
 //
-// One 128-lane workgroup (two wave64) per 16x16 tile; each lane owns the two
-// pixels (x, y) and (x + 8, y) of one row, so the row-dependent terms of the
-// quadratic form and every LDS read are shared by two pixels.  The tile's
-// depth-sorted list is walked in batches of 128: each lane gathers one
+// One workgroup per 16x16 tile; by default 128 lanes (two wave64), each lane
+// owning the two pixels (x, y) and (x + 8, y) of one row, so the
+// row-dependent terms of the quadratic form and every LDS read are shared by
+// two pixels.  The tile's depth-sorted list is walked in batches of one
+// record per lane: each lane gathers one
 // Gaussian record into LDS (the 48-byte records of all Gaussians fit the
 // 256 MB Infinity Cache, so these gathers rarely reach HBM), then every lane
 // composites the batch for its pixels from LDS broadcasts.  A pixel stops
@@ -18,39 +19,57 @@
 
 namespace {
 
-constexpr int kRenderThreads = 128;  // two wave64; each lane owns two pixels of one row
-
 // Tiles go to workgroups in row-major order.  The dispatcher deals
 // workgroups round-robin to the 8 XCDs, so each XCD receives every 8th tile of
 // every row band: the heavy tiles of a dense region are spread over all XCDs
 // (measured faster than giving each XCD a contiguous band of tiles, which
 // keeps shared Gaussians in one L2 but leaves the XCDs unevenly loaded).
-// Composites one tile of one image (the workgroup's 128 lanes).
+//
+// Launch shape: PPL pixels per lane, all in one row of the tile, 16/PPL
+// apart (256/PPL lanes per tile).  The row terms of the quadratic form and
+// every LDS read are shared by a lane's PPL pixels; the batch staged in LDS
+// holds one record per lane.  qb_render_ex selects PPL (1, 2 or 4).
+template <int PPL>
 __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x, const uint2* __restrict__ ranges,
                                             const uint32_t* __restrict__ ids, const float4* __restrict__ splats,
                                             float bg0, float bg1, float bg2, float* __restrict__ image,
                                             float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
                                             uint32_t* __restrict__ n_touched)
 {
-    __shared__ float4 s_geo[kRenderThreads];   // u, v, -a/2, -b
-    __shared__ float4 s_opa[kRenderThreads];   // -c/2, o, -gamma/2, unused
-    __shared__ float4 s_col[kRenderThreads];   // r, g, b, unused
+    constexpr int NT = 256 / PPL;        // lanes per tile
+    constexpr int LX = QB_TILE / PPL;    // lanes per tile row
+    __shared__ float4 s_geo[NT];   // u, v, -a/2, -b
+    __shared__ float4 s_opa[NT];   // -c/2, o, -gamma/2, unused
+    __shared__ float4 s_col[NT];   // r, g, b, unused
 
     int tx = tile % tiles_x, ty = tile / tiles_x;
-    int lx = threadIdx.x & 7, ly = threadIdx.x >> 3;
-    int px0 = tx * QB_TILE + lx, px1 = px0 + 8, py = ty * QB_TILE + ly;
-    bool in0 = px0 < W && py < H, in1 = px1 < W && py < H;
-    float fx0 = (float)px0, fx1 = (float)px1, fy = (float)py;
+    int lx = threadIdx.x % LX, ly = threadIdx.x / LX;
+    int py = ty * QB_TILE + ly;
+    float fy = (float)py;
+    bool in[PPL], done[PPL];
+    float fxp[PPL], T[PPL], c0[PPL], c1[PPL], c2[PPL];
+    uint32_t last[PPL], stop[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        int px = tx * QB_TILE + lx + q * LX;
+        in[q] = px < W && py < H;
+        done[q] = !in[q];
+        fxp[q] = (float)px;
+        T[q] = 1.0f;
+        c0[q] = c1[q] = c2[q] = 0.0f;
+        last[q] = stop[q] = 0u;
+    }
+    auto all_done = [&]() {
+        bool d = true;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) d = d && done[q];
+        return d;
+    };
 
     uint2 rg = ranges[tile];
     int64_t start = rg.x, end = rg.y;
-    bool done0 = !in0, done1 = !in1;
-    float T0 = 1.0f, T1 = 1.0f;
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, b0c = 0.0f, b1c = 0.0f, b2c = 0.0f;
-    uint32_t last0 = 0, last1 = 0, stop0 = 0, stop1 = 0;
-
-    for (int64_t base = start; base < end; base += kRenderThreads) {
-        if (__syncthreads_count(done0 && done1) == kRenderThreads) break;
+    for (int64_t base = start; base < end; base += NT) {
+        if (__syncthreads_count(all_done()) == NT) break;
         int64_t j = base + threadIdx.x;
         if (j < end) {
             uint32_t id = ids[j];
@@ -62,8 +81,8 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             s_col[threadIdx.x] = c;
         }
         __syncthreads();
-        if (done0 && done1) continue;
-        int cnt = (int)min((int64_t)kRenderThreads, end - base);
+        if (all_done()) continue;
+        int cnt = (int)min((int64_t)NT, end - base);
         uint32_t idx0 = (uint32_t)(base - start);
         for (int k = 0; k < cnt; ++k) {
             float4 g = s_geo[k];
@@ -72,115 +91,135 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             float dy = g.y - fy;
             float nbdy = g.w * dy;
             float hcdy2 = (o.x * dy) * dy;
-            float dx0 = g.x - fx0, dx1 = g.x - fx1;
-            float p0 = fmaf(fmaf(g.z, dx0, nbdy), dx0, hcdy2);
-            float p1 = fmaf(fmaf(g.z, dx1, nbdy), dx1, hcdy2);
-            bool act0 = !done0 && !(p0 > 0.0f || p0 < o.z);
-            bool act1 = !done1 && !(p1 > 0.0f || p1 < o.z);
+            float p[PPL];
+            bool act[PPL];
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                float dx = g.x - fxp[q];
+                p[q] = fmaf(fmaf(g.z, dx, nbdy), dx, hcdy2);
+                act[q] = !done[q] && !(p[q] > 0.0f || p[q] < o.z);
+                any = any || act[q];
+            }
             // branch only when the whole wave agrees; per pixel, select
-            if (!__any(act0 || act1)) continue;
+            if (!__any(any)) continue;
             float4 col = s_col[k];
             uint32_t at = idx0 + (uint32_t)k + 1u;
-            {
-                float alpha = fminf(0.99f, o.y * __expf(p0));
-                float test_T = T0 * (1.0f - alpha);
-                bool stop = act0 && test_T < 1e-4f;
-                bool add = act0 && !(test_T < 1e-4f);
-                float w = add ? alpha * T0 : 0.0f;
-                a0 = fmaf(col.x, w, a0);
-                a1 = fmaf(col.y, w, a1);
-                a2 = fmaf(col.z, w, a2);
-                T0 = add ? test_T : T0;
-                last0 = add ? at : last0;
-                stop0 = stop ? at : stop0;
-                done0 = done0 || stop;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                float alpha = fminf(0.99f, o.y * __expf(p[q]));
+                float test_T = T[q] * (1.0f - alpha);
+                bool stp = act[q] && test_T < 1e-4f;
+                bool add = act[q] && !(test_T < 1e-4f);
+                float w = add ? alpha * T[q] : 0.0f;
+                c0[q] = fmaf(col.x, w, c0[q]);
+                c1[q] = fmaf(col.y, w, c1[q]);
+                c2[q] = fmaf(col.z, w, c2[q]);
+                T[q] = add ? test_T : T[q];
+                last[q] = add ? at : last[q];
+                stop[q] = stp ? at : stop[q];
+                done[q] = done[q] || stp;
             }
-            {
-                float alpha = fminf(0.99f, o.y * __expf(p1));
-                float test_T = T1 * (1.0f - alpha);
-                bool stop = act1 && test_T < 1e-4f;
-                bool add = act1 && !(test_T < 1e-4f);
-                float w = add ? alpha * T1 : 0.0f;
-                b0c = fmaf(col.x, w, b0c);
-                b1c = fmaf(col.y, w, b1c);
-                b2c = fmaf(col.z, w, b2c);
-                T1 = add ? test_T : T1;
-                last1 = add ? at : last1;
-                stop1 = stop ? at : stop1;
-                done1 = done1 || stop;
-            }
-            if (__all(done0 && done1)) break;
+            if (__all(all_done())) break;
         }
     }
     uint32_t len = (uint32_t)(end - start);
     int64_t plane = (int64_t)W * H;
-    if (in0) {
-        int64_t p = (int64_t)py * W + px0;
-        image[p] = fmaf(T0, bg0, a0);
-        image[plane + p] = fmaf(T0, bg1, a1);
-        image[2 * plane + p] = fmaf(T0, bg2, a2);
-        if (final_T) final_T[p] = T0;
-        if (n_contrib) n_contrib[p] = last0;
-        if (n_touched) n_touched[p] = done0 ? stop0 : len;
-    }
-    if (in1) {
-        int64_t p = (int64_t)py * W + px1;
-        image[p] = fmaf(T1, bg0, b0c);
-        image[plane + p] = fmaf(T1, bg1, b1c);
-        image[2 * plane + p] = fmaf(T1, bg2, b2c);
-        if (final_T) final_T[p] = T1;
-        if (n_contrib) n_contrib[p] = last1;
-        if (n_touched) n_touched[p] = done1 ? stop1 : len;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        if (!in[q]) continue;
+        int64_t pix = (int64_t)py * W + tx * QB_TILE + lx + q * LX;
+        image[pix] = fmaf(T[q], bg0, c0[q]);
+        image[plane + pix] = fmaf(T[q], bg1, c1[q]);
+        image[2 * plane + pix] = fmaf(T[q], bg2, c2[q]);
+        if (final_T) final_T[pix] = T[q];
+        if (n_contrib) n_contrib[pix] = last[q];
+        if (n_touched) n_touched[pix] = done[q] ? stop[q] : len;
     }
 }
 
-__global__ __launch_bounds__(kRenderThreads) void k_render(
+template <int PPL>
+__global__ __launch_bounds__(256 / PPL) void k_render(
     int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splats, float bg0, float bg1, float bg2, float* __restrict__ image,
     float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_touched)
 {
-    render_tile((int)blockIdx.x, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T, n_contrib,
-                n_touched);
+    render_tile<PPL>((int)blockIdx.x, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T, n_contrib,
+                     n_touched);
 }
 
 // Every tile of every view in one launch: workgroup b takes global tile b,
 // whose view is found in the (at most QB_MAX_VIEWS) tile offsets.
-__global__ __launch_bounds__(kRenderThreads) void k_render_views(QbViewTable vt, float bg0, float bg1, float bg2)
+template <int PPL>
+__global__ __launch_bounds__(256 / PPL) void k_render_views(QbViewTable vt, float bg0, float bg1, float bg2)
 {
     int b = (int)blockIdx.x;
     int v = qb_view_of(vt, b);
     const qb_view& w = vt.view[v];
-    render_tile(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
-                w.ids, reinterpret_cast<const float4*>(w.splats), bg0, bg1, bg2, w.image, w.final_T, w.n_contrib,
-                nullptr);
+    render_tile<PPL>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
+                     w.ids, reinterpret_cast<const float4*>(w.splats), bg0, bg1, bg2, w.image, w.final_T, w.n_contrib,
+                     nullptr);
 }
 
 }  // namespace
+
+extern "C" qb_status qb_render_ex(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
+                                  const qb_splat* splats, const float* bg, float* image, float* final_T,
+                                  uint32_t* n_contrib, uint32_t* n_touched, int32_t variant, qb_stream_t stream)
+{
+    if (width <= 0 || height <= 0 || width > 32767 * QB_TILE || height > 32767 * QB_TILE || !ranges ||
+        !image || !bg || variant < 0 || variant >= QB_RENDER_VARIANTS)
+        return QB_ERR_INVALID_ARG;
+    int tiles_x = (int)qb_div_up(width, QB_TILE);
+    int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
+    if (tiles > (1 << 24)) return QB_ERR_INVALID_ARG;
+    hipStream_t s = qb_hip_stream(stream);
+    const uint2* rg = reinterpret_cast<const uint2*>(ranges);
+    const float4* sp = reinterpret_cast<const float4*>(splats);
+    switch (variant) {
+    case QB_RENDER_2PX:
+        QB_LAUNCH(k_render<2>, tiles, 128, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0], bg[1], bg[2],
+                  image, final_T, n_contrib, n_touched);
+        break;
+    case QB_RENDER_1PX:
+        QB_LAUNCH(k_render<1>, tiles, 256, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0], bg[1], bg[2],
+                  image, final_T, n_contrib, n_touched);
+        break;
+    default:
+        QB_LAUNCH(k_render<4>, tiles, 64, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0], bg[1], bg[2],
+                  image, final_T, n_contrib, n_touched);
+        break;
+    }
+    return QB_OK;
+}
 
 extern "C" qb_status qb_render(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
                                const qb_splat* splats, const float* bg, float* image, float* final_T,
                                uint32_t* n_contrib, uint32_t* n_touched, qb_stream_t stream)
 {
-    if (width <= 0 || height <= 0 || width > 32767 * QB_TILE || height > 32767 * QB_TILE || !ranges ||
-        !image || !bg)
-        return QB_ERR_INVALID_ARG;
-    int tiles_x = (int)qb_div_up(width, QB_TILE);
-    int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
-    if (tiles > (1 << 24)) return QB_ERR_INVALID_ARG;
-    QB_LAUNCH(k_render, tiles, kRenderThreads, 0, qb_hip_stream(stream), (int)width, (int)height, tiles_x,
-              reinterpret_cast<const uint2*>(ranges), ids, reinterpret_cast<const float4*>(splats), bg[0], bg[1],
-              bg[2], image, final_T, n_contrib, n_touched);
+    return qb_render_ex(width, height, ranges, ids, splats, bg, image, final_T, n_contrib, n_touched, QB_RENDER_2PX,
+                        stream);
+}
+
+extern "C" qb_status qb_render_views_ex(int32_t num_views, const qb_view* views, const float* bg, int32_t variant,
+                                        qb_stream_t stream)
+{
+    if (!bg || variant < 0 || variant >= QB_RENDER_VARIANTS) return QB_ERR_INVALID_ARG;
+    QbViewTable vt;
+    qb_status st = qb_make_view_table(num_views, views, false, &vt);
+    if (st != QB_OK) return st;
+    int tiles = vt.tile_start[num_views];
+    if (tiles == 0) return QB_OK;
+    hipStream_t s = qb_hip_stream(stream);
+    switch (variant) {
+    case QB_RENDER_2PX: QB_LAUNCH(k_render_views<2>, tiles, 128, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_1PX: QB_LAUNCH(k_render_views<1>, tiles, 256, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    default: QB_LAUNCH(k_render_views<4>, tiles, 64, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    }
     return QB_OK;
 }
 
 extern "C" qb_status qb_render_views(int32_t num_views, const qb_view* views, const float* bg, qb_stream_t stream)
 {
-    if (!bg) return QB_ERR_INVALID_ARG;
-    QbViewTable vt;
-    qb_status st = qb_make_view_table(num_views, views, false, &vt);
-    if (st != QB_OK) return st;
-    if (vt.tile_start[num_views] == 0) return QB_OK;
-    QB_LAUNCH(k_render_views, vt.tile_start[num_views], kRenderThreads, 0, qb_hip_stream(stream), vt, bg[0], bg[1],
-              bg[2]);
-    return QB_OK;
+    return qb_render_views_ex(num_views, views, bg, QB_RENDER_2PX, stream);
 }

@@ -22,6 +22,8 @@ SPLAT_FLOATS = 12   # qb_splat: u v depth o | a b c gamma | r g b visible
 RECT_SHORTS = 16    # qb_rects: 4 x (tx0, tx1, ty0, ty1)
 
 QB_OK, QB_ERR_INVALID_ARG, QB_ERR_CAPACITY, QB_ERR_HIP, QB_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+# render launch shapes (qb_render_variant): pixels per lane of a tile row
+RENDER_VARIANTS = {"2px": 0, "1px": 1, "4px": 2}
 
 
 class QBError(RuntimeError):
@@ -69,8 +71,12 @@ def lib():
     L.qb_sort.restype = i32
     L.qb_render.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.qb_render.restype = i32
+    L.qb_render_ex.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]
+    L.qb_render_ex.restype = i32
     L.qb_render_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp]
     L.qb_render_backward.restype = i32
+    L.qb_render_backward_ex.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp, i32, vp]
+    L.qb_render_backward_ex.restype = i32
     L.qb_project_backward.argtypes = [i64, vp, vp, vp, vp, vp, i32, C.POINTER(CCamera), vp, vp, vp, vp, vp, vp, vp,
                                       vp]
     L.qb_project_backward.restype = i32
@@ -79,8 +85,12 @@ def lib():
     L.qb_project_views.restype = i32
     L.qb_render_views.argtypes = [i32, C.POINTER(CView), vp, vp]
     L.qb_render_views.restype = i32
+    L.qb_render_views_ex.argtypes = [i32, C.POINTER(CView), vp, i32, vp]
+    L.qb_render_views_ex.restype = i32
     L.qb_render_backward_views.argtypes = [i32, C.POINTER(CView), vp, i64, vp]
     L.qb_render_backward_views.restype = i32
+    L.qb_render_backward_views_ex.argtypes = [i32, C.POINTER(CView), vp, i64, i32, vp]
+    L.qb_render_backward_views_ex.restype = i32
     L.qb_project_backward_views.argtypes = [i64, vp, vp, vp, vp, vp, i32, pc, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.qb_project_backward_views.restype = i32
     L.qb_status_string.argtypes = [i32]
@@ -186,18 +196,19 @@ def sort(capacity, num_pairs, num_tiles, pair_tiles, pair_ids, splats, keys, ids
         _ptr(ids), _ptr(ranges), _ptr(ws), ws.numel() * ws.element_size(), _stream()))
 
 
-def render(width, height, ranges, ids, splats, bg, image, final_T=None, n_contrib=None, n_touched=None):
+def render(width, height, ranges, ids, splats, bg, image, final_T=None, n_contrib=None, n_touched=None,
+           variant=0):
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
-    _check("qb_render", lib().qb_render(
-        width, height, _ptr(ranges), _ptr(ids), _ptr(splats), C.cast(bgv, C.c_void_p), _ptr(image),
-        _ptr(final_T), _ptr(n_contrib), _ptr(n_touched), _stream()))
+    _check("qb_render_ex", lib().qb_render_ex(
+        width, height, _ptr(ranges), _ptr(ids), _ptr(splats), C.cast(bgv, C.c_void_p), _ptr(image), _ptr(final_T),
+        _ptr(n_contrib), _ptr(n_touched), int(variant), _stream()))
 
 
-def render_backward(width, height, ranges, ids, splats, bg, final_T, n_contrib, dl_dimage, n, grad2d):
+def render_backward(width, height, ranges, ids, splats, bg, final_T, n_contrib, dl_dimage, n, grad2d, variant=0):
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
-    _check("qb_render_backward", lib().qb_render_backward(
+    _check("qb_render_backward_ex", lib().qb_render_backward_ex(
         width, height, _ptr(ranges), _ptr(ids), _ptr(splats), C.cast(bgv, C.c_void_p), _ptr(final_T),
-        _ptr(n_contrib), _ptr(dl_dimage), n, _ptr(grad2d), _stream()))
+        _ptr(n_contrib), _ptr(dl_dimage), n, _ptr(grad2d), int(variant), _stream()))
 
 
 def project_backward(g: Gaussians, cam, splats, grad2d, d_means, d_log_scales, d_quats, d_logits, d_sh):
@@ -226,6 +237,8 @@ class Rasterizer:
         self.num_tiles = cam.tiles_x * cam.tiles_y
         self.write_keys = write_keys
         self.mode = "quadbox"
+        self.render_variant = RENDER_VARIANTS["2px"]
+        self.backward_variant = RENDER_VARIANTS["2px"]
         d = device
         self.splats = torch.empty((max(n, 1), SPLAT_FLOATS), dtype=torch.float32, device=d)
         self.rects = torch.empty((max(n, 1), RECT_SHORTS), dtype=torch.int16, device=d)
@@ -265,7 +278,7 @@ class Rasterizer:
 
     def render(self, bg=(0.0, 0.0, 0.0)):
         render(self.W, self.H, self.ranges, self.ids_sorted, self.splats, bg, self.image, self.final_T,
-               self.n_contrib, self.n_touched)
+               self.n_contrib, self.n_touched, self.render_variant)
 
     def forward(self, g: Gaussians, mode="quadbox", bg=(0.0, 0.0, 0.0), sync_count=True):
         self.project(g, mode)
@@ -301,7 +314,8 @@ class _Rasterize(torch.autograd.Function):
         r, g = ctx.rast, ctx.g
         dl = dl_dimage.contiguous().float()
         grad2d = torch.empty((max(g.n, 1), 9), dtype=torch.float32, device=dl.device)
-        render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, ctx.bg, r.final_T, r.n_contrib, dl, g.n, grad2d)
+        render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, ctx.bg, r.final_T, r.n_contrib, dl, g.n, grad2d,
+                        r.backward_variant)
         d = [torch.empty_like(t) for t in g.tensors()]
         project_backward(g, ctx.cam, r.splats, grad2d, *d)
         ctx.grad2d = grad2d
@@ -326,15 +340,16 @@ def project_views(g: Gaussians, cam_array, num_views, mode, splats, rects, count
         num_views, _mode(mode), _ptr(splats), _ptr(rects), _ptr(counts), _stream()))
 
 
-def render_views(view_array, num_views, bg):
+def render_views(view_array, num_views, bg, variant=0):
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
-    _check("qb_render_views", lib().qb_render_views(num_views, view_array, C.cast(bgv, C.c_void_p), _stream()))
+    _check("qb_render_views_ex", lib().qb_render_views_ex(num_views, view_array, C.cast(bgv, C.c_void_p),
+                                                          int(variant), _stream()))
 
 
-def render_backward_views(view_array, num_views, bg, n):
+def render_backward_views(view_array, num_views, bg, n, variant=0):
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
-    _check("qb_render_backward_views", lib().qb_render_backward_views(
-        num_views, view_array, C.cast(bgv, C.c_void_p), n, _stream()))
+    _check("qb_render_backward_views_ex", lib().qb_render_backward_views_ex(
+        num_views, view_array, C.cast(bgv, C.c_void_p), n, int(variant), _stream()))
 
 
 def project_backward_views(g: Gaussians, cam_array, num_views, splats, grad2d, d_means, d_log_scales, d_quats,
@@ -377,6 +392,8 @@ class MultiView:
         self.grad2d = torch.empty((V, n1, 9), dtype=torch.float32, device=d)
         self.capacity = [0] * V
         self.mode = "quadbox"
+        self.render_variant = RENDER_VARIANTS["2px"]
+        self.backward_variant = RENDER_VARIANTS["2px"]
         self.grads = None
         self._table = None
 
@@ -439,17 +456,83 @@ class MultiView:
             self._intersect(v)
             sort(self.capacity[v], self.num_pairs[v:v + 1], self.num_tiles[v], self.pair_tiles[v], self.pair_ids[v],
                  self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort)
-        render_views(self._table, self.V, bg)
+        render_views(self._table, self.V, bg, self.render_variant)
         return self.images
+
+    def render(self, bg=(0.0, 0.0, 0.0)):
+        render_views(self._table, self.V, bg, self.render_variant)
 
     def backward(self, g: Gaussians, bg=(0.0, 0.0, 0.0)):
         """Gradients of sum over views of <dl[v], image[v]> (fill self.dl
         first); returns (d_means, d_log_scales, d_quats, d_logits, d_sh)."""
         if self.grads is None:
             self.grads = [torch.empty_like(t) for t in g.tensors()]
-        render_backward_views(self._table, self.V, bg, self.n)
+        render_backward_views(self._table, self.V, bg, self.n, self.backward_variant)
         project_backward_views(g, self.cam_array, self.V, self.splats, self.grad2d, *self.grads)
         return self.grads
 
     def overflowed(self) -> bool:
         return any(p > c for p, c in zip(self.num_pairs.cpu().tolist(), self.capacity))
+
+
+# ---- autotuner -----------------------------------------------------------------
+
+def _best(fn, reps, trials):
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(trials):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / reps)
+    return best
+
+
+def autotune_backward(run, bg=(0.0, 0.0, 0.0), dl=None, grad2d=None, reps=5, trials=3):
+    """Times every launch shape of the render backward on the frame `run`
+    holds -- a MultiView after forward with its dl filled, or a Rasterizer
+    after forward given dl [3, H, W] and a grad2d [n, 9] buffer -- keeps the
+    fastest in run.backward_variant and returns {shape: ms}."""
+    times = {}
+    for name, v in RENDER_VARIANTS.items():
+        if isinstance(run, MultiView):
+            fn = (lambda v=v: render_backward_views(run._table, run.V, bg, run.n, v))
+        else:
+            fn = (lambda v=v: render_backward(run.W, run.H, run.ranges, run.ids_sorted, run.splats, bg, run.final_T,
+                                              run.n_contrib, dl, run.n, grad2d, v))
+        times[name] = _best(fn, reps, trials)
+    pick = min(times, key=times.get)
+    run.backward_variant = RENDER_VARIANTS[pick]
+    return times
+
+
+def autotune_render(run, bg=(0.0, 0.0, 0.0), reps=10, trials=3):
+    """Times every render launch shape on the frame `run` (a Rasterizer or a
+    MultiView after a forward) holds, keeps the fastest in
+    run.render_variant and returns {shape: ms}.  The shapes give identical
+    images, so the choice only affects speed."""
+    times = {}
+    for name, v in RENDER_VARIANTS.items():
+        run.render_variant = v
+        run.render(bg)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(trials):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                run.render(bg)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / reps)
+        times[name] = best
+    pick = min(times, key=times.get)
+    run.render_variant = RENDER_VARIANTS[pick]
+    run.render(bg)
+    return times

@@ -32,10 +32,13 @@ def qb():
     return quadbox
 
 
-def gpu_grads(qb, scene, cam, target, bg=(0.0, 0.0, 0.0), mask=None):
+def gpu_grads(qb, scene, cam, target, bg=(0.0, 0.0, 0.0), mask=None, variant=None):
     params = [torch.tensor(x, device="cuda", requires_grad=True)
               for x in (scene.means, scene.log_scales, scene.quats, scene.logits, scene.sh)]
-    img = qb.rasterize(*params, cam, "quadbox", bg)
+    r = qb.Rasterizer(scene.n, cam, write_keys=False)
+    if variant is not None:
+        r.backward_variant = variant
+    img = qb.rasterize(*params, cam, "quadbox", bg, rasterizer=r)
     t = torch.tensor(target, device="cuda", dtype=torch.float32)
     diff = (img - t).abs()
     if mask is not None:
@@ -94,17 +97,19 @@ def test_tiny_scene_against_oracle(oracle, qb):
     compare(G, G_ref, "tiny")
 
 
-def test_rotated_camera_background(oracle, qb):
-    """5000 Gaussians, 160x96 with a rotated, offset camera and a background."""
+@pytest.mark.parametrize("shape", ["2px", "1px", "4px"])
+def test_rotated_camera_background(oracle, qb, shape):
+    """5000 Gaussians, 160x96 with a rotated, offset camera and a background;
+    every launch shape of the render backward."""
     from scipy.spatial.transform import Rotation
     scene, _ = scenes.random_scene(46, 5000, 160, 96, 150.0, sh_degree=3, log_scale_mu=-3.0, log_scale_sd=0.6)
     R = Rotation.from_euler("xyz", [0.05, 0.1, -0.08]).as_matrix().astype(np.float32)
     cam = scenes.pinhole(160, 96, 150.0, R, np.array([0.1, 0.05, 0.2], np.float32))
     target = scenes.target_image(47, cam.width, cam.height).astype(np.float64)
     bg = (0.3, 0.2, 0.1)
-    say("rotated")
+    say("rotated", shape)
     mask = decided_mask(oracle, scene, cam, bg=bg)
-    G, dl = gpu_grads(qb, scene, cam, target, bg, mask=mask)
+    G, dl = gpu_grads(qb, scene, cam, target, bg, mask=mask, variant=qb.RENDER_VARIANTS[shape])
     G_ref = oracle.backward64(scene, cam, dl, bg)
     compare(G, G_ref, "rotated")
 

@@ -251,3 +251,62 @@ def test_full_size_clusters(oracle, qb, mode):
     tiles = np.unique(np.concatenate([rng.choice(cam.num_tiles, 140, replace=False), busy]))
     _sampled_tile_check(oracle, gpu, g, cam, tiles, label)
     _sampled_render_check(oracle, gpu, g, cam, tiles[:40], label)
+
+
+@pytest.mark.parametrize("zoom", [1, 4, 8])
+def test_full_size_aniso_zoom(oracle, qb, zoom):
+    """The 3M highly anisotropic Gaussians at 1920x1080 with focal 1920*zoom
+    (the zoom-in sweep), QuadBox boxes: projection and counts bit-exact,
+    keys sorted with consistent depth bits, ranges exact, sampled tile lists
+    and pixels against the oracle."""
+    scene, cams = scenes.aniso_scene()
+    cam = cams[zoom - 1]
+    label = f"aniso-3M x{zoom}"
+    say("running", label)
+    gpu, _ = gpu_forward(qb, scene, cam, "quadbox")
+    g = oracle.project(scene, cam, "quadbox")
+    check_project(oracle, gpu, g, label)
+    check_counts(oracle, gpu, g, cam.tiles_x, label)
+    keys, ids = gpu["keys"], gpu["ids"]
+    assert np.all(keys[1:] >= keys[:-1])
+    tie = keys[1:] == keys[:-1]
+    assert np.all(ids[1:][tie] > ids[:-1][tie])
+    assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), bits(g["depth"])[ids])
+    assert np.array_equal(gpu["ranges"], oracle.ranges(keys, cam.num_tiles))
+    say(label, "pairs", gpu["P"])
+    rng = np.random.default_rng(10 + zoom)
+    busy = np.argsort(gpu["ranges"][:, 1] - gpu["ranges"][:, 0])[-10:]
+    tiles = np.unique(np.concatenate([rng.choice(cam.num_tiles, 60, replace=False), busy]))
+    _sampled_tile_check(oracle, gpu, g, cam, tiles, label)
+    _sampled_render_check(oracle, gpu, g, cam, tiles[:20], label)
+
+
+def test_render_launch_shapes_identical(oracle, qb):
+    """Every render launch shape (1, 2 or 4 pixels per lane) gives the same
+    image, T and contributor counts bit for bit, and the autotuner keeps one
+    of them; checked on a ragged image against the oracle too."""
+    scene, _ = scenes.random_scene(105, 6000, 333, 250, 300.0, sh_degree=2)
+    cam = scenes.pinhole(333, 250, 300.0)
+    bg = (0.25, 0.5, 0.75)
+    g = qb.Gaussians(scene)
+    r = qb.Rasterizer(scene.n, cam)
+    r.forward(g, "quadbox", bg)
+    torch.cuda.synchronize()
+    ref = oracle.forward(scene, cam, "quadbox", bg)
+    outs = {}
+    for name, v in qb.RENDER_VARIANTS.items():
+        r.render_variant = v
+        r.render(bg)
+        torch.cuda.synchronize()
+        outs[name] = (r.image.clone(), r.final_T.clone(), r.n_contrib.clone())
+        gpu = dict(image=outs[name][0].cpu().numpy(), T=outs[name][1].cpu().numpy(),
+                   n_contrib=outs[name][2].cpu().numpy().view(np.uint32))
+        check_image(ref["image"], ref["T"], ref["n_contrib"], ref["near"], gpu, f"render shape {name}")
+    for name in outs:
+        for a, b in zip(outs[name], outs["2px"]):
+            assert torch.equal(a, b), name
+    times = qb.autotune_render(r, bg, reps=3, trials=1)
+    say("render shapes (ms)", {k: round(v, 4) for k, v in times.items()}, "picked", r.render_variant)
+    assert r.render_variant in qb.RENDER_VARIANTS.values()
+    torch.cuda.synchronize()
+    assert torch.equal(r.image, outs["2px"][0])

@@ -195,3 +195,16 @@ def test_views_full_size_matches_single_view(qb):
         assert torch.equal(r.n_contrib, mv.n_contrib[v]), v
         del r
     say("sampled views equal the single-view path")
+    for v in range(mv.V):
+        mv.dl[v].fill_(1.0 / mv.dl[v].numel())
+    t_bwd = qb.autotune_backward(mv, reps=1, trials=1)
+    say("backward shapes (ms, all views)", {k: round(x, 3) for k, x in t_bwd.items()}, "picked", mv.backward_variant)
+    want = [x.clone() for x in mv.images]
+    times = qb.autotune_render(mv, reps=2, trials=1)
+    say("render shapes (ms, all views)", {k: round(v, 3) for k, v in times.items()}, "picked", mv.render_variant)
+    for name, v in qb.RENDER_VARIANTS.items():
+        mv.render_variant = v
+        mv.render()
+        torch.cuda.synchronize()
+        for a, b in zip(mv.images, want):
+            assert torch.equal(a, b), name
