@@ -98,6 +98,8 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials):
     torch.cuda.synchronize()
     pairs = r.pairs()
     r._alloc_pairs(pairs)
+    r.forward(g, mode, sync_count=False)
+    shapes = qb.autotune_render(r, reps=5, trials=2)   # launch shape of the render for this frame
     for _ in range(warmup):
         r.forward(g, mode, sync_count=False)
     torch.cuda.synchronize()
@@ -130,7 +132,9 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials):
     wall = sorted(t[1] for t in trial_ms)[len(trial_ms) // 2]
     stage = timer.ms()
     evals = render_evaluations(torch, r)
-    return dict(ms=dev, wall_ms=wall, pairs=pairs, stage_ms=stage, evals=evals, rast=r)
+    names = {v: k for k, v in qb.RENDER_VARIANTS.items()}
+    return dict(ms=dev, wall_ms=wall, pairs=pairs, stage_ms=stage, evals=evals, rast=r,
+                render_shape=names[r.render_variant], shape_ms={k: round(v, 4) for k, v in shapes.items()})
 
 
 def run_fwd_bwd(torch, qb, g, cam, steps, warmup, trials):
@@ -332,14 +336,17 @@ def cpu_baseline(scene, cam):
                       f"{t2 - t1:.2f} s, render {t3 - t2:.2f} s"}
 
 
-def render_traffic(workload, mode):
-    """HBM bytes per k_render launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
-    from the committed counter summary, or None when that summary was taken on
-    another workload or on a different render source."""
+def render_traffic(workload, mode, kernel):
+    """HBM bytes per launch of the render kernel `kernel` (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated) from the committed counter summary, or None
+    when that summary was taken on another workload, another kernel or a
+    different render source."""
     path = os.path.join(ROOT, "profiles", "k_render_clusters_1M_counters.json")
     if workload != "clusters" or mode != "quadbox" or not os.path.exists(path):
         return None
     meta = json.load(open(path))
+    if meta.get("kernel") != kernel:
+        return None
     src = os.path.join(ROOT, "paper_2605_04844_amd", "csrc", "render.hip")
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != meta["render_source_sha256"]:
         return None
@@ -403,9 +410,10 @@ def main():
     # events around the call time that kernel)
     render_ms = stage["render"]
     achieved = q["evals"] * RENDER_OPS_PER_EVAL / (render_ms * 1e-3) / 1e12
+    kname = f"k_render<{q['render_shape'][0]}, false>"
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
-            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": render_traffic(args.workload, modes[0]),
-            "kernel": "k_render", "evaluations_per_launch": q["evals"], "ops_per_evaluation": RENDER_OPS_PER_EVAL,
+            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": render_traffic(args.workload, modes[0], kname),
+            "kernel": kname, "evaluations_per_launch": q["evals"], "ops_per_evaluation": RENDER_OPS_PER_EVAL,
             "launch_ms": round(render_ms, 4)}
     out = {
         "metric": METRIC,
@@ -424,6 +432,7 @@ def main():
         "pairs_per_frame": q["pairs"],
         "modes": {m: {"fps": round(1000.0 / r["ms"], 2), "ms": round(r["ms"], 4), "pairs": r["pairs"],
                       "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
+                      "render_shape": r["render_shape"], "render_shape_ms": r["shape_ms"],
                       **image_delta(torch, r["rast"].image, q["rast"].image)}
                   for m, r in results.items()},
         "fwd_bwd_ms_per_view": round(fwd_bwd, 4) if fwd_bwd is not None else None,

@@ -29,7 +29,7 @@ namespace {
 // apart (256/PPL lanes per tile).  The row terms of the quadratic form and
 // every LDS read are shared by a lane's PPL pixels; the batch staged in LDS
 // holds one record per lane.  qb_render_ex selects PPL (1, 2 or 4).
-template <int PPL>
+template <int PPL, bool COUNT>
 __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x, const uint2* __restrict__ ranges,
                                             const uint32_t* __restrict__ ids, const float4* __restrict__ splats,
                                             float bg0, float bg1, float bg2, float* __restrict__ image,
@@ -117,7 +117,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
                 c2[q] = fmaf(col.z, w, c2[q]);
                 T[q] = add ? test_T : T[q];
                 last[q] = add ? at : last[q];
-                stop[q] = stp ? at : stop[q];
+                if (COUNT) stop[q] = stp ? at : stop[q];
                 done[q] = done[q] || stp;
             }
             if (__all(all_done())) break;
@@ -134,17 +134,19 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
         image[2 * plane + pix] = fmaf(T[q], bg2, c2[q]);
         if (final_T) final_T[pix] = T[q];
         if (n_contrib) n_contrib[pix] = last[q];
-        if (n_touched) n_touched[pix] = done[q] ? stop[q] : len;
+        if (COUNT) n_touched[pix] = done[q] ? stop[q] : len;
     }
 }
 
-template <int PPL>
+// COUNT: also write n_touched (entries examined per pixel), compiled out of
+// the launches that do not ask for it.
+template <int PPL, bool COUNT>
 __global__ __launch_bounds__(256 / PPL) void k_render(
     int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splats, float bg0, float bg1, float bg2, float* __restrict__ image,
     float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_touched)
 {
-    render_tile<PPL>((int)blockIdx.x, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T, n_contrib,
+    render_tile<PPL, COUNT>((int)blockIdx.x, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T, n_contrib,
                      n_touched);
 }
 
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(256 / PPL) void k_render_views(QbViewTable vt, floa
     int b = (int)blockIdx.x;
     int v = qb_view_of(vt, b);
     const qb_view& w = vt.view[v];
-    render_tile<PPL>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
+    render_tile<PPL, false>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
                      w.ids, reinterpret_cast<const float4*>(w.splats), bg0, bg1, bg2, w.image, w.final_T, w.n_contrib,
                      nullptr);
 }
@@ -176,19 +178,24 @@ extern "C" qb_status qb_render_ex(int32_t width, int32_t height, const uint32_t*
     hipStream_t s = qb_hip_stream(stream);
     const uint2* rg = reinterpret_cast<const uint2*>(ranges);
     const float4* sp = reinterpret_cast<const float4*>(splats);
-    switch (variant) {
-    case QB_RENDER_2PX:
-        QB_LAUNCH(k_render<2>, tiles, 128, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0], bg[1], bg[2],
-                  image, final_T, n_contrib, n_touched);
-        break;
-    case QB_RENDER_1PX:
-        QB_LAUNCH(k_render<1>, tiles, 256, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0], bg[1], bg[2],
-                  image, final_T, n_contrib, n_touched);
-        break;
-    default:
-        QB_LAUNCH(k_render<4>, tiles, 64, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0], bg[1], bg[2],
-                  image, final_T, n_contrib, n_touched);
-        break;
+    if (n_touched) {
+        switch (variant) {
+        case QB_RENDER_2PX: QB_LAUNCH((k_render<2, true>), tiles, 128, 0, s, (int)width, (int)height, tiles_x, rg, ids,
+                                      sp, bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+        case QB_RENDER_1PX: QB_LAUNCH((k_render<1, true>), tiles, 256, 0, s, (int)width, (int)height, tiles_x, rg, ids,
+                                      sp, bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+        default: QB_LAUNCH((k_render<4, true>), tiles, 64, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0],
+                           bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+        }
+    } else {
+        switch (variant) {
+        case QB_RENDER_2PX: QB_LAUNCH((k_render<2, false>), tiles, 128, 0, s, (int)width, (int)height, tiles_x, rg,
+                                      ids, sp, bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+        case QB_RENDER_1PX: QB_LAUNCH((k_render<1, false>), tiles, 256, 0, s, (int)width, (int)height, tiles_x, rg,
+                                      ids, sp, bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+        default: QB_LAUNCH((k_render<4, false>), tiles, 64, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp,
+                           bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+        }
     }
     return QB_OK;
 }
