@@ -15,7 +15,9 @@
 //   intermediates and applies the chain rule through the conic inverse, the
 //   EWA covariance J W Sigma W^T J^T (with the clamped Jacobian), the mean
 //   projection, Sigma = R S S^T R^T, the quaternion normalisation, the scale
-//   and opacity activations and the SH colour.
+//   and opacity activations (k_geometry_backward, binary64 like the
+//   forward's covariance chain), then the SH colour and its view direction
+//   (k_sh_backward, a lighter kernel at higher occupancy).
 #include "qb_common.h"
 
 namespace {
@@ -51,12 +53,13 @@ __device__ __forceinline__ float wave_sum(float v)
     return (r0 + r1) + (r2 + r3);
 }
 
+
 // Backward of one tile of one image: 256 / PPL lanes, each owning PPL pixels
 // of one tile row, 16 / PPL apart.  The list is walked back to front from the
 // furthest last contributor of the tile, in batches of one record per lane
 // staged in LDS.  Per entry, a lane sums its pixels' shares, the wave sums
-// its lanes (DPP), and one lane adds the nine totals to grad2d (float
-// atomics: order-dependent rounding).
+// its lanes (DPP), and lanes 0..8 add the nine totals to grad2d in one
+// atomic instruction (float atomics: order-dependent rounding).
 template <int PPL>
 __device__ __forceinline__ void render_backward_tile(
     int tile, int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
@@ -70,11 +73,14 @@ __device__ __forceinline__ void render_backward_tile(
     __shared__ float4 s_col[NT];   // r, g, b, b
     __shared__ float s_c[NT];      // c
     __shared__ uint32_t s_id[NT];
+    __shared__ int s_rows[NT];     // tile rows that can pass the cutoff (entry_rows)
     __shared__ uint32_t s_maxlast;
 
+    constexpr int kRowsPerWave = 64 / LX;   // tile rows a wave covers
     int tx = tile % tiles_x, ty = tile / tiles_x;
     int lx = threadIdx.x % LX, ly = threadIdx.x / LX;
     int py = ty * QB_TILE + ly;
+    int wrow0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64) * kRowsPerWave);
     float fy = (float)py;
     int lane = threadIdx.x & 63;
     int64_t plane = (int64_t)W * H;
@@ -121,10 +127,17 @@ __device__ __forceinline__ void render_backward_tile(
             s_col[threadIdx.x] = make_float4(c.x, c.y, c.z, b.y);
             s_c[threadIdx.x] = b.z;
             s_id[threadIdx.x] = id;
+            if (kRowsPerWave < QB_TILE) s_rows[threadIdx.x] = entry_rows(a.y, b.x, b.y, b.z, b.w, ty);
         }
         __syncthreads();
         for (int k = (int)(b1 - b0) - 1; k >= 0; --k) {
             uint32_t idx = (uint32_t)(b0 + k);  // list index of this entry
+            if (kRowsPerWave < QB_TILE) {
+                // the entry's ellipse misses this wave's rows: no lane takes part
+                int rr = __builtin_amdgcn_readfirstlane(s_rows[k]);
+                int r0 = (int)(int16_t)(rr & 0xFFFF), r1 = rr >> 16;
+                if (r1 < wrow0 || r0 > wrow0 + kRowsPerWave - 1) continue;
+            }
             float4 g = s_geo[k];
             float4 o = s_opa[k];
             float dy = g.y - fy;
@@ -150,12 +163,14 @@ __device__ __forceinline__ void render_backward_tile(
                     float e = __expf(power[q]);
                     float raw = o.y * e;
                     float alpha = fminf(0.99f, raw);
-                    float Ti = T[q] / (1.0f - alpha);           // transmittance in front of this Gaussian
+                    // 1 / (1 - alpha) by the hardware reciprocal (1 ulp; 1 - alpha >= 0.01):
+                    // the transmittance in front of this Gaussian is T / (1 - alpha)
+                    float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                    float Ti = T[q] * inv;
                     float w = alpha * Ti;
                     gr = fmaf(w, dC[q][0], gr);
                     gg = fmaf(w, dC[q][1], gg);
                     gbl = fmaf(w, dC[q][2], gbl);
-                    float inv = 1.0f / (1.0f - alpha);
                     float dalpha = dC[q][0] * (col.x * Ti - rest[q][0] * inv) +
                                    dC[q][1] * (col.y * Ti - rest[q][1] * inv) +
                                    dC[q][2] * (col.z * Ti - rest[q][2] * inv);
@@ -175,27 +190,13 @@ __device__ __forceinline__ void render_backward_tile(
                     }
                 }
             }
-            gu = wave_sum(gu);
-            gv = wave_sum(gv);
-            ga = wave_sum(ga);
-            gb = wave_sum(gb);
-            gc = wave_sum(gc);
-            go = wave_sum(go);
-            gr = wave_sum(gr);
-            gg = wave_sum(gg);
-            gbl = wave_sum(gbl);
-            if (lane == 0) {
-                float* d = grad2d + 9 * (int64_t)s_id[k];
-                atomicAdd(d + 0, gu);
-                atomicAdd(d + 1, gv);
-                atomicAdd(d + 2, ga);
-                atomicAdd(d + 3, gb);
-                atomicAdd(d + 4, gc);
-                atomicAdd(d + 5, go);
-                atomicAdd(d + 6, gr);
-                atomicAdd(d + 7, gg);
-                atomicAdd(d + 8, gbl);
-            }
+            // the nine wave totals are uniform; lane j adds total j, so the
+            // wave issues one atomic instruction over 36 contiguous bytes
+            float t0 = wave_sum(gu), t1 = wave_sum(gv), t2 = wave_sum(ga), t3 = wave_sum(gb), t4 = wave_sum(gc);
+            float t5 = wave_sum(go), t6 = wave_sum(gr), t7 = wave_sum(gg), t8 = wave_sum(gbl);
+            float mine = lane == 0 ? t0 : lane == 1 ? t1 : lane == 2 ? t2 : lane == 3 ? t3 : lane == 4 ? t4 :
+                         lane == 5 ? t5 : lane == 6 ? t6 : lane == 7 ? t7 : t8;
+            if (lane < 9) atomicAdd(grad2d + 9 * (int64_t)s_id[k] + lane, mine);
         }
     }
 }
@@ -333,10 +334,6 @@ __device__ __forceinline__ void geometry_backward(int64_t i, int64_t n, const fl
     double M[9];
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) M[r * 3 + c] = Rq[r * 3 + c] * s[c];
-    double S[9];
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c)
-            S[r * 3 + c] = (M[r * 3 + 0] * M[c * 3 + 0] + M[r * 3 + 1] * M[c * 3 + 1]) + M[r * 3 + 2] * M[c * 3 + 2];
     float xs = px / pz, ys = py / pz;
     float clx = xs < -cam.limx ? -1.f : (xs > cam.limx ? 1.f : 0.f);
     float cly = ys < -cam.limy ? -1.f : (ys > cam.limy ? 1.f : 0.f);
@@ -351,13 +348,16 @@ __device__ __forceinline__ void geometry_backward(int64_t i, int64_t n, const fl
         T[c] = J00 * (double)R[c] + J02 * (double)R[6 + c];
         T[3 + c] = J11 * (double)R[3 + c] + J12 * (double)R[6 + c];
     }
-    double U[6];
+    // Sigma2D = V V^T + 0.3 I with V = T M (2x3): the backward never needs
+    // Sigma3D itself (binary64 throughout; the rounding differs from the
+    // forward's T Sigma3D T^T only at the 1e-16 level)
+    double V[6];
     for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 3; ++c)
-            U[r * 3 + c] = (T[r * 3 + 0] * S[c] + T[r * 3 + 1] * S[3 + c]) + T[r * 3 + 2] * S[6 + c];
-    double A = ((U[0] * T[0] + U[1] * T[1]) + U[2] * T[2]) + 0.3;
-    double B = (U[0] * T[3] + U[1] * T[4]) + U[2] * T[5];
-    double C = ((U[3] * T[3] + U[4] * T[4]) + U[5] * T[5]) + 0.3;
+            V[r * 3 + c] = (T[r * 3 + 0] * M[c] + T[r * 3 + 1] * M[3 + c]) + T[r * 3 + 2] * M[6 + c];
+    double A = ((V[0] * V[0] + V[1] * V[1]) + V[2] * V[2]) + 0.3;
+    double B = (V[0] * V[3] + V[1] * V[4]) + V[2] * V[5];
+    double C = ((V[3] * V[3] + V[4] * V[4]) + V[5] * V[5]) + 0.3;
     double det = A * C - B * B;
     double id2 = 1.0 / (det * det);
     // conic (a, b, c) = (C, -B, A) / det
@@ -366,18 +366,15 @@ __device__ __forceinline__ void geometry_backward(int64_t i, int64_t n, const fl
     double dCc = (da * (-B * B) + db * (B * A) + dc * (-A * A)) * id2;
     // Sigma2D = T Sigma T^T with symmetric cotangent G
     double G00 = dA, G01 = 0.5 * dB, G11 = dCc;
-    double GT[6];  // G T (2x3)
+    double GV[6];  // G V (2x3)
     for (int c = 0; c < 3; ++c) {
-        GT[c] = G00 * T[c] + G01 * T[3 + c];
-        GT[3 + c] = G01 * T[c] + G11 * T[3 + c];
+        GV[c] = G00 * V[c] + G01 * V[3 + c];
+        GV[3 + c] = G01 * V[c] + G11 * V[3 + c];
     }
-    double dS[9];  // T^T G T
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) dS[r * 3 + c] = T[r] * GT[c] + T[3 + r] * GT[3 + c];
-    double dT[6];  // 2 G T S
+    double dT[6];  // 2 G T Sigma3D = 2 (G V) M^T
     for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 3; ++c)
-            dT[r * 3 + c] = 2.0 * (GT[r * 3 + 0] * S[c] + GT[r * 3 + 1] * S[3 + c] + GT[r * 3 + 2] * S[6 + c]);
+            dT[r * 3 + c] = 2.0 * (GV[r * 3 + 0] * M[c * 3 + 0] + GV[r * 3 + 1] * M[c * 3 + 1] + GV[r * 3 + 2] * M[c * 3 + 2]);
     double dJ00 = 0.0, dJ02 = 0.0, dJ11 = 0.0, dJ12 = 0.0;
     for (int c = 0; c < 3; ++c) {
         dJ00 += dT[c] * (double)R[c];
@@ -399,10 +396,9 @@ __device__ __forceinline__ void geometry_backward(int64_t i, int64_t n, const fl
     for (int c = 0; c < 3; ++c)
         dm[c] += (double)R[c] * dp[0] + (double)R[3 + c] * dp[1] + (double)R[6 + c] * dp[2];
     // Sigma = M M^T, M = R diag(s)
-    double dM[9];
+    double dM[9];  // 2 T^T G T M = 2 T^T (G V)
     for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c)
-            dM[r * 3 + c] = 2.0 * (dS[r * 3 + 0] * M[c] + dS[r * 3 + 1] * M[3 + c] + dS[r * 3 + 2] * M[6 + c]);
+        for (int c = 0; c < 3; ++c) dM[r * 3 + c] = 2.0 * (T[r] * GV[c] + T[3 + r] * GV[3 + c]);
     double dR[9];
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) dR[r * 3 + c] = dM[r * 3 + c] * s[c];
@@ -441,39 +437,54 @@ __device__ __forceinline__ float view_dir(float mx, float my, float mz, const fl
     return dn;
 }
 
-__global__ __launch_bounds__(QB_BLOCK) void k_project_backward(
+// Single view, geometry: the mean (through the projection), log-scales,
+// quaternion and logit (the colour's share of the mean gradient follows in
+// k_sh_backward).  Invisible Gaussians get zero gradients.
+__global__ __launch_bounds__(QB_BLOCK) void k_geometry_backward(
     int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
-    const float* __restrict__ quats, const float* __restrict__ logits, const float* __restrict__ sh, int sh_degree,
-    BwdCam cam, const float4* __restrict__ splats, const float* __restrict__ grad2d, float* __restrict__ d_means,
-    float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_logits,
-    float* __restrict__ d_sh)
+    const float* __restrict__ quats, const float* __restrict__ logits, BwdCam cam,
+    const float4* __restrict__ splats, const float* __restrict__ grad2d, float* __restrict__ d_means,
+    float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_logits)
 {
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
-    int K = (sh_degree + 1) * (sh_degree + 1);
-    float4 s2 = splats[3 * i + 2];
     double dm[3] = {0.0, 0.0, 0.0}, dls[3] = {0.0, 0.0, 0.0}, dq[4] = {0.0, 0.0, 0.0, 0.0};
     float dlogit = 0.f;
-    if (s2.w != 1.0f) {
-        for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = 0.f;
-    } else {
-        const float* g2 = grad2d + 9 * i;
-        geometry_backward(i, n, means, log_scales, quats, logits, cam, g2, dm, dls, dq, dlogit);
-        float dir[3], drgb[3], ddir[3];
-        float dn = view_dir(means[i], means[n + i], means[2 * n + i], cam.campos, dir);
-        colour_grad(s2, g2, drgb);
-        sh_colour_backward(sh, n, i, sh_degree, dir[0], dir[1], dir[2], drgb, d_sh, ddir);
-        if (dn > 0.0f) {
-            float dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
-            for (int c = 0; c < 3; ++c) dm[c] += (double)((ddir[c] - dir[c] * dd) / dn);
-        }
-    }
+    if (splats[3 * i + 2].w == 1.0f)
+        geometry_backward(i, n, means, log_scales, quats, logits, cam, grad2d + 9 * i, dm, dls, dq, dlogit);
     for (int c = 0; c < 3; ++c) {
         d_means[c * n + i] = (float)dm[c];
         d_log_scales[c * n + i] = (float)dls[c];
     }
     for (int c = 0; c < 4; ++c) d_quats[c * n + i] = (float)dq[c];
     d_logits[i] = dlogit;
+}
+
+// Single view, colour: SH coefficients, and the colour's share of the mean
+// gradient (through the view direction) added to d_means.
+template <int DEG>
+__global__ __launch_bounds__(QB_BLOCK) void k_sh_backward(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ sh, BwdCam cam,
+    const float4* __restrict__ splats, const float* __restrict__ grad2d, float* __restrict__ d_means,
+    float* __restrict__ d_sh)
+{
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    float4 s2 = splats[3 * i + 2];
+    if (s2.w != 1.0f) {
+#pragma unroll
+        for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = 0.f;
+        return;
+    }
+    float dir[3], drgb[3], ddir[3];
+    float dn = view_dir(means[i], means[n + i], means[2 * n + i], cam.campos, dir);
+    colour_grad(s2, grad2d + 9 * i, drgb);
+    sh_colour_backward(sh, n, i, DEG, dir[0], dir[1], dir[2], drgb, d_sh, ddir);
+    if (dn > 0.0f) {
+        float dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
+        for (int c = 0; c < 3; ++c) d_means[c * n + i] += (ddir[c] - dir[c] * dd) / dn;
+    }
 }
 
 // Views: the geometry part summed over views (the colour's share of the
@@ -640,9 +651,17 @@ extern "C" qb_status qb_project_backward(int64_t n, const float* means, const fl
         return QB_ERR_INVALID_ARG;
     BwdCam bc;
     make_bwd_cam(*cam, &bc);
-    QB_LAUNCH(k_project_backward, qb_div_up(n, QB_BLOCK), QB_BLOCK, 0, qb_hip_stream(stream), n, means, log_scales,
-              quats, opacity_logits, sh, (int)sh_degree, bc, reinterpret_cast<const float4*>(splats), grad2d, d_means,
-              d_log_scales, d_quats, d_opacity_logits, d_sh);
+    hipStream_t s = qb_hip_stream(stream);
+    int64_t grid = qb_div_up(n, QB_BLOCK);
+    const float4* sp = reinterpret_cast<const float4*>(splats);
+    QB_LAUNCH(k_geometry_backward, grid, QB_BLOCK, 0, s, n, means, log_scales, quats, opacity_logits, bc, sp, grad2d,
+              d_means, d_log_scales, d_quats, d_opacity_logits);
+    switch (sh_degree) {
+    case 0: QB_LAUNCH(k_sh_backward<0>, grid, QB_BLOCK, 0, s, n, means, sh, bc, sp, grad2d, d_means, d_sh); break;
+    case 1: QB_LAUNCH(k_sh_backward<1>, grid, QB_BLOCK, 0, s, n, means, sh, bc, sp, grad2d, d_means, d_sh); break;
+    case 2: QB_LAUNCH(k_sh_backward<2>, grid, QB_BLOCK, 0, s, n, means, sh, bc, sp, grad2d, d_means, d_sh); break;
+    default: QB_LAUNCH(k_sh_backward<3>, grid, QB_BLOCK, 0, s, n, means, sh, bc, sp, grad2d, d_means, d_sh); break;
+    }
     return QB_OK;
 }
 

@@ -46,6 +46,23 @@ struct QRect {
     int x0, x1, y0, y1;
 };
 
+// Tile-local rows [r0, r1] (packed r0 | r1 << 16, clamped to [-1, 16]) that
+// can hold a pixel passing the cutoff of a Gaussian with mean row v, conic
+// (a, b, c) and gamma: the ellipse power >= -gamma/2 spans v +- sqrt(gamma
+// Sigma_yy) with Sigma_yy = a / (a c - b^2).  Widened by 1% + 0.5 px so that
+// binary32 rounding of the power can never pass a pixel outside the range.
+__host__ __device__ __forceinline__ int entry_rows(float v, float a, float b, float c, float gamma, int ty)
+{
+    // a c - b^2 of a needle's conic cancels: binary64 (the products are exact)
+    double det = (double)a * (double)c - (double)b * (double)b;
+    float h = det > 0.0 && gamma > 0.0f && a > 0.0f ? (float)sqrt((double)gamma * (double)a / det) : 3.0e4f;
+    h = h * 1.01f + 0.5f;
+    float y0 = v - h - (float)(ty * QB_TILE), y1 = v + h - (float)(ty * QB_TILE);
+    int r0 = y0 < -1.0f ? -1 : (y0 > 16.0f ? 16 : (int)floorf(y0));
+    int r1 = y1 < -1.0f ? -1 : (y1 > 16.0f ? 16 : (int)ceilf(y1));
+    return (r0 & 0xFFFF) | (r1 << 16);
+}
+
 // Per-view table of a batched call, passed by value as a kernel argument
 // (about 2.6 KB at QB_MAX_VIEWS views).  tile_start[v] is the first global
 // tile of view v; tile_start[num] is the total.
