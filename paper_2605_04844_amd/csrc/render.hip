@@ -29,7 +29,6 @@ namespace {
 // apart (256/PPL lanes per tile).  The row terms of the quadratic form and
 // every LDS read are shared by a lane's PPL pixels; the batch staged in LDS
 // holds one record per lane.  qb_render_ex selects PPL (1, 2 or 4).
-
 template <int PPL, bool COUNT>
 __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x, const uint2* __restrict__ ranges,
                                             const uint32_t* __restrict__ ids, const float4* __restrict__ splats,
