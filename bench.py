@@ -216,7 +216,8 @@ def run_multiview(torch, qb, steps, warmup, trials):
              "render_backward_ms": qb.autotune_backward(mv, reps=2, trials=2)}
     tuned = {k: {s: round(x, 4) for s, x in v.items()} for k, v in tuned.items()}
     names = {v: k for k, v in qb.RENDER_VARIANTS.items()}
-    tuned["picked"] = {"render": names[mv.render_variant], "render_backward": names[mv.backward_variant]}
+    bnames = {v: k for k, v in qb.BACKWARD_VARIANTS.items()}
+    tuned["picked"] = {"render": names[mv.render_variant], "render_backward": bnames[mv.backward_variant]}
     log("autotune", tuned)
 
     def batched():
@@ -410,7 +411,7 @@ def main():
     # events around the call time that kernel)
     render_ms = stage["render"]
     achieved = q["evals"] * RENDER_OPS_PER_EVAL / (render_ms * 1e-3) / 1e12
-    kname = f"k_render<{q['render_shape'][0]}, false>"
+    kname = f"k_render<{q['render_shape'][0]}, false, {'true' if q['render_shape'].endswith('rows') else 'false'}>"
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
             "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": render_traffic(args.workload, modes[0], kname),
             "kernel": kname, "evaluations_per_launch": q["evals"], "ops_per_evaluation": RENDER_OPS_PER_EVAL,

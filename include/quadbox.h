@@ -198,12 +198,17 @@ qb_status qb_render(int32_t width, int32_t height, const uint32_t* ranges, const
                     uint32_t* n_contrib, uint32_t* n_touched, qb_stream_t stream);
 
 /* Launch shapes of the render (the same image, T and counts from each):
- * pixels per lane of a tile row; 256 / pixels lanes per 16x16 tile. */
+ * pixels per lane of a tile row (256 / pixels lanes per 16x16 tile), and
+ * whether each wave first drops the batch entries whose cutoff ellipse cannot
+ * reach its rows (a per-entry row range; pays off for loose boxes).  The
+ * render backward accepts the first three and always drops such entries. */
 typedef enum {
-    QB_RENDER_2PX = 0,   /* 128 lanes, 2 pixels each (qb_render's shape)       */
-    QB_RENDER_1PX = 1,   /* 256 lanes, 1 pixel each                            */
-    QB_RENDER_4PX = 2,   /* 64 lanes, 4 pixels each                            */
-    QB_RENDER_VARIANTS = 3
+    QB_RENDER_2PX = 0,        /* 128 lanes, 2 pixels each (qb_render's shape)  */
+    QB_RENDER_1PX = 1,        /* 256 lanes, 1 pixel each                       */
+    QB_RENDER_4PX = 2,        /* 64 lanes, 4 pixels each                       */
+    QB_RENDER_2PX_ROWS = 3,   /* 2 pixels each, row-range entry skip           */
+    QB_RENDER_1PX_ROWS = 4,   /* 1 pixel each, row-range entry skip            */
+    QB_RENDER_VARIANTS = 5
 } qb_render_variant;
 
 /* qb_render_ex -- qb_render with an explicit launch shape (chosen, for

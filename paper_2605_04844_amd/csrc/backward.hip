@@ -130,14 +130,30 @@ __device__ __forceinline__ void render_backward_tile(
             if (kRowsPerWave < QB_TILE) s_rows[threadIdx.x] = entry_rows(a.y, b.x, b.y, b.z, b.w, ty);
         }
         __syncthreads();
-        for (int k = (int)(b1 - b0) - 1; k >= 0; --k) {
-            uint32_t idx = (uint32_t)(b0 + k);  // list index of this entry
-            if (kRowsPerWave < QB_TILE) {
-                // the entry's ellipse misses this wave's rows: no lane takes part
-                int rr = __builtin_amdgcn_readfirstlane(s_rows[k]);
+        // entries of this batch whose ellipse can reach this wave's rows, one
+        // bit each (uniform masks), walked from the back
+        constexpr int NM = NT / 64;
+        int cnt = (int)(b1 - b0);
+        uint64_t mask[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            int kk = m * 64 + lane;
+            bool rel = kk < cnt;
+            if (kRowsPerWave < QB_TILE && rel) {
+                int rr = s_rows[kk];
                 int r0 = (int)(int16_t)(rr & 0xFFFF), r1 = rr >> 16;
-                if (r1 < wrow0 || r0 > wrow0 + kRowsPerWave - 1) continue;
+                rel = !(r1 < wrow0 || r0 > wrow0 + kRowsPerWave - 1);
             }
+            mask[m] = __ballot(rel);
+        }
+#pragma unroll
+        for (int m = NM - 1; m >= 0; --m) {
+          uint64_t bits = mask[m];
+          while (bits) {
+            int hb = 63 - (int)__builtin_clzll(bits);
+            bits &= ~(1ull << hb);
+            int k = m * 64 + hb;
+            uint32_t idx = (uint32_t)(b0 + k);  // list index of this entry
             float4 g = s_geo[k];
             float4 o = s_opa[k];
             float dy = g.y - fy;
@@ -197,6 +213,7 @@ __device__ __forceinline__ void render_backward_tile(
             float mine = lane == 0 ? t0 : lane == 1 ? t1 : lane == 2 ? t2 : lane == 3 ? t3 : lane == 4 ? t4 :
                          lane == 5 ? t5 : lane == 6 ? t6 : lane == 7 ? t7 : t8;
             if (lane < 9) atomicAdd(grad2d + 9 * (int64_t)s_id[k] + lane, mine);
+          }
         }
     }
 }
@@ -599,7 +616,7 @@ extern "C" qb_status qb_render_backward_ex(int32_t width, int32_t height, const 
 {
     if (width <= 0 || height <= 0 || width > 32767 * QB_TILE || height > 32767 * QB_TILE || !ranges || !bg ||
         !final_T || !n_contrib || !dL_dimage || n < 0 || (n > 0 && (!grad2d || !splats)) || variant < 0 ||
-        variant >= QB_RENDER_VARIANTS)
+        variant > QB_RENDER_4PX)
         return QB_ERR_INVALID_ARG;
     int tiles_x = (int)qb_div_up(width, QB_TILE);
     int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
@@ -668,7 +685,7 @@ extern "C" qb_status qb_project_backward(int64_t n, const float* means, const fl
 extern "C" qb_status qb_render_backward_views_ex(int32_t num_views, const qb_view* views, const float* bg,
                                                  int64_t n, int32_t variant, qb_stream_t stream)
 {
-    if (!bg || n < 0 || variant < 0 || variant >= QB_RENDER_VARIANTS) return QB_ERR_INVALID_ARG;
+    if (!bg || n < 0 || variant < 0 || variant > QB_RENDER_4PX) return QB_ERR_INVALID_ARG;
     QbViewTable vt;
     qb_status st = qb_make_view_table(num_views, views, true, &vt);
     if (st != QB_OK) return st;

@@ -28,8 +28,11 @@ namespace {
 // Launch shape: PPL pixels per lane, all in one row of the tile, 16/PPL
 // apart (256/PPL lanes per tile).  The row terms of the quadratic form and
 // every LDS read are shared by a lane's PPL pixels; the batch staged in LDS
-// holds one record per lane.  qb_render_ex selects PPL (1, 2 or 4).
-template <int PPL, bool COUNT>
+// holds one record per lane.  qb_render_ex selects PPL (1, 2 or 4).  When a
+// wave covers fewer than 16 rows (PPL 1 or 2), each staged batch also gets,
+// per wave, a ballot mask of the entries whose cutoff ellipse can reach the
+// wave's rows (entry_rows), and the wave walks only those entries.
+template <int PPL, bool COUNT, bool SKIP>
 __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x, const uint2* __restrict__ ranges,
                                             const uint32_t* __restrict__ ids, const float4* __restrict__ splats,
                                             float bg0, float bg1, float bg2, float* __restrict__ image,
@@ -41,10 +44,16 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
     __shared__ float4 s_geo[NT];   // u, v, -a/2, -b
     __shared__ float4 s_opa[NT];   // -c/2, o, -gamma/2, unused
     __shared__ float4 s_col[NT];   // r, g, b, unused
+    __shared__ int s_rows[NT];     // tile rows that can pass the cutoff (entry_rows)
 
+    constexpr int kRowsPerWave = 64 / LX;   // tile rows a wave covers
+    constexpr bool kSkip = SKIP && kRowsPerWave < QB_TILE;
+    constexpr int NM = NT / 64;             // 64-entry masks per batch
     int tx = tile % tiles_x, ty = tile / tiles_x;
     int lx = threadIdx.x % LX, ly = threadIdx.x / LX;
     int py = ty * QB_TILE + ly;
+    int lane = threadIdx.x & 63;
+    int wrow0 = (int)(threadIdx.x / 64) * kRowsPerWave;
     float fy = (float)py;
     bool in[PPL], done[PPL];
     float fxp[PPL], T[PPL], c0[PPL], c1[PPL], c2[PPL];
@@ -79,12 +88,14 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             s_geo[threadIdx.x] = make_float4(a.x, a.y, -0.5f * b.x, -b.y);
             s_opa[threadIdx.x] = make_float4(-0.5f * b.z, a.w, -0.5f * b.w, 0.0f);
             s_col[threadIdx.x] = c;
+            if (kSkip) s_rows[threadIdx.x] = entry_rows(a.y, b.x, b.y, b.z, b.w, ty);
         }
         __syncthreads();
-        if (all_done()) continue;
         int cnt = (int)min((int64_t)NT, end - base);
         uint32_t idx0 = (uint32_t)(base - start);
-        for (int k = 0; k < cnt; ++k) {
+        // one list entry k of the batch for every pixel of the lane; returns
+        // true when the whole wave has stopped
+        auto entry = [&](int k) -> bool {
             float4 g = s_geo[k];
             float4 o = s_opa[k];
             // the terms of the quadratic form that depend on the row only
@@ -102,7 +113,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
                 any = any || act[q];
             }
             // branch only when the whole wave agrees; per pixel, select
-            if (!__any(any)) continue;
+            if (!__any(any)) return false;
             float4 col = s_col[k];
             uint32_t at = idx0 + (uint32_t)k + 1u;
 #pragma unroll
@@ -120,7 +131,40 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
                 if (COUNT) stop[q] = stp ? at : stop[q];
                 done[q] = done[q] || stp;
             }
-            if (__all(all_done())) break;
+            return __all(all_done());
+        };
+        if (kSkip) {
+            // entries of this batch whose ellipse can reach this wave's rows,
+            // one bit each (uniform masks), walked in order.  Leave the batch
+            // only when the whole wave is done: every lane takes part in the
+            // ballots (lane l contributes entry m * 64 + l).
+            if (__all(all_done())) continue;
+            uint64_t mask[NM];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                int k = m * 64 + lane;
+                bool rel = k < cnt;
+                if (rel) {
+                    int rr = s_rows[k];
+                    int r0 = (int)(int16_t)(rr & 0xFFFF), r1 = rr >> 16;
+                    rel = !(r1 < wrow0 || r0 > wrow0 + kRowsPerWave - 1);
+                }
+                mask[m] = __ballot(rel);
+            }
+            bool finished = false;
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                uint64_t bits = finished ? 0ull : mask[m];
+                while (bits) {
+                    int k = m * 64 + (int)__builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    if (entry(k)) { finished = true; break; }
+                }
+            }
+        } else {
+            if (all_done()) continue;
+            for (int k = 0; k < cnt; ++k)
+                if (entry(k)) break;
         }
     }
     uint32_t len = (uint32_t)(end - start);
@@ -140,30 +184,51 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
 
 // COUNT: also write n_touched (entries examined per pixel), compiled out of
 // the launches that do not ask for it.
-template <int PPL, bool COUNT>
+template <int PPL, bool COUNT, bool SKIP>
 __global__ __launch_bounds__(256 / PPL) void k_render(
     int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splats, float bg0, float bg1, float bg2, float* __restrict__ image,
     float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_touched)
 {
-    render_tile<PPL, COUNT>((int)blockIdx.x, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T, n_contrib,
+    render_tile<PPL, COUNT, SKIP>((int)blockIdx.x, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T, n_contrib,
                      n_touched);
 }
 
 // Every tile of every view in one launch: workgroup b takes global tile b,
 // whose view is found in the (at most QB_MAX_VIEWS) tile offsets.
-template <int PPL>
+template <int PPL, bool SKIP>
 __global__ __launch_bounds__(256 / PPL) void k_render_views(QbViewTable vt, float bg0, float bg1, float bg2)
 {
     int b = (int)blockIdx.x;
     int v = qb_view_of(vt, b);
     const qb_view& w = vt.view[v];
-    render_tile<PPL, false>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
+    render_tile<PPL, false, SKIP>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
                      w.ids, reinterpret_cast<const float4*>(w.splats), bg0, bg1, bg2, w.image, w.final_T, w.n_contrib,
                      nullptr);
 }
 
 }  // namespace
+
+// Launches render variant `variant` (qb_render_variant) over `tiles` tiles.
+template <bool COUNT>
+static qb_status launch_render(int variant, int64_t tiles, hipStream_t s, int W, int H, int tiles_x,
+                               const uint2* rg, const uint32_t* ids, const float4* sp, const float* bg, float* image,
+                               float* final_T, uint32_t* n_contrib, uint32_t* n_touched)
+{
+    switch (variant) {
+    case QB_RENDER_2PX: QB_LAUNCH((k_render<2, COUNT, false>), tiles, 128, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
+                                  bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+    case QB_RENDER_1PX: QB_LAUNCH((k_render<1, COUNT, false>), tiles, 256, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
+                                  bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+    case QB_RENDER_4PX: QB_LAUNCH((k_render<4, COUNT, false>), tiles, 64, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
+                                  bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+    case QB_RENDER_2PX_ROWS: QB_LAUNCH((k_render<2, COUNT, true>), tiles, 128, 0, s, W, H, tiles_x, rg, ids, sp,
+                                       bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+    default: QB_LAUNCH((k_render<1, COUNT, true>), tiles, 256, 0, s, W, H, tiles_x, rg, ids, sp, bg[0], bg[1],
+                       bg[2], image, final_T, n_contrib, n_touched); break;
+    }
+    return QB_OK;
+}
 
 extern "C" qb_status qb_render_ex(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
                                   const qb_splat* splats, const float* bg, float* image, float* final_T,
@@ -178,26 +243,11 @@ extern "C" qb_status qb_render_ex(int32_t width, int32_t height, const uint32_t*
     hipStream_t s = qb_hip_stream(stream);
     const uint2* rg = reinterpret_cast<const uint2*>(ranges);
     const float4* sp = reinterpret_cast<const float4*>(splats);
-    if (n_touched) {
-        switch (variant) {
-        case QB_RENDER_2PX: QB_LAUNCH((k_render<2, true>), tiles, 128, 0, s, (int)width, (int)height, tiles_x, rg, ids,
-                                      sp, bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
-        case QB_RENDER_1PX: QB_LAUNCH((k_render<1, true>), tiles, 256, 0, s, (int)width, (int)height, tiles_x, rg, ids,
-                                      sp, bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
-        default: QB_LAUNCH((k_render<4, true>), tiles, 64, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0],
-                           bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
-        }
-    } else {
-        switch (variant) {
-        case QB_RENDER_2PX: QB_LAUNCH((k_render<2, false>), tiles, 128, 0, s, (int)width, (int)height, tiles_x, rg,
-                                      ids, sp, bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
-        case QB_RENDER_1PX: QB_LAUNCH((k_render<1, false>), tiles, 256, 0, s, (int)width, (int)height, tiles_x, rg,
-                                      ids, sp, bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
-        default: QB_LAUNCH((k_render<4, false>), tiles, 64, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp,
-                           bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
-        }
-    }
-    return QB_OK;
+    if (n_touched)
+        return launch_render<true>(variant, tiles, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg, image, final_T,
+                                   n_contrib, n_touched);
+    return launch_render<false>(variant, tiles, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg, image, final_T,
+                                n_contrib, n_touched);
 }
 
 extern "C" qb_status qb_render(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
@@ -219,9 +269,11 @@ extern "C" qb_status qb_render_views_ex(int32_t num_views, const qb_view* views,
     if (tiles == 0) return QB_OK;
     hipStream_t s = qb_hip_stream(stream);
     switch (variant) {
-    case QB_RENDER_2PX: QB_LAUNCH(k_render_views<2>, tiles, 128, 0, s, vt, bg[0], bg[1], bg[2]); break;
-    case QB_RENDER_1PX: QB_LAUNCH(k_render_views<1>, tiles, 256, 0, s, vt, bg[0], bg[1], bg[2]); break;
-    default: QB_LAUNCH(k_render_views<4>, tiles, 64, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_2PX: QB_LAUNCH((k_render_views<2, false>), tiles, 128, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_1PX: QB_LAUNCH((k_render_views<1, false>), tiles, 256, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_4PX: QB_LAUNCH((k_render_views<4, false>), tiles, 64, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_2PX_ROWS: QB_LAUNCH((k_render_views<2, true>), tiles, 128, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    default: QB_LAUNCH((k_render_views<1, true>), tiles, 256, 0, s, vt, bg[0], bg[1], bg[2]); break;
     }
     return QB_OK;
 }

@@ -22,8 +22,10 @@ SPLAT_FLOATS = 12   # qb_splat: u v depth o | a b c gamma | r g b visible
 RECT_SHORTS = 16    # qb_rects: 4 x (tx0, tx1, ty0, ty1)
 
 QB_OK, QB_ERR_INVALID_ARG, QB_ERR_CAPACITY, QB_ERR_HIP, QB_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
-# render launch shapes (qb_render_variant): pixels per lane of a tile row
-RENDER_VARIANTS = {"2px": 0, "1px": 1, "4px": 2}
+# render launch shapes (qb_render_variant): pixels per lane of a tile row, and
+# (_rows) whether waves drop batch entries whose ellipse misses their rows
+RENDER_VARIANTS = {"2px": 0, "1px": 1, "4px": 2, "2px_rows": 3, "1px_rows": 4}
+BACKWARD_VARIANTS = {"2px": 0, "1px": 1, "4px": 2}
 
 
 class QBError(RuntimeError):
@@ -499,7 +501,7 @@ def autotune_backward(run, bg=(0.0, 0.0, 0.0), dl=None, grad2d=None, reps=5, tri
     after forward given dl [3, H, W] and a grad2d [n, 9] buffer -- keeps the
     fastest in run.backward_variant and returns {shape: ms}."""
     times = {}
-    for name, v in RENDER_VARIANTS.items():
+    for name, v in BACKWARD_VARIANTS.items():
         if isinstance(run, MultiView):
             fn = (lambda v=v: render_backward_views(run._table, run.V, bg, run.n, v))
         else:
@@ -507,7 +509,7 @@ def autotune_backward(run, bg=(0.0, 0.0, 0.0), dl=None, grad2d=None, reps=5, tri
                                               run.n_contrib, dl, run.n, grad2d, v))
         times[name] = _best(fn, reps, trials)
     pick = min(times, key=times.get)
-    run.backward_variant = RENDER_VARIANTS[pick]
+    run.backward_variant = BACKWARD_VARIANTS[pick]
     return times
 
 

@@ -109,7 +109,7 @@ def test_rotated_camera_background(oracle, qb, shape):
     bg = (0.3, 0.2, 0.1)
     say("rotated", shape)
     mask = decided_mask(oracle, scene, cam, bg=bg)
-    G, dl = gpu_grads(qb, scene, cam, target, bg, mask=mask, variant=qb.RENDER_VARIANTS[shape])
+    G, dl = gpu_grads(qb, scene, cam, target, bg, mask=mask, variant=qb.BACKWARD_VARIANTS[shape])
     G_ref = oracle.backward64(scene, cam, dl, bg)
     compare(G, G_ref, "rotated")
 
