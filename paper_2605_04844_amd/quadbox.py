@@ -14,7 +14,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libquadbox.so")
+# QB_LIBRARY selects another build of the library (e.g. one built with other
+# tile shapes); the default is the in-tree build
+LIB_PATH = os.environ.get("QB_LIBRARY", os.path.join(HERE, "libquadbox.so"))
 
 BOX_MODES = {"3sigma": 0, "adr": 1, "quadbox": 2, "dualbox": 3, "quadbox_naive": 4}
 TILE = 16
