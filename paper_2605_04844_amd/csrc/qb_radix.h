@@ -14,6 +14,9 @@
 //               then written out as contiguous runs (coalesced stores).
 #pragma once
 
+#include <climits>
+#include <type_traits>
+
 #include "qb_common.h"
 
 namespace qbr {
@@ -29,28 +32,54 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kFusedBlocks = 320;
 
-// Inclusive scan across one wave64 (Hillis-Steele over lane shuffles).
+// DPP lane shift within the wave (update_dpp with `identity` where the
+// source lane falls outside the row or the row is masked off).  Controls:
+// 0x111/0x112/0x114/0x118 = row_shr 1/2/4/8 (rows of 16 lanes), 0x142 =
+// row_bcast 15 (lane 15 of each row to the next row; rows 1 and 3 written),
+// 0x143 = row_bcast 31 (lane 31 to rows 2 and 3).  Every lane of the wave
+// must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_shift(int v, int identity)
+{
+    return __builtin_amdgcn_update_dpp(identity, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// Inclusive scan across one wave64.  32-bit integers: Hillis-Steele within
+// rows of 16 by DPP row shifts, then the row broadcasts (six full-rate VALU
+// adds).  64-bit: over lane shuffles.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T v)
 {
-    int lane = threadIdx.x & 63;
+    static_assert(std::is_integral<T>::value, "integer scans only");
+    if constexpr (sizeof(T) == 4) {
+        int x = (int)v;
+        x += dpp_shift<0x111, 0xF>(x, 0);
+        x += dpp_shift<0x112, 0xF>(x, 0);
+        x += dpp_shift<0x114, 0xF>(x, 0);
+        x += dpp_shift<0x118, 0xF>(x, 0);
+        x += dpp_shift<0x142, 0xA>(x, 0);
+        x += dpp_shift<0x143, 0xC>(x, 0);
+        return (T)x;
+    } else {
+        int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        T o = __shfl_up(v, off, 64);
-        if (lane >= off) v += o;
+        for (int off = 1; off < 64; off <<= 1) {
+            T o = __shfl_up(v, off, 64);
+            if (lane >= off) v += o;
+        }
+        return v;
     }
-    return v;
 }
 
-// Inclusive running maximum across one wave64.
+// Inclusive running maximum across one wave64 (DPP, as above).
 __device__ __forceinline__ int wave_inclusive_max(int v)
 {
-    int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int o = __shfl_up(v, off, 64);
-        if (lane >= off) v = max(v, o);
-    }
+    v = max(v, dpp_shift<0x111, 0xF>(v, INT_MIN));
+    v = max(v, dpp_shift<0x112, 0xF>(v, INT_MIN));
+    v = max(v, dpp_shift<0x114, 0xF>(v, INT_MIN));
+    v = max(v, dpp_shift<0x118, 0xF>(v, INT_MIN));
+    v = max(v, dpp_shift<0x142, 0xA>(v, INT_MIN));
+    v = max(v, dpp_shift<0x143, 0xC>(v, INT_MIN));
     return v;
 }
 
