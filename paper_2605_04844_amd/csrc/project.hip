@@ -92,15 +92,75 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t 
     for (int ch = 0; ch < 3; ++ch) rgb[ch] = acc[ch] > 0.0f ? acc[ch] : 0.0f;
 }
 
-// Projects Gaussian i for one camera and writes its splat, rects and count.
-__device__ __forceinline__ void project_one(int64_t i, int64_t n, const float* __restrict__ means,
-                                            const float* __restrict__ log_scales, const float* __restrict__ quats,
-                                            const float* __restrict__ logits, const float* __restrict__ sh,
-                                            int sh_degree, const ProjCam& cam, int mode,
-                                            float4* __restrict__ out_splat, int4* __restrict__ out_rects,
-                                            int32_t* __restrict__ out_count)
+// View-independent part of one Gaussian: the activations (binary64, rounded
+// once), the unit quaternion (binary32) and Sigma3D = M M^T with
+// M = R(q) diag(s) in binary64 (6 unique entries: S00 S01 S02 S11 S12 S22).
+struct GaussPre {
+    float o, gam;
+    double S[6];
+    bool ok;   // false for a zero or non-finite quaternion: culled in every view
+};
+
+__device__ __forceinline__ void gauss_pre(int64_t i, int64_t n, const float* __restrict__ log_scales,
+                                          const float* __restrict__ quats, const float* __restrict__ logits,
+                                          GaussPre& g)
 {
-    float mx = means[i], my = means[n + i], mz = means[2 * n + i];
+    float sx = (float)exp((double)log_scales[i]);
+    float sy = (float)exp((double)log_scales[n + i]);
+    float sz = (float)exp((double)log_scales[2 * n + i]);
+    g.o = (float)(1.0 / (1.0 + exp(-(double)logits[i])));
+    g.gam = (float)(2.0 * log(255.0 * (double)g.o));
+    float qw = quats[i], qx = quats[n + i], qy = quats[2 * n + i], qz = quats[3 * n + i];
+    float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    g.ok = n2 > 0.0f && isfinite(n2);
+    if (!g.ok) return;
+    float nr = sqrtf(n2);
+    float w = qw / nr, x = qx / nr, y = qy / nr, z = qz / nr;
+    // Sigma3D, the EWA projection and the conic in binary64, each result
+    // rounded once to binary32: for needle-like Gaussians Sigma2D is nearly
+    // singular (condition up to ~1e6), and binary32 entries would lose up to
+    // a percent of the conic to cancellation in A C - B^2.
+    double dw = w, dxq = x, dyq = y, dzq = z;
+    double Rq[9];
+    Rq[0] = 1.0 - 2.0 * (dyq * dyq + dzq * dzq);
+    Rq[1] = 2.0 * (dxq * dyq - dw * dzq);
+    Rq[2] = 2.0 * (dxq * dzq + dw * dyq);
+    Rq[3] = 2.0 * (dxq * dyq + dw * dzq);
+    Rq[4] = 1.0 - 2.0 * (dxq * dxq + dzq * dzq);
+    Rq[5] = 2.0 * (dyq * dzq - dw * dxq);
+    Rq[6] = 2.0 * (dxq * dzq - dw * dyq);
+    Rq[7] = 2.0 * (dyq * dzq + dw * dxq);
+    Rq[8] = 1.0 - 2.0 * (dxq * dxq + dyq * dyq);
+    double M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        M[r * 3 + 0] = Rq[r * 3 + 0] * (double)sx;
+        M[r * 3 + 1] = Rq[r * 3 + 1] * (double)sy;
+        M[r * 3 + 2] = Rq[r * 3 + 2] * (double)sz;
+    }
+    int k = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = r; c < 3; ++c)
+            g.S[k++] = (M[r * 3 + 0] * M[c * 3 + 0] + M[r * 3 + 1] * M[c * 3 + 1]) + M[r * 3 + 2] * M[c * 3 + 2];
+}
+
+// Sigma3D entry (r, c) from the 6 stored (symmetric: the products of (r, c)
+// and (c, r) are the same, summed in the same order).
+__device__ __forceinline__ double s3(const GaussPre& g, int r, int c)
+{
+    int lo = r < c ? r : c, hi = r < c ? c : r;
+    return g.S[lo == 0 ? hi : (lo == 1 ? 2 + hi : 5)];
+}
+
+// Projects Gaussian i (mean mx, my, mz; view-independent part g) for one
+// camera and writes its splat, rects and count.
+__device__ __forceinline__ void project_view(int64_t i, int64_t n, float mx, float my, float mz, const GaussPre& g,
+                                             const float* __restrict__ sh, int sh_degree, const ProjCam& cam, int mode,
+                                             float4* __restrict__ out_splat, int4* __restrict__ out_rects,
+                                             int32_t* __restrict__ out_count)
+{
     const float* R = cam.R;
     float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + cam.t[0];
     float py = ((R[3] * mx + R[4] * my) + R[5] * mz) + cam.t[1];
@@ -110,50 +170,11 @@ __device__ __forceinline__ void project_one(int64_t i, int64_t n, const float* _
            s2 = make_float4(0.f, 0.f, 0.f, 0.f);
     QRect rr[4] = {{1, 0, 1, 0}, {1, 0, 1, 0}, {1, 0, 1, 0}, {1, 0, 1, 0}};
     int count = 0;
-    bool vis = false;
 
     do {
         if (!(pz > cam.near_plane) || !isfinite(px) || !isfinite(py) || !isfinite(pz)) break;
-        float sx = (float)exp((double)log_scales[i]);
-        float sy = (float)exp((double)log_scales[n + i]);
-        float sz = (float)exp((double)log_scales[2 * n + i]);
-        float o = (float)(1.0 / (1.0 + exp(-(double)logits[i])));
-        float gam = (float)(2.0 * log(255.0 * (double)o));
-
-        float qw = quats[i], qx = quats[n + i], qy = quats[2 * n + i], qz = quats[3 * n + i];
-        float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
-        if (!(n2 > 0.0f) || !isfinite(n2)) break;
-        float nr = sqrtf(n2);
-        float w = qw / nr, x = qx / nr, y = qy / nr, z = qz / nr;
-        // Sigma3D, the EWA projection and the conic in binary64, each result
-        // rounded once to binary32: for needle-like Gaussians Sigma2D is
-        // nearly singular (condition up to ~1e6), and binary32 entries would
-        // lose up to a percent of the conic to cancellation in A C - B^2.
-        double dw = w, dxq = x, dyq = y, dzq = z;
-        double Rq[9];
-        Rq[0] = 1.0 - 2.0 * (dyq * dyq + dzq * dzq);
-        Rq[1] = 2.0 * (dxq * dyq - dw * dzq);
-        Rq[2] = 2.0 * (dxq * dzq + dw * dyq);
-        Rq[3] = 2.0 * (dxq * dyq + dw * dzq);
-        Rq[4] = 1.0 - 2.0 * (dxq * dxq + dzq * dzq);
-        Rq[5] = 2.0 * (dyq * dzq - dw * dxq);
-        Rq[6] = 2.0 * (dxq * dzq - dw * dyq);
-        Rq[7] = 2.0 * (dyq * dzq + dw * dxq);
-        Rq[8] = 1.0 - 2.0 * (dxq * dxq + dyq * dyq);
-        double M[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            M[r * 3 + 0] = Rq[r * 3 + 0] * (double)sx;
-            M[r * 3 + 1] = Rq[r * 3 + 1] * (double)sy;
-            M[r * 3 + 2] = Rq[r * 3 + 2] * (double)sz;
-        }
-        double S[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                S[r * 3 + c] = (M[r * 3 + 0] * M[c * 3 + 0] + M[r * 3 + 1] * M[c * 3 + 1]) +
-                               M[r * 3 + 2] * M[c * 3 + 2];
+        if (!g.ok) break;
+        float o = g.o, gam = g.gam;
 
         // Jacobian at the view-space mean with its image-plane slope clamped
         // to 1.3x the half field of view (binary32 slope, binary64 Jacobian)
@@ -175,8 +196,7 @@ __device__ __forceinline__ void project_one(int64_t i, int64_t n, const float* _
         for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                U[r * 3 + c] = (T[r * 3 + 0] * S[0 * 3 + c] + T[r * 3 + 1] * S[1 * 3 + c]) +
-                               T[r * 3 + 2] * S[2 * 3 + c];
+                U[r * 3 + c] = (T[r * 3 + 0] * s3(g, 0, c) + T[r * 3 + 1] * s3(g, 1, c)) + T[r * 3 + 2] * s3(g, 2, c);
         double A64 = ((U[0] * T[0] + U[1] * T[1]) + U[2] * T[2]) + 0.3;
         double B64 = (U[0] * T[3] + U[1] * T[4]) + U[2] * T[5];
         double C64 = ((U[3] * T[3] + U[4] * T[4]) + U[5] * T[5]) + 0.3;
@@ -247,9 +267,7 @@ __device__ __forceinline__ void project_one(int64_t i, int64_t n, const float* _
         s0 = make_float4(u, v, pz, o);
         s1 = make_float4(ca, cb, cc, gam);
         s2 = make_float4(rgb[0], rgb[1], rgb[2], 1.0f);
-        vis = true;
     } while (0);
-    (void)vis;
 
     out_splat[3 * i + 0] = s0;
     out_splat[3 * i + 1] = s1;
@@ -266,6 +284,19 @@ __device__ __forceinline__ void project_one(int64_t i, int64_t n, const float* _
     out_rects[2 * i + 0] = p0;
     out_rects[2 * i + 1] = p1;
     out_count[i] = count;
+}
+
+__device__ __forceinline__ void project_one(int64_t i, int64_t n, const float* __restrict__ means,
+                                            const float* __restrict__ log_scales, const float* __restrict__ quats,
+                                            const float* __restrict__ logits, const float* __restrict__ sh,
+                                            int sh_degree, const ProjCam& cam, int mode,
+                                            float4* __restrict__ out_splat, int4* __restrict__ out_rects,
+                                            int32_t* __restrict__ out_count)
+{
+    GaussPre g;
+    gauss_pre(i, n, log_scales, quats, logits, g);
+    project_view(i, n, means[i], means[n + i], means[2 * n + i], g, sh, sh_degree, cam, mode, out_splat, out_rects,
+                 out_count);
 }
 
 __global__ __launch_bounds__(QB_BLOCK) void k_project(
@@ -285,18 +316,23 @@ struct ProjCamTable {
     ProjCam cam[QB_MAX_VIEWS];
 };
 
-// blockIdx.y is the view; view v writes the block of records starting at v*n.
+// One lane per Gaussian: the view-independent part once, then every view
+// (view v writes the block of records starting at v*n).  Per view the same
+// arithmetic as k_project, so the records are identical.
 __global__ __launch_bounds__(QB_BLOCK) void k_project_views(
-    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    int64_t n, int nv, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int sh_degree, ProjCamTable cams, int mode,
     float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
 {
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
-    int64_t v = blockIdx.y;
-    project_one(i, n, means, log_scales, quats, logits, sh, sh_degree, cams.cam[v], mode, out_splat + 3 * v * n,
-                out_rects + 2 * v * n, out_count + v * n);
+    GaussPre g;
+    gauss_pre(i, n, log_scales, quats, logits, g);
+    float mx = means[i], my = means[n + i], mz = means[2 * n + i];
+    for (int v = 0; v < nv; ++v)
+        project_view(i, n, mx, my, mz, g, sh, sh_degree, cams.cam[v], mode, out_splat + 3 * (int64_t)v * n,
+                     out_rects + 2 * (int64_t)v * n, out_count + (int64_t)v * n);
 }
 
 }  // namespace
@@ -369,8 +405,8 @@ extern "C" qb_status qb_project_views(int64_t n, const float* means, const float
     if (!means || !log_scales || !quats || !opacity_logits || !sh || !out_splats || !out_rects ||
         !out_counts)
         return QB_ERR_INVALID_ARG;
-    QB_LAUNCH(k_project_views, dim3((unsigned)qb_div_up(n, QB_BLOCK), (unsigned)num_views), QB_BLOCK, 0,
-              qb_hip_stream(stream), n, means, log_scales, quats, opacity_logits, sh, (int)sh_degree, ct, (int)mode,
+    QB_LAUNCH(k_project_views, qb_div_up(n, QB_BLOCK), QB_BLOCK, 0, qb_hip_stream(stream), n, (int)num_views, means,
+              log_scales, quats, opacity_logits, sh, (int)sh_degree, ct, (int)mode,
               reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects), out_counts);
     return QB_OK;
 }
