@@ -85,3 +85,43 @@ def test_intersect_sort_render_reject_bad_arguments():
     assert L.qb_sort(100, None, 12, d, d, d, d, C.c_void_p(512), d, d, sws, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_render(0, 48, d, d, d, d, d, None, None, None, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_render(64, 48, None, d, d, d, d, None, None, None, None) == qb.QB_ERR_INVALID_ARG
+
+
+def test_launch_shape_and_view_entry_points_reject_bad_arguments():
+    L = qb.lib()
+    d = C.c_void_p(256)
+    bg = (C.c_float * 3)(0.0, 0.0, 0.0)
+    bgp = C.cast(bg, C.c_void_p)
+    # launch shapes out of range
+    assert L.qb_render_ex(64, 48, d, d, d, bgp, d, None, None, None, 5, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_ex(64, 48, d, d, d, bgp, d, None, None, None, -1, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_backward_ex(64, 48, d, d, d, bgp, d, d, d, 10, d, 3, None) == qb.QB_ERR_INVALID_ARG
+    # view tables: count, null table, bad sizes, missing buffers
+    views = (qb.CView * (qb.MAX_VIEWS + 1))()
+    for v in views:
+        v.width, v.height = 64, 48
+        v.ranges = v.ids = v.splats = v.image = v.final_T = v.n_contrib = v.dL_dimage = v.grad2d = 256
+    assert L.qb_render_views(0, views, bgp, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_views(qb.MAX_VIEWS + 1, views, bgp, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_views(1, None, bgp, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_views_ex(1, views, bgp, 9, None) == qb.QB_ERR_INVALID_ARG
+    views[1].width = 0
+    assert L.qb_render_views(2, views, bgp, None) == qb.QB_ERR_INVALID_ARG
+    views[1].width = 64
+    views[1].image = None
+    assert L.qb_render_views(2, views, bgp, None) == qb.QB_ERR_INVALID_ARG
+    views[1].dL_dimage = None
+    assert L.qb_render_backward_views(2, views, bgp, 10, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_backward_views_ex(1, views, bgp, 10, 4, None) == qb.QB_ERR_INVALID_ARG
+    cams = (qb.CCamera * (qb.MAX_VIEWS + 1))(*[_cam() for _ in range(qb.MAX_VIEWS + 1)])
+    assert L.qb_project_views(10, d, d, d, d, d, 0, cams, 0, 2, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_project_views(10, d, d, d, d, d, 0, cams, qb.MAX_VIEWS + 1, 2, d, d, d, None) == \
+        qb.QB_ERR_INVALID_ARG
+    assert L.qb_project_views(10, d, d, d, d, d, 0, cams, 2, 7, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    cams[1].fx = 0.0
+    assert L.qb_project_views(10, d, d, d, d, d, 0, cams, 2, 2, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_project_backward_views(10, d, d, d, d, d, 0, cams, 2, d, d, d, d, d, d, d, None) == \
+        qb.QB_ERR_INVALID_ARG
+    cams[1].fx = 64.0
+    assert L.qb_project_backward_views(10, d, d, d, d, d, 4, cams, 2, d, d, d, d, d, d, d, None) == \
+        qb.QB_ERR_INVALID_ARG

@@ -208,3 +208,27 @@ def test_views_full_size_matches_single_view(qb):
         torch.cuda.synchronize()
         for a, b in zip(mv.images, want):
             assert torch.equal(a, b), name
+
+
+def test_views_capacity_overflow(qb):
+    """A view whose pair count exceeds its capacity renders empty (background)
+    and is reported by overflowed(); the other views are unaffected."""
+    scene, cams = small_views()
+    bg = (0.3, 0.6, 0.9)
+    g = qb.Gaussians(scene)
+    mv = qb.MultiView(scene.n, cams)
+    mv.size_pairs(g, "quadbox")
+    mv.forward(g, bg)
+    torch.cuda.synchronize()
+    want = [x.clone() for x in mv.images]
+    assert not mv.overflowed()
+    mv.capacity[1] = 256
+    mv.forward(g, bg)
+    torch.cuda.synchronize()
+    assert mv.overflowed()
+    empty = torch.tensor(bg, device="cuda", dtype=torch.float32)[:, None, None].expand_as(mv.images[1])
+    assert torch.equal(mv.images[1], empty)
+    for v in range(mv.V):
+        if v != 1:
+            assert torch.equal(mv.images[v], want[v]), v
+    say("overflowed view renders the background; the others are unchanged")
