@@ -24,8 +24,10 @@ namespace {
 
 // Sum over the 64 lanes of a wave, returned to every lane.  Rows of 16 are
 // reduced with four DPP adds (neighbour, pair of neighbours, half-row mirror,
-// row mirror), then the four row sums are read with v_readlane.  Every lane
-// of the wave must be active.
+// row mirror: every lane of a row then holds the row sum), the row sums are
+// chained by the row broadcasts 15 (rows 1, 3) and 31 (rows 2, 3), and lane
+// 63's total is read with one v_readlane.  Every lane of the wave must be
+// active.
 __device__ __forceinline__ float dpp_add(float v, int ctrl_sel)
 {
     int x = __float_as_int(v);
@@ -34,7 +36,9 @@ __device__ __forceinline__ float dpp_add(float v, int ctrl_sel)
     case 0: y = __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
     case 1: y = __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
     case 2: y = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
-    default: y = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false); break; // row_mirror
+    case 3: y = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false); break;  // row_mirror
+    case 4: y = __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false); break;  // row_bcast 15
+    default: y = __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false); break; // row_bcast 31
     }
     return v + __int_as_float(y);
 }
@@ -45,14 +49,10 @@ __device__ __forceinline__ float wave_sum(float v)
     v = dpp_add(v, 1);
     v = dpp_add(v, 2);
     v = dpp_add(v, 3);
-    int x = __float_as_int(v);
-    float r0 = __int_as_float(__builtin_amdgcn_readlane(x, 0));
-    float r1 = __int_as_float(__builtin_amdgcn_readlane(x, 16));
-    float r2 = __int_as_float(__builtin_amdgcn_readlane(x, 32));
-    float r3 = __int_as_float(__builtin_amdgcn_readlane(x, 48));
-    return (r0 + r1) + (r2 + r3);
+    v = dpp_add(v, 4);
+    v = dpp_add(v, 5);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
-
 
 // Backward of one tile of one image: 256 / PPL lanes, each owning PPL pixels
 // of one tile row, 16 / PPL apart.  The list is walked back to front from the
