@@ -374,18 +374,23 @@ class MultiView:
     buffers are sized (size_pairs); a frame whose pair count exceeds its
     view's capacity renders that view empty (check overflowed())."""
 
-    def __init__(self, n: int, cams, device="cuda"):
+    def __init__(self, n: int, cams, device="cuda", streams: int = 4):
         self.V = len(cams)
         if not 1 <= self.V <= MAX_VIEWS:
             raise ValueError(f"1..{MAX_VIEWS} views per MultiView")
         self.n, self.cams, self.device = n, list(cams), device
+        # the per-view intersect and sort chains are independent: views go
+        # round-robin to `streams` side streams (default priority), each with
+        # its own workspaces, and join the caller's stream before the render
+        self.S = max(1, min(int(streams), self.V))
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(self.S)] if self.S > 1 else []
         self.cam_array = (CCamera * self.V)(*[camera_struct(c) for c in cams])
         d, V, n1 = device, self.V, max(n, 1)
         self.splats = torch.empty((V, n1, SPLAT_FLOATS), dtype=torch.float32, device=d)
         self.rects = torch.empty((V, n1, RECT_SHORTS), dtype=torch.int16, device=d)
         self.counts = torch.empty((V, n1), dtype=torch.int32, device=d)
         self.num_pairs = torch.zeros(V, dtype=torch.int64, device=d)
-        self.ws_isect = torch.empty(intersect_workspace_size(n), dtype=torch.uint8, device=d)
+        self.ws_isect = [torch.empty(intersect_workspace_size(n), dtype=torch.uint8, device=d) for _ in range(self.S)]
         self.sizes = [(int(c.width), int(c.height)) for c in cams]
         self.num_tiles = [int(c.tiles_x * c.tiles_y) for c in cams]
         self.ranges = [torch.zeros(2 * t, dtype=torch.int32, device=d) for t in self.num_tiles]
@@ -409,7 +414,7 @@ class MultiView:
         w, h = self.sizes[v]
         cap = self.capacity[v]
         intersect(self.n, s, r, c, w, h, cap, self.pair_tiles[v] if cap else None,
-                  self.pair_ids[v] if cap else None, npairs, self.ws_isect, self.mode)
+                  self.pair_ids[v] if cap else None, npairs, self.ws_isect[v % self.S], self.mode)
 
     def size_pairs(self, g: Gaussians, mode="quadbox", slack=1.1):
         """Runs the projection and counting once (one host synchronisation)
@@ -436,7 +441,8 @@ class MultiView:
             self.ids_sorted.append(flat_s[o:o + cap])
             o += cap
         self._flat = (flat_t, flat_i, flat_s)
-        self.ws_sort = torch.empty(max(sort_workspace_size(c) for c in self.capacity), dtype=torch.uint8, device=d)
+        self.ws_sort = [torch.empty(max(sort_workspace_size(c) for c in self.capacity), dtype=torch.uint8, device=d)
+                        for _ in range(self.S)]
         views = (CView * self.V)()
         for v in range(self.V):
             w, h = self.sizes[v]
@@ -452,14 +458,33 @@ class MultiView:
         self._table = views
         return counts
 
+    def _per_view(self, fn):
+        """Runs fn(v) for every view, round-robin over the side streams
+        (forked from and joined back into the current stream)."""
+        if not self.streams:
+            for v in range(self.V):
+                fn(v)
+            return
+        main = torch.cuda.current_stream()
+        for st in self.streams:
+            st.wait_stream(main)
+        for v in range(self.V):
+            with torch.cuda.stream(self.streams[v % self.S]):
+                fn(v)
+        for st in self.streams:
+            main.wait_stream(st)
+
     def forward(self, g: Gaussians, bg=(0.0, 0.0, 0.0)):
         if self._table is None:
             raise RuntimeError("call size_pairs() first")
         project_views(g, self.cam_array, self.V, self.mode, self.splats, self.rects, self.counts)
-        for v in range(self.V):
+
+        def prep(v):
             self._intersect(v)
             sort(self.capacity[v], self.num_pairs[v:v + 1], self.num_tiles[v], self.pair_tiles[v], self.pair_ids[v],
-                 self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort)
+                 self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort[v % self.S])
+
+        self._per_view(prep)
         render_views(self._table, self.V, bg, self.render_variant)
         return self.images
 
