@@ -95,27 +95,9 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
         uint32_t idx0 = (uint32_t)(base - start);
         // one list entry k of the batch for every pixel of the lane; returns
         // true when the whole wave has stopped
-        auto entry = [&](int k) -> bool {
-            float4 g = s_geo[k];
-            float4 o = s_opa[k];
-            // the terms of the quadratic form that depend on the row only
-            float dy = g.y - fy;
-            float nbdy = g.w * dy;
-            float hcdy2 = (o.x * dy) * dy;
-            float p[PPL];
-            bool act[PPL];
-            bool any = false;
-#pragma unroll
-            for (int q = 0; q < PPL; ++q) {
-                float dx = g.x - fxp[q];
-                p[q] = fmaf(fmaf(g.z, dx, nbdy), dx, hcdy2);
-                act[q] = !done[q] && !(p[q] > 0.0f || p[q] < o.z);
-                any = any || act[q];
-            }
-            // branch only when the whole wave agrees; per pixel, select
-            if (!__any(any)) return false;
-            float4 col = s_col[k];
-            uint32_t at = idx0 + (uint32_t)k + 1u;
+        // composites one entry (opacity in o.y, colour col, list position
+        // at) into the lane's pixels whose power p passed (act)
+        auto composite = [&](const float4& o, const float4& col, const float* p, const bool* act, uint32_t at) {
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
                 float alpha = fminf(0.99f, o.y * __expf(p[q]));
@@ -131,6 +113,49 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
                 if (COUNT) stop[q] = stp ? at : stop[q];
                 done[q] = done[q] || stp;
             }
+        };
+        // the cutoff test of entry k for the lane's pixels; returns whether any passed
+        auto test = [&](int k, float4& g, float4& o, float* p, bool* act) -> bool {
+            g = s_geo[k];
+            o = s_opa[k];
+            // the terms of the quadratic form that depend on the row only
+            float dy = g.y - fy;
+            float nbdy = g.w * dy;
+            float hcdy2 = (o.x * dy) * dy;
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                float dx = g.x - fxp[q];
+                p[q] = fmaf(fmaf(g.z, dx, nbdy), dx, hcdy2);
+                act[q] = !done[q] && !(p[q] > 0.0f || p[q] < o.z);
+                any = any || act[q];
+            }
+            return any;
+        };
+        // one list entry k of the batch; returns true when the whole wave has stopped
+        auto entry = [&](int k) -> bool {
+            float4 g, o;
+            float p[PPL];
+            bool act[PPL];
+            bool any = test(k, g, o, p, act);
+            // branch only when the whole wave agrees; per pixel, select
+            if (!__any(any)) return false;
+            composite(o, s_col[k], p, act, idx0 + (uint32_t)k + 1u);
+            return __all(all_done());
+        };
+        // entries k and k + 1: both tests first (independent), one uniform
+        // branch for the pair, then the two composites in list order
+        auto entry2 = [&](int k) -> bool {
+            float4 ga, oa, gb, ob;
+            float pa[PPL], pb[PPL];
+            bool acta[PPL], actb[PPL];
+            bool any = test(k, ga, oa, pa, acta);
+            any = test(k + 1, gb, ob, pb, actb) || any;
+            if (!__any(any)) return false;
+            composite(oa, s_col[k], pa, acta, idx0 + (uint32_t)k + 1u);
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) actb[q] = actb[q] && !done[q];   // a pixel may have stopped at k
+            composite(ob, s_col[k + 1], pb, actb, idx0 + (uint32_t)k + 2u);
             return __all(all_done());
         };
         if (kSkip) {
@@ -163,8 +188,11 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             }
         } else {
             if (all_done()) continue;
-            for (int k = 0; k < cnt; ++k)
-                if (entry(k)) break;
+            bool finished = false;
+            int k = 0;
+            for (; k + 1 < cnt; k += 2)
+                if (entry2(k)) { finished = true; break; }
+            if (!finished && k < cnt) entry(k);
         }
     }
     uint32_t len = (uint32_t)(end - start);
