@@ -310,3 +310,24 @@ def test_render_launch_shapes_identical(oracle, qb):
     assert r.render_variant in qb.RENDER_VARIANTS.values()
     torch.cuda.synchronize()
     assert torch.equal(r.image, outs["2px"][0])
+
+
+@pytest.mark.parametrize("mode", ["quadbox", "3sigma", "adr"])
+def test_degenerate_inputs(oracle, qb, mode):
+    """Zero and non-finite quaternions, NaN means, scales that overflow
+    Sigma2D, vanishing and saturated opacities, on a one-pixel image, a
+    ragged 17x15 image and a normal one: every culling decision and every
+    surviving record bit-exact with the oracle."""
+    scene, _ = scenes.random_scene(110, 400, 64, 48, 64.0, sh_degree=1)
+    n = scene.n
+    scene.quats[:, 0:10] = 0.0                       # zero quaternion
+    scene.quats[1, 10:15] = np.nan                   # NaN quaternion
+    scene.means[0, 15:20] = np.nan                   # NaN mean
+    scene.log_scales[:, 20:30] = 60.0                # Sigma2D overflows binary32
+    scene.log_scales[:, 30:40] = -30.0               # vanishing scale (only the 0.3 low-pass)
+    scene.logits[40:60] = -40.0                      # opacity below 1/255
+    scene.logits[60:80] = 40.0                       # opacity 1
+    assert n == 400
+    for w, h in [(1, 1), (17, 15), (64, 48)]:
+        cam = scenes.pinhole(w, h, 64.0)
+        full_check(oracle, qb, scene, cam, mode, bg=(0.1, 0.2, 0.3))
