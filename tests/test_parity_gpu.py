@@ -331,3 +331,35 @@ def test_degenerate_inputs(oracle, qb, mode):
     for w, h in [(1, 1), (17, 15), (64, 48)]:
         cam = scenes.pinhole(w, h, 64.0)
         full_check(oracle, qb, scene, cam, mode, bg=(0.1, 0.2, 0.3))
+
+
+def test_activation_sweep(oracle, qb):
+    """o = RN32(sigmoid(x)) and gamma = RN32(2 ln(255 o)) (binary64, rounded
+    once), and the opacity cull gamma <= 0, through qb_project for 2^22
+    logits: 2^21 consecutive binary32 values centred on the cull boundary
+    x = -ln 254 and 2^21 values spread over [-6, 17].  Bit-exact with the
+    oracle (both sides evaluate the transcendentals in binary64 with their
+    own libraries; a last-ulp difference near a binary32 rounding boundary
+    would show up here)."""
+    n = 1 << 22
+    half = n // 2
+    x0 = np.float32(-np.log(254.0))
+    bits0 = np.int64(x0.view(np.int32))
+    # negative floats: larger bit patterns are more negative; centre the run on x0
+    near = (bits0 + np.arange(-half // 2, half // 2, dtype=np.int64)).astype(np.int32).view(np.float32)
+    spread = np.linspace(-6.0, 17.0, half).astype(np.float32)
+    logits = np.concatenate([near, spread]).astype(np.float32)
+    scene, _ = scenes.random_scene(120, n, 64, 48, 64.0, sh_degree=0, log_scale_mu=-3.0, log_scale_sd=0.1)
+    scene.means[:] = np.array([[0.0], [0.0], [3.0]], np.float32)
+    scene.logits[:] = logits
+    cam = scenes.pinhole(64, 48, 64.0)
+    gpu, _ = gpu_forward(qb, scene, cam, "quadbox")
+    g = oracle.project(scene, cam, "quadbox")
+    vis_o = g["visible"] == 1
+    vis_g = gpu["splats"][:, 11] == 1.0
+    assert np.array_equal(vis_o, vis_g), int((vis_o != vis_g).sum())
+    assert 0 < vis_o.sum() < n          # the cull boundary lies inside the sweep
+    for col, name in [(3, "opacity"), (7, "gamma")]:
+        diff = np.nonzero(bits(gpu["splats"][vis_o, col]) != bits(g[name][vis_o]))[0]
+        assert diff.size == 0, (name, diff.size)
+    say(f"activation sweep: {n} logits, {int(vis_o.sum())} above the cutoff, all bit-exact")
