@@ -3,7 +3,8 @@
 //  1. key every Gaussian by its depth bits (0xFFFFFFFF when it covers no
 //     tile) and stable-radix-sort the ids: the (depth, id) order that orders
 //     the Gaussians within every tile
-//  2. gather the tile counts in that order and scan them: the pair offsets
+//  2. gather the tile counts in that order (in the sort's last pass) and
+//     scan them: the pair offsets and the total
 //  3. emit: a 256-lane workgroup takes 256 consecutive Gaussians of that
 //     order and runs QPass for each (one lane per Gaussian); the non-empty
 //     runs (blocks of scanlines with one tile interval) go to a run list in
@@ -35,15 +36,6 @@ __global__ __launch_bounds__(QB_BLOCK) void k_depth_keys(int64_t n, const float4
     float d = splats[3 * i].z;
     keys[i] = counts[i] > 0 ? __float_as_uint(d) : 0xFFFFFFFFu;
     vals[i] = (uint32_t)i;
-}
-
-__global__ __launch_bounds__(QB_BLOCK) void k_gather_counts(int64_t n, const uint32_t* __restrict__ order,
-                                                            const int32_t* __restrict__ counts,
-                                                            uint32_t* __restrict__ out)
-{
-    int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
-    if (i >= n) return;
-    out[i] = (uint32_t)counts[order[i]];
 }
 
 __global__ void k_store_total(const uint64_t* __restrict__ tot, int64_t* __restrict__ num_pairs)
@@ -178,7 +170,6 @@ struct IsectWs {
     uint32_t *dk0, *dv0, *dk1, *dv1;  // depth sort ping-pong; dv0 ends as the order
     uint32_t* csorted;                // counts in that order
     uint64_t* offs;                   // pair offsets
-    uint64_t* total;
     uint64_t* scan64;
     uint32_t* radix;
 };
@@ -192,7 +183,6 @@ IsectWs carve(QbArena& a, int64_t n)
     w.dv1 = a.take<uint32_t>(n);
     w.csorted = a.take<uint32_t>(n);
     w.offs = a.take<uint64_t>(n + 1);
-    w.total = a.take<uint64_t>(1);
     w.scan64 = a.take<uint64_t>(qbr::scan_scratch(n));
     w.radix = a.take<uint32_t>((int64_t)(qbr::radix_scratch_bytes<kDepthNT, kDepthNI>(n) / sizeof(uint32_t)));
     return w;
@@ -235,11 +225,13 @@ extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_re
     int64_t grid = qb_div_up(n, QB_BLOCK);
     QB_LAUNCH(k_depth_keys, grid, QB_BLOCK, 0, s, n, reinterpret_cast<const float4*>(splats), counts, w.dk0, w.dv0);
     // four 8-bit passes: (dk0, dv0) -> (dk1, dv1) -> (dk0, dv0) -> ...
+    // (the last pass also gathers the tile counts in the sorted order)
     QB_CHECK((qbr::radix_sort<uint32_t, kDepthNT, kDepthNI>(w.dk0, w.dv0, w.dk0, w.dv0, w.dk1, w.dv1,
-                                                            (const int64_t*)nullptr, n, n, 0, 32, w.radix, s)));
-    QB_LAUNCH(k_gather_counts, grid, QB_BLOCK, 0, s, n, (const uint32_t*)w.dv0, counts, w.csorted);
-    QB_CHECK((qbr::exclusive_scan<uint32_t, uint64_t>(w.csorted, w.offs, n, w.scan64, w.total, s)));
-    QB_LAUNCH(k_store_total, 1, 1, 0, s, (const uint64_t*)w.total, num_pairs);
+                                                            (const int64_t*)nullptr, n, n, 0, 32, w.radix, s,
+                                                            counts, w.csorted)));
+    // pair offsets; the total (a count, below 2^63) lands in *num_pairs
+    QB_CHECK((qbr::exclusive_scan<uint32_t, uint64_t>(w.csorted, w.offs, n, w.scan64,
+                                                      reinterpret_cast<uint64_t*>(num_pairs), s)));
     if (pair_capacity > 0 && mode == QB_BOX_QUADBOX_NAIVE)
         QB_LAUNCH(k_emit_naive, grid, QB_BLOCK, 0, s, n, (const uint32_t*)w.dv0, (const uint64_t*)w.offs,
                   reinterpret_cast<const int4*>(rects), counts, tiles_x, pair_capacity, (const int64_t*)num_pairs,

@@ -129,13 +129,24 @@ __device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
 
 // Block scan of NT*NI items: coalesced load to LDS, per-thread serial scan of
 // NI consecutive items, block scan of the thread totals, coalesced store.
+// The block's base is block_base[b] (scanned block totals) or, when
+// block_sums is given instead, the sum of the raw totals of blocks 0..b-1.
 template <typename TIn, typename T, int NT, int NI>
 __global__ __launch_bounds__(NT) void k_scan_apply(const TIn* __restrict__ in, int64_t n,
-                                                   const T* __restrict__ block_base, T* __restrict__ out,
+                                                   const T* __restrict__ block_base,
+                                                   const T* __restrict__ block_sums, T* __restrict__ out,
                                                    T* __restrict__ total_out)
 {
     __shared__ T tile[NT * NI + NT * NI / 32];
     __shared__ T lds[NT / 64];
+    T b0 = 0;
+    if (block_base) {
+        b0 = block_base[blockIdx.x];
+    } else if (block_sums) {
+        T part = 0;
+        for (int i = threadIdx.x; i < (int)blockIdx.x; i += NT) part += block_sums[i];
+        block_exclusive_scan<T, NT>(part, &b0, lds);
+    }
     int64_t base = (int64_t)blockIdx.x * (NT * NI);
     const TIn* src = in + base;
     int lim = (int)min((int64_t)(NT * NI), n - base);
@@ -150,7 +161,7 @@ __global__ __launch_bounds__(NT) void k_scan_apply(const TIn* __restrict__ in, i
     for (int k = 0; k < NI; ++k) s += tile[pad32(threadIdx.x * NI + k)];
     T tot;
     T tb = block_exclusive_scan<T, NT>(s, &tot, lds);
-    T run = (block_base ? block_base[blockIdx.x] : (T)0) + tb;
+    T run = b0 + tb;
     T bb = run - tb;
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
@@ -167,6 +178,10 @@ __global__ __launch_bounds__(NT) void k_scan_apply(const TIn* __restrict__ in, i
     }
     if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = bb + tot;
 }
+
+// Up to this many blocks, each apply block sums the raw block totals before
+// it itself (at most kDirectSums reads), which saves the scan of the totals.
+constexpr int64_t kDirectSums = 1024;
 
 // Scratch elements of type T the recursive scan of n items needs.
 inline int64_t scan_scratch(int64_t n)
@@ -186,13 +201,13 @@ qb_status exclusive_scan(const TIn* in, T* out, int64_t n, T* scratch, T* total_
     if (n <= 0) return QB_OK;
     if (n <= kScanTile) {
         QB_LAUNCH((k_scan_apply<TIn, T, kScanThreads, kScanItems>), 1, kScanThreads, 0, s, in, n,
-                  (const T*)nullptr, out, total_out);
+                  (const T*)nullptr, (const T*)nullptr, out, total_out);
         return QB_OK;
     }
     if constexpr (sizeof(T) == 4) {
         if (n <= kBigScanTile) {
             QB_LAUNCH((k_scan_apply<TIn, T, kBigScanThreads, kBigScanItems>), 1, kBigScanThreads, 0, s, in, n,
-                      (const T*)nullptr, out, total_out);
+                      (const T*)nullptr, (const T*)nullptr, out, total_out);
             return QB_OK;
         }
     }
@@ -201,9 +216,14 @@ qb_status exclusive_scan(const TIn* in, T* out, int64_t n, T* scratch, T* total_
     T* sums = scratch;
     T* sums_scan = scratch + pad;
     QB_LAUNCH((k_scan_reduce<TIn, T>), nb, kScanThreads, 0, s, in, n, sums);
+    if (nb <= kDirectSums) {
+        QB_LAUNCH((k_scan_apply<TIn, T, kScanThreads, kScanItems>), nb, kScanThreads, 0, s, in, n,
+                  (const T*)nullptr, (const T*)sums, out, total_out);
+        return QB_OK;
+    }
     QB_CHECK((exclusive_scan<T, T>(sums, sums_scan, nb, scratch + 2 * pad, (T*)nullptr, s)));
     QB_LAUNCH((k_scan_apply<TIn, T, kScanThreads, kScanItems>), nb, kScanThreads, 0, s, in, n,
-              (const T*)sums_scan, out, total_out);
+              (const T*)sums_scan, (const T*)nullptr, out, total_out);
     return QB_OK;
 }
 
@@ -277,12 +297,14 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
 // FUSED: `offs` holds the raw block-major histograms of every block, and the
 // workgroup derives its global digit offsets from them (digit totals scanned
 // over digits, plus the counts of the earlier blocks); otherwise `offs` is the
-// scanned digit-major histogram.
-template <typename K, int NT, int NI, bool FUSED>
+// scanned digit-major histogram.  GATHER also writes gdst[pos] = gsrc[value]
+// beside each moved value.
+template <typename K, int NT, int NI, bool FUSED, bool GATHER>
 __global__ __launch_bounds__(NT) void k_radix_downsweep(
     const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, K* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const int64_t* n_dev, int64_t n_host, int64_t cap, int shift, int bits,
-    const uint32_t* __restrict__ offs, int64_t nblocks)
+    const uint32_t* __restrict__ offs, int64_t nblocks, const int32_t* __restrict__ gsrc,
+    uint32_t* __restrict__ gdst)
 {
     constexpr int NW = NT / 64;
     constexpr int TILE = NT * NI;
@@ -392,8 +414,10 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
         K k = s_key[i];
         uint32_t d = digit_of(k, shift, mask);
         uint32_t pos = gbase[d] + (uint32_t)i - lstart[d];
+        uint32_t v = s_val[i];
         keys_out[pos] = k;
-        vals_out[pos] = s_val[i];
+        vals_out[pos] = v;
+        if (GATHER) gdst[pos] = (uint32_t)gsrc[v];
     }
 }
 
@@ -423,15 +447,18 @@ __global__ __launch_bounds__(QB_BLOCK) void k_copy_items(const K* __restrict__ k
 // (kout, vout), and uses (ktmp, vtmp) for the intermediate passes; kin may
 // alias kout only when the pass count is even.  The item count is *n_dev when
 // n_dev is given (clamped as in sort_count), else n_host; cap sizes the grid.
+// gsrc/gdst (both or neither): the last pass also writes gdst[i] = gsrc[vout[i]].
 template <typename K, int NT, int NI>
 qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, K* ktmp, uint32_t* vtmp,
                      const int64_t* n_dev, int64_t n_host, int64_t cap, int lo_bit, int hi_bit,
-                     uint32_t* scratch, hipStream_t s)
+                     uint32_t* scratch, hipStream_t s, const int32_t* gsrc = nullptr, uint32_t* gdst = nullptr)
 {
     if (cap <= 0) return QB_OK;
+    if ((gsrc != nullptr) != (gdst != nullptr) || (gsrc && hi_bit <= lo_bit)) return QB_ERR_INVALID_ARG;
     int total_bits = hi_bit - lo_bit;
     int np = total_bits > 0 ? (total_bits + kRadixBits - 1) / kRadixBits : 0;
     if (np == 0) {
+        if (gsrc) return QB_ERR_INVALID_ARG;
         if ((const void*)kin != (const void*)kout) {
             int64_t g = qb_div_up(cap, QB_BLOCK);
             if (g > 4096) g = 4096;
@@ -456,18 +483,25 @@ qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout,
         K* dk = to_out ? kout : ktmp;
         uint32_t* dv = to_out ? vout : vtmp;
         int64_t hn_used = (int64_t)(1 << bits) * nb;
+        bool gather = gsrc && p == np - 1;
+        const uint32_t* o = (const uint32_t*)hist;
         if (fused) {
             QB_LAUNCH((k_radix_upsweep<K, NT, NI, true>), nb, NT, 0, s, src_k, n_dev, n_host, cap, shift, bits,
                       hist, nb);
-            QB_LAUNCH((k_radix_downsweep<K, NT, NI, true>), nb, NT, 0, s, src_k, src_v, dk, dv, n_dev, n_host, cap,
-                      shift, bits, (const uint32_t*)hist, nb);
         } else {
             QB_LAUNCH((k_radix_upsweep<K, NT, NI, false>), nb, NT, 0, s, src_k, n_dev, n_host, cap, shift, bits,
                       hist, nb);
             QB_CHECK((exclusive_scan<uint32_t, uint32_t>(hist, offs, hn_used, sscr, (uint32_t*)nullptr, s)));
-            QB_LAUNCH((k_radix_downsweep<K, NT, NI, false>), nb, NT, 0, s, src_k, src_v, dk, dv, n_dev, n_host,
-                      cap, shift, bits, (const uint32_t*)offs, nb);
+            o = (const uint32_t*)offs;
         }
+#define QB_DOWNSWEEP(F, G)                                                                                    \
+    QB_LAUNCH((k_radix_downsweep<K, NT, NI, F, G>), nb, NT, 0, s, src_k, src_v, dk, dv, n_dev, n_host, cap,  \
+              shift, bits, o, nb, G ? gsrc : (const int32_t*)nullptr, G ? gdst : (uint32_t*)nullptr)
+        if (fused && gather) QB_DOWNSWEEP(true, true);
+        else if (fused) QB_DOWNSWEEP(true, false);
+        else if (gather) QB_DOWNSWEEP(false, true);
+        else QB_DOWNSWEEP(false, false);
+#undef QB_DOWNSWEEP
         src_k = dk;
         src_v = dv;
         shift += bits;
