@@ -45,7 +45,7 @@ __global__ void k_store_total(const uint64_t* __restrict__ tot, int64_t* __restr
 
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     int64_t n, const uint32_t* __restrict__ order, const uint64_t* __restrict__ goff,
-    const int4* __restrict__ rects, const int32_t* __restrict__ counts, int tiles_x, int64_t cap,
+    const int4* __restrict__ rects, const uint32_t* __restrict__ sorted_counts, int tiles_x, int64_t cap,
     const int64_t* __restrict__ num_pairs, uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id)
 {
     constexpr int kRuns = kEmitThreads * QB_MAX_SEG;
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     q.axis = 0;
     if (k < n) {
         gi = order[k];
-        if (counts[gi] > 0) qbb::gaussian_runs(rects, gi, q);
+        if (sorted_counts[k] > 0) qbb::gaussian_runs(rects, gi, q);
     }
     uint32_t cnt = (uint32_t)q.total;
     uint32_t nr = 0;
@@ -145,14 +145,14 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
 
 __global__ __launch_bounds__(QB_BLOCK) void k_emit_naive(
     int64_t n, const uint32_t* __restrict__ order, const uint64_t* __restrict__ goff,
-    const int4* __restrict__ rects, const int32_t* __restrict__ counts, int tiles_x, int64_t cap,
+    const int4* __restrict__ rects, const uint32_t* __restrict__ sorted_counts, int tiles_x, int64_t cap,
     const int64_t* __restrict__ num_pairs, uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id)
 {
     if (*num_pairs > cap) return;  // overflow: the caller re-runs with more capacity
     int64_t k = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (k >= n) return;
     uint32_t gi = order[k];
-    if (counts[gi] <= 0) return;
+    if (sorted_counts[k] == 0) return;
     int4 p0 = rects[2 * (int64_t)gi], p1 = rects[2 * (int64_t)gi + 1];
     QRect r[4] = {qbb::unpack_rect(p0.x, p0.y), qbb::unpack_rect(p0.z, p0.w), qbb::unpack_rect(p1.x, p1.y),
                   qbb::unpack_rect(p1.z, p1.w)};
@@ -232,13 +232,13 @@ extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_re
     // pair offsets; the total (a count, below 2^63) lands in *num_pairs
     QB_CHECK((qbr::exclusive_scan<uint32_t, uint64_t>(w.csorted, w.offs, n, w.scan64,
                                                       reinterpret_cast<uint64_t*>(num_pairs), s)));
+    const uint32_t* order = w.dv0;
+    const int4* r4 = reinterpret_cast<const int4*>(rects);
     if (pair_capacity > 0 && mode == QB_BOX_QUADBOX_NAIVE)
-        QB_LAUNCH(k_emit_naive, grid, QB_BLOCK, 0, s, n, (const uint32_t*)w.dv0, (const uint64_t*)w.offs,
-                  reinterpret_cast<const int4*>(rects), counts, tiles_x, pair_capacity, (const int64_t*)num_pairs,
-                  pair_tiles, pair_ids);
+        QB_LAUNCH(k_emit_naive, grid, QB_BLOCK, 0, s, n, order, (const uint64_t*)w.offs, r4,
+                  (const uint32_t*)w.csorted, tiles_x, pair_capacity, (const int64_t*)num_pairs, pair_tiles, pair_ids);
     else if (pair_capacity > 0)
-        QB_LAUNCH(k_emit, qb_div_up(n, kEmitThreads), kEmitThreads, 0, s, n, (const uint32_t*)w.dv0,
-                  (const uint64_t*)w.offs, reinterpret_cast<const int4*>(rects), counts, tiles_x, pair_capacity,
-                  (const int64_t*)num_pairs, pair_tiles, pair_ids);
+        QB_LAUNCH(k_emit, qb_div_up(n, kEmitThreads), kEmitThreads, 0, s, n, order, (const uint64_t*)w.offs, r4,
+                  (const uint32_t*)w.csorted, tiles_x, pair_capacity, (const int64_t*)num_pairs, pair_tiles, pair_ids);
     return QB_OK;
 }
