@@ -6,8 +6,9 @@
 //   cutoff and alpha exactly, recovers the transmittance in front of the
 //   Gaussian by dividing out (1 - alpha), and forms the pixel's share of
 //   dL/d(u, v, conic, opacity, rgb) of Eq. (2).  The shares are summed over a
-//   lane's pixels, then across each wave64 (DPP, skipped when no lane of the
-//   wave takes part), and one lane per wave adds them to the Gaussian's 2D
+//   lane's pixels, then across each wave64 (DPP row sums and two permlane
+//   swap folds, skipped when no lane of the wave takes part), and nine lanes
+//   per wave add them to the Gaussian's 2D
 //   gradient with global float atomics; the order of those additions is not
 //   fixed, so the result is deterministic only up to float reassociation.
 //
@@ -22,43 +23,64 @@
 
 namespace {
 
-// Sum over the 64 lanes of a wave, returned to every lane.  Rows of 16 are
-// reduced with four DPP adds (neighbour, pair of neighbours, half-row mirror,
-// row mirror: every lane of a row then holds the row sum), the row sums are
-// chained by the row broadcasts 15 (rows 1, 3) and 31 (rows 2, 3), and lane
-// 63's total is read with one v_readlane.  Every lane of the wave must be
-// active.
-__device__ __forceinline__ float dpp_add(float v, int ctrl_sel)
+// v + the value of v in another lane of the same row of 16 (DPP): step 0
+// pairs neighbours, 1 pairs of neighbours, 2 the half-row mirror, 3 the row
+// mirror; after the four steps every lane of a row holds the row's sum.
+// Every lane of the wave must be active.
+__device__ __forceinline__ float dpp_add(float v, int step)
 {
     int x = __float_as_int(v);
     int y;
-    switch (ctrl_sel) {
+    switch (step) {
     case 0: y = __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
     case 1: y = __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
     case 2: y = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
-    case 3: y = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false); break;  // row_mirror
-    case 4: y = __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false); break;  // row_bcast 15
-    default: y = __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false); break; // row_bcast 31
+    default: y = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false); break; // row_mirror
     }
     return v + __int_as_float(y);
 }
 
-__device__ __forceinline__ float wave_sum(float v)
+// x + x of lane ^ 32, and x + x of lane ^ 16: the gfx950 permlane swaps
+// exchange the two halves of the wave (32) or the rows of each half (16)
+// between two registers; with x in both, the two results at a lane are x
+// there and x at the partner lane, whichever way round.
+__device__ __forceinline__ float fold_lanes32(float x)
 {
-    v = dpp_add(v, 0);
-    v = dpp_add(v, 1);
-    v = dpp_add(v, 2);
-    v = dpp_add(v, 3);
-    v = dpp_add(v, 4);
-    v = dpp_add(v, 5);
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float fold_lanes16(float x)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Adds the wave totals of v[0..8] to g[0..8].  The nine row reductions run
+// interleaved, step by step (independent DPP chains, no wait states); lane
+// 16 r + j of row r then keeps row r's sum of value j, and two swap folds add
+// the four rows' sums of that one value, so lanes 0..8 hold the nine totals
+// and issue one atomic instruction over 36 contiguous bytes.  Every lane of
+// the wave must be active.
+__device__ __forceinline__ void wave_add9(float v[9], float* g, int lane)
+{
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = dpp_add(v[j], s);
+    int j = lane & 15;
+    float mine = v[0];
+#pragma unroll
+    for (int t = 1; t < 9; ++t) mine = j == t ? v[t] : mine;
+    mine = fold_lanes16(fold_lanes32(mine));
+    if (lane < 9) atomicAdd(g + lane, mine);
 }
 
 // Backward of one tile of one image: 256 / PPL lanes, each owning PPL pixels
 // of one tile row, 16 / PPL apart.  The list is walked back to front from the
 // furthest last contributor of the tile, in batches of one record per lane
 // staged in LDS.  Per entry, a lane sums its pixels' shares, the wave sums
-// its lanes (DPP), and lanes 0..8 add the nine totals to grad2d in one
+// its lanes (wave_add9), and lanes 0..8 add the nine totals to grad2d in one
 // atomic instruction (float atomics: order-dependent rounding).
 template <int PPL>
 __device__ __forceinline__ void render_backward_tile(
@@ -206,13 +228,8 @@ __device__ __forceinline__ void render_backward_tile(
                     }
                 }
             }
-            // the nine wave totals are uniform; lane j adds total j, so the
-            // wave issues one atomic instruction over 36 contiguous bytes
-            float t0 = wave_sum(gu), t1 = wave_sum(gv), t2 = wave_sum(ga), t3 = wave_sum(gb), t4 = wave_sum(gc);
-            float t5 = wave_sum(go), t6 = wave_sum(gr), t7 = wave_sum(gg), t8 = wave_sum(gbl);
-            float mine = lane == 0 ? t0 : lane == 1 ? t1 : lane == 2 ? t2 : lane == 3 ? t3 : lane == 4 ? t4 :
-                         lane == 5 ? t5 : lane == 6 ? t6 : lane == 7 ? t7 : t8;
-            if (lane < 9) atomicAdd(grad2d + 9 * (int64_t)s_id[k] + lane, mine);
+            float v9[9] = {gu, gv, ga, gb, gc, go, gr, gg, gbl};
+            wave_add9(v9, grad2d + 9 * (int64_t)s_id[k], lane);
           }
         }
     }
