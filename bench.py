@@ -355,10 +355,15 @@ def image_delta(torch, img, ref):
             "psnr_vs_headline": None if mse == 0.0 else round(10.0 * math.log10(1.0 / mse), 2)}
 
 
-def cpu_baseline(scene, cam):
+def cpu_baseline(scene, cam, exact_stride=10):
     """The oracle (as it stands) on one whole frame of the same workload:
     project, all pairs with qsort, ranges, and the per-pixel render; timed
-    wall-clock on every host core the process may use."""
+    wall-clock on every host core the process may use.  Also the oracle's
+    exact-sample pair count (tiles holding a pixel sample that passes the
+    cutoff) on every `exact_stride`-th projected Gaussian: the lower bound of
+    any conservative tile set, against the QuadBox, AdR and 3-sigma counts of
+    the same sample (untimed)."""
+    import numpy as np
     from oracle import oracle as O
     threads = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
@@ -370,9 +375,21 @@ def cpu_baseline(scene, cam):
     O.render(g, cam.width, cam.height, rt, ids)
     t3 = time.perf_counter()
     frame_s = t3 - t0
-    return {"value": round(1.0 / frame_s, 4), "unit": "frames/s", "cores": threads, "kind": "oracle",
+    base = {"value": round(1.0 / frame_s, 4), "unit": "frames/s", "cores": threads, "kind": "oracle",
             "sample": f"one full frame of the same workload: project {t1 - t0:.2f} s, pairs+sort+ranges "
                       f"{t2 - t1:.2f} s, render {t3 - t2:.2f} s"}
+    sub = np.ascontiguousarray(g[::exact_stride])
+    missed, exact, _ = O.coverage_audit(sub, cam.width, cam.height)
+    quad = int(O.tile_counts(sub, cam.tiles_x).sum())
+    exact_pairs = {"estimate": exact * exact_stride, "quadbox_over_exact": round(quad / max(exact, 1), 4),
+                   "missed_by_quadbox": missed}
+    for mode in ("adr", "3sigma"):
+        gm = np.ascontiguousarray(O.project(scene, cam, mode)[::exact_stride])
+        exact_pairs[f"{mode}_over_exact"] = round(int(O.tile_counts(gm, cam.tiles_x).sum()) / max(exact, 1), 4)
+    exact_pairs.update({
+                   "sample": f"every {exact_stride}th Gaussian of the oracle's projection ({len(sub)}), "
+                             f"{exact} exact and {quad} QuadBox pairs, scaled by {exact_stride}"})
+    return base, exact_pairs
 
 
 def render_traffic(workload, mode, kernel):
@@ -486,7 +503,7 @@ def main():
     }
     if not args.no_cpu:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(scene, cam)
+        out["cpu_baseline"], out["pairs_exact"] = cpu_baseline(scene, cam)
     print(json.dumps(out), flush=True)
 
 
