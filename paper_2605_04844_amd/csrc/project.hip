@@ -44,10 +44,25 @@ __device__ __forceinline__ QRect box_rect(float x0, float x1, float y0, float y1
     return r;
 }
 
-// Real SH basis of degree <= 3 (Condon-Shortley phase, index l*l + l + m).
-__device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t n, int64_t i,
-                                          int deg, float x, float y, float z, float rgb[3])
+// SH coefficients of one Gaussian, (DEG+1)^2 x 3 (plane k*3 + ch of sh).
+template <int DEG>
+struct ShCoef {
+    static constexpr int K = (DEG + 1) * (DEG + 1);
+    float c[K * 3];
+};
+
+template <int DEG>
+__device__ __forceinline__ void sh_load(const float* __restrict__ sh, int64_t n, int64_t i, ShCoef<DEG>& s)
 {
+#pragma unroll
+    for (int k = 0; k < ShCoef<DEG>::K * 3; ++k) s.c[k] = __ldg(sh + (int64_t)k * n + i);
+}
+
+// Real SH basis of degree <= 3 (Condon-Shortley phase, index l*l + l + m).
+template <int DEG>
+__device__ __forceinline__ void sh_colour(const ShCoef<DEG>& s, float x, float y, float z, float rgb[3])
+{
+    constexpr int deg = DEG;
     const float k00 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
     const float k1 = 0.48860251190291992f;    // sqrt(3 / (4 pi))
     const float k2a = 1.0925484305920792f;    // sqrt(15 / pi) / 2
@@ -61,7 +76,7 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t 
     float Y[16];
     float xx = x * x, yy = y * y, zz = z * z;
     Y[0] = k00;
-    int K = (deg + 1) * (deg + 1);
+    constexpr int K = ShCoef<DEG>::K;
     if (deg >= 1) {
         Y[1] = -k1 * y;
         Y[2] = k1 * z;
@@ -84,9 +99,10 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t 
         Y[15] = -k3a * x * (xx - 3.0f * yy);
     }
     float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) acc[ch] = fmaf(Y[k], __ldg(sh + (int64_t)(k * 3 + ch) * n + i), acc[ch]);
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = fmaf(Y[k], s.c[k * 3 + ch], acc[ch]);
     }
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) rgb[ch] = acc[ch] > 0.0f ? acc[ch] : 0.0f;
@@ -155,11 +171,14 @@ __device__ __forceinline__ double s3(const GaussPre& g, int r, int c)
 }
 
 // Projects Gaussian i (mean mx, my, mz; view-independent part g) for one
-// camera and writes its splat, rects and count.
+// camera and writes its splat, rects and count.  The SH coefficients come
+// from `pre` when given (loaded once for several views), else they are
+// loaded here, only for a Gaussian that survives the culls before its colour.
+template <int DEG>
 __device__ __forceinline__ void project_view(int64_t i, int64_t n, float mx, float my, float mz, const GaussPre& g,
-                                             const float* __restrict__ sh, int sh_degree, const ProjCam& cam, int mode,
-                                             float4* __restrict__ out_splat, int4* __restrict__ out_rects,
-                                             int32_t* __restrict__ out_count)
+                                             const float* __restrict__ sh, const ShCoef<DEG>* pre,
+                                             const ProjCam& cam, int mode, float4* __restrict__ out_splat,
+                                             int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
 {
     const float* R = cam.R;
     float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + cam.t[0];
@@ -218,7 +237,13 @@ __device__ __forceinline__ void project_view(int64_t i, int64_t n, float mx, flo
             float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
             float nn = sqrtf(dx * dx + dy * dy + dz * dz);
             if (nn > 0.0f) { dx /= nn; dy /= nn; dz /= nn; }
-            sh_colour(sh, n, i, sh_degree, dx, dy, dz, rgb);
+            if (pre) {
+                sh_colour<DEG>(*pre, dx, dy, dz, rgb);
+            } else {
+                ShCoef<DEG> c;
+                sh_load<DEG>(sh, n, i, c);
+                sh_colour<DEG>(c, dx, dy, dz, rgb);
+            }
         }
 
         if (mode == QB_BOX_3SIGMA) {
@@ -286,28 +311,19 @@ __device__ __forceinline__ void project_view(int64_t i, int64_t n, float mx, flo
     out_count[i] = count;
 }
 
-__device__ __forceinline__ void project_one(int64_t i, int64_t n, const float* __restrict__ means,
-                                            const float* __restrict__ log_scales, const float* __restrict__ quats,
-                                            const float* __restrict__ logits, const float* __restrict__ sh,
-                                            int sh_degree, const ProjCam& cam, int mode,
-                                            float4* __restrict__ out_splat, int4* __restrict__ out_rects,
-                                            int32_t* __restrict__ out_count)
-{
-    GaussPre g;
-    gauss_pre(i, n, log_scales, quats, logits, g);
-    project_view(i, n, means[i], means[n + i], means[2 * n + i], g, sh, sh_degree, cam, mode, out_splat, out_rects,
-                 out_count);
-}
-
+template <int DEG>
 __global__ __launch_bounds__(QB_BLOCK) void k_project(
     int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, int sh_degree, ProjCam cam, int mode,
+    const float* __restrict__ sh, ProjCam cam, int mode,
     float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
 {
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
-    project_one(i, n, means, log_scales, quats, logits, sh, sh_degree, cam, mode, out_splat, out_rects, out_count);
+    GaussPre g;
+    gauss_pre(i, n, log_scales, quats, logits, g);
+    project_view<DEG>(i, n, means[i], means[n + i], means[2 * n + i], g, sh, (const ShCoef<DEG>*)nullptr, cam, mode,
+                      out_splat, out_rects, out_count);
 }
 
 // Cameras of a batched call, by value as a kernel argument (3.3 KB at
@@ -316,24 +332,39 @@ struct ProjCamTable {
     ProjCam cam[QB_MAX_VIEWS];
 };
 
-// One lane per Gaussian: the view-independent part once, then every view
-// (view v writes the block of records starting at v*n).  Per view the same
-// arithmetic as k_project, so the records are identical.
+// One lane per Gaussian: the view-independent part (activations, Sigma3D
+// and the SH coefficients) once, then every view (view v writes the block of
+// records starting at v*n).  Per view the same arithmetic as k_project, so
+// the records are identical.
+template <int DEG>
 __global__ __launch_bounds__(QB_BLOCK) void k_project_views(
     int64_t n, int nv, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, int sh_degree, ProjCamTable cams, int mode,
+    const float* __restrict__ sh, ProjCamTable cams, int mode,
     float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
 {
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
     GaussPre g;
     gauss_pre(i, n, log_scales, quats, logits, g);
+    ShCoef<DEG> c;
+    sh_load<DEG>(sh, n, i, c);
     float mx = means[i], my = means[n + i], mz = means[2 * n + i];
     for (int v = 0; v < nv; ++v)
-        project_view(i, n, mx, my, mz, g, sh, sh_degree, cams.cam[v], mode, out_splat + 3 * (int64_t)v * n,
-                     out_rects + 2 * (int64_t)v * n, out_count + (int64_t)v * n);
+        project_view<DEG>(i, n, mx, my, mz, g, sh, &c, cams.cam[v], mode, out_splat + 3 * (int64_t)v * n,
+                          out_rects + 2 * (int64_t)v * n, out_count + (int64_t)v * n);
 }
+
+// Launches kernel template K for the SH degree (0..3).
+#define QB_LAUNCH_DEG(K, deg, grid, ...)                                                  \
+    do {                                                                                  \
+        switch (deg) {                                                                    \
+        case 0: QB_LAUNCH(K<0>, grid, QB_BLOCK, 0, __VA_ARGS__); break;                   \
+        case 1: QB_LAUNCH(K<1>, grid, QB_BLOCK, 0, __VA_ARGS__); break;                   \
+        case 2: QB_LAUNCH(K<2>, grid, QB_BLOCK, 0, __VA_ARGS__); break;                   \
+        default: QB_LAUNCH(K<3>, grid, QB_BLOCK, 0, __VA_ARGS__); break;                  \
+        }                                                                                 \
+    } while (0)
 
 }  // namespace
 
@@ -380,9 +411,9 @@ extern "C" qb_status qb_project(int64_t n, const float* means, const float* log_
     ProjCam pc;
     make_proj_cam(*cam, &pc);
     int64_t grid = qb_div_up(n, QB_BLOCK);
-    QB_LAUNCH(k_project, grid, QB_BLOCK, 0, qb_hip_stream(stream), n, means, log_scales, quats,
-              opacity_logits, sh, (int)sh_degree, pc, (int)mode,
-              reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects), out_counts);
+    QB_LAUNCH_DEG(k_project, sh_degree, grid, qb_hip_stream(stream), n, means, log_scales, quats, opacity_logits, sh,
+                  pc, (int)mode, reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects),
+                  out_counts);
     return QB_OK;
 }
 
@@ -405,8 +436,8 @@ extern "C" qb_status qb_project_views(int64_t n, const float* means, const float
     if (!means || !log_scales || !quats || !opacity_logits || !sh || !out_splats || !out_rects ||
         !out_counts)
         return QB_ERR_INVALID_ARG;
-    QB_LAUNCH(k_project_views, qb_div_up(n, QB_BLOCK), QB_BLOCK, 0, qb_hip_stream(stream), n, (int)num_views, means,
-              log_scales, quats, opacity_logits, sh, (int)sh_degree, ct, (int)mode,
-              reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects), out_counts);
+    QB_LAUNCH_DEG(k_project_views, sh_degree, qb_div_up(n, QB_BLOCK), qb_hip_stream(stream), n, (int)num_views,
+                  means, log_scales, quats, opacity_logits, sh, ct, (int)mode,
+                  reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects), out_counts);
     return QB_OK;
 }
