@@ -188,9 +188,18 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             }
         } else {
             if (all_done()) continue;
+            // whether the whole wave has stopped is asked once per 8 pairs:
+            // after that, entries find no active pixel and only run the
+            // tests, which is cheaper than the vote on every pair
             bool finished = false;
             int k = 0;
-            for (; k + 1 < cnt; k += 2)
+            constexpr int kPairsPerCheck = 8;
+            for (; k + 2 * kPairsPerCheck - 1 < cnt; k += 2 * kPairsPerCheck) {
+#pragma unroll
+                for (int c = 0; c < kPairsPerCheck - 1; ++c) entry2(k + 2 * c);
+                if (entry2(k + 2 * (kPairsPerCheck - 1))) { finished = true; break; }
+            }
+            for (; !finished && k + 1 < cnt; k += 2)
                 if (entry2(k)) { finished = true; break; }
             if (!finished && k < cnt) entry(k);
         }
