@@ -3,7 +3,9 @@
 // Both are reduce-then-scan: no workgroup ever waits on another, so there is
 // no inter-workgroup spin and no forward-progress assumption.
 //   scan:  up to 32768 items in one 1024-lane workgroup; beyond that a
-//          per-block reduction -> recursive scan of block totals -> per-block scan
+//          per-block reduction, then the per-block scan, whose workgroups
+//          add up the raw totals of the blocks before them (up to 1024
+//          blocks; beyond that the totals are scanned recursively first)
 //   radix pass (<= 8 bits):
 //     upsweep   per-block digit histogram in LDS, stored digit-major
 //     scan      exclusive scan of the digit-major histogram (global offsets)
