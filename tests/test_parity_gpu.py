@@ -363,3 +363,40 @@ def test_activation_sweep(oracle, qb):
         diff = np.nonzero(bits(gpu["splats"][vis_o, col]) != bits(g[name][vis_o]))[0]
         assert diff.size == 0, (name, diff.size)
     say(f"activation sweep: {n} logits, {int(vis_o.sum())} above the cutoff, all bit-exact")
+
+
+@pytest.mark.parametrize("n", [2_097_152, 2_097_153])
+def test_scan_block_boundary(oracle, qb, n):
+    """The pair-offset scan over n tile counts: 1024 blocks of 2048 (each
+    block adds the raw totals of the blocks before it) and 1025 blocks (the
+    totals are scanned first).  Small Gaussians on a 64x64 image, everything
+    against the oracle."""
+    scene, cam = scenes.random_scene(121, n, 64, 64, 64.0, sh_degree=0, log_scale_mu=-4.0)
+    gpu, ref = full_check(oracle, qb, scene, cam, "quadbox")
+    say(f"scan boundary n={n}: {gpu['P']} pairs")
+
+
+def test_full_size_3sigma_zoom(oracle, qb):
+    """The 3M anisotropic Gaussians at 1920x1080, focal x4, with 3-sigma
+    boxes: ~2.5e8 pairs, so the tile sort's histogram scans take more than
+    1024 blocks.  Keys globally sorted with consistent depth bits, ranges
+    exact, sampled tile lists against the oracle."""
+    scene, cams = scenes.aniso_scene()
+    cam = cams[3]
+    label = "aniso-3M x4 3sigma"
+    say("running", label)
+    gpu, _ = gpu_forward(qb, scene, cam, "3sigma")
+    assert gpu["P"] > 134_217_728   # more than 1024 scan blocks of 64-digit histograms
+    g = oracle.project(scene, cam, "3sigma")
+    check_counts(oracle, gpu, g, cam.tiles_x, label)
+    keys, ids = gpu["keys"], gpu["ids"]
+    assert np.all(keys[1:] >= keys[:-1])
+    tie = keys[1:] == keys[:-1]
+    assert np.all(ids[1:][tie] > ids[:-1][tie])
+    assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), bits(g["depth"])[ids])
+    assert np.array_equal(gpu["ranges"], oracle.ranges(keys, cam.num_tiles))
+    say(label, "pairs", gpu["P"])
+    rng = np.random.default_rng(31)
+    busy = np.argsort(gpu["ranges"][:, 1] - gpu["ranges"][:, 0])[-5:]
+    tiles = np.unique(np.concatenate([rng.choice(cam.num_tiles, 30, replace=False), busy]))
+    _sampled_tile_check(oracle, gpu, g, cam, tiles, label)
