@@ -409,6 +409,18 @@ def render_traffic(workload, mode, kernel):
     return int(meta["fetch_bytes_per_launch"] + meta["write_bytes_per_launch"])
 
 
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Achieved HBM rate of a plain device-to-device copy (bytes read plus
+    written per second): the practical ceiling of the HBM-bound stages, next
+    to the published 8 TB/s."""
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    ms = _time(torch, lambda: b.copy_(a), reps, 2, 3)
+    del a, b
+    return round(2.0 * (mib << 20) / (ms * 1e-3) / 1e9, 1)
+
+
 def calibrate_copy(torch, mib=1024):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
@@ -500,6 +512,7 @@ def main():
         "quadbox_vs_adr": round(results["adr"]["ms"] / q["ms"], 3) if "adr" in results else None,
         "dominant_stage": dominant,
         "roofline": roof,
+        "hbm_copy_gbs": copy_bandwidth(torch),
     }
     if not args.no_cpu:
         log("cpu baseline")
