@@ -31,8 +31,9 @@ METRIC = "FPS & tile pairs/frame (QuadBox vs AABB); fwd+bwd ms/view, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 # Render roofline.  One evaluation of Eq. (2) at a (pixel, list entry) that
 # composites: 2 sub (offsets), 5 mul/fma (quadratic form), 2 compares (1/255
-# cutoff and the sign test), exp, scale by o, cap at 0.99, 1 - alpha, times T,
-# compare with 1e-4, alpha * T, 3 fma (colour) = 21 VALU lane operations.
+# cutoff and the sign test), exp as 2 (scale by log2 e, exp2), scale by o,
+# cap at 0.99, 1 - alpha, times T, compare with 1e-4, alpha * T, 3 fma
+# (colour), the T update (select) = 21 VALU lane operations.
 RENDER_OPS_PER_EVAL = 21
 # VALU issue peak without packed math: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
