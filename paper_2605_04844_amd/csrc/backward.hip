@@ -107,7 +107,10 @@ __device__ __forceinline__ void render_backward_tile(
     int lane = threadIdx.x & 63;
     int64_t plane = (int64_t)W * H;
 
-    float fxp[PPL], T[PPL], dC[PPL][3], rest[PPL][3];
+    // per pixel: T in front of the current entry, dL/dC, and
+    // R = sum_c dL/dC_c * (colour of everything behind the current entry,
+    // background included), so that dL/dalpha = T_i (dC . rgb) - R / (1 - alpha)
+    float fxp[PPL], T[PPL], dC[PPL][3], R[PPL];
     uint32_t last[PPL];
     uint32_t lmax = 0;
 #pragma unroll
@@ -121,9 +124,7 @@ __device__ __forceinline__ void render_backward_tile(
         dC[q][0] = inside ? dL_dimg[pix] : 0.f;
         dC[q][1] = inside ? dL_dimg[plane + pix] : 0.f;
         dC[q][2] = inside ? dL_dimg[2 * plane + pix] : 0.f;
-        rest[q][0] = T[q] * bg0;
-        rest[q][1] = T[q] * bg1;
-        rest[q][2] = T[q] * bg2;
+        R[q] = T[q] * ((dC[q][0] * bg0 + dC[q][1] * bg1) + dC[q][2] * bg2);
         lmax = max(lmax, last[q]);
     }
 
@@ -194,7 +195,11 @@ __device__ __forceinline__ void render_backward_tile(
             if (!__any(any)) continue;
             float4 col = s_col[k];
             float cc = s_c[k];
-            float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+            // per pixel: A = dL/dC . rgb of this entry; the geometric shares
+            // are summed over the lane's pixels as P = sum dpow,
+            // S1 = sum dpow dx and Q = sum dpow dx^2 (the pixels share the
+            // row offset dy), and turned into (u, v, a, b, c) once per lane
+            float P = 0.f, S1 = 0.f, Q = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
                 if (act[q]) {
@@ -209,25 +214,24 @@ __device__ __forceinline__ void render_backward_tile(
                     gr = fmaf(w, dC[q][0], gr);
                     gg = fmaf(w, dC[q][1], gg);
                     gbl = fmaf(w, dC[q][2], gbl);
-                    float dalpha = dC[q][0] * (col.x * Ti - rest[q][0] * inv) +
-                                   dC[q][1] * (col.y * Ti - rest[q][1] * inv) +
-                                   dC[q][2] * (col.z * Ti - rest[q][2] * inv);
-                    rest[q][0] = fmaf(col.x, w, rest[q][0]);
-                    rest[q][1] = fmaf(col.y, w, rest[q][1]);
-                    rest[q][2] = fmaf(col.z, w, rest[q][2]);
+                    float A = fmaf(dC[q][2], col.z, fmaf(dC[q][1], col.y, dC[q][0] * col.x));
+                    float dalpha = Ti * A - R[q] * inv;
+                    R[q] = fmaf(w, A, R[q]);
                     T[q] = Ti;
                     if (raw <= 0.99f) {
                         float dpow = dalpha * alpha;
-                        go += dalpha * e;
-                        float a = o.w, b = col.w, ddx = dx[q];
-                        gu -= dpow * (a * ddx + b * dy);
-                        gv -= dpow * (cc * dy + b * ddx);
-                        ga -= 0.5f * dpow * ddx * ddx;
-                        gb -= dpow * ddx * dy;
-                        gc -= 0.5f * dpow * dy * dy;
+                        go = fmaf(dalpha, e, go);
+                        float t = dpow * dx[q];
+                        P += dpow;
+                        S1 += t;
+                        Q = fmaf(t, dx[q], Q);
                     }
                 }
             }
+            // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 with dx = u - x, dy = v - y
+            float a = o.w, b = col.w, dyP = dy * P;
+            float gu = -fmaf(a, S1, b * dyP), gv = -fmaf(b, S1, cc * dyP);
+            float ga = -0.5f * Q, gb = -(dy * S1), gc = -0.5f * (dy * dyP);
             float v9[9] = {gu, gv, ga, gb, gc, go, gr, gg, gbl};
             wave_add9(v9, grad2d + 9 * (int64_t)s_id[k], lane);
           }
