@@ -2,8 +2,8 @@
 
 Workload: the 1M-Gaussian clustered scene (64 isotropic clusters, SH degree
 3) rendered at 1280x720 -- the configuration the headline metric is quoted on.
-One step = one whole forward (project -> intersect -> sort -> render) with the
-Gaussian parameters already resident in HBM.  The pair buffers are sized once
+One step = one whole forward (project -> intersect -> sort -> tile order ->
+render) with the Gaussian parameters already resident in HBM.  The pair buffers are sized once
 from a warm-up frame, so a step issues no host synchronisation.  Each mode is
 timed eagerly (with per-stage HIP events) and as the same frame captured in a
 HIP graph and replayed (no host work between launches; every replay is
@@ -108,7 +108,7 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials):
         r.forward(g, mode, sync_count=False)
     torch.cuda.synchronize()
     trial_ms = []
-    timer = StageTimer(torch, ["project", "intersect", "sort", "render"])
+    timer = StageTimer(torch, ["project", "intersect", "sort", "order", "render"])
     for _ in range(trials):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -121,12 +121,15 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials):
             e2 = timer.mark()
             r.sort()
             e3 = timer.mark()
-            r.render()
+            r.schedule()
             e4 = timer.mark()
+            r.render()
+            e5 = timer.mark()
             timer.add("project", e0, e1)
             timer.add("intersect", e1, e2)
             timer.add("sort", e2, e3)
-            timer.add("render", e3, e4)
+            timer.add("order", e3, e4)
+            timer.add("render", e4, e5)
         end = timer.mark()
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3 / steps
@@ -148,6 +151,7 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials):
         r.project(g, mode)
         r.intersect()
         r.sort()
+        r.schedule()
         r.render()
     graph_trials = []
     for _ in range(trials):
@@ -169,10 +173,15 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials):
     # the stream the library launches on; the per-stage events above also
     # catch any gap before a stage's first kernel starts
     render_launch_ms = _time(torch, r.render, 20, 2, trials)
+    # the same launches with the tiles in row-major order (no qb_tile_order):
+    # what the work-ordered dispatch gains
+    r.balance = False
+    rowmajor_ms = _time(torch, r.render, 20, 2, trials)
+    r.balance = True
     evals = render_evaluations(torch, r)
     names = {v: k for k, v in qb.RENDER_VARIANTS.items()}
     return dict(ms=min(dev, graph_ms), eager_ms=dev, graph_ms=graph_ms, wall_ms=wall, pairs=pairs, stage_ms=stage,
-                render_launch_ms=render_launch_ms, evals=evals, rast=r,
+                render_launch_ms=render_launch_ms, render_rowmajor_ms=rowmajor_ms, evals=evals, rast=r,
                 render_shape=names[r.render_variant], shape_ms={k: round(v, 4) for k, v in shapes.items()})
 
 
@@ -196,7 +205,7 @@ def run_fwd_bwd(torch, qb, g, cam, steps, warmup, trials):
         r.forward(g, "quadbox", sync_count=False)
         dl = torch.sign(r.image - target) * inv
         qb.render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, (0.0, 0.0, 0.0), r.final_T, r.n_contrib,
-                           dl, g.n, grad2d, r.backward_variant)
+                           dl, g.n, grad2d, r.backward_variant, r.tile_order())
         qb.project_backward(g, cam, r.splats, grad2d, *grads)
 
     for _ in range(warmup):
@@ -297,7 +306,7 @@ def run_multiview(torch, qb, steps, warmup, trials):
             r.forward(g, "quadbox", sync_count=False)
             dl = torch.sign(r.image - targets[v]) * (1.0 / r.image.numel())
             qb.render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, (0.0, 0.0, 0.0), r.final_T,
-                               r.n_contrib, dl, g.n, grad2d)
+                               r.n_contrib, dl, g.n, grad2d, r.backward_variant, r.tile_order())
             qb.project_backward(g, cams[v], r.splats, grad2d, *part)
             for t, p in zip(total, part):
                 t.add_(p)
@@ -503,6 +512,7 @@ def main():
                       "eager_ms": round(r["eager_ms"], 4), "graph_ms": round(r["graph_ms"], 4),
                       "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
                       "render_launch_ms": round(r["render_launch_ms"], 4),
+                      "render_rowmajor_ms": round(r["render_rowmajor_ms"], 4),
                       "render_shape": r["render_shape"], "render_shape_ms": r["shape_ms"],
                       **image_delta(torch, r["rast"].image, q["rast"].image)}
                   for m, r in results.items()},

@@ -9,6 +9,8 @@
  *   qb_intersect  Sec. 2 (DuplicateWithKeys), Sec. 3.2 (QPass)
  *   qb_sort       Sec. 2 (SortPairs) and the per-tile ranges
  *   qb_render     Sec. 2, Eq. (2) (front-to-back alpha compositing)
+ *   qb_tile_order the order in which the render takes tiles (scheduling only:
+ *                 results do not depend on it)
  *   qb_render_backward, qb_project_backward
  *                 gradients (the rasterizer is trained through, Sec. 4.1)
  *   qb_*_views    the same stages over several views per launch
@@ -211,12 +213,36 @@ typedef enum {
     QB_RENDER_VARIANTS = 5
 } qb_render_variant;
 
+/* qb_tile_order -- the order in which the render's workgroups (one per
+ * tile) take tiles, heaviest first.  Scheduling only: the render and its
+ * backward compute every tile exactly as in row-major order; on a frame
+ * where all tiles' workgroups are resident at once, this order decides how
+ * evenly the work spreads over the compute units.
+ *   work[t]   estimated cost of tile t: the number of list entries the tile's
+ *             centre pixel (x0 + w/2, y0 + h/2 of the tile's pixel rect)
+ *             examines before its transmittance drops below 1e-4 (Eq. (2)),
+ *             followed over the first 256 entries with the transmittance
+ *             carried as a sum of log2(1 - alpha) in binary32; a pixel still
+ *             open there gets 256 * log2(1e-4) / log2(T_256) (its stop at the
+ *             same rate of attenuation), capped at the list length, or the
+ *             list length when T_256 = 1
+ *   order     a permutation of 0 .. tiles-1, tiles in non-increasing
+ *             min(work, 4095); equal values in no fixed order
+ *   ranges, ids, splats   from qb_sort / qb_project for this frame
+ *   work, order           [tiles_x * tiles_y] uint32 each                    */
+qb_status qb_tile_order(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
+                        const qb_splat* splats, uint32_t* work, uint32_t* order, qb_stream_t stream);
+
 /* qb_render_ex -- qb_render with an explicit launch shape (chosen, for
- * example, by timing each on the workload).  Same arguments as qb_render
- * plus `variant` (a qb_render_variant); results identical for every variant. */
+ * example, by timing each on the workload) and tile order.  Same arguments
+ * as qb_render plus `variant` (a qb_render_variant) and `tile_order`
+ * (qb_tile_order's order, or NULL for row-major; entries >= the tile count
+ * are skipped, so an order must be a permutation to render every tile);
+ * results identical for every variant and order. */
 qb_status qb_render_ex(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
                        const qb_splat* splats, const float* bg, float* image, float* final_T,
-                       uint32_t* n_contrib, uint32_t* n_touched, int32_t variant, qb_stream_t stream);
+                       uint32_t* n_contrib, uint32_t* n_touched, int32_t variant, const uint32_t* tile_order,
+                       qb_stream_t stream);
 
 /* qb_render_backward -- gradient of Eq. (2) (the rasterizer is trained
  * through; Sec. 4.1) with respect to each Gaussian's 2D parameters.  For
@@ -236,12 +262,14 @@ qb_status qb_render_backward(int32_t width, int32_t height, const uint32_t* rang
                              qb_stream_t stream);
 
 /* qb_render_backward_ex -- qb_render_backward with an explicit launch shape
- * (a qb_render_variant: pixels per lane); the same gradients up to the order
+ * (a qb_render_variant: pixels per lane) and tile order (as for qb_render_ex;
+ * the forward's order fits, the work per tile being alike); the same
+ * gradients up to the order
  * of the float atomic additions. */
 qb_status qb_render_backward_ex(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
                                 const qb_splat* splats, const float* bg, const float* final_T,
                                 const uint32_t* n_contrib, const float* dL_dimage, int64_t n, float* grad2d,
-                                int32_t variant, qb_stream_t stream);
+                                int32_t variant, const uint32_t* tile_order, qb_stream_t stream);
 
 /* qb_project_backward -- chain rule from grad2d (qb_render_backward) to the
  * inputs of qb_project (Sec. 2, Eq. 1; the projection of Sec. 2): through the
@@ -302,9 +330,17 @@ qb_status qb_project_views(int64_t n, const float* means, const float* log_scale
  * Same image, T and contributor counts per view as qb_render. */
 qb_status qb_render_views(int32_t num_views, const qb_view* views, const float* bg, qb_stream_t stream);
 
-/* qb_render_views_ex -- qb_render_views with a launch shape (qb_render_variant). */
+/* qb_tile_order_views -- qb_tile_order over the tiles of every view, in
+ * one order: global tile b is tile b - start(v) of view v, where start(v) is
+ * the tile count of views 0 .. v-1.  views as for qb_render_views (uses
+ * width, height, ranges, ids, splats); work, order [total tiles] uint32. */
+qb_status qb_tile_order_views(int32_t num_views, const qb_view* views, uint32_t* work, uint32_t* order,
+                              qb_stream_t stream);
+
+/* qb_render_views_ex -- qb_render_views with a launch shape (qb_render_variant)
+ * and a tile order over global tiles (qb_tile_order_views, or NULL). */
 qb_status qb_render_views_ex(int32_t num_views, const qb_view* views, const float* bg, int32_t variant,
-                             qb_stream_t stream);
+                             const uint32_t* tile_order, qb_stream_t stream);
 
 /* qb_render_backward_views -- qb_render_backward of every view in one
  * launch; each view's grad2d ([n][9]) is cleared first.  Uses every field of
@@ -312,9 +348,10 @@ qb_status qb_render_views_ex(int32_t num_views, const qb_view* views, const floa
 qb_status qb_render_backward_views(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
                                    qb_stream_t stream);
 
-/* qb_render_backward_views_ex -- with a launch shape (qb_render_variant). */
+/* qb_render_backward_views_ex -- with a launch shape (qb_render_variant) and a
+ * tile order over global tiles (qb_tile_order_views, or NULL). */
 qb_status qb_render_backward_views_ex(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
-                                      int32_t variant, qb_stream_t stream);
+                                      int32_t variant, const uint32_t* tile_order, qb_stream_t stream);
 
 /* qb_project_backward_views -- gradients of the loss summed over views:
  * one lane per Gaussian runs the chain rule of qb_project_backward for each

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libquadbox.so")
-SOURCES = ["api.hip", "project.hip", "intersect.hip", "sort.hip", "render.hip", "backward.hip"]
+SOURCES = ["api.hip", "project.hip", "intersect.hip", "sort.hip", "order.hip", "render.hip", "backward.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -243,18 +243,25 @@ template <int PPL>
 __global__ __launch_bounds__(256 / PPL) void k_render_backward(
     int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splats, float bg0, float bg1, float bg2, const float* __restrict__ final_T,
-    const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimg, float* __restrict__ grad2d)
+    const uint32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimg, float* __restrict__ grad2d,
+    const uint32_t* __restrict__ order)
 {
-    render_backward_tile<PPL>((int)blockIdx.x, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, final_T,
-                              n_contrib, dL_dimg, grad2d);
+    // workgroup i takes tile order[i] (qb_tile_order) or tile i
+    uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
+    if (tile >= gridDim.x) return;
+    render_backward_tile<PPL>((int)tile, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, final_T, n_contrib,
+                              dL_dimg, grad2d);
 }
 
-// Every tile of every view in one launch (global tile b = blockIdx.x).
+// Every tile of every view in one launch (global tile order[i] or i).
 template <int PPL>
-__global__ __launch_bounds__(256 / PPL) void k_render_backward_views(QbViewTable vt, float bg0, float bg1,
-                                                                     float bg2)
+__global__ __launch_bounds__(256 / PPL) void k_render_backward_views(QbViewTable vt,
+                                                                     const uint32_t* __restrict__ order, float bg0,
+                                                                     float bg1, float bg2)
 {
-    int b = (int)blockIdx.x;
+    uint32_t g = order ? order[blockIdx.x] : blockIdx.x;
+    if (g >= gridDim.x) return;
+    int b = (int)g;
     int v = qb_view_of(vt, b);
     const qb_view& w = vt.view[v];
     render_backward_tile<PPL>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v],
@@ -633,7 +640,8 @@ void make_bwd_cam(const qb_camera& cam, BwdCam* bc)
 extern "C" qb_status qb_render_backward_ex(int32_t width, int32_t height, const uint32_t* ranges,
                                            const uint32_t* ids, const qb_splat* splats, const float* bg,
                                            const float* final_T, const uint32_t* n_contrib, const float* dL_dimage,
-                                           int64_t n, float* grad2d, int32_t variant, qb_stream_t stream)
+                                           int64_t n, float* grad2d, int32_t variant, const uint32_t* tile_order,
+                                           qb_stream_t stream)
 {
     if (width <= 0 || height <= 0 || width > 32767 * QB_TILE || height > 32767 * QB_TILE || !ranges || !bg ||
         !final_T || !n_contrib || !dL_dimage || n < 0 || (n > 0 && (!grad2d || !splats)) || variant < 0 ||
@@ -652,15 +660,15 @@ extern "C" qb_status qb_render_backward_ex(int32_t width, int32_t height, const 
     switch (variant) {
     case QB_RENDER_2PX:
         QB_LAUNCH(k_render_backward<2>, tiles, 128, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0],
-                  bg[1], bg[2], final_T, n_contrib, dL_dimage, grad2d);
+                  bg[1], bg[2], final_T, n_contrib, dL_dimage, grad2d, tile_order);
         break;
     case QB_RENDER_1PX:
         QB_LAUNCH(k_render_backward<1>, tiles, 256, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0],
-                  bg[1], bg[2], final_T, n_contrib, dL_dimage, grad2d);
+                  bg[1], bg[2], final_T, n_contrib, dL_dimage, grad2d, tile_order);
         break;
     default:
         QB_LAUNCH(k_render_backward<4>, tiles, 64, 0, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg[0],
-                  bg[1], bg[2], final_T, n_contrib, dL_dimage, grad2d);
+                  bg[1], bg[2], final_T, n_contrib, dL_dimage, grad2d, tile_order);
         break;
     }
     return QB_OK;
@@ -672,7 +680,7 @@ extern "C" qb_status qb_render_backward(int32_t width, int32_t height, const uin
                                         float* grad2d, qb_stream_t stream)
 {
     return qb_render_backward_ex(width, height, ranges, ids, splats, bg, final_T, n_contrib, dL_dimage, n, grad2d,
-                                 QB_RENDER_2PX, stream);
+                                 QB_RENDER_2PX, nullptr, stream);
 }
 
 extern "C" qb_status qb_project_backward(int64_t n, const float* means, const float* log_scales,
@@ -704,7 +712,8 @@ extern "C" qb_status qb_project_backward(int64_t n, const float* means, const fl
 }
 
 extern "C" qb_status qb_render_backward_views_ex(int32_t num_views, const qb_view* views, const float* bg,
-                                                 int64_t n, int32_t variant, qb_stream_t stream)
+                                                 int64_t n, int32_t variant, const uint32_t* tile_order,
+                                                 qb_stream_t stream)
 {
     if (!bg || n < 0 || variant < 0 || variant > QB_RENDER_4PX) return QB_ERR_INVALID_ARG;
     QbViewTable vt;
@@ -718,9 +727,9 @@ extern "C" qb_status qb_render_backward_views_ex(int32_t num_views, const qb_vie
     int tiles = vt.tile_start[num_views];
     if (tiles == 0) return QB_OK;
     switch (variant) {
-    case QB_RENDER_2PX: QB_LAUNCH(k_render_backward_views<2>, tiles, 128, 0, s, vt, bg[0], bg[1], bg[2]); break;
-    case QB_RENDER_1PX: QB_LAUNCH(k_render_backward_views<1>, tiles, 256, 0, s, vt, bg[0], bg[1], bg[2]); break;
-    default: QB_LAUNCH(k_render_backward_views<4>, tiles, 64, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_2PX: QB_LAUNCH(k_render_backward_views<2>, tiles, 128, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_1PX: QB_LAUNCH(k_render_backward_views<1>, tiles, 256, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
+    default: QB_LAUNCH(k_render_backward_views<4>, tiles, 64, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
     }
     return QB_OK;
 }
@@ -728,7 +737,7 @@ extern "C" qb_status qb_render_backward_views_ex(int32_t num_views, const qb_vie
 extern "C" qb_status qb_render_backward_views(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
                                               qb_stream_t stream)
 {
-    return qb_render_backward_views_ex(num_views, views, bg, n, QB_RENDER_2PX, stream);
+    return qb_render_backward_views_ex(num_views, views, bg, n, QB_RENDER_2PX, nullptr, stream);
 }
 
 extern "C" qb_status qb_project_backward_views(int64_t n, const float* means, const float* log_scales,

@@ -19,11 +19,12 @@
 
 namespace {
 
-// Tiles go to workgroups in row-major order.  The dispatcher deals
-// workgroups round-robin to the 8 XCDs, so each XCD receives every 8th tile of
-// every row band: the heavy tiles of a dense region are spread over all XCDs
-// (measured faster than giving each XCD a contiguous band of tiles, which
-// keeps shared Gaussians in one L2 but leaves the XCDs unevenly loaded).
+// Tiles go to workgroups in the order qb_tile_order computes (estimated
+// work, heaviest first: every workgroup is resident from the start, so this
+// order decides how evenly the SIMDs are loaded), or in row-major order
+// without one.  Row-major was measured faster than giving each XCD a
+// contiguous band of tiles (the dispatcher deals workgroups round-robin to
+// the 8 XCDs, so row-major spreads a dense region over all of them).
 //
 // Launch shape: PPL pixels per lane, all in one row of the tile, 16/PPL
 // apart (256/PPL lanes per tile).  The row terms of the quadratic form and
@@ -220,23 +221,32 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
 }
 
 // COUNT: also write n_touched (entries examined per pixel), compiled out of
-// the launches that do not ask for it.
+// the launches that do not ask for it.  Workgroup i takes tile order[i]
+// (qb_tile_order), or tile i when order is NULL; an entry past the last tile
+// is skipped.
 template <int PPL, bool COUNT, bool SKIP>
 __global__ __launch_bounds__(256 / PPL) void k_render(
     int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splats, float bg0, float bg1, float bg2, float* __restrict__ image,
-    float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_touched)
+    float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_touched,
+    const uint32_t* __restrict__ order)
 {
-    render_tile<PPL, COUNT, SKIP>((int)blockIdx.x, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T, n_contrib,
-                     n_touched);
+    uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
+    if (tile >= gridDim.x) return;
+    render_tile<PPL, COUNT, SKIP>((int)tile, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T,
+                                  n_contrib, n_touched);
 }
 
-// Every tile of every view in one launch: workgroup b takes global tile b,
-// whose view is found in the (at most QB_MAX_VIEWS) tile offsets.
+// Every tile of every view in one launch: workgroup i takes global tile
+// order[i] (or i), whose view is found in the (at most QB_MAX_VIEWS) tile
+// offsets.
 template <int PPL, bool SKIP>
-__global__ __launch_bounds__(256 / PPL) void k_render_views(QbViewTable vt, float bg0, float bg1, float bg2)
+__global__ __launch_bounds__(256 / PPL) void k_render_views(QbViewTable vt, const uint32_t* __restrict__ order,
+                                                            float bg0, float bg1, float bg2)
 {
-    int b = (int)blockIdx.x;
+    uint32_t g = order ? order[blockIdx.x] : blockIdx.x;
+    if (g >= gridDim.x) return;
+    int b = (int)g;
     int v = qb_view_of(vt, b);
     const qb_view& w = vt.view[v];
     render_tile<PPL, false, SKIP>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
@@ -250,26 +260,27 @@ __global__ __launch_bounds__(256 / PPL) void k_render_views(QbViewTable vt, floa
 template <bool COUNT>
 static qb_status launch_render(int variant, int64_t tiles, hipStream_t s, int W, int H, int tiles_x,
                                const uint2* rg, const uint32_t* ids, const float4* sp, const float* bg, float* image,
-                               float* final_T, uint32_t* n_contrib, uint32_t* n_touched)
+                               float* final_T, uint32_t* n_contrib, uint32_t* n_touched, const uint32_t* order)
 {
     switch (variant) {
     case QB_RENDER_2PX: QB_LAUNCH((k_render<2, COUNT, false>), tiles, 128, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
-                                  bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, order); break;
     case QB_RENDER_1PX: QB_LAUNCH((k_render<1, COUNT, false>), tiles, 256, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
-                                  bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, order); break;
     case QB_RENDER_4PX: QB_LAUNCH((k_render<4, COUNT, false>), tiles, 64, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
-                                  bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, order); break;
     case QB_RENDER_2PX_ROWS: QB_LAUNCH((k_render<2, COUNT, true>), tiles, 128, 0, s, W, H, tiles_x, rg, ids, sp,
-                                       bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched); break;
+                                       bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched, order); break;
     default: QB_LAUNCH((k_render<1, COUNT, true>), tiles, 256, 0, s, W, H, tiles_x, rg, ids, sp, bg[0], bg[1],
-                       bg[2], image, final_T, n_contrib, n_touched); break;
+                       bg[2], image, final_T, n_contrib, n_touched, order); break;
     }
     return QB_OK;
 }
 
 extern "C" qb_status qb_render_ex(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
                                   const qb_splat* splats, const float* bg, float* image, float* final_T,
-                                  uint32_t* n_contrib, uint32_t* n_touched, int32_t variant, qb_stream_t stream)
+                                  uint32_t* n_contrib, uint32_t* n_touched, int32_t variant,
+                                  const uint32_t* tile_order, qb_stream_t stream)
 {
     if (width <= 0 || height <= 0 || width > 32767 * QB_TILE || height > 32767 * QB_TILE || !ranges ||
         !image || !bg || variant < 0 || variant >= QB_RENDER_VARIANTS)
@@ -282,9 +293,9 @@ extern "C" qb_status qb_render_ex(int32_t width, int32_t height, const uint32_t*
     const float4* sp = reinterpret_cast<const float4*>(splats);
     if (n_touched)
         return launch_render<true>(variant, tiles, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg, image, final_T,
-                                   n_contrib, n_touched);
+                                   n_contrib, n_touched, tile_order);
     return launch_render<false>(variant, tiles, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg, image, final_T,
-                                n_contrib, n_touched);
+                                n_contrib, n_touched, tile_order);
 }
 
 extern "C" qb_status qb_render(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
@@ -292,11 +303,11 @@ extern "C" qb_status qb_render(int32_t width, int32_t height, const uint32_t* ra
                                uint32_t* n_contrib, uint32_t* n_touched, qb_stream_t stream)
 {
     return qb_render_ex(width, height, ranges, ids, splats, bg, image, final_T, n_contrib, n_touched, QB_RENDER_2PX,
-                        stream);
+                        nullptr, stream);
 }
 
 extern "C" qb_status qb_render_views_ex(int32_t num_views, const qb_view* views, const float* bg, int32_t variant,
-                                        qb_stream_t stream)
+                                        const uint32_t* tile_order, qb_stream_t stream)
 {
     if (!bg || variant < 0 || variant >= QB_RENDER_VARIANTS) return QB_ERR_INVALID_ARG;
     QbViewTable vt;
@@ -306,16 +317,16 @@ extern "C" qb_status qb_render_views_ex(int32_t num_views, const qb_view* views,
     if (tiles == 0) return QB_OK;
     hipStream_t s = qb_hip_stream(stream);
     switch (variant) {
-    case QB_RENDER_2PX: QB_LAUNCH((k_render_views<2, false>), tiles, 128, 0, s, vt, bg[0], bg[1], bg[2]); break;
-    case QB_RENDER_1PX: QB_LAUNCH((k_render_views<1, false>), tiles, 256, 0, s, vt, bg[0], bg[1], bg[2]); break;
-    case QB_RENDER_4PX: QB_LAUNCH((k_render_views<4, false>), tiles, 64, 0, s, vt, bg[0], bg[1], bg[2]); break;
-    case QB_RENDER_2PX_ROWS: QB_LAUNCH((k_render_views<2, true>), tiles, 128, 0, s, vt, bg[0], bg[1], bg[2]); break;
-    default: QB_LAUNCH((k_render_views<1, true>), tiles, 256, 0, s, vt, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_2PX: QB_LAUNCH((k_render_views<2, false>), tiles, 128, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_1PX: QB_LAUNCH((k_render_views<1, false>), tiles, 256, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_4PX: QB_LAUNCH((k_render_views<4, false>), tiles, 64, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_2PX_ROWS: QB_LAUNCH((k_render_views<2, true>), tiles, 128, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
+    default: QB_LAUNCH((k_render_views<1, true>), tiles, 256, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
     }
     return QB_OK;
 }
 
 extern "C" qb_status qb_render_views(int32_t num_views, const qb_view* views, const float* bg, qb_stream_t stream)
 {
-    return qb_render_views_ex(num_views, views, bg, QB_RENDER_2PX, stream);
+    return qb_render_views_ex(num_views, views, bg, QB_RENDER_2PX, nullptr, stream);
 }

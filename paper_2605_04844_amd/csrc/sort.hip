@@ -5,8 +5,8 @@
 // sort over the tile bits alone: ceil(log2 tiles) bits in passes of at most
 // 8 (one pass at 256 tiles, two of 6-7 bits at 3600-8160).  Each pass stages
 // its items in LDS by digit and writes them as contiguous runs.  Ranges come
-// from two binary searches per tile over the sorted tiles (lower bounds of t
-// and t+1), which also places empty tiles exactly.  The 64-bit keys
+// from two searches per tile over the sorted tiles (lower bounds of t and
+// t+1), which also places empty tiles exactly.  The 64-bit keys
 // tile << 32 | bits(depth) are written only when asked for.
 #include "qb_radix.h"
 
@@ -14,25 +14,43 @@ namespace {
 
 constexpr int kSortNT = 512, kSortNI = 8;  // 4096 pairs per workgroup (measured best at 10^7 pairs)
 
+// One wave per tile: lanes 0-31 find the first index whose tile is >= t,
+// lanes 32-63 the first whose tile is >= t + 1, each half by a 32-ary
+// search.  Invariant: every index below lo holds a smaller tile, every index
+// from hi on a tile >= the target.  A round probes 32 points that split
+// [lo, hi) into 33 parts; the probes below the target form a prefix (the
+// list is sorted), so their count c (one ballot) names the part that holds
+// the bound.  Once hi - lo <= 32 the candidates themselves are probed.  At
+// 10^7 - 10^8 pairs that is five rounds of one gather each, against the 25
+// dependent loads of a per-thread binary search.
 __global__ __launch_bounds__(QB_BLOCK) void k_ranges(const uint16_t* __restrict__ tiles,
                                                      const int64_t* __restrict__ num_pairs, int64_t cap,
                                                      int num_tiles, uint32_t* __restrict__ ranges)
 {
-    int t = blockIdx.x * QB_BLOCK + threadIdx.x;
+    int t = blockIdx.x * (QB_BLOCK / 64) + (int)(threadIdx.x / 64);
     if (t >= num_tiles) return;
+    int lane = threadIdx.x & 63, half = lane >> 5, k = lane & 31;
     int64_t n = qbr::sort_count(num_pairs, 0, cap);
-    uint32_t bound[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        uint32_t target = (uint32_t)(t + e);
-        int64_t lo = 0, hi = n;
-        while (lo < hi) {
-            int64_t mid = lo + ((hi - lo) >> 1);
-            if ((uint32_t)tiles[mid] < target) lo = mid + 1; else hi = mid;
+    uint32_t target = (uint32_t)(t + half);
+    int64_t lo = 0, hi = n;
+    for (;;) {
+        bool wide = hi - lo > 32;
+        if (!__any(wide)) break;
+        bool below = false;
+        if (wide) below = (uint32_t)tiles[lo + ((hi - lo) * (k + 1)) / 33] < target;
+        int c = __popc((uint32_t)(__ballot(below) >> (32 * half)));
+        if (wide) {
+            int64_t span = hi - lo;
+            int64_t nlo = c == 0 ? lo : lo + (span * c) / 33 + 1;
+            int64_t nhi = c == 32 ? hi : lo + (span * (c + 1)) / 33;
+            lo = nlo;
+            hi = nhi;
         }
-        bound[e] = (uint32_t)lo;
     }
-    reinterpret_cast<uint2*>(ranges)[t] = make_uint2(bound[0], bound[1]);
+    bool below = lo + k < hi && (uint32_t)tiles[lo + k] < target;
+    uint32_t bound = (uint32_t)(lo + __popc((uint32_t)(__ballot(below) >> (32 * half))));
+    uint32_t upper = __shfl(bound, 32);
+    if (lane == 0) reinterpret_cast<uint2*>(ranges)[t] = make_uint2(bound, upper);
 }
 
 __global__ __launch_bounds__(QB_BLOCK) void k_make_keys(const uint16_t* __restrict__ tiles,
@@ -109,7 +127,7 @@ extern "C" qb_status qb_sort(int64_t pair_capacity, const int64_t* num_pairs, in
                       reinterpret_cast<const float4*>(splats), num_pairs, pair_capacity, keys);
         }
     }
-    QB_LAUNCH(k_ranges, qb_div_up(num_tiles, QB_BLOCK), QB_BLOCK, 0, s, (const uint16_t*)w.tiles_sorted, num_pairs,
+    QB_LAUNCH(k_ranges, qb_div_up(num_tiles, QB_BLOCK / 64), QB_BLOCK, 0, s, (const uint16_t*)w.tiles_sorted, num_pairs,
               pair_capacity, (int)num_tiles, ranges);
     return QB_OK;
 }

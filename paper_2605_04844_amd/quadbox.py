@@ -75,11 +75,13 @@ def lib():
     L.qb_sort.restype = i32
     L.qb_render.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.qb_render.restype = i32
-    L.qb_render_ex.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]
+    L.qb_render_ex.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]
     L.qb_render_ex.restype = i32
     L.qb_render_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp]
     L.qb_render_backward.restype = i32
-    L.qb_render_backward_ex.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp, i32, vp]
+    L.qb_render_backward_ex.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp, i32, vp, vp]
+    L.qb_tile_order.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
+    L.qb_tile_order.restype = i32
     L.qb_render_backward_ex.restype = i32
     L.qb_project_backward.argtypes = [i64, vp, vp, vp, vp, vp, i32, C.POINTER(CCamera), vp, vp, vp, vp, vp, vp, vp,
                                       vp]
@@ -89,11 +91,13 @@ def lib():
     L.qb_project_views.restype = i32
     L.qb_render_views.argtypes = [i32, C.POINTER(CView), vp, vp]
     L.qb_render_views.restype = i32
-    L.qb_render_views_ex.argtypes = [i32, C.POINTER(CView), vp, i32, vp]
+    L.qb_render_views_ex.argtypes = [i32, C.POINTER(CView), vp, i32, vp, vp]
+    L.qb_tile_order_views.argtypes = [i32, C.POINTER(CView), vp, vp, vp]
+    L.qb_tile_order_views.restype = i32
     L.qb_render_views_ex.restype = i32
     L.qb_render_backward_views.argtypes = [i32, C.POINTER(CView), vp, i64, vp]
     L.qb_render_backward_views.restype = i32
-    L.qb_render_backward_views_ex.argtypes = [i32, C.POINTER(CView), vp, i64, i32, vp]
+    L.qb_render_backward_views_ex.argtypes = [i32, C.POINTER(CView), vp, i64, i32, vp, vp]
     L.qb_render_backward_views_ex.restype = i32
     L.qb_project_backward_views.argtypes = [i64, vp, vp, vp, vp, vp, i32, pc, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.qb_project_backward_views.restype = i32
@@ -200,19 +204,25 @@ def sort(capacity, num_pairs, num_tiles, pair_tiles, pair_ids, splats, keys, ids
         _ptr(ids), _ptr(ranges), _ptr(ws), ws.numel() * ws.element_size(), _stream()))
 
 
+def tile_order(width, height, ranges, ids, splats, work, order):
+    _check("qb_tile_order", lib().qb_tile_order(
+        width, height, _ptr(ranges), _ptr(ids), _ptr(splats), _ptr(work), _ptr(order), _stream()))
+
+
 def render(width, height, ranges, ids, splats, bg, image, final_T=None, n_contrib=None, n_touched=None,
-           variant=0):
+           variant=0, order=None):
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
     _check("qb_render_ex", lib().qb_render_ex(
         width, height, _ptr(ranges), _ptr(ids), _ptr(splats), C.cast(bgv, C.c_void_p), _ptr(image), _ptr(final_T),
-        _ptr(n_contrib), _ptr(n_touched), int(variant), _stream()))
+        _ptr(n_contrib), _ptr(n_touched), int(variant), _ptr(order), _stream()))
 
 
-def render_backward(width, height, ranges, ids, splats, bg, final_T, n_contrib, dl_dimage, n, grad2d, variant=0):
+def render_backward(width, height, ranges, ids, splats, bg, final_T, n_contrib, dl_dimage, n, grad2d, variant=0,
+                    order=None):
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
     _check("qb_render_backward_ex", lib().qb_render_backward_ex(
         width, height, _ptr(ranges), _ptr(ids), _ptr(splats), C.cast(bgv, C.c_void_p), _ptr(final_T),
-        _ptr(n_contrib), _ptr(dl_dimage), n, _ptr(grad2d), int(variant), _stream()))
+        _ptr(n_contrib), _ptr(dl_dimage), n, _ptr(grad2d), int(variant), _ptr(order), _stream()))
 
 
 def project_backward(g: Gaussians, cam, splats, grad2d, d_means, d_log_scales, d_quats, d_logits, d_sh):
@@ -233,10 +243,14 @@ class Rasterizer:
     nothing is read back and a frame that overflowed renders empty tiles
     (check ``pairs() <= capacity`` afterwards).  ``write_keys`` selects
     whether the sorted 64-bit keys are materialised (the render needs only
-    the sorted ids)."""
+    the sorted ids).  With ``balance`` (the default) the forward runs
+    qb_tile_order after the sort and the render and its backward take the
+    tiles heaviest first; results are the same either way."""
 
-    def __init__(self, n: int, cam, device="cuda", capacity: int = 0, write_keys: bool = True):
+    def __init__(self, n: int, cam, device="cuda", capacity: int = 0, write_keys: bool = True,
+                 balance: bool = True):
         self.n, self.cam, self.device = n, cam, device
+        self.balance = balance
         self.W, self.H = int(cam.width), int(cam.height)
         self.num_tiles = cam.tiles_x * cam.tiles_y
         self.write_keys = write_keys
@@ -250,6 +264,8 @@ class Rasterizer:
         self.num_pairs = torch.zeros(1, dtype=torch.int64, device=d)
         self.ws_isect = torch.empty(intersect_workspace_size(n), dtype=torch.uint8, device=d)
         self.ranges = torch.empty((self.num_tiles, 2), dtype=torch.int32, device=d)
+        self.work = torch.zeros(self.num_tiles, dtype=torch.int32, device=d)
+        self.order = torch.arange(self.num_tiles, dtype=torch.int32, device=d)
         self.image = torch.empty((3, self.H, self.W), dtype=torch.float32, device=d)
         self.final_T = torch.empty((self.H, self.W), dtype=torch.float32, device=d)
         self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=d)
@@ -280,9 +296,18 @@ class Rasterizer:
         sort(self.capacity, self.num_pairs, self.num_tiles, self.pair_tiles, self.pair_ids, self.splats,
              self.keys_sorted, self.ids_sorted, self.ranges, self.ws_sort)
 
+    def schedule(self):
+        """qb_tile_order for the sorted frame (a no-op without balance)."""
+        if self.balance:
+            tile_order(self.W, self.H, self.ranges, self.ids_sorted, self.splats, self.work, self.order)
+
+    def tile_order(self):
+        """The order the render takes tiles in (None: row-major)."""
+        return self.order if self.balance else None
+
     def render(self, bg=(0.0, 0.0, 0.0)):
         render(self.W, self.H, self.ranges, self.ids_sorted, self.splats, bg, self.image, self.final_T,
-               self.n_contrib, self.n_touched, self.render_variant)
+               self.n_contrib, self.n_touched, self.render_variant, self.tile_order())
 
     def forward(self, g: Gaussians, mode="quadbox", bg=(0.0, 0.0, 0.0), sync_count=True):
         self.project(g, mode)
@@ -293,6 +318,7 @@ class Rasterizer:
                 self._alloc_pairs(int(p * 1.1) + 1024)
                 self.intersect()
         self.sort()
+        self.schedule()
         self.render(bg)
         return self.image
 
@@ -304,7 +330,8 @@ class Rasterizer:
 
 class _Rasterize(torch.autograd.Function):
     """Forward: qb_project -> qb_intersect -> qb_sort -> qb_render.
-    Backward: qb_render_backward -> qb_project_backward."""
+    Backward: qb_render_backward (in the forward's tile order) ->
+    qb_project_backward."""
 
     @staticmethod
     def forward(ctx, means, log_scales, quats, logits, sh, cam, mode, bg, rast):
@@ -319,7 +346,7 @@ class _Rasterize(torch.autograd.Function):
         dl = dl_dimage.contiguous().float()
         grad2d = torch.empty((max(g.n, 1), 9), dtype=torch.float32, device=dl.device)
         render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, ctx.bg, r.final_T, r.n_contrib, dl, g.n, grad2d,
-                        r.backward_variant)
+                        r.backward_variant, r.tile_order())
         d = [torch.empty_like(t) for t in g.tensors()]
         project_backward(g, ctx.cam, r.splats, grad2d, *d)
         ctx.grad2d = grad2d
@@ -344,16 +371,21 @@ def project_views(g: Gaussians, cam_array, num_views, mode, splats, rects, count
         num_views, _mode(mode), _ptr(splats), _ptr(rects), _ptr(counts), _stream()))
 
 
-def render_views(view_array, num_views, bg, variant=0):
+def tile_order_views(view_array, num_views, work, order):
+    _check("qb_tile_order_views", lib().qb_tile_order_views(num_views, view_array, _ptr(work), _ptr(order),
+                                                            _stream()))
+
+
+def render_views(view_array, num_views, bg, variant=0, order=None):
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
     _check("qb_render_views_ex", lib().qb_render_views_ex(num_views, view_array, C.cast(bgv, C.c_void_p),
-                                                          int(variant), _stream()))
+                                                          int(variant), _ptr(order), _stream()))
 
 
-def render_backward_views(view_array, num_views, bg, n, variant=0):
+def render_backward_views(view_array, num_views, bg, n, variant=0, order=None):
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
     _check("qb_render_backward_views_ex", lib().qb_render_backward_views_ex(
-        num_views, view_array, C.cast(bgv, C.c_void_p), n, int(variant), _stream()))
+        num_views, view_array, C.cast(bgv, C.c_void_p), n, int(variant), _ptr(order), _stream()))
 
 
 def project_backward_views(g: Gaussians, cam_array, num_views, splats, grad2d, d_means, d_log_scales, d_quats,
@@ -372,9 +404,11 @@ class MultiView:
     qb_project_backward_views (gradients summed over views).  The buffers
     persist, so a whole step can be captured in a HIP graph once the pair
     buffers are sized (size_pairs); a frame whose pair count exceeds its
-    view's capacity renders that view empty (check overflowed())."""
+    view's capacity renders that view empty (check overflowed()).  With
+    ``balance`` (the default) qb_tile_order_views orders every view's tiles
+    in one list, heaviest first, for the render and its backward."""
 
-    def __init__(self, n: int, cams, device="cuda", streams: int = 4):
+    def __init__(self, n: int, cams, device="cuda", streams: int = 4, balance: bool = True):
         self.V = len(cams)
         if not 1 <= self.V <= MAX_VIEWS:
             raise ValueError(f"1..{MAX_VIEWS} views per MultiView")
@@ -399,6 +433,10 @@ class MultiView:
         self.n_contrib = [torch.zeros((h, w), dtype=torch.int32, device=d) for w, h in self.sizes]
         self.dl = [torch.zeros((3, h, w), dtype=torch.float32, device=d) for w, h in self.sizes]
         self.grad2d = torch.empty((V, n1, 9), dtype=torch.float32, device=d)
+        self.balance = balance
+        total_tiles = sum(self.num_tiles)
+        self.work = torch.zeros(total_tiles, dtype=torch.int32, device=d)
+        self.order = torch.arange(total_tiles, dtype=torch.int32, device=d)
         self.capacity = [0] * V
         self.mode = "quadbox"
         self.render_variant = RENDER_VARIANTS["2px"]
@@ -485,18 +523,24 @@ class MultiView:
                  self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort[v % self.S])
 
         self._per_view(prep)
-        render_views(self._table, self.V, bg, self.render_variant)
+        if self.balance:
+            tile_order_views(self._table, self.V, self.work, self.order)
+        self.render(bg)
         return self.images
 
+    def tile_order(self):
+        """The order the render takes global tiles in (None: row-major)."""
+        return self.order if self.balance else None
+
     def render(self, bg=(0.0, 0.0, 0.0)):
-        render_views(self._table, self.V, bg, self.render_variant)
+        render_views(self._table, self.V, bg, self.render_variant, self.tile_order())
 
     def backward(self, g: Gaussians, bg=(0.0, 0.0, 0.0)):
         """Gradients of sum over views of <dl[v], image[v]> (fill self.dl
         first); returns (d_means, d_log_scales, d_quats, d_logits, d_sh)."""
         if self.grads is None:
             self.grads = [torch.empty_like(t) for t in g.tensors()]
-        render_backward_views(self._table, self.V, bg, self.n, self.backward_variant)
+        render_backward_views(self._table, self.V, bg, self.n, self.backward_variant, self.tile_order())
         project_backward_views(g, self.cam_array, self.V, self.splats, self.grad2d, *self.grads)
         return self.grads
 
@@ -530,10 +574,10 @@ def autotune_backward(run, bg=(0.0, 0.0, 0.0), dl=None, grad2d=None, reps=5, tri
     times = {}
     for name, v in BACKWARD_VARIANTS.items():
         if isinstance(run, MultiView):
-            fn = (lambda v=v: render_backward_views(run._table, run.V, bg, run.n, v))
+            fn = (lambda v=v: render_backward_views(run._table, run.V, bg, run.n, v, run.tile_order()))
         else:
             fn = (lambda v=v: render_backward(run.W, run.H, run.ranges, run.ids_sorted, run.splats, bg, run.final_T,
-                                              run.n_contrib, dl, run.n, grad2d, v))
+                                              run.n_contrib, dl, run.n, grad2d, v, run.tile_order()))
         times[name] = _best(fn, reps, trials)
     pick = min(times, key=times.get)
     run.backward_variant = BACKWARD_VARIANTS[pick]

@@ -93,9 +93,9 @@ def test_launch_shape_and_view_entry_points_reject_bad_arguments():
     bg = (C.c_float * 3)(0.0, 0.0, 0.0)
     bgp = C.cast(bg, C.c_void_p)
     # launch shapes out of range
-    assert L.qb_render_ex(64, 48, d, d, d, bgp, d, None, None, None, 5, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_render_ex(64, 48, d, d, d, bgp, d, None, None, None, -1, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_render_backward_ex(64, 48, d, d, d, bgp, d, d, d, 10, d, 3, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_ex(64, 48, d, d, d, bgp, d, None, None, None, 5, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_ex(64, 48, d, d, d, bgp, d, None, None, None, -1, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_backward_ex(64, 48, d, d, d, bgp, d, d, d, 10, d, 3, None, None) == qb.QB_ERR_INVALID_ARG
     # view tables: count, null table, bad sizes, missing buffers
     views = (qb.CView * (qb.MAX_VIEWS + 1))()
     for v in views:
@@ -104,7 +104,7 @@ def test_launch_shape_and_view_entry_points_reject_bad_arguments():
     assert L.qb_render_views(0, views, bgp, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_render_views(qb.MAX_VIEWS + 1, views, bgp, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_render_views(1, None, bgp, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_render_views_ex(1, views, bgp, 9, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_views_ex(1, views, bgp, 9, None, None) == qb.QB_ERR_INVALID_ARG
     views[1].width = 0
     assert L.qb_render_views(2, views, bgp, None) == qb.QB_ERR_INVALID_ARG
     views[1].width = 64
@@ -112,7 +112,15 @@ def test_launch_shape_and_view_entry_points_reject_bad_arguments():
     assert L.qb_render_views(2, views, bgp, None) == qb.QB_ERR_INVALID_ARG
     views[1].dL_dimage = None
     assert L.qb_render_backward_views(2, views, bgp, 10, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_render_backward_views_ex(1, views, bgp, 10, 4, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_backward_views_ex(1, views, bgp, 10, 4, None, None) == qb.QB_ERR_INVALID_ARG
+    # tile order: sizes, null buffers, view tables
+    assert L.qb_tile_order(0, 48, d, d, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_tile_order(64, 48, None, d, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_tile_order(64, 48, d, d, d, None, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_tile_order(64, 48, d, d, d, d, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_tile_order_views(0, views, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_tile_order_views(1, views, None, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_tile_order_views(2, views, d, d, None) == qb.QB_ERR_INVALID_ARG   # view 1 has no image
     cams = (qb.CCamera * (qb.MAX_VIEWS + 1))(*[_cam() for _ in range(qb.MAX_VIEWS + 1)])
     assert L.qb_project_views(10, d, d, d, d, d, 0, cams, 0, 2, d, d, d, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_project_views(10, d, d, d, d, d, 0, cams, qb.MAX_VIEWS + 1, 2, d, d, d, None) == \
