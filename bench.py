@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--no-backward", action="store_true", help="skip the forward+backward timing")
     ap.add_argument("--no-multiview", action="store_true", help="skip the 32-view forward+backward timing")
     ap.add_argument("--no-zoom", action="store_true", help="skip the 3M anisotropic zoom sweep")
+    ap.add_argument("--no-rowmajor", action="store_true",
+                    help="skip timing the render with row-major tiles (keeps a kernel trace's render average to "
+                         "the work-ordered launches)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -94,7 +97,7 @@ class StageTimer:
         return {n: sum(a.elapsed_time(b) for a, b in v) / max(len(v), 1) for n, v in self.ev.items()}
 
 
-def run_mode(torch, qb, g, cam, mode, steps, warmup, trials):
+def run_mode(torch, qb, g, cam, mode, steps, warmup, trials, rowmajor=True):
     # the timed frames leave the sorted 64-bit keys unmaterialised: the render
     # reads only the sorted ids and the ranges
     r = qb.Rasterizer(g.n, cam, write_keys=False)
@@ -175,9 +178,11 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials):
     render_launch_ms = _time(torch, r.render, 20, 2, trials)
     # the same launches with the tiles in row-major order (no qb_tile_order):
     # what the work-ordered dispatch gains
-    r.balance = False
-    rowmajor_ms = _time(torch, r.render, 20, 2, trials)
-    r.balance = True
+    rowmajor_ms = None
+    if rowmajor:
+        r.balance = False
+        rowmajor_ms = _time(torch, r.render, 20, 2, trials)
+        r.balance = True
     evals = render_evaluations(torch, r)
     names = {v: k for k, v in qb.RENDER_VARIANTS.items()}
     return dict(ms=min(dev, graph_ms), eager_ms=dev, graph_ms=graph_ms, wall_ms=wall, pairs=pairs, stage_ms=stage,
@@ -334,7 +339,7 @@ def run_zoom_sweep(torch, qb, steps, trials):
     for k, cam in enumerate(cams, start=1):
         row = {"zoom": k}
         for mode in ("quadbox", "adr", "3sigma"):
-            res = run_mode(torch, qb, g, cam, mode, steps, 2, trials)
+            res = run_mode(torch, qb, g, cam, mode, steps, 2, trials, rowmajor=False)
             row[mode] = {"pairs": res["pairs"], "fps": round(1000.0 / res["ms"], 2), "ms": round(res["ms"], 4)}
             del res
         row["quadbox_vs_3sigma"] = round(row["3sigma"]["ms"] / row["quadbox"]["ms"], 3)
@@ -463,7 +468,8 @@ def main():
     modes = args.modes.split(",")
     for mode in modes:
         log("mode", mode)
-        results[mode] = run_mode(torch, qb, g, cam, mode, args.steps, args.warmup, args.trials)
+        results[mode] = run_mode(torch, qb, g, cam, mode, args.steps, args.warmup, args.trials,
+                                 rowmajor=not args.no_rowmajor)
         res = results[mode]
         log(mode, f"{res['ms']:.3f} ms/frame, {res['pairs']} pairs, stages",
             {k: round(v, 4) for k, v in res["stage_ms"].items()})
@@ -512,7 +518,8 @@ def main():
                       "eager_ms": round(r["eager_ms"], 4), "graph_ms": round(r["graph_ms"], 4),
                       "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
                       "render_launch_ms": round(r["render_launch_ms"], 4),
-                      "render_rowmajor_ms": round(r["render_rowmajor_ms"], 4),
+                      "render_rowmajor_ms": (round(r["render_rowmajor_ms"], 4)
+                                             if r["render_rowmajor_ms"] is not None else None),
                       "render_shape": r["render_shape"], "render_shape_ms": r["shape_ms"],
                       **image_delta(torch, r["rast"].image, q["rast"].image)}
                   for m, r in results.items()},
