@@ -201,3 +201,38 @@ def test_tile_order_views(qb):
         o += t
         assert torch.equal(mv.images[v], mv0.images[v]), v
         assert torch.equal(mv.n_contrib[v], mv0.n_contrib[v]), v
+
+
+def test_tile_order_in_graph_replay(qb):
+    """A single-view forward captured in a HIP graph recomputes the tile
+    order on every replay: with the order overwritten between replays (every
+    entry tile 0: in range, not a permutation) the replayed image still
+    equals the eager one, and the estimates are rewritten."""
+    scene, _ = scenes.random_scene(205, 8000, 300, 180, 300.0, sh_degree=1)
+    cam = scenes.pinhole(300, 180, 300.0)
+    g = qb.Gaussians(scene)
+    r = qb.Rasterizer(scene.n, cam, write_keys=False)
+    r.forward(g, "quadbox")
+    torch.cuda.synchronize()
+    r._alloc_pairs(r.pairs() + 1024)
+    r.forward(g, "quadbox", sync_count=False)
+    torch.cuda.synchronize()
+    want, want_work = r.image.clone(), r.work.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        r.forward(g, "quadbox", sync_count=False)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        r.forward(g, "quadbox", sync_count=False)
+    for rep in range(3):
+        r.image.fill_(-1.0)
+        r.order.zero_()
+        r.work.fill_(7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(r.image, want), rep
+        assert torch.equal(r.work, want_work), rep
+        check_order(r.work.cpu().numpy().astype(np.int64), r.order.cpu().numpy().astype(np.int64), f"replay {rep}")

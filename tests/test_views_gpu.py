@@ -150,6 +150,7 @@ def test_views_graph_replay(qb):
     torch.cuda.synchronize()
     want_img = [x.clone() for x in mv.images]
     want_grad = [x.clone() for x in mv.grads]
+    want_work = mv.work.clone()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -163,10 +164,17 @@ def test_views_graph_replay(qb):
             x.fill_(-1.0)
         for x in mv.grads:
             x.fill_(123.0)
+        # a replay must recompute the tile order: with every entry naming
+        # tile 0 (in range, but not a permutation) the images would be wrong
+        mv.order.zero_()
+        mv.work.fill_(7)
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
         assert not mv.overflowed()
+        assert torch.equal(mv.work, want_work), rep
+        order = mv.order.cpu().numpy()
+        assert np.array_equal(np.sort(order), np.arange(len(order))), rep
         for v in range(mv.V):
             assert torch.equal(mv.images[v], want_img[v]), (rep, v)
         for a, b in zip(mv.grads, want_grad):
