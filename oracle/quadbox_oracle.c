@@ -37,6 +37,10 @@
 #define OC_TILE 16
 
 enum { OC_BOX_3SIGMA = 0, OC_BOX_ADR = 1, OC_BOX_QUADBOX = 2, OC_BOX_DUALBOX = 3 };
+/* Flag added to an opacity-aware mode: each sub-box's tile rect is
+ * intersected with the tile rect of the 3-sigma square (the reading that
+ * keeps every tile set inside the 3-sigma baseline's, Sec. 2 vs Sec. 3.1). */
+enum { OC_CLIP_3SIGMA = 16 };
 
 /* Camera: world->camera rotation R (row-major) and translation t, pinhole
  * intrinsics; x right, y down, z forward; pixel (i, j) samples the point (i, j). */
@@ -133,6 +137,7 @@ static int oc_box_rect(float x0, float x1, float y0, float y1, int W, int H, int
 int oc_pixel_boxes(const oc_gauss* g, int mode, float box[4][4])
 {
     float u = g->u, v = g->v, A = g->A, B = g->B, C = g->C, gam = g->gamma;
+    mode &= ~OC_CLIP_3SIGMA;   /* the clip acts on tile rects (oc_build_boxes) */
     if (mode == OC_BOX_3SIGMA) {
         /* square of side 6 sqrt(lambda_max) (Sec. 2), radius rounded up to a
          * whole pixel, discriminant floored at 0.1 */
@@ -180,15 +185,33 @@ int oc_pixel_boxes(const oc_gauss* g, int mode, float box[4][4])
     return nb;
 }
 
-/* Tile rects of the boxes; empty ones are dropped.  Fills g->rect / g->nrect. */
+/* Tile rects of the boxes; empty ones are dropped.  Fills g->rect / g->nrect.
+ * With OC_CLIP_3SIGMA each rect is cut to the 3-sigma square's tile rect. */
 void oc_build_boxes(oc_gauss* g, int mode, int W, int H)
 {
     float box[4][4];
-    int nb = oc_pixel_boxes(g, mode, box);
+    int nb = oc_pixel_boxes(g, mode & ~OC_CLIP_3SIGMA, box);
+    int32_t sq[4];
+    int have_sq = 1;
+    if (mode & OC_CLIP_3SIGMA) {
+        float b3[4][4];
+        oc_pixel_boxes(g, OC_BOX_3SIGMA, b3);
+        have_sq = oc_box_rect(b3[0][0], b3[0][1], b3[0][2], b3[0][3], W, H, sq);
+    }
     g->nrect = 0;
-    for (int k = 0; k < nb; k++)
-        if (oc_box_rect(box[k][0], box[k][1], box[k][2], box[k][3], W, H, g->rect[g->nrect]))
-            g->nrect++;
+    for (int k = 0; k < nb; k++) {
+        int32_t* r = g->rect[g->nrect];
+        if (!oc_box_rect(box[k][0], box[k][1], box[k][2], box[k][3], W, H, r)) continue;
+        if (mode & OC_CLIP_3SIGMA) {
+            if (!have_sq) continue;
+            if (r[0] < sq[0]) r[0] = sq[0];
+            if (r[1] > sq[1]) r[1] = sq[1];
+            if (r[2] < sq[2]) r[2] = sq[2];
+            if (r[3] > sq[3]) r[3] = sq[3];
+            if (r[0] > r[1] || r[2] > r[3]) continue;
+        }
+        g->nrect++;
+    }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -294,7 +317,7 @@ void oc_project_one(const oc_camera* cam, const float mean[3], const float lscal
         return;
 
     /* opacity-aware modes drop Gaussians that can never reach alpha_min */
-    if (mode != OC_BOX_3SIGMA && !(g->gamma > 0.0f)) return;
+    if ((mode & ~OC_CLIP_3SIGMA) != OC_BOX_3SIGMA && !(g->gamma > 0.0f)) return;
 
     /* view-dependent colour from SH, binary64 */
     {

@@ -246,3 +246,55 @@ def test_pair_counts_ordering(oracle):
     assert exact <= counts["quadbox"] <= counts["adr"]
     assert counts["dualbox"] <= counts["quadbox"]
     assert counts["adr"] < counts["3sigma"]
+
+
+@pytest.mark.parametrize("which", ["small", "aniso"])
+def test_clip_3sigma_tile_sets(oracle, which):
+    """The 3-sigma clip (each sub-box tile rect cut to the 3-sigma square's
+    tile rect): the clipped QuadBox tile set is the QuadBox set intersected
+    with the 3-sigma set for every Gaussian (rect-wise cuts distribute over
+    the union), so it lies inside the 3-sigma set even where gamma > 9; it
+    still holds every tile of the 3-sigma set with a pixel sample inside the
+    1/255 ellipse (conservative relative to the 3-sigma pipeline); DualBox and
+    AdR clip the same way."""
+    if which == "small":
+        scene, cam = scenes.small_scene(n=3000)
+    else:
+        scene, cam = scenes.random_scene(6, 3000, 256, 192, 700.0, sh_degree=0, log_scale_mu=-4.0)
+        rng = np.random.default_rng(6)
+        half = 0.5 * rng.uniform(0, math.log(100.0), scene.n).astype(np.float32)
+        scene.log_scales[0] += half
+        scene.log_scales[1] -= half
+        scene.log_scales[2] -= half
+    W, H, tx = cam.width, cam.height, cam.tiles_x
+    modes = ("quadbox", "3sigma", "quadbox_clip3sigma", "adr", "adr_clip3sigma", "dualbox", "dualbox_clip3sigma")
+    g = {m: oracle.project(scene, cam, m) for m in modes}
+    cut = 0
+    for i in range(scene.n):
+        if not g["quadbox"][i]["visible"]:
+            assert not g["quadbox_clip3sigma"][i]["visible"]
+            continue
+        ts = {m: set(oracle.tile_set(g[m], i, tx).tolist()) for m in modes}
+        s = ts["3sigma"]
+        for base in ("quadbox", "adr", "dualbox"):
+            assert ts[base + "_clip3sigma"] == ts[base] & s, (i, base)
+        need, _ = _required_tiles(g["quadbox"][i], W, H, 2e-3)
+        assert need & s <= ts["quadbox_clip3sigma"], i
+        cut += not ts["quadbox"] <= s
+    assert cut > 0   # the clip changes some Gaussians (gamma > 9)
+
+
+def test_clip_3sigma_image_equals_3sigma_image(oracle):
+    """With the clip, the render sees every contribution the 3-sigma pipeline
+    sees and no other (QuadBox is conservative, and the clipped set is inside
+    the 3-sigma set), so the image and final T equal the 3-sigma ones; the
+    unclipped QuadBox image differs where gamma > 9 ellipses leave the
+    3-sigma squares."""
+    scene, cam = scenes.small_scene(n=4000)
+    f3 = oracle.forward(scene, cam, "3sigma")
+    fc = oracle.forward(scene, cam, "quadbox_clip3sigma")
+    fq = oracle.forward(scene, cam, "quadbox")
+    assert np.array_equal(fc["image"], f3["image"])
+    assert np.array_equal(fc["T"], f3["T"])
+    assert len(fc["ids"]) <= len(f3["ids"]) and len(fc["ids"]) <= len(fq["ids"])
+    assert not np.array_equal(fq["image"], f3["image"])
