@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--workload", default="clusters", choices=["clusters", "small"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--trials", type=int, default=3)
-    ap.add_argument("--modes", default="quadbox,adr,3sigma,dualbox,quadbox_naive",
+    ap.add_argument("--modes", default="quadbox,adr,3sigma,dualbox,quadbox_naive,quadbox_clip3sigma",
                     help="box modes to time; the first one is the headline value")
     ap.add_argument("--no-backward", action="store_true", help="skip the forward+backward timing")
     ap.add_argument("--no-multiview", action="store_true", help="skip the 32-view forward+backward timing")

@@ -68,6 +68,17 @@ typedef enum {
                            after sorting and image as QB_BOX_QUADBOX.            */
 } qb_box_mode;
 
+/* Flag added to an opacity-aware qb_box_mode (ADR, QUADBOX, DUALBOX,
+ * QUADBOX_NAIVE) in qb_project, qb_project_views and qb_intersect: each
+ * sub-box's tile rect is intersected with the tile rect of the 3-sigma square
+ * (QB_BOX_3SIGMA's box).  The tile set is then the mode's set intersected
+ * with the 3-sigma set for every Gaussian, so it never exceeds the 3-sigma
+ * baseline's (the unclipped set does where gamma > 9, i.e. o > e^4.5/255: the
+ * 1/255 ellipse leaves the 3-sigma square), and with ADR or QUADBOX the image
+ * equals the 3-sigma image (the render finds the same contributions).  The
+ * unclipped modes are the paper's. */
+#define QB_CLIP_3SIGMA 16
+
 /* Pinhole camera.  R (row-major) and t map world to camera coordinates:
  * p = R mu + t, x right, y down, z forward; pixel (i, j) samples the image
  * point (i, j); u = fx x/z + cx.  campos is the camera centre in world space

@@ -17,7 +17,8 @@ BOX_3SIGMA, BOX_ADR, BOX_QUADBOX, BOX_DUALBOX = 0, 1, 2, 3
 CLIP_3SIGMA = 16   # added to an opacity-aware mode: sub-box tile rects cut to the 3-sigma square's
 MODES = {"3sigma": BOX_3SIGMA, "adr": BOX_ADR, "quadbox": BOX_QUADBOX, "dualbox": BOX_DUALBOX,
          "quadbox_naive": BOX_QUADBOX, "quadbox_clip3sigma": BOX_QUADBOX | CLIP_3SIGMA,
-         "adr_clip3sigma": BOX_ADR | CLIP_3SIGMA, "dualbox_clip3sigma": BOX_DUALBOX | CLIP_3SIGMA}
+         "adr_clip3sigma": BOX_ADR | CLIP_3SIGMA, "dualbox_clip3sigma": BOX_DUALBOX | CLIP_3SIGMA,
+         "quadbox_naive_clip3sigma": BOX_QUADBOX | CLIP_3SIGMA}
 TILE = 16
 
 GAUSS_DTYPE = np.dtype({

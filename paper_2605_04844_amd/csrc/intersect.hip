@@ -204,8 +204,7 @@ extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_re
                                   uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs, void* workspace,
                                   size_t workspace_bytes, qb_stream_t stream)
 {
-    if (n < 0 || n >= (int64_t)1 << 31 || width <= 0 || height <= 0 || mode < QB_BOX_3SIGMA ||
-        mode > QB_BOX_QUADBOX_NAIVE || pair_capacity < 0 ||
+    if (n < 0 || n >= (int64_t)1 << 31 || width <= 0 || height <= 0 || !qb_valid_mode(mode) || pair_capacity < 0 ||
         pair_capacity > (int64_t)0xFFFFFFFF || !num_pairs || !workspace)
         return QB_ERR_INVALID_ARG;
     int tiles_x = (int)qb_div_up(width, QB_TILE);
@@ -234,7 +233,7 @@ extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_re
                                                       reinterpret_cast<uint64_t*>(num_pairs), s)));
     const uint32_t* order = w.dv0;
     const int4* r4 = reinterpret_cast<const int4*>(rects);
-    if (pair_capacity > 0 && mode == QB_BOX_QUADBOX_NAIVE)
+    if (pair_capacity > 0 && (mode & ~QB_CLIP_3SIGMA) == QB_BOX_QUADBOX_NAIVE)
         QB_LAUNCH(k_emit_naive, grid, QB_BLOCK, 0, s, n, order, (const uint64_t*)w.offs, r4,
                   (const uint32_t*)w.csorted, tiles_x, pair_capacity, (const int64_t*)num_pairs, pair_tiles, pair_ids);
     else if (pair_capacity > 0)

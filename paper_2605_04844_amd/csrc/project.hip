@@ -177,9 +177,11 @@ __device__ __forceinline__ double s3(const GaussPre& g, int r, int c)
 template <int DEG>
 __device__ __forceinline__ void project_view(int64_t i, int64_t n, float mx, float my, float mz, const GaussPre& g,
                                              const float* __restrict__ sh, const ShCoef<DEG>* pre,
-                                             const ProjCam& cam, int mode, float4* __restrict__ out_splat,
+                                             const ProjCam& cam, int mode_arg, float4* __restrict__ out_splat,
                                              int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
 {
+    const int mode = mode_arg & ~QB_CLIP_3SIGMA;
+    const bool clip = (mode_arg & QB_CLIP_3SIGMA) != 0;
     const float* R = cam.R;
     float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + cam.t[0];
     float py = ((R[3] * mx + R[4] * my) + R[5] * mz) + cam.t[1];
@@ -246,13 +248,18 @@ __device__ __forceinline__ void project_view(int64_t i, int64_t n, float mx, flo
             }
         }
 
-        if (mode == QB_BOX_3SIGMA) {
+        // the 3-sigma square (Sec. 2): the 3SIGMA mode's box, and the rect the
+        // sub-boxes are cut to under QB_CLIP_3SIGMA
+        auto square = [&]() {
             float mid = 0.5f * (A + C);
             float disc = mid * mid - det;
             if (disc < 0.1f) disc = 0.1f;
             float lam = mid + sqrtf(disc);
             float r = ceilf(3.0f * sqrtf(lam));
-            rr[0] = box_rect(u - r, u + r, v - r, v + r, cam.W, cam.H);
+            return box_rect(u - r, u + r, v - r, v + r, cam.W, cam.H);
+        };
+        if (mode == QB_BOX_3SIGMA) {
+            rr[0] = square();
         } else {
             float xm = sqrtf(gam * A);
             float ym = sqrtf(gam * C);
@@ -280,6 +287,22 @@ __device__ __forceinline__ void project_view(int64_t i, int64_t n, float mx, flo
                     float y1 = qsy > 0 ? v + bh : v;
                     rr[q] = box_rect(x0, x1, y0, y1, cam.W, cam.H);
                 }
+            }
+        }
+        if (clip && mode != QB_BOX_3SIGMA) {
+            // cut each sub-box's tile rect to the square's (an empty square
+            // empties them all; a cut rect keeps the centre tile, so the union
+            // stays one interval per scanline for QPass)
+            QRect sq = square();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                QRect& c = rr[q];
+                if (c.x0 > c.x1 || c.y0 > c.y1) continue;
+                c.x0 = max(c.x0, sq.x0);
+                c.x1 = min(c.x1, sq.x1);
+                c.y0 = max(c.y0, sq.y0);
+                c.y1 = min(c.y1, sq.y1);
+                if (c.x0 > c.x1 || c.y0 > c.y1) c = QRect{1, 0, 1, 0};
             }
         }
         if (mode == QB_BOX_QUADBOX_NAIVE) {
@@ -402,7 +425,7 @@ extern "C" qb_status qb_project(int64_t n, const float* means, const float* log_
                                 qb_stream_t stream)
 {
     if (n < 0 || n >= (int64_t)1 << 31 || !cam || sh_degree < 0 || sh_degree > 3) return QB_ERR_INVALID_ARG;
-    if (mode < QB_BOX_3SIGMA || mode > QB_BOX_QUADBOX_NAIVE) return QB_ERR_INVALID_ARG;
+    if (!qb_valid_mode(mode)) return QB_ERR_INVALID_ARG;
     if (!valid_camera(*cam)) return QB_ERR_INVALID_ARG;
     if (n == 0) return QB_OK;
     if (!means || !log_scales || !quats || !opacity_logits || !sh || !out_splats || !out_rects ||
@@ -426,7 +449,7 @@ extern "C" qb_status qb_project_views(int64_t n, const float* means, const float
     if (n < 0 || n >= (int64_t)1 << 31 || !cams || sh_degree < 0 || sh_degree > 3 || num_views < 1 ||
         num_views > QB_MAX_VIEWS)
         return QB_ERR_INVALID_ARG;
-    if (mode < QB_BOX_3SIGMA || mode > QB_BOX_QUADBOX_NAIVE) return QB_ERR_INVALID_ARG;
+    if (!qb_valid_mode(mode)) return QB_ERR_INVALID_ARG;
     ProjCamTable ct;
     for (int v = 0; v < num_views; ++v) {
         if (!valid_camera(cams[v])) return QB_ERR_INVALID_ARG;

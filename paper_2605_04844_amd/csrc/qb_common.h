@@ -26,6 +26,14 @@ static inline hipStream_t qb_hip_stream(qb_stream_t s) { return reinterpret_cast
 
 static inline int64_t qb_div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// A qb_box_mode, optionally with QB_CLIP_3SIGMA on an opacity-aware mode.
+static inline bool qb_valid_mode(int32_t mode)
+{
+    int32_t base = mode & ~QB_CLIP_3SIGMA;
+    if (base < QB_BOX_3SIGMA || base > QB_BOX_QUADBOX_NAIVE) return false;
+    return !((mode & QB_CLIP_3SIGMA) && base == QB_BOX_3SIGMA);
+}
+
 // Bump allocator over a caller workspace; every slice is 256-byte aligned.
 struct QbArena {
     char* base;

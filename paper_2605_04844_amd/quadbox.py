@@ -19,6 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("QB_LIBRARY", os.path.join(HERE, "libquadbox.so"))
 
 BOX_MODES = {"3sigma": 0, "adr": 1, "quadbox": 2, "dualbox": 3, "quadbox_naive": 4}
+CLIP_3SIGMA = 16   # QB_CLIP_3SIGMA: added to an opacity-aware mode
+BOX_MODES.update({m + "_clip3sigma": BOX_MODES[m] | CLIP_3SIGMA for m in ("adr", "quadbox", "dualbox", "quadbox_naive")})
 TILE = 16
 SPLAT_FLOATS = 12   # qb_splat: u v depth o | a b c gamma | r g b visible
 RECT_SHORTS = 16    # qb_rects: 4 x (tx0, tx1, ty0, ty1)

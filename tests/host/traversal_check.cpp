@@ -3,7 +3,8 @@
 // visit every tile of the union of the sub-box rects exactly once, and report
 // its size.  The rects are quadrant boxes around one centre, as QuadBox and
 // DualBox build them (QPass's per-scanline min/max relies on that shape),
-// with random extents, empty and dropped sub-boxes, clipped to the image.
+// with random extents, empty and dropped sub-boxes, clipped to the image, and
+// in half of the cases cut to a common square around the centre.
 // Prints "cases N bad M" and exits non-zero on any mismatch.
 #include "../../paper_2605_04844_amd/csrc/qb_common.h"
 
@@ -41,6 +42,23 @@ static void quadrant_rects(std::mt19937& rng, QRect r[4])
         r[q] = QRect{1, 0, 1, 0};
         if (axis_tiles(x0, x1, W, &a, &b) && axis_tiles(y0, y1, H, &c, &d)) r[q] = QRect{a, b, c, d};
         if (rng() % 9 == 0) r[q] = QRect{1, 0, 1, 0};  // a sub-box dropped (DualBox)
+    }
+    // every other case: all rects cut to the tile rect of a square around the
+    // same centre (the 3-sigma clip), as k_project applies it
+    if (rng() % 2 == 0) {
+        float rad = (float)(rng() % 15000) / 100.0f;
+        int a, b, c, d;
+        bool sq = axis_tiles(u - rad, u + rad, W, &a, &b) && axis_tiles(v - rad, v + rad, H, &c, &d);
+        for (int q = 0; q < 4; ++q) {
+            QRect& k = r[q];
+            if (k.x0 > k.x1 || k.y0 > k.y1) continue;
+            if (!sq) { k = QRect{1, 0, 1, 0}; continue; }
+            k.x0 = k.x0 > a ? k.x0 : a;
+            k.x1 = k.x1 < b ? k.x1 : b;
+            k.y0 = k.y0 > c ? k.y0 : c;
+            k.y1 = k.y1 < d ? k.y1 : d;
+            if (k.x0 > k.x1 || k.y0 > k.y1) k = QRect{1, 0, 1, 0};
+        }
     }
 }
 

@@ -19,7 +19,8 @@ from paper_2605_04844_amd import scenes  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["3sigma", "adr", "quadbox", "dualbox", "quadbox_naive"]
+MODES = ["3sigma", "adr", "quadbox", "dualbox", "quadbox_naive", "quadbox_clip3sigma", "adr_clip3sigma",
+         "quadbox_naive_clip3sigma"]
 IMG_TOL = 1e-4
 RGB_TOL = 1e-5
 
@@ -400,3 +401,20 @@ def test_full_size_3sigma_zoom(oracle, qb):
     busy = np.argsort(gpu["ranges"][:, 1] - gpu["ranges"][:, 0])[-5:]
     tiles = np.unique(np.concatenate([rng.choice(cam.num_tiles, 30, replace=False), busy]))
     _sampled_tile_check(oracle, gpu, g, cam, tiles, label)
+
+
+def test_clip_3sigma_image_equals_3sigma_on_gpu(oracle, qb):
+    """QuadBox with the 3-sigma clip renders the 3-sigma image bit for bit
+    (same contributions per pixel, same arithmetic) with fewer pairs, while
+    unclipped QuadBox differs where gamma > 9; the oracle agrees on the
+    clipped pair count."""
+    scene, cam = scenes.small_scene()
+    out = {m: gpu_forward(qb, scene, cam, m)[0] for m in ("3sigma", "quadbox", "quadbox_clip3sigma")}
+    assert np.array_equal(out["quadbox_clip3sigma"]["image"], out["3sigma"]["image"])
+    assert np.array_equal(out["quadbox_clip3sigma"]["T"], out["3sigma"]["T"])
+    assert not np.array_equal(out["quadbox"]["image"], out["3sigma"]["image"])
+    assert out["quadbox_clip3sigma"]["P"] < out["3sigma"]["P"]
+    assert out["quadbox_clip3sigma"]["P"] <= out["quadbox"]["P"]
+    ref = oracle.forward(scene, cam, "quadbox_clip3sigma")
+    assert out["quadbox_clip3sigma"]["P"] == len(ref["ids"])
+    say("pairs 3sigma / quadbox / clipped:", out["3sigma"]["P"], out["quadbox"]["P"], out["quadbox_clip3sigma"]["P"])
