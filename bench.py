@@ -57,8 +57,9 @@ def parse():
     ap.add_argument("--no-multiview", action="store_true", help="skip the 32-view forward+backward timing")
     ap.add_argument("--no-zoom", action="store_true", help="skip the 3M anisotropic zoom sweep")
     ap.add_argument("--no-rowmajor", action="store_true",
-                    help="skip timing the render with row-major tiles (keeps a kernel trace's render average to "
-                         "the work-ordered launches)")
+                    help="skip the extra timings (the render with row-major tiles, the frame with the pair count "
+                         "read back, standalone stage launches): keeps a kernel trace to the timed frames and the "
+                         "work-ordered render launches")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -97,7 +98,7 @@ class StageTimer:
         return {n: sum(a.elapsed_time(b) for a, b in v) / max(len(v), 1) for n, v in self.ev.items()}
 
 
-def run_mode(torch, qb, g, cam, mode, steps, warmup, trials, rowmajor=True):
+def run_mode(torch, qb, g, cam, mode, steps, warmup, trials, extras=True):
     # the timed frames leave the sorted 64-bit keys unmaterialised: the render
     # reads only the sorted ids and the ranges
     r = qb.Rasterizer(g.n, cam, write_keys=False)
@@ -178,15 +179,24 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials, rowmajor=True):
     render_launch_ms = _time(torch, r.render, 20, 2, trials)
     # the same launches with the tiles in row-major order (no qb_tile_order):
     # what the work-ordered dispatch gains
-    rowmajor_ms = None
-    if rowmajor:
+    rowmajor_ms = sync_ms = stage_launch = None
+    if extras:
         r.balance = False
         rowmajor_ms = _time(torch, r.render, 20, 2, trials)
         r.balance = True
+        # the frame with its pair count read back to the host (one
+        # synchronisation per frame, as a caller sizing buffers would)
+        sync_ms = _time(torch, lambda: r.forward(g, mode, sync_count=True), steps, 2, trials)
+        # back-to-back launches of the HBM-bound stages on the frame's buffers
+        stage_launch = {"project": _time(torch, lambda: r.project(g, mode), 20, 2, trials),
+                        "intersect": _time(torch, r.intersect, 20, 2, trials),
+                        "sort": _time(torch, r.sort, 20, 2, trials)}
+        torch.cuda.synchronize()
     evals = render_evaluations(torch, r)
     names = {v: k for k, v in qb.RENDER_VARIANTS.items()}
     return dict(ms=min(dev, graph_ms), eager_ms=dev, graph_ms=graph_ms, wall_ms=wall, pairs=pairs, stage_ms=stage,
-                render_launch_ms=render_launch_ms, render_rowmajor_ms=rowmajor_ms, evals=evals, rast=r,
+                render_launch_ms=render_launch_ms, render_rowmajor_ms=rowmajor_ms, sync_ms=sync_ms,
+                stage_launch_ms=stage_launch, evals=evals, rast=r,
                 render_shape=names[r.render_variant], shape_ms={k: round(v, 4) for k, v in shapes.items()})
 
 
@@ -339,7 +349,7 @@ def run_zoom_sweep(torch, qb, steps, trials):
     for k, cam in enumerate(cams, start=1):
         row = {"zoom": k}
         for mode in ("quadbox", "adr", "3sigma"):
-            res = run_mode(torch, qb, g, cam, mode, steps, 2, trials, rowmajor=False)
+            res = run_mode(torch, qb, g, cam, mode, steps, 2, trials, extras=False)
             row[mode] = {"pairs": res["pairs"], "fps": round(1000.0 / res["ms"], 2), "ms": round(res["ms"], 4)}
             del res
         row["quadbox_vs_3sigma"] = round(row["3sigma"]["ms"] / row["quadbox"]["ms"], 3)
@@ -359,6 +369,35 @@ def render_evaluations(torch, r):
     ev = int(r.n_touched.to(torch.int64).sum().item())
     r.n_touched = None
     return ev
+
+
+def stage_bytes(n, sh_degree, pairs):
+    """Bytes each HBM-bound stage moves by its design, per frame:
+    project: the SoA inputs (12 + 12 + 16 + 4 + 12 (d+1)^2 B) read, the 48-byte
+      record, 32-byte rects and the count written, per Gaussian;
+    intersect: depth keys (8 B read, 8 written), 4 depth-sort passes (8 B read
+      and written, 4 B upsweep read), the count gather (8 B), the offset scan
+      (4 B read, 8 written), the emission's reads (rects 32 B, order, count,
+      offset 16 B) per Gaussian, and 6 B written per pair;
+    sort: 2 tile passes of 6 B read and written plus a 2-byte upsweep read,
+      per pair."""
+    proj = n * (44 + 12 * (sh_degree + 1) ** 2 + 84)
+    isect = n * (16 + 4 * 20 + 8 + 12 + 48) + pairs * 6
+    sort = pairs * 28
+    return {"project": proj, "intersect": isect, "sort": sort}
+
+
+def stage_bandwidth(q, g, copy_gbs):
+    """Achieved bandwidth of the HBM-bound stages (design bytes over the
+    stage's back-to-back launch time) against the 8 TB/s peak and the
+    measured device-copy rate."""
+    b = stage_bytes(g.n, g.sh_degree, q["pairs"])
+    out = {}
+    for k, ms in q["stage_launch_ms"].items():
+        gbs = b[k] / (ms * 1e-3) / 1e9
+        out[k] = {"bytes": int(b[k]), "ms": round(ms, 4), "gbs": round(gbs, 1),
+                  "frac_of_peak": round(gbs / HBM_PEAK_GBS, 3), "frac_of_copy": round(gbs / copy_gbs, 3)}
+    return out
 
 
 def image_delta(torch, img, ref):
@@ -469,7 +508,7 @@ def main():
     for mode in modes:
         log("mode", mode)
         results[mode] = run_mode(torch, qb, g, cam, mode, args.steps, args.warmup, args.trials,
-                                 rowmajor=not args.no_rowmajor)
+                                 extras=not args.no_rowmajor)
         res = results[mode]
         log(mode, f"{res['ms']:.3f} ms/frame, {res['pairs']} pairs, stages",
             {k: round(v, 4) for k, v in res["stage_ms"].items()})
@@ -520,6 +559,7 @@ def main():
                       "render_launch_ms": round(r["render_launch_ms"], 4),
                       "render_rowmajor_ms": (round(r["render_rowmajor_ms"], 4)
                                              if r["render_rowmajor_ms"] is not None else None),
+                      "ms_with_count_readback": round(r["sync_ms"], 4) if r["sync_ms"] is not None else None,
                       "render_shape": r["render_shape"], "render_shape_ms": r["shape_ms"],
                       **image_delta(torch, r["rast"].image, q["rast"].image)}
                   for m, r in results.items()},
@@ -530,8 +570,11 @@ def main():
         "quadbox_vs_adr": round(results["adr"]["ms"] / q["ms"], 3) if "adr" in results else None,
         "dominant_stage": dominant,
         "roofline": roof,
-        "hbm_copy_gbs": copy_bandwidth(torch),
     }
+    copy_gbs = copy_bandwidth(torch)
+    out["hbm_copy_gbs"] = copy_gbs
+    if q["stage_launch_ms"] is not None:
+        out["stage_bandwidth"] = stage_bandwidth(q, g, copy_gbs)
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"], out["pairs_exact"] = cpu_baseline(scene, cam)
