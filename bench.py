@@ -12,9 +12,13 @@ checked against the eager image); a mode's `ms` is the faster of the two.
 Prints one JSON line: FPS of the QuadBox forward (`value`), tile pairs per
 frame, the same forward with the 3-sigma AABB and the opacity-aware AABB
 boxes, the ablation modes of Table 3 (DualBox, and QuadBox enumerated without
-QPass) with each mode's image compared with the QuadBox image, per-stage
-times from HIP events, forward+backward ms per view, the roofline of the
-dominant kernel, and the CPU oracle timed on a bounded sample.
+QPass) and QuadBox cut to the 3-sigma tiles, with each mode's image compared
+with the QuadBox image, per-stage times from HIP events, the render's launch
+time with tiles in work order and in row-major order, the frame time with
+the pair count read back to the host, the achieved bandwidth of the
+HBM-bound stages, forward+backward ms per view, the 32-view training step,
+the zoom sweep, the roofline of the dominant kernel, and the CPU oracle timed
+on a bounded sample.
 """
 import argparse
 import hashlib
