@@ -103,8 +103,10 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             for (int q = 0; q < PPL; ++q) {
                 float alpha = fminf(0.99f, o.y * __expf(p[q]));
                 float test_T = T[q] * (1.0f - alpha);
-                bool stp = act[q] && test_T < 1e-4f;
-                bool add = act[q] && !(test_T < 1e-4f);
+                // T is never NaN, so !(test_T < 1e-4) is test_T >= 1e-4; one
+                // compare gives both masks
+                bool add = act[q] && test_T >= 1e-4f;
+                bool stp = act[q] && !add;
                 float w = add ? alpha * T[q] : 0.0f;
                 c0[q] = fmaf(col.x, w, c0[q]);
                 c1[q] = fmaf(col.y, w, c1[q]);
