@@ -56,15 +56,19 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
     int lane = threadIdx.x & 63;
     int wrow0 = (int)(threadIdx.x / 64) * kRowsPerWave;
     float fy = (float)py;
-    bool in[PPL], done[PPL];
+    // A pixel that has stopped (or lies outside the image) has its x set to
+    // +inf: dx is then -inf and, the conic's a being positive, its power
+    // -inf, so the cutoff test rejects it by itself (a NaN power, possible
+    // only there, is rejected too).
+    constexpr float kStopped = __builtin_huge_valf();
+    bool in[PPL];
     float fxp[PPL], T[PPL], c0[PPL], c1[PPL], c2[PPL];
     uint32_t last[PPL], stop[PPL];
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
         int px = tx * QB_TILE + lx + q * LX;
         in[q] = px < W && py < H;
-        done[q] = !in[q];
-        fxp[q] = (float)px;
+        fxp[q] = in[q] ? (float)px : kStopped;
         T[q] = 1.0f;
         c0[q] = c1[q] = c2[q] = 0.0f;
         last[q] = stop[q] = 0u;
@@ -72,7 +76,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
     auto all_done = [&]() {
         bool d = true;
 #pragma unroll
-        for (int q = 0; q < PPL; ++q) d = d && done[q];
+        for (int q = 0; q < PPL; ++q) d = d && fxp[q] == kStopped;
         return d;
     };
 
@@ -98,7 +102,8 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
         // true when the whole wave has stopped
         // composites one entry (opacity in o.y, colour col, list position
         // at) into the lane's pixels whose power p passed (act)
-        auto composite = [&](const float4& o, const float4& col, const float* p, const bool* act, uint32_t at) {
+        auto composite = [&](const float4& o, const float4& col, const float* p, const bool* act, uint32_t at,
+                             bool* stopped) {
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
                 float alpha = fminf(0.99f, o.y * __expf(p[q]));
@@ -114,7 +119,8 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
                 T[q] = add ? test_T : T[q];
                 last[q] = add ? at : last[q];
                 if (COUNT) stop[q] = stp ? at : stop[q];
-                done[q] = done[q] || stp;
+                fxp[q] = stp ? kStopped : fxp[q];
+                stopped[q] = stp;
             }
         };
         // the cutoff test of entry k for the lane's pixels; returns whether any passed
@@ -130,7 +136,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             for (int q = 0; q < PPL; ++q) {
                 float dx = g.x - fxp[q];
                 p[q] = fmaf(fmaf(g.z, dx, nbdy), dx, hcdy2);
-                act[q] = !done[q] && !(p[q] > 0.0f || p[q] < o.z);
+                act[q] = !(p[q] > 0.0f) && p[q] >= o.z;
                 any = any || act[q];
             }
             return any;
@@ -143,7 +149,8 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             bool any = test(k, g, o, p, act);
             // branch only when the whole wave agrees; per pixel, select
             if (!__any(any)) return false;
-            composite(o, s_col[k], p, act, idx0 + (uint32_t)k + 1u);
+            bool stopped[PPL];
+            composite(o, s_col[k], p, act, idx0 + (uint32_t)k + 1u, stopped);
             return __all(all_done());
         };
         // entries k and k + 1: both tests first (independent), one uniform
@@ -155,10 +162,11 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             bool any = test(k, ga, oa, pa, acta);
             any = test(k + 1, gb, ob, pb, actb) || any;
             if (!__any(any)) return false;
-            composite(oa, s_col[k], pa, acta, idx0 + (uint32_t)k + 1u);
+            bool stopped[PPL];
+            composite(oa, s_col[k], pa, acta, idx0 + (uint32_t)k + 1u, stopped);
 #pragma unroll
-            for (int q = 0; q < PPL; ++q) actb[q] = actb[q] && !done[q];   // a pixel may have stopped at k
-            composite(ob, s_col[k + 1], pb, actb, idx0 + (uint32_t)k + 2u);
+            for (int q = 0; q < PPL; ++q) actb[q] = actb[q] && !stopped[q];   // a pixel may have stopped at k
+            composite(ob, s_col[k + 1], pb, actb, idx0 + (uint32_t)k + 2u, stopped);
             return __all(all_done());
         };
         if (kSkip) {
@@ -218,7 +226,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
         image[2 * plane + pix] = fmaf(T[q], bg2, c2[q]);
         if (final_T) final_T[pix] = T[q];
         if (n_contrib) n_contrib[pix] = last[q];
-        if (COUNT) n_touched[pix] = done[q] ? stop[q] : len;
+        if (COUNT) n_touched[pix] = fxp[q] == kStopped ? stop[q] : len;
     }
 }
 
