@@ -13,8 +13,10 @@ Prints one JSON line: FPS of the QuadBox forward (`value`), tile pairs per
 frame, the same forward with the 3-sigma AABB and the opacity-aware AABB
 boxes, the ablation modes of Table 3 (DualBox, and QuadBox enumerated without
 QPass) and QuadBox cut to the 3-sigma tiles, with each mode's image compared
-with the QuadBox image, per-stage times from HIP events, the render's launch
-time with tiles in work order and in row-major order, the frame time with
+with the QuadBox image, per-stage times from HIP events inside the frame and
+each stage's back-to-back launch time (the dominant stage is taken from the
+latter), the render's launch time with tiles in work order and in row-major
+order, the frame time with
 the pair count read back to the host, the achieved bandwidth of the
 HBM-bound stages, forward+backward ms per view, the 32-view training step,
 the zoom sweep, the roofline of the dominant kernel, and the CPU oracle timed
@@ -39,8 +41,15 @@ HBM_PEAK_GBS = 8000.0
 # cap at 0.99, 1 - alpha, times T, compare with 1e-4, alpha * T, 3 fma
 # (colour), the T update (select) = 21 VALU lane operations.
 RENDER_OPS_PER_EVAL = 21
-# VALU issue peak without packed math: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# ALU peak in lane operations: the FP32 vector rate, 157.3 TFLOP/s = 256 CUs
+# x 2.4 GHz x 128 lane-FMAs per clock per CU = 78.6 T lane-operations/s (an
+# FMA counted as one operation).  One wave64 instruction per 4 cycles per
+# SIMD -- 256 x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T -- is not a ceiling on
+# this part: plain FMA chains issue at 36 T (valu_rate_probe), while the
+# render's own instruction stream issues above 39.3 T, so part of its mix
+# issues faster than one instruction per 4 cycles.
+VALU_PEAK_TOPS = 256 * 2.4e9 * 128 / 1e12
+VALU_SINGLE_ISSUE_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -194,7 +203,9 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials, extras=True):
         # back-to-back launches of the HBM-bound stages on the frame's buffers
         stage_launch = {"project": _time(torch, lambda: r.project(g, mode), 20, 2, trials),
                         "intersect": _time(torch, r.intersect, 20, 2, trials),
-                        "sort": _time(torch, r.sort, 20, 2, trials)}
+                        "sort": _time(torch, r.sort, 20, 2, trials),
+                        "order": _time(torch, r.schedule, 20, 2, trials),
+                        "render": render_launch_ms}
         torch.cuda.synchronize()
     evals = render_evaluations(torch, r)
     names = {v: k for k, v in qb.RENDER_VARIANTS.items()}
@@ -398,6 +409,8 @@ def stage_bandwidth(q, g, copy_gbs):
     b = stage_bytes(g.n, g.sh_degree, q["pairs"])
     out = {}
     for k, ms in q["stage_launch_ms"].items():
+        if k not in b:
+            continue
         gbs = b[k] / (ms * 1e-3) / 1e9
         out[k] = {"bytes": int(b[k]), "ms": round(ms, 4), "gbs": round(gbs, 1),
                   "frac_of_peak": round(gbs / HBM_PEAK_GBS, 3), "frac_of_copy": round(gbs / copy_gbs, 3)}
@@ -531,7 +544,11 @@ def main():
         log("zoom sweep")
         zoom = run_zoom_sweep(torch, qb, max(2, args.steps // 5), 1)
     q = results[modes[0]]
-    stage = q["stage_ms"]
+    # the dominant stage by the stages' own back-to-back launch times where
+    # they were taken: the in-frame events also charge a stage any gap before
+    # its first kernel starts (host issue), which lands on whichever stage
+    # the host fell behind on
+    stage = q["stage_launch_ms"] if q["stage_launch_ms"] is not None else q["stage_ms"]
     dominant = max(stage, key=stage.get)
     # roofline of the render kernel (qb_render launches k_render alone, so
     # events around back-to-back calls time that kernel)
@@ -541,7 +558,8 @@ def main():
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
             "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": render_traffic(args.workload, modes[0], kname),
             "kernel": kname, "evaluations_per_launch": q["evals"], "ops_per_evaluation": RENDER_OPS_PER_EVAL,
-            "launch_ms": round(render_ms, 4)}
+            "launch_ms": round(render_ms, 4), "single_issue_peak": round(VALU_SINGLE_ISSUE_TOPS, 2),
+            "frac_of_single_issue": round(achieved / VALU_SINGLE_ISSUE_TOPS, 4)}
     out = {
         "metric": METRIC,
         "value": round(1000.0 / q["ms"], 2),
@@ -573,6 +591,8 @@ def main():
         "quadbox_vs_3sigma": round(results["3sigma"]["ms"] / q["ms"], 3) if "3sigma" in results else None,
         "quadbox_vs_adr": round(results["adr"]["ms"] / q["ms"], 3) if "adr" in results else None,
         "dominant_stage": dominant,
+        "stage_launch_ms": ({k: round(v, 4) for k, v in q["stage_launch_ms"].items()}
+                            if q["stage_launch_ms"] is not None else None),
         "roofline": roof,
     }
     copy_gbs = copy_bandwidth(torch)
