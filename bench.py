@@ -120,7 +120,7 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials, extras=True):
     pairs = r.pairs()
     r._alloc_pairs(pairs)
     r.forward(g, mode, sync_count=False)
-    shapes = qb.autotune_render(r, reps=10, trials=3)   # launch shape of the render for this frame
+    shapes = qb.autotune_render(r, reps=10, trials=5)   # launch shape of the render for this frame
     for _ in range(warmup):
         r.forward(g, mode, sync_count=False)
     torch.cuda.synchronize()
@@ -465,19 +465,19 @@ def cpu_baseline(scene, cam, exact_stride=10):
 
 def render_traffic(workload, mode, kernel):
     """HBM bytes per launch of the render kernel `kernel` (FETCH_SIZE +
-    WRITE_SIZE, copy-calibrated) from the committed counter summary, or None
-    when that summary was taken on another workload, another kernel or a
-    different render source."""
+    WRITE_SIZE, copy-calibrated) from the committed counter summary, which
+    holds every launch shape of the frame (the autotuner launches each), or
+    None when that summary was taken on another workload or a different
+    render source."""
     path = os.path.join(ROOT, "profiles", "k_render_clusters_1M_counters.json")
     if workload != "clusters" or mode != "quadbox" or not os.path.exists(path):
         return None
     meta = json.load(open(path))
-    if meta.get("kernel") != kernel:
-        return None
     src = os.path.join(ROOT, "paper_2605_04844_amd", "csrc", "render.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != meta["render_source_sha256"]:
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != meta.get("render_source_sha256"):
         return None
-    return int(meta["fetch_bytes_per_launch"] + meta["write_bytes_per_launch"])
+    k = meta.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"])
 
 
 def copy_bandwidth(torch, mib=1024, reps=10):

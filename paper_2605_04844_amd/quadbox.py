@@ -552,19 +552,25 @@ class MultiView:
 
 # ---- autotuner -----------------------------------------------------------------
 
-def _best(fn, reps, trials):
-    fn()
+def _interleaved_best(fns, reps, trials):
+    """{name: best ms per call} of every callable in `fns`, each run once
+    untimed first; the timed trials go round-robin over the callables so
+    that a clock ramp or drift during tuning falls on every shape alike
+    rather than on the one timed first."""
+    for fn in fns.values():
+        fn()
     torch.cuda.synchronize()
-    best = float("inf")
+    best = {name: float("inf") for name in fns}
     for _ in range(trials):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        best = min(best, e0.elapsed_time(e1) / reps)
+        for name, fn in fns.items():
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best[name] = min(best[name], e0.elapsed_time(e1) / reps)
     return best
 
 
@@ -573,14 +579,15 @@ def autotune_backward(run, bg=(0.0, 0.0, 0.0), dl=None, grad2d=None, reps=5, tri
     holds -- a MultiView after forward with its dl filled, or a Rasterizer
     after forward given dl [3, H, W] and a grad2d [n, 9] buffer -- keeps the
     fastest in run.backward_variant and returns {shape: ms}."""
-    times = {}
+    fns = {}
     for name, v in BACKWARD_VARIANTS.items():
         if isinstance(run, MultiView):
-            fn = (lambda v=v: render_backward_views(run._table, run.V, bg, run.n, v, run.tile_order()))
+            fns[name] = (lambda v=v: render_backward_views(run._table, run.V, bg, run.n, v, run.tile_order()))
         else:
-            fn = (lambda v=v: render_backward(run.W, run.H, run.ranges, run.ids_sorted, run.splats, bg, run.final_T,
-                                              run.n_contrib, dl, run.n, grad2d, v, run.tile_order()))
-        times[name] = _best(fn, reps, trials)
+            fns[name] = (lambda v=v: render_backward(run.W, run.H, run.ranges, run.ids_sorted, run.splats, bg,
+                                                     run.final_T, run.n_contrib, dl, run.n, grad2d, v,
+                                                     run.tile_order()))
+    times = _interleaved_best(fns, reps, trials)
     pick = min(times, key=times.get)
     run.backward_variant = BACKWARD_VARIANTS[pick]
     return times
@@ -591,22 +598,13 @@ def autotune_render(run, bg=(0.0, 0.0, 0.0), reps=10, trials=3):
     MultiView after a forward) holds, keeps the fastest in
     run.render_variant and returns {shape: ms}.  The shapes give identical
     images, so the choice only affects speed."""
-    times = {}
-    for name, v in RENDER_VARIANTS.items():
-        run.render_variant = v
-        run.render(bg)
-        torch.cuda.synchronize()
-        best = float("inf")
-        for _ in range(trials):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                run.render(bg)
-            e1.record()
-            torch.cuda.synchronize()
-            best = min(best, e0.elapsed_time(e1) / reps)
-        times[name] = best
+    def shape(v):
+        def fn():
+            run.render_variant = v
+            run.render(bg)
+        return fn
+
+    times = _interleaved_best({name: shape(v) for name, v in RENDER_VARIANTS.items()}, reps, trials)
     pick = min(times, key=times.get)
     run.render_variant = RENDER_VARIANTS[pick]
     run.render(bg)
