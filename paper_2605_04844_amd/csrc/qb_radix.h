@@ -264,19 +264,32 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
     int64_t base = (int64_t)blockIdx.x * (NT * NI) + (int64_t)wave * 64 * NI;
     // the histogram ignores order: when the wave's 64*NI keys are all valid
     // and 16-byte aligned, each lane reads NI consecutive keys as 16-byte
-    // vectors; otherwise one key per lane per step
+    // vectors and adds each run of equal digits among them with one atomic
+    // (runs are common where neighbouring keys share their high bits, and
+    // same-address LDS atomics from many lanes serialise); otherwise one key
+    // per lane per step
     constexpr int kPerVec = 16 / sizeof(K);
     const K* wk = keys + base;
     bool vec = (NI * sizeof(K)) % 16 == 0 && base + 64 * NI <= n && ((uintptr_t)wk & 15u) == 0;
     if (vec) {
         const uint4* src = reinterpret_cast<const uint4*>(wk + (int64_t)lane * NI);
+        uint32_t cur = 0u, run = 0u;
 #pragma unroll
         for (int q = 0; q < (int)(NI * sizeof(K) / 16); ++q) {
             uint4 x = src[q];
             const K* e = reinterpret_cast<const K*>(&x);
 #pragma unroll
-            for (int u = 0; u < kPerVec; ++u) atomicAdd(&h[wave][digit_of(e[u], shift, mask)], 1u);
+            for (int u = 0; u < kPerVec; ++u) {
+                uint32_t d = digit_of(e[u], shift, mask);
+                if (run != 0u && d != cur) {
+                    atomicAdd(&h[wave][cur], run);
+                    run = 0u;
+                }
+                cur = d;
+                ++run;
+            }
         }
+        atomicAdd(&h[wave][cur], run);   // run >= 1: the lane read NI >= 1 keys
     } else {
 #pragma unroll 4
         for (int r = 0; r < NI; ++r) {
