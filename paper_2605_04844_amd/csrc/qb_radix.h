@@ -255,13 +255,22 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
                                                       uint32_t* __restrict__ hist, int64_t nblocks)
 {
     constexpr int NW = NT / 64;
-    __shared__ uint32_t h[NW][kRadix];
+    // kSub histograms per wave, a lane adding into copy lane % kSub; rows
+    // padded by one word so that one digit lies in a different bank in each
+    // copy: lanes holding the same digit (common in the high bits of sorted
+    // neighbours) meet kSub-fold less often on one address
+    constexpr int kSub = 4;
+    constexpr int kRow = kRadix + 1;
+    __shared__ uint32_t h[NW * kSub][kRow];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int d = threadIdx.x; d < NW * kRadix; d += NT) (&h[0][0])[d] = 0;
+    uint32_t mask = (1u << bits) - 1u;
+    // only the digits this pass can produce (0..mask) are cleared and summed
+    for (int r = wave; r < NW * kSub; r += NW)
+        for (int c = lane; c <= (int)mask; c += 64) h[r][c] = 0;
     __syncthreads();
     int64_t n = sort_count(n_dev, n_host, cap);
-    uint32_t mask = (1u << bits) - 1u;
     int64_t base = (int64_t)blockIdx.x * (NT * NI) + (int64_t)wave * 64 * NI;
+    uint32_t* hw = h[wave * kSub + (lane & (kSub - 1))];
     // the histogram ignores order: when the wave's 64*NI keys are all valid
     // and 16-byte aligned, each lane reads NI consecutive keys as 16-byte
     // vectors and adds each run of equal digits among them with one atomic
@@ -282,26 +291,28 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
             for (int u = 0; u < kPerVec; ++u) {
                 uint32_t d = digit_of(e[u], shift, mask);
                 if (run != 0u && d != cur) {
-                    atomicAdd(&h[wave][cur], run);
+                    atomicAdd(&hw[cur], run);
                     run = 0u;
                 }
                 cur = d;
                 ++run;
             }
         }
-        atomicAdd(&h[wave][cur], run);   // run >= 1: the lane read NI >= 1 keys
+        atomicAdd(&hw[cur], run);   // run >= 1: the lane read NI >= 1 keys
     } else {
 #pragma unroll 4
         for (int r = 0; r < NI; ++r) {
             int64_t idx = base + r * 64 + lane;
-            if (idx < n) atomicAdd(&h[wave][digit_of(keys[idx], shift, mask)], 1u);
+            if (idx < n) atomicAdd(&hw[digit_of(keys[idx], shift, mask)], 1u);
         }
     }
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += NT) {
         uint32_t t = 0;
+        if (d <= (int)mask) {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) t += h[w][d];
+            for (int w = 0; w < NW * kSub; ++w) t += h[w][d];
+        }
         if (BLOCK_MAJOR)
             hist[(int64_t)blockIdx.x * kRadix + d] = t;
         else if (d <= (int)mask)
