@@ -70,6 +70,7 @@ def lib():
         L.oc_backward64.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, vp, dbl, vp, vp, vp]
         L.oc_pixel_boxes.argtypes = [vp, i32, vp]
         L.oc_pixel_boxes.restype = i32
+        L.oc_project64.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp]
         lay = np.zeros(6, np.int64)
         L.oc_layout(lay.ctypes.data)
         assert lay[0] == GAUSS_DTYPE.itemsize and lay[1] == 44 and lay[2] == 48
@@ -248,6 +249,18 @@ def forward64(scene, cam, bg=(0.0, 0.0, 0.0), pert=None) -> np.ndarray:
     pi, pp, ph = pert if pert is not None else (-1, 0, 0.0)
     L.oc_forward64(C.byref(cs), scene.n, *[_p(a) for a in arrs], scene.sh_degree, _p(bgv), pi, pp, ph, _p(img))
     return img
+
+
+PROJ64_FIELDS = ("visible", "u", "v", "depth", "A", "B", "C", "a", "b", "c", "opacity", "gamma", "r", "g", "b_")
+
+
+def project64(scene, cam) -> dict:
+    """The binary64 projection behind forward64/backward64: {field: [N]}."""
+    arrs = _scene_arrays(scene)
+    cs = camera_struct(cam)
+    out = np.zeros((scene.n, 16), np.float64)
+    lib().oc_project64(C.byref(cs), scene.n, *[_p(a) for a in arrs], scene.sh_degree, _p(out))
+    return {f: out[:, k] for k, f in enumerate(PROJ64_FIELDS)}
 
 
 def backward64(scene, cam, dl_dimg, bg=(0.0, 0.0, 0.0), band=1e-4, with_near=False, with_2d=False):

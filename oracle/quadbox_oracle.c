@@ -28,6 +28,12 @@
  *   oc_ranges         pinned: binary search definition vs linear scan
  *   oc_render         pinned: Eq. (2) closed forms for one and two Gaussians,
  *                     tile-free brute-force render
+ *   oc_pixel_boxes    3-sigma square pinned: radius against numpy's eigvalsh
+ *                     (isotropic closed form in the floored regime), tile set
+ *                     against pixel-sample enumeration
+ *   oc_project64,     pinned: agreement with the binary32 projection and the
+ *   oc_forward64      binary32 tiled render, both pinned on their own
+ *   oc_backward64     pinned: central finite differences of oc_forward64
  */
 #include <math.h>
 #include <stdint.h>
@@ -864,6 +870,27 @@ static void oc_unpack(const float* means, const float* ls, const float* quats, c
     for (int k = 0; k < 4; k++) q[k] = quats[k * n + i] + (dd ? dd[6 + k] : 0);
     *x = logits[i] + (dd ? dd[10] : 0);
     for (int k = 0; k < K * 3; k++) shc[k] = sh[(int64_t)k * n + i] + (dd ? dd[11 + k] : 0);
+}
+
+/* The binary64 projection of every Gaussian (no perturbation), 16 doubles
+ * each: visible, u, v, depth, A, B, C, a, b, c, o, gamma, r, g, b, 0.
+ * Exposed so that the binary64 path can be checked against the binary32
+ * projection (oc_project), which is pinned on its own. */
+void oc_project64(const oc_camera* cam, int64_t n, const float* means, const float* ls, const float* quats,
+                  const float* logits, const float* sh, int sh_degree, double* out)
+{
+    int K = (sh_degree + 1) * (sh_degree + 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        double m[3], l[3], q[4], x, shc[48];
+        oc_g64 g;
+        oc_unpack(means, ls, quats, logits, sh, n, i, K, NULL, m, l, q, &x, shc);
+        oc_project64_one(cam, m, l, q, x, shc, K, &g);
+        double* o = out + 16 * i;
+        o[0] = g.visible; o[1] = g.u; o[2] = g.v; o[3] = g.p[2];
+        o[4] = g.A; o[5] = g.B; o[6] = g.C; o[7] = g.a; o[8] = g.b; o[9] = g.c;
+        o[10] = g.o; o[11] = g.gamma; o[12] = g.rgb[0]; o[13] = g.rgb[1]; o[14] = g.rgb[2]; o[15] = 0.0;
+    }
 }
 
 /* Binary64 render of all pixels; optional perturbation of one parameter of
