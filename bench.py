@@ -35,21 +35,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FPS & tile pairs/frame (QuadBox vs AABB); fwd+bwd ms/view, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-# Render roofline.  One evaluation of Eq. (2) at a (pixel, list entry) that
-# composites: 2 sub (offsets), 5 mul/fma (quadratic form), 2 compares (1/255
-# cutoff and the sign test), exp as 2 (scale by log2 e, exp2), scale by o,
-# cap at 0.99, 1 - alpha, times T, compare with 1e-4, alpha * T, 3 fma
-# (colour), the T update (select) = 21 VALU lane operations.
-RENDER_OPS_PER_EVAL = 21
-# ALU peak in lane operations: the FP32 vector rate, 157.3 TFLOP/s = 256 CUs
-# x 2.4 GHz x 128 lane-FMAs per clock per CU = 78.6 T lane-operations/s (an
-# FMA counted as one operation).  One wave64 instruction per 4 cycles per
-# SIMD -- 256 x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T -- is not a ceiling on
-# this part: plain FMA chains issue at 36 T (valu_rate_probe), while the
-# render's own instruction stream issues above 39.3 T, so part of its mix
-# issues faster than one instruction per 4 cycles.
-VALU_PEAK_TOPS = 256 * 2.4e9 * 128 / 1e12
-VALU_SINGLE_ISSUE_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Roofline of the render (Eq. (2)) and its backward, in FLOPs itemised per
+# (pixel, list entry) evaluation the algorithm performs, an FMA counting 2
+# and exp 1 (compares, min and selects count 0):
+#   every examined entry: dx, dy (2), the quadratic form (-b)dy, (-c/2)dy,
+#     times dy, two fma (3 + 4) = 9;
+#   an entry that composites, in addition: exp, o e, 1 - alpha,
+#     T (1 - alpha), alpha T, three fma into the colour = 11.
+# The backward examines, per pixel, the entries before its last contributor
+# (the same 9 each) and, for each composited one: exp, o e, 1 - alpha, its
+# reciprocal, T / (1 - alpha), alpha T, three fma into dL/drgb, the dot
+# dL/dC . rgb (5), dL/dalpha (3), the colour-behind update (fma), dpow, the
+# opacity share (fma), and its sums dpow, dpow dx, dpow dx^2 (1 + 1 + 1 + 2)
+# = 30.
+RENDER_FLOPS_EXAMINED, RENDER_FLOPS_COMPOSITED = 9, 11
+BACKWARD_FLOPS_EXAMINED, BACKWARD_FLOPS_COMPOSITED = 9, 30
+# Published MI355X FP32 vector peak, 157.3 TFLOP/s (256 CUs x 2.4 GHz x 256
+# FLOP per clock per CU: 128 lane-FMAs).  In lane operations per second
+# that is 78.6 T, the ceiling the measured VALU instruction rate
+# (SQ_INSTS_VALU x 64) is read against.
+FP32_PEAK_TFLOPS = 157.3
+VALU_LANE_PEAK_T = 256 * 2.4e9 * 128 / 1e12
 
 
 def log(*a):
@@ -207,11 +213,11 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials, extras=True):
                         "order": _time(torch, r.schedule, 20, 2, trials),
                         "render": render_launch_ms}
         torch.cuda.synchronize()
-    evals = render_evaluations(torch, r)
+    work = render_work(torch, qb, r)
     names = {v: k for k, v in qb.RENDER_VARIANTS.items()}
     return dict(ms=min(dev, graph_ms), eager_ms=dev, graph_ms=graph_ms, wall_ms=wall, pairs=pairs, stage_ms=stage,
                 render_launch_ms=render_launch_ms, render_rowmajor_ms=rowmajor_ms, sync_ms=sync_ms,
-                stage_launch_ms=stage_launch, evals=evals, rast=r,
+                stage_launch_ms=stage_launch, work=work, rast=r,
                 render_shape=names[r.render_variant], shape_ms={k: round(v, 4) for k, v in shapes.items()})
 
 
@@ -251,8 +257,16 @@ def run_fwd_bwd(torch, qb, g, cam, steps, warmup, trials):
         e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1) / steps)
-    assert r.pairs() <= r.capacity
-    return sorted(times)[len(times) // 2]
+    r.check_capacity()
+    # the render backward call on its own, back to back on the last frame's
+    # buffers: the 36-byte-per-Gaussian clear of grad2d, then k_render_backward
+    dl = torch.sign(r.image - target) * inv
+    bwd_ms = _time(torch, lambda: qb.render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, (0.0, 0.0, 0.0),
+                                                     r.final_T, r.n_contrib, dl, g.n, grad2d, r.backward_variant,
+                                                     r.tile_order()), 20, 2, trials)
+    names = {v: k for k, v in qb.BACKWARD_VARIANTS.items()}
+    return dict(ms=sorted(times)[len(times) // 2], render_backward_ms=bwd_ms, work=render_work(torch, qb, r),
+                shape=names[r.backward_variant])
 
 
 def _time(torch, fn, steps, warmup, trials):
@@ -306,6 +320,18 @@ def run_multiview(torch, qb, steps, warmup, trials):
         mv.backward(g)
 
     batched_ms = _time(torch, batched, steps, warmup, trials)
+    work = {"examined": 0, "composited": 0, "contributors": 0}
+    for v in range(V):
+        w = render_work(torch, qb, None, view=(mv, v))
+        for k in work:
+            work[k] += w[k]
+    fwd_ms = tuned["render_ms"][tuned["picked"]["render"]]
+    bwd_ms = tuned["render_backward_ms"][tuned["picked"]["render_backward"]]
+    rooflines = {"render_views": alu_roofline(render_flops(work), fwd_ms,
+                                              f"k_render_views<{tuned['picked']['render'][0]}>", work),
+                 "render_backward_views": alu_roofline(backward_flops(work), bwd_ms,
+                                                       f"k_render_backward_views<{tuned['picked']['render_backward'][0]}>",
+                                                       work, note="launch time includes the clear of every view's grad2d")}
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -315,7 +341,7 @@ def run_multiview(torch, qb, steps, warmup, trials):
     with torch.cuda.graph(graph):
         batched()
     graph_ms = _time(torch, graph.replay, steps, warmup, trials)
-    assert not mv.overflowed()
+    mv.check_capacity()
     del graph
 
     rasts = []
@@ -350,7 +376,7 @@ def run_multiview(torch, qb, steps, warmup, trials):
             "batched_ms_per_view": round(batched_ms / V, 4),
             "batched_graph_ms_per_view": round(graph_ms / V, 4),
             "graph_speedup_vs_per_view": round(per_view_ms / graph_ms, 3),
-            "autotune": tuned}
+            "autotune": tuned, "rooflines": rooflines}
 
 
 def run_zoom_sweep(torch, qb, steps, trials):
@@ -374,16 +400,48 @@ def run_zoom_sweep(torch, qb, steps, trials):
                         "focal 1920*k, forward", "rows": rows}
 
 
-def render_evaluations(torch, r):
-    """(pixel, list entry) evaluations of Eq. (2) the render performs: every
-    list entry up to the pixel's stop (qb_render's n_touched output), taken
-    from one extra, untimed render of the same frame."""
-    r.n_touched = torch.empty((r.H, r.W), dtype=torch.int32, device=r.device)
-    r.render()
+def render_work(torch, qb, r, view=None):
+    """The render's work on the frame a Rasterizer `r` (or view v of a
+    MultiView, view=(mv, v)) holds, from one extra, untimed qb_render_stats
+    launch: list entries examined (each pixel's stop index, or its list
+    length), entries composited, and the sum of the contributor counts (the
+    entries the backward examines)."""
+    if view is not None:
+        mv, v = view
+        W, H = mv.sizes[v]
+        args = (mv.ranges[v], mv.ids_sorted[v], mv.splats[v])
+        order = None
+    else:
+        W, H = r.W, r.H
+        args = (r.ranges, r.ids_sorted, r.splats)
+        order = r.tile_order()
+    dev = args[0].device
+    img = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    T = torch.empty((H, W), dtype=torch.float32, device=dev)
+    nc, nt, nk = (torch.empty((H, W), dtype=torch.int32, device=dev) for _ in range(3))
+    qb.render_stats(W, H, *args, (0.0, 0.0, 0.0), img, T, nc, nt, nk, 0, order)
     torch.cuda.synchronize()
-    ev = int(r.n_touched.to(torch.int64).sum().item())
-    r.n_touched = None
-    return ev
+    return {"examined": int(nt.to(torch.int64).sum()), "composited": int(nk.to(torch.int64).sum()),
+            "contributors": int(nc.to(torch.int64).sum())}
+
+
+def render_flops(work):
+    return RENDER_FLOPS_EXAMINED * work["examined"] + RENDER_FLOPS_COMPOSITED * work["composited"]
+
+
+def backward_flops(work):
+    return BACKWARD_FLOPS_EXAMINED * work["contributors"] + BACKWARD_FLOPS_COMPOSITED * work["composited"]
+
+
+def alu_roofline(flops, ms, kernel, work, traffic=None, note=None):
+    """FLOPs per launch over the launch time, against the FP32 vector peak."""
+    tf = flops / (ms * 1e-3) / 1e12
+    out = {"bound": "alu", "achieved": round(tf, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(tf / FP32_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": kernel,
+           "flops_per_launch": int(flops), "launch_ms": round(ms, 4), **{f"{k}_per_launch": v for k, v in work.items()}}
+    if note:
+        out["note"] = note
+    return out
 
 
 def stage_bytes(n, sh_degree, pairs):
@@ -426,29 +484,46 @@ def image_delta(torch, img, ref):
             "psnr_vs_headline": None if mse == 0.0 else round(10.0 * math.log10(1.0 / mse), 2)}
 
 
-def cpu_baseline(scene, cam, exact_stride=10):
-    """The oracle (as it stands) on one whole frame of the same workload:
-    project, all pairs with qsort, ranges, and the per-pixel render; timed
-    wall-clock on every host core the process may use.  Also the oracle's
-    exact-sample pair count (tiles holding a pixel sample that passes the
-    cutoff) on every `exact_stride`-th projected Gaussian: the lower bound of
-    any conservative tile set, against the QuadBox, AdR and 3-sigma counts of
+def cpu_baseline(scene, cam, exact_stride=10, trials=3):
+    """The oracle (as it stands) on whole frames of the same workload:
+    project, all pairs (parallel chunk sort and merge), ranges, and the
+    per-pixel render; wall-clock, one untimed warm-up frame, the median of
+    `trials` frames on every worker thread the oracle runs, then one frame
+    on a single thread.  Also the oracle's exact-sample pair count (tiles
+    holding a pixel sample that passes the cutoff) on every
+    `exact_stride`-th projected Gaussian: the lower bound of any
+    conservative tile set, against the QuadBox, AdR and 3-sigma counts of
     the same sample (untimed)."""
     import numpy as np
     from oracle import oracle as O
-    threads = len(os.sched_getaffinity(0))
-    t0 = time.perf_counter()
-    g = O.project(scene, cam, "quadbox")
-    t1 = time.perf_counter()
-    keys, ids = O.pairs(g, cam.tiles_x)
-    rt = O.ranges(keys, cam.num_tiles)
-    t2 = time.perf_counter()
-    O.render(g, cam.width, cam.height, rt, ids)
-    t3 = time.perf_counter()
-    frame_s = t3 - t0
-    base = {"value": round(1.0 / frame_s, 4), "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": f"one full frame of the same workload: project {t1 - t0:.2f} s, pairs+sort+ranges "
-                      f"{t2 - t1:.2f} s, render {t3 - t2:.2f} s"}
+    threads = O.threads()
+
+    def frame():
+        t0 = time.perf_counter()
+        g = O.project(scene, cam, "quadbox")
+        t1 = time.perf_counter()
+        keys, ids = O.pairs(g, cam.tiles_x)
+        rt = O.ranges(keys, cam.num_tiles)
+        t2 = time.perf_counter()
+        O.render(g, cam.width, cam.height, rt, ids)
+        t3 = time.perf_counter()
+        return (t3 - t0, t1 - t0, t2 - t1, t3 - t2), g
+
+    frame()
+    runs = sorted((frame()[0] for _ in range(trials)), key=lambda t: t[0])
+    med = runs[len(runs) // 2]
+    O.set_threads(1)
+    try:
+        one, g = frame()
+    finally:
+        O.set_threads(threads)
+    base = {"value": round(1.0 / med[0], 4), "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": f"whole frames of the same workload, median of {trials} after one warm-up on {threads} "
+                      f"threads: {med[0]:.2f} s (project {med[1]:.2f}, pairs+sort+ranges {med[2]:.2f}, "
+                      f"render {med[3]:.2f}); trials {', '.join(f'{t[0]:.2f}' for t in runs)} s",
+            "single_core": {"value": round(1.0 / one[0], 4), "unit": "frames/s", "cores": 1,
+                            "sample": f"one frame on 1 thread: {one[0]:.2f} s (project {one[1]:.2f}, "
+                                      f"pairs+sort+ranges {one[2]:.2f}, render {one[3]:.2f})"}}
     sub = np.ascontiguousarray(g[::exact_stride])
     missed, exact, _ = O.coverage_audit(sub, cam.width, cam.height)
     quad = int(O.tile_counts(sub, cam.tiles_x).sum())
@@ -463,13 +538,17 @@ def cpu_baseline(scene, cam, exact_stride=10):
     return base, exact_pairs
 
 
-def render_traffic(workload, mode, kernel):
-    """HBM bytes per launch of the render kernel `kernel` (FETCH_SIZE +
-    WRITE_SIZE, copy-calibrated) from the committed counter summary, which
-    holds every launch shape of the frame (the autotuner launches each), or
-    None when that summary was taken on another workload or a different
-    render source."""
-    path = os.path.join(ROOT, "profiles", "k_render_clusters_1M_counters.json")
+COUNTERS = os.path.join("profiles", "k_render_clusters_1M_counters.json")
+
+
+def render_counters(workload, mode, kernel):
+    """Counters per launch of the render kernel `kernel` from the committed
+    summary (every launch shape of the frame; the autotuner launches each):
+    HBM bytes (FETCH_SIZE + WRITE_SIZE, copy-calibrated) and VALU
+    instructions (SQ_INSTS_VALU), or None when the summary was taken on
+    another workload or on a different render source (its sha256 is
+    recorded)."""
+    path = os.path.join(ROOT, COUNTERS)
     if workload != "clusters" or mode != "quadbox" or not os.path.exists(path):
         return None
     meta = json.load(open(path))
@@ -477,7 +556,10 @@ def render_traffic(workload, mode, kernel):
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != meta.get("render_source_sha256"):
         return None
     k = meta.get("kernels", {}).get(kernel)
-    return None if k is None else int(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"])
+    if k is None:
+        return None
+    return {"traffic": int(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]),
+            "valu_insts": k.get("valu_insts_per_launch")}
 
 
 def copy_bandwidth(torch, mib=1024, reps=10):
@@ -533,7 +615,7 @@ def main():
     if args.workload == "clusters" and not args.no_backward:
         log("forward + backward")
         fwd_bwd = run_fwd_bwd(torch, qb, g, cam, args.steps, args.warmup, args.trials)
-        log(f"fwd+bwd {fwd_bwd:.3f} ms/view")
+        log(f"fwd+bwd {fwd_bwd['ms']:.3f} ms/view")
     multiview = None
     if args.workload == "clusters" and not args.no_multiview:
         log("multi-view forward + backward")
@@ -553,13 +635,22 @@ def main():
     # roofline of the render kernel (qb_render launches k_render alone, so
     # events around back-to-back calls time that kernel)
     render_ms = q["render_launch_ms"]
-    achieved = q["evals"] * RENDER_OPS_PER_EVAL / (render_ms * 1e-3) / 1e12
     kname = f"k_render<{q['render_shape'][0]}, false, {'true' if q['render_shape'].endswith('rows') else 'false'}>"
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
-            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": render_traffic(args.workload, modes[0], kname),
-            "kernel": kname, "evaluations_per_launch": q["evals"], "ops_per_evaluation": RENDER_OPS_PER_EVAL,
-            "launch_ms": round(render_ms, 4), "single_issue_peak": round(VALU_SINGLE_ISSUE_TOPS, 2),
-            "frac_of_single_issue": round(achieved / VALU_SINGLE_ISSUE_TOPS, 4)}
+    ctr = render_counters(args.workload, modes[0], kname)
+    roof = alu_roofline(render_flops(q["work"]), render_ms, kname, q["work"],
+                        traffic=ctr["traffic"] if ctr else None)
+    roof["flops_per_examined"] = RENDER_FLOPS_EXAMINED
+    roof["flops_per_composited"] = RENDER_FLOPS_COMPOSITED
+    if ctr:
+        roof["traffic_source"] = (f"{COUNTERS}: FETCH_SIZE + WRITE_SIZE per launch of this kernel, copy-calibrated, "
+                                  "taken by rocprofv3 on this render source (sha256 recorded there)")
+        if ctr.get("valu_insts"):
+            lane_rate = ctr["valu_insts"] * 64 / (render_ms * 1e-3) / 1e12
+            roof["valu_issue"] = {"insts_per_launch": int(ctr["valu_insts"]),
+                                  "lane_insts_per_examined": round(ctr["valu_insts"] * 64 / q["work"]["examined"], 2),
+                                  "lane_rate_T": round(lane_rate, 2), "peak_T": round(VALU_LANE_PEAK_T, 2),
+                                  "frac": round(lane_rate / VALU_LANE_PEAK_T, 4),
+                                  "source": f"{COUNTERS}: SQ_INSTS_VALU per launch"}
     out = {
         "metric": METRIC,
         "value": round(1000.0 / q["ms"], 2),
@@ -585,7 +676,11 @@ def main():
                       "render_shape": r["render_shape"], "render_shape_ms": r["shape_ms"],
                       **image_delta(torch, r["rast"].image, q["rast"].image)}
                   for m, r in results.items()},
-        "fwd_bwd_ms_per_view": round(fwd_bwd, 4) if fwd_bwd is not None else None,
+        "fwd_bwd_ms_per_view": round(fwd_bwd["ms"], 4) if fwd_bwd is not None else None,
+        "render_backward_roofline": (alu_roofline(backward_flops(fwd_bwd["work"]), fwd_bwd["render_backward_ms"],
+                                                  f"k_render_backward<{fwd_bwd['shape'][0]}>", fwd_bwd["work"],
+                                                  note="launch time includes the clear of grad2d (36 B per Gaussian)")
+                                     if fwd_bwd is not None else None),
         "multiview": multiview,
         "zoom_sweep": zoom,
         "quadbox_vs_3sigma": round(results["3sigma"]["ms"] / q["ms"], 3) if "3sigma" in results else None,

@@ -19,8 +19,8 @@
  *   - Array arguments are DEVICE pointers owned by the caller; the library never
  *     allocates, frees or retains caller memory.  Scratch memory comes from a
  *     caller-provided workspace of qb_*_workspace_size() bytes (256-byte aligned).
- *   - Every call is asynchronous on the given HIP stream (0 = null stream) and
- *     returns after enqueueing its kernels.
+ *   - Every call but qb_check_capacity is asynchronous on the given HIP
+ *     stream (0 = null stream) and returns after enqueueing its kernels.
  *   - Argument errors (null pointers, negative or oversized counts, bad modes,
  *     bad image sizes) are detected on the host before anything is launched and
  *     return QB_ERR_INVALID_ARG; a failed launch returns QB_ERR_HIP.  Nothing
@@ -83,7 +83,10 @@ typedef enum {
  * p = R mu + t, x right, y down, z forward; pixel (i, j) samples the image
  * point (i, j); u = fx x/z + cx.  campos is the camera centre in world space
  * (used for the view direction of the SH colour).  Gaussians with p.z <=
- * near_plane are culled. */
+ * near_plane are culled.  Every entry point that takes a camera returns
+ * QB_ERR_INVALID_ARG unless width, height, fx, fy and near_plane are
+ * positive and every field is finite (depth keys are the binary32 bits of
+ * p.z, which sort correctly only for positive depths). */
 typedef struct {
     int32_t width, height;
     float fx, fy, cx, cy;
@@ -255,6 +258,18 @@ qb_status qb_render_ex(int32_t width, int32_t height, const uint32_t* ranges, co
                        uint32_t* n_contrib, uint32_t* n_touched, int32_t variant, const uint32_t* tile_order,
                        qb_stream_t stream);
 
+/* qb_render_stats -- qb_render_ex that also counts the work of Eq. (2) per
+ * pixel, for measurement (the same image, T and contributor counts):
+ *   n_touched      [H][W] uint32, required: list entries the pixel examined
+ *                  (as in qb_render)
+ *   n_composited   [H][W] uint32, required: entries that passed the 1/255
+ *                  cutoff and were composited (the pixel's stop excluded)
+ * Other arguments as qb_render_ex. */
+qb_status qb_render_stats(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
+                          const qb_splat* splats, const float* bg, float* image, float* final_T,
+                          uint32_t* n_contrib, uint32_t* n_touched, uint32_t* n_composited, int32_t variant,
+                          const uint32_t* tile_order, qb_stream_t stream);
+
 /* qb_render_backward -- gradient of Eq. (2) (the rasterizer is trained
  * through; Sec. 4.1) with respect to each Gaussian's 2D parameters.  For
  * every pixel, walks its tile's list back to front from its last contributor,
@@ -299,7 +314,6 @@ qb_status qb_project_backward(int64_t n, const float* means, const float* log_sc
                               float* d_means, float* d_log_scales, float* d_quats, float* d_opacity_logits,
                               float* d_sh, qb_stream_t stream);
 
-/* Human-readable name of a status code (static string). */
 /* ---- Several views of one Gaussian set in one launch per stage ------------
  * For multi-view training (many cameras of one scene per step).  Each view
  * keeps its own projected splats, pairs, ranges and image; the preprocessing
@@ -374,6 +388,28 @@ qb_status qb_project_backward_views(int64_t n, const float* means, const float* 
                                     const float* grad2d, float* d_means, float* d_log_scales, float* d_quats,
                                     float* d_opacity_logits, float* d_sh, qb_stream_t stream);
 
+/* qb_check_capacity -- the pair-capacity check of a frame (Sec. 2: the pair
+ * buffers of DuplicateWithKeys are sized before the frame).  qb_intersect
+ * writes the true pair count P to its device num_pairs also when P exceeds
+ * pair_capacity; it then emits no pair, qb_sort writes empty ranges and the
+ * frame renders no Gaussian.  Because the count lives on the device, no
+ * asynchronous call can report the overflow; this call does, once per frame
+ * (or per multi-view step), outside any HIP graph capture:
+ *   count        number of frames (views) to check, >= 1
+ *   num_pairs    DEVICE array [count] int64: the num_pairs of each frame's
+ *                qb_intersect (for one frame, its single int64)
+ *   capacities   HOST array [count] int64: the pair_capacity each was given
+ *   out_counts   HOST array [count] int64 receiving the counts, or NULL when
+ *                count <= 64
+ * Waits for the work queued on `stream` (the counts are read after it) and
+ * returns QB_ERR_CAPACITY when any count exceeds its capacity (the caller
+ * grows the pair and sort buffers and runs the frame again), QB_ERR_HIP when
+ * the copy or the wait fails, QB_OK otherwise.  The only entry point that
+ * synchronises. */
+qb_status qb_check_capacity(int32_t count, const int64_t* num_pairs, const int64_t* capacities,
+                            int64_t* out_counts, qb_stream_t stream);
+
+/* Human-readable name of a status code (static string). */
 const char* qb_status_string(qb_status s);
 
 /* Library version, major*10000 + minor*100 + patch. */

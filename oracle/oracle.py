@@ -71,6 +71,8 @@ def lib():
         L.oc_pixel_boxes.argtypes = [vp, i32, vp]
         L.oc_pixel_boxes.restype = i32
         L.oc_project64.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp]
+        L.oc_set_threads.argtypes = [i32]
+        L.oc_threads.restype = i32
         lay = np.zeros(6, np.int64)
         L.oc_layout(lay.ctypes.data)
         assert lay[0] == GAUSS_DTYPE.itemsize and lay[1] == 44 and lay[2] == 48
@@ -81,6 +83,15 @@ def lib():
 
 def _p(a):
     return a.ctypes.data
+
+
+def set_threads(t: int) -> None:
+    """Worker threads of the oracle's parallel loops."""
+    lib().oc_set_threads(int(t))
+
+
+def threads() -> int:
+    return int(lib().oc_threads())
 
 
 def camera_struct(cam) -> _Cam:

@@ -24,7 +24,8 @@
  *                     isotropic projection, support-function brute force (Eq. 8)
  *   oc_sh_basis       pinned: complex spherical harmonics of scipy
  *   oc_tile_set       pinned: brute-force conservativeness, set inclusions
- *   oc_pairs          pinned: library sort (qsort) + uniqueness/inclusion tests
+ *   oc_pairs          pinned: library sort (qsort of chunks, merged) +
+ *                     uniqueness/inclusion tests, a single qsort of the list
  *   oc_ranges         pinned: binary search definition vs linear scan
  *   oc_render         pinned: Eq. (2) closed forms for one and two Gaussians,
  *                     tile-free brute-force render
@@ -421,6 +422,47 @@ static uint64_t oc_depth_bits(float d)
     return (uint64_t)u;
 }
 
+/* Sorts the pairs ascending by (key, id): chunks sorted with qsort in
+ * parallel, then merged pairwise, round by round.  The comparator is a total
+ * order (no two pairs share key and id), so the result is the one a single
+ * qsort of the whole list gives. */
+static void oc_sort_pairs(oc_pair* pr, int64_t total)
+{
+    const int64_t min_chunk = 1 << 16;
+    int64_t chunks = 1;
+    while (chunks < 64 && total / (chunks * 2) >= min_chunk) chunks *= 2;
+    if (chunks == 1) {
+        qsort(pr, (size_t)total, sizeof(oc_pair), oc_pair_cmp);
+        return;
+    }
+    int64_t step = (total + chunks - 1) / chunks;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < chunks; c++) {
+        int64_t lo = c * step, hi = lo + step < total ? lo + step : total;
+        if (hi > lo) qsort(pr + lo, (size_t)(hi - lo), sizeof(oc_pair), oc_pair_cmp);
+    }
+    oc_pair* tmp = (oc_pair*)malloc(sizeof(oc_pair) * (size_t)total);
+    oc_pair *src = pr, *dst = tmp;
+    for (int64_t width = step; width < total; width *= 2) {
+        int64_t merges = (total + 2 * width - 1) / (2 * width);
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t m = 0; m < merges; m++) {
+            int64_t lo = m * 2 * width;
+            int64_t mid = lo + width < total ? lo + width : total;
+            int64_t hi = lo + 2 * width < total ? lo + 2 * width : total;
+            int64_t a = lo, b = mid, o = lo;
+            while (a < mid && b < hi) dst[o++] = oc_pair_cmp(&src[b], &src[a]) < 0 ? src[b++] : src[a++];
+            while (a < mid) dst[o++] = src[a++];
+            while (b < hi) dst[o++] = src[b++];
+        }
+        oc_pair* t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != pr) memcpy(pr, src, sizeof(oc_pair) * (size_t)total);
+    free(tmp);
+}
+
 /* Emits and sorts every pair; returns P (or -1 when P > capacity). */
 int64_t oc_pairs(const oc_gauss* g, int64_t n, int tiles_x, int64_t capacity, uint64_t* keys,
                  uint32_t* ids)
@@ -454,7 +496,7 @@ int64_t oc_pairs(const oc_gauss* g, int64_t n, int tiles_x, int64_t capacity, ui
         }
         free(tl);
     }
-    qsort(pr, (size_t)total, sizeof(oc_pair), oc_pair_cmp);
+    oc_sort_pairs(pr, total);
     for (int64_t k = 0; k < total; k++) {
         keys[k] = pr[k].key;
         ids[k] = pr[k].id;
@@ -678,6 +720,17 @@ int64_t oc_coverage_audit(const oc_gauss* g, int64_t n, int W, int H, double mar
     if (exact_pairs) *exact_pairs = exact;
     return missed;
 }
+
+/* Worker threads of the parallel loops (the CPU baseline times the oracle
+ * on all cores and on one). */
+#ifdef _OPENMP
+#include <omp.h>
+void oc_set_threads(int32_t t) { omp_set_num_threads(t > 0 ? t : 1); }
+int32_t oc_threads(void) { return (int32_t)omp_get_max_threads(); }
+#else
+void oc_set_threads(int32_t t) { (void)t; }
+int32_t oc_threads(void) { return 1; }
+#endif
 
 /* Struct layout, so the Python side can check its view of oc_gauss. */
 #include <stddef.h>

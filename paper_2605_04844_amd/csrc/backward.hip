@@ -690,7 +690,7 @@ extern "C" qb_status qb_project_backward(int64_t n, const float* means, const fl
                                          float* d_opacity_logits, float* d_sh, qb_stream_t stream)
 {
     if (n < 0 || n >= (int64_t)1 << 31 || !cam || sh_degree < 0 || sh_degree > 3) return QB_ERR_INVALID_ARG;
-    if (cam->width <= 0 || cam->height <= 0 || !(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return QB_ERR_INVALID_ARG;
+    if (!qb_valid_camera(*cam)) return QB_ERR_INVALID_ARG;
     if (n == 0) return QB_OK;
     if (!means || !log_scales || !quats || !opacity_logits || !sh || !splats || !grad2d || !d_means ||
         !d_log_scales || !d_quats || !d_opacity_logits || !d_sh)
@@ -753,7 +753,7 @@ extern "C" qb_status qb_project_backward_views(int64_t n, const float* means, co
     BwdCamTable ct;
     for (int v = 0; v < num_views; ++v) {
         const qb_camera& c = cams[v];
-        if (c.width <= 0 || c.height <= 0 || !(c.fx > 0.0f) || !(c.fy > 0.0f)) return QB_ERR_INVALID_ARG;
+        if (!qb_valid_camera(c)) return QB_ERR_INVALID_ARG;
         make_bwd_cam(c, &ct.cam[v]);
     }
     if (n == 0) return QB_OK;

@@ -393,12 +393,6 @@ __global__ __launch_bounds__(QB_BLOCK) void k_project_views(
 
 namespace {
 
-bool valid_camera(const qb_camera& c)
-{
-    return c.width > 0 && c.height > 0 && c.width <= 32767 * QB_TILE && c.height <= 32767 * QB_TILE &&
-           c.fx > 0.0f && c.fy > 0.0f;
-}
-
 void make_proj_cam(const qb_camera& cam, ProjCam* pc)
 {
     pc->W = cam.width;
@@ -426,7 +420,7 @@ extern "C" qb_status qb_project(int64_t n, const float* means, const float* log_
 {
     if (n < 0 || n >= (int64_t)1 << 31 || !cam || sh_degree < 0 || sh_degree > 3) return QB_ERR_INVALID_ARG;
     if (!qb_valid_mode(mode)) return QB_ERR_INVALID_ARG;
-    if (!valid_camera(*cam)) return QB_ERR_INVALID_ARG;
+    if (!qb_valid_camera(*cam)) return QB_ERR_INVALID_ARG;
     if (n == 0) return QB_OK;
     if (!means || !log_scales || !quats || !opacity_logits || !sh || !out_splats || !out_rects ||
         !out_counts)
@@ -452,7 +446,7 @@ extern "C" qb_status qb_project_views(int64_t n, const float* means, const float
     if (!qb_valid_mode(mode)) return QB_ERR_INVALID_ARG;
     ProjCamTable ct;
     for (int v = 0; v < num_views; ++v) {
-        if (!valid_camera(cams[v])) return QB_ERR_INVALID_ARG;
+        if (!qb_valid_camera(cams[v])) return QB_ERR_INVALID_ARG;
         make_proj_cam(cams[v], &ct.cam[v]);
     }
     if (n == 0) return QB_OK;

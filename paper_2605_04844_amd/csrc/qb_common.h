@@ -34,6 +34,22 @@ static inline bool qb_valid_mode(int32_t mode)
     return !((mode & QB_CLIP_3SIGMA) && base == QB_BOX_3SIGMA);
 }
 
+// A usable camera: positive image size within the tile-id range, positive
+// focal lengths, a positive near plane (depth keys are the binary32 bits of
+// the view depth, which order correctly only for positive depths), and
+// finite intrinsics, pose and centre.
+static inline bool qb_valid_camera(const qb_camera& c)
+{
+    if (c.width <= 0 || c.height <= 0 || c.width > 32767 * QB_TILE || c.height > 32767 * QB_TILE) return false;
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !(c.near_plane > 0.0f)) return false;
+    float all[7 + 9 + 3 + 3] = {c.fx, c.fy, c.cx, c.cy, c.near_plane};
+    for (int k = 0; k < 9; ++k) all[7 + k] = c.R[k];
+    for (int k = 0; k < 3; ++k) all[16 + k] = c.t[k], all[19 + k] = c.campos[k];
+    for (float x : all)
+        if (!(x - x == 0.0f)) return false;   // NaN or infinite
+    return true;
+}
+
 // Bump allocator over a caller workspace; every slice is 256-byte aligned.
 struct QbArena {
     char* base;

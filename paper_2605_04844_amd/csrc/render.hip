@@ -38,7 +38,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
                                             const uint32_t* __restrict__ ids, const float4* __restrict__ splats,
                                             float bg0, float bg1, float bg2, float* __restrict__ image,
                                             float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
-                                            uint32_t* __restrict__ n_touched)
+                                            uint32_t* __restrict__ n_touched, uint32_t* __restrict__ n_composited)
 {
     constexpr int NT = 256 / PPL;        // lanes per tile
     constexpr int LX = QB_TILE / PPL;    // lanes per tile row
@@ -63,7 +63,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
     constexpr float kStopped = __builtin_huge_valf();
     bool in[PPL];
     float fxp[PPL], T[PPL], c0[PPL], c1[PPL], c2[PPL];
-    uint32_t last[PPL], stop[PPL];
+    uint32_t last[PPL], stop[PPL], comp[PPL];
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
         int px = tx * QB_TILE + lx + q * LX;
@@ -71,7 +71,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
         fxp[q] = in[q] ? (float)px : kStopped;
         T[q] = 1.0f;
         c0[q] = c1[q] = c2[q] = 0.0f;
-        last[q] = stop[q] = 0u;
+        last[q] = stop[q] = comp[q] = 0u;
     }
     auto all_done = [&]() {
         bool d = true;
@@ -119,6 +119,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
                 T[q] = add ? test_T : T[q];
                 last[q] = add ? at : last[q];
                 if (COUNT) stop[q] = stp ? at : stop[q];
+                if (COUNT) comp[q] += add ? 1u : 0u;
                 fxp[q] = stp ? kStopped : fxp[q];
                 stopped[q] = stp;
             }
@@ -227,11 +228,13 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
         if (final_T) final_T[pix] = T[q];
         if (n_contrib) n_contrib[pix] = last[q];
         if (COUNT) n_touched[pix] = fxp[q] == kStopped ? stop[q] : len;
+        if (COUNT && n_composited) n_composited[pix] = comp[q];
     }
 }
 
-// COUNT: also write n_touched (entries examined per pixel), compiled out of
-// the launches that do not ask for it.  Workgroup i takes tile order[i]
+// COUNT: also write n_touched (entries examined per pixel) and, when given,
+// n_composited (entries composited per pixel), compiled out of the launches
+// that do not ask for them.  Workgroup i takes tile order[i]
 // (qb_tile_order), or tile i when order is NULL; an entry past the last tile
 // is skipped.
 template <int PPL, bool COUNT, bool SKIP>
@@ -239,12 +242,12 @@ __global__ __launch_bounds__(256 / PPL) void k_render(
     int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splats, float bg0, float bg1, float bg2, float* __restrict__ image,
     float* __restrict__ final_T, uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ n_touched,
-    const uint32_t* __restrict__ order)
+    uint32_t* __restrict__ n_composited, const uint32_t* __restrict__ order)
 {
     uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     if (tile >= gridDim.x) return;
     render_tile<PPL, COUNT, SKIP>((int)tile, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T,
-                                  n_contrib, n_touched);
+                                  n_contrib, n_touched, n_composited);
 }
 
 // Every tile of every view in one launch: workgroup i takes global tile
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(256 / PPL) void k_render_views(QbViewTable vt, cons
     const qb_view& w = vt.view[v];
     render_tile<PPL, false, SKIP>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
                      w.ids, reinterpret_cast<const float4*>(w.splats), bg0, bg1, bg2, w.image, w.final_T, w.n_contrib,
-                     nullptr);
+                     nullptr, nullptr);
 }
 
 }  // namespace
@@ -270,19 +273,20 @@ __global__ __launch_bounds__(256 / PPL) void k_render_views(QbViewTable vt, cons
 template <bool COUNT>
 static qb_status launch_render(int variant, int64_t tiles, hipStream_t s, int W, int H, int tiles_x,
                                const uint2* rg, const uint32_t* ids, const float4* sp, const float* bg, float* image,
-                               float* final_T, uint32_t* n_contrib, uint32_t* n_touched, const uint32_t* order)
+                               float* final_T, uint32_t* n_contrib, uint32_t* n_touched, uint32_t* n_composited,
+                               const uint32_t* order)
 {
     switch (variant) {
     case QB_RENDER_2PX: QB_LAUNCH((k_render<2, COUNT, false>), tiles, 128, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
-                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, order); break;
+                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, n_composited, order); break;
     case QB_RENDER_1PX: QB_LAUNCH((k_render<1, COUNT, false>), tiles, 256, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
-                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, order); break;
+                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, n_composited, order); break;
     case QB_RENDER_4PX: QB_LAUNCH((k_render<4, COUNT, false>), tiles, 64, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
-                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, order); break;
+                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, n_composited, order); break;
     case QB_RENDER_2PX_ROWS: QB_LAUNCH((k_render<2, COUNT, true>), tiles, 128, 0, s, W, H, tiles_x, rg, ids, sp,
-                                       bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched, order); break;
+                                       bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched, n_composited, order); break;
     default: QB_LAUNCH((k_render<1, COUNT, true>), tiles, 256, 0, s, W, H, tiles_x, rg, ids, sp, bg[0], bg[1],
-                       bg[2], image, final_T, n_contrib, n_touched, order); break;
+                       bg[2], image, final_T, n_contrib, n_touched, n_composited, order); break;
     }
     return QB_OK;
 }
@@ -303,9 +307,25 @@ extern "C" qb_status qb_render_ex(int32_t width, int32_t height, const uint32_t*
     const float4* sp = reinterpret_cast<const float4*>(splats);
     if (n_touched)
         return launch_render<true>(variant, tiles, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg, image, final_T,
-                                   n_contrib, n_touched, tile_order);
+                                   n_contrib, n_touched, nullptr, tile_order);
     return launch_render<false>(variant, tiles, s, (int)width, (int)height, tiles_x, rg, ids, sp, bg, image, final_T,
-                                n_contrib, n_touched, tile_order);
+                                n_contrib, nullptr, nullptr, tile_order);
+}
+
+extern "C" qb_status qb_render_stats(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,
+                                     const qb_splat* splats, const float* bg, float* image, float* final_T,
+                                     uint32_t* n_contrib, uint32_t* n_touched, uint32_t* n_composited,
+                                     int32_t variant, const uint32_t* tile_order, qb_stream_t stream)
+{
+    if (width <= 0 || height <= 0 || width > 32767 * QB_TILE || height > 32767 * QB_TILE || !ranges ||
+        !image || !bg || !n_touched || !n_composited || variant < 0 || variant >= QB_RENDER_VARIANTS)
+        return QB_ERR_INVALID_ARG;
+    int tiles_x = (int)qb_div_up(width, QB_TILE);
+    int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
+    if (tiles > (1 << 24)) return QB_ERR_INVALID_ARG;
+    return launch_render<true>(variant, tiles, qb_hip_stream(stream), (int)width, (int)height, tiles_x,
+                               reinterpret_cast<const uint2*>(ranges), ids, reinterpret_cast<const float4*>(splats),
+                               bg, image, final_T, n_contrib, n_touched, n_composited, tile_order);
 }
 
 extern "C" qb_status qb_render(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* ids,

@@ -107,6 +107,10 @@ def lib():
     L.qb_status_string.restype = C.c_char_p
     L.qb_version.argtypes = []
     L.qb_version.restype = i32
+    L.qb_render_stats.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]
+    L.qb_render_stats.restype = i32
+    L.qb_check_capacity.argtypes = [i32, vp, vp, vp, vp]
+    L.qb_check_capacity.restype = i32
     _lib = L
     return L
 
@@ -122,6 +126,15 @@ def _check(fn, s):
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(cond, msg):
+    if not cond:
+        raise ValueError(msg)
+
+
+def _rows(t):
+    return 0 if t is None else int(t.shape[0])
 
 
 def _stream():
@@ -179,6 +192,7 @@ class Gaussians:
 # ---- one call per ABI entry point --------------------------------------------
 
 def project(g: Gaussians, cam, mode, splats, rects, counts):
+    _need(min(_rows(splats), _rows(rects), _rows(counts)) >= g.n, "qb_project: output buffers hold fewer than n rows")
     _check("qb_project", lib().qb_project(
         g.n, _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats), _ptr(g.logits), _ptr(g.sh), g.sh_degree,
         C.byref(camera_struct(cam)), _mode(mode), _ptr(splats), _ptr(rects), _ptr(counts), _stream()))
@@ -190,6 +204,9 @@ def intersect_workspace_size(n: int) -> int:
 
 def intersect(n, splats, rects, counts, width, height, capacity, pair_tiles, pair_ids, num_pairs, ws,
               mode="quadbox"):
+    _need(min(_rows(splats), _rows(rects), _rows(counts)) >= n, "qb_intersect: inputs hold fewer than n rows")
+    _need(capacity == 0 or min(_rows(pair_tiles), _rows(pair_ids)) >= capacity,
+          "qb_intersect: pair buffers hold fewer than capacity entries")
     _check("qb_intersect", lib().qb_intersect(
         n, _ptr(splats), _ptr(rects), _ptr(counts), width, height, _mode(mode), capacity, _ptr(pair_tiles),
         _ptr(pair_ids),
@@ -219,8 +236,19 @@ def render(width, height, ranges, ids, splats, bg, image, final_T=None, n_contri
         _ptr(n_contrib), _ptr(n_touched), int(variant), _ptr(order), _stream()))
 
 
+def render_stats(width, height, ranges, ids, splats, bg, image, final_T, n_contrib, n_touched, n_composited,
+                 variant=0, order=None):
+    """qb_render_stats: the render plus per-pixel counts of the examined and
+    the composited list entries."""
+    bgv = (C.c_float * 3)(*[float(x) for x in bg])
+    _check("qb_render_stats", lib().qb_render_stats(
+        width, height, _ptr(ranges), _ptr(ids), _ptr(splats), C.cast(bgv, C.c_void_p), _ptr(image), _ptr(final_T),
+        _ptr(n_contrib), _ptr(n_touched), _ptr(n_composited), int(variant), _ptr(order), _stream()))
+
+
 def render_backward(width, height, ranges, ids, splats, bg, final_T, n_contrib, dl_dimage, n, grad2d, variant=0,
                     order=None):
+    _need(n == 0 or min(_rows(grad2d), _rows(splats)) >= n, "qb_render_backward: grad2d/splats hold fewer than n rows")
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
     _check("qb_render_backward_ex", lib().qb_render_backward_ex(
         width, height, _ptr(ranges), _ptr(ids), _ptr(splats), C.cast(bgv, C.c_void_p), _ptr(final_T),
@@ -228,10 +256,27 @@ def render_backward(width, height, ranges, ids, splats, bg, final_T, n_contrib, 
 
 
 def project_backward(g: Gaussians, cam, splats, grad2d, d_means, d_log_scales, d_quats, d_logits, d_sh):
+    _need(min(_rows(splats), _rows(grad2d)) >= g.n, "qb_project_backward: splats/grad2d hold fewer than n rows")
     _check("qb_project_backward", lib().qb_project_backward(
         g.n, _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats), _ptr(g.logits), _ptr(g.sh), g.sh_degree,
         C.byref(camera_struct(cam)), _ptr(splats), _ptr(grad2d), _ptr(d_means), _ptr(d_log_scales), _ptr(d_quats),
         _ptr(d_logits), _ptr(d_sh), _stream()))
+
+
+def check_capacity(num_pairs, capacities, raise_on_overflow=True):
+    """qb_check_capacity: waits for the work queued on the current stream,
+    returns the pair counts of the frames whose device counts `num_pairs`
+    (int64 [count]) holds, and raises QBError(QB_ERR_CAPACITY) when one
+    exceeds its capacity (unless raise_on_overflow is False)."""
+    caps = [int(c) for c in capacities]
+    _need(num_pairs.dtype == torch.int64 and num_pairs.numel() >= len(caps) >= 1, "check_capacity: bad arguments")
+    cap_arr = (C.c_int64 * len(caps))(*caps)
+    out = (C.c_int64 * len(caps))()
+    s = lib().qb_check_capacity(len(caps), _ptr(num_pairs), C.cast(cap_arr, C.c_void_p), C.cast(out, C.c_void_p),
+                                _stream())
+    if s != QB_ERR_CAPACITY or raise_on_overflow:
+        _check("qb_check_capacity", s)
+    return list(out)
 
 
 # ---- whole forward with persistent buffers -------------------------------------
@@ -252,6 +297,7 @@ class Rasterizer:
     def __init__(self, n: int, cam, device="cuda", capacity: int = 0, write_keys: bool = True,
                  balance: bool = True):
         self.n, self.cam, self.device = n, cam, device
+        self.generation = 0   # forwards run so far (a backward must follow its own forward)
         self.balance = balance
         self.W, self.H = int(cam.width), int(cam.height)
         self.num_tiles = cam.tiles_x * cam.tiles_y
@@ -286,7 +332,15 @@ class Rasterizer:
         self.ws_sort = torch.empty(sort_workspace_size(cap), dtype=torch.uint8, device=d)
         self.capacity = cap
 
+    def use_camera(self, cam):
+        """Render later frames from `cam` (same image size: the image, tile
+        and range buffers are sized for it)."""
+        _need(int(cam.width) == self.W and int(cam.height) == self.H,
+              f"camera {cam.width}x{cam.height} does not match the rasterizer's {self.W}x{self.H}")
+        self.cam = cam
+
     def project(self, g: Gaussians, mode):
+        _need(g.n == self.n, f"{g.n} Gaussians given to a rasterizer sized for {self.n}")
         project(g, self.cam, mode, self.splats, self.rects, self.counts)
         self.mode = mode
 
@@ -311,11 +365,20 @@ class Rasterizer:
         render(self.W, self.H, self.ranges, self.ids_sorted, self.splats, bg, self.image, self.final_T,
                self.n_contrib, self.n_touched, self.render_variant, self.tile_order())
 
-    def forward(self, g: Gaussians, mode="quadbox", bg=(0.0, 0.0, 0.0), sync_count=True):
+    def forward(self, g: Gaussians, mode="quadbox", bg=(0.0, 0.0, 0.0), sync_count=True, cam=None):
+        """One frame.  With sync_count, the pair count is checked after
+        qb_intersect (qb_check_capacity) and the pair buffers grown and the
+        intersection re-run when it overflowed; without it nothing is read
+        back, and check_capacity() afterwards raises if the frame overflowed
+        (it then rendered no Gaussian).  `cam` (same size) replaces the
+        rasterizer's camera from this frame on."""
+        if cam is not None:
+            self.use_camera(cam)
+        self.generation += 1
         self.project(g, mode)
         self.intersect()
         if sync_count:
-            p = int(self.num_pairs.item())
+            p = check_capacity(self.num_pairs, [self.capacity], raise_on_overflow=False)[0]
             if p > self.capacity:
                 self._alloc_pairs(int(p * 1.1) + 1024)
                 self.intersect()
@@ -326,6 +389,11 @@ class Rasterizer:
 
     def pairs(self) -> int:
         return int(self.num_pairs.item())
+
+    def check_capacity(self) -> int:
+        """The last frame's pair count; raises QBError(QB_ERR_CAPACITY) when
+        it exceeded the pair capacity."""
+        return check_capacity(self.num_pairs, [self.capacity])[0]
 
 
 # ---- autograd ------------------------------------------------------------------
@@ -338,13 +406,17 @@ class _Rasterize(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, logits, sh, cam, mode, bg, rast):
         g = Gaussians(tensors=(means.detach(), log_scales.detach(), quats.detach(), logits.detach(), sh.detach()))
-        rast.forward(g, mode, bg)
+        rast.forward(g, mode, bg, cam=cam)
         ctx.rast, ctx.cam, ctx.bg, ctx.g = rast, cam, bg, g
+        ctx.generation = rast.generation
         return rast.image.clone()
 
     @staticmethod
     def backward(ctx, dl_dimage):
         r, g = ctx.rast, ctx.g
+        if r.generation != ctx.generation:
+            raise RuntimeError("the Rasterizer ran another forward since this one; its backward needs that "
+                               "forward's buffers (use one Rasterizer per pending backward)")
         dl = dl_dimage.contiguous().float()
         grad2d = torch.empty((max(g.n, 1), 9), dtype=torch.float32, device=dl.device)
         render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, ctx.bg, r.final_T, r.n_contrib, dl, g.n, grad2d,
@@ -362,6 +434,9 @@ def rasterize(means, log_scales, quats, logits, sh, cam, mode="quadbox", bg=(0.0
     n = int(means.shape[1])
     if rasterizer is None:
         rasterizer = Rasterizer(n, cam, device=means.device, write_keys=False)
+    _need(rasterizer.n == n, f"rasterizer sized for {rasterizer.n} Gaussians, {n} given")
+    _need(int(cam.width) == rasterizer.W and int(cam.height) == rasterizer.H,
+          "camera size differs from the rasterizer's")
     return _Rasterize.apply(means, log_scales, quats, logits, sh, cam, mode, tuple(bg), rasterizer)
 
 
@@ -456,9 +531,11 @@ class MultiView:
         intersect(self.n, s, r, c, w, h, cap, self.pair_tiles[v] if cap else None,
                   self.pair_ids[v] if cap else None, npairs, self.ws_isect[v % self.S], self.mode)
 
-    def size_pairs(self, g: Gaussians, mode="quadbox", slack=1.1):
+    def size_pairs(self, g: Gaussians, mode="quadbox", slack=1.1, pad=1024):
         """Runs the projection and counting once (one host synchronisation)
-        and sizes every view's pair buffers with `slack`."""
+        and sizes every view's pair buffers: count * slack + pad, rounded up
+        to 256 pairs."""
+        _need(g.n == self.n, f"{g.n} Gaussians given to a MultiView sized for {self.n}")
         self.mode = mode
         self.capacity = [0] * self.V
         project_views(g, self.cam_array, self.V, mode, self.splats, self.rects, self.counts)
@@ -467,7 +544,7 @@ class MultiView:
         counts = self.num_pairs.cpu().tolist()
         # capacities in multiples of 256 pairs keep every view's slice of the
         # flat pair buffers 512-byte aligned
-        self.capacity = [(int(p * slack) + 1024 + 255) // 256 * 256 for p in counts]
+        self.capacity = [(int(p * slack) + int(pad) + 255) // 256 * 256 for p in counts]
         total = sum(self.capacity)
         d = self.device
         flat_t = torch.empty(total, dtype=torch.int16, device=d)
@@ -517,6 +594,7 @@ class MultiView:
     def forward(self, g: Gaussians, bg=(0.0, 0.0, 0.0)):
         if self._table is None:
             raise RuntimeError("call size_pairs() first")
+        _need(g.n == self.n, f"{g.n} Gaussians given to a MultiView sized for {self.n}")
         project_views(g, self.cam_array, self.V, self.mode, self.splats, self.rects, self.counts)
 
         def prep(v):
@@ -547,7 +625,17 @@ class MultiView:
         return self.grads
 
     def overflowed(self) -> bool:
-        return any(p > c for p, c in zip(self.num_pairs.cpu().tolist(), self.capacity))
+        """Whether a view of the last step had more pairs than its capacity
+        (that view then rendered no Gaussian and got no gradient)."""
+        counts = check_capacity(self.num_pairs, self.capacity, raise_on_overflow=False)
+        return any(p > c for p, c in zip(counts, self.capacity))
+
+    def check_capacity(self):
+        """Per-view pair counts of the last step; raises
+        QBError(QB_ERR_CAPACITY) when a view overflowed (call once per step,
+        outside a graph capture, e.g. after each replay; re-size with
+        size_pairs and capture again on overflow)."""
+        return check_capacity(self.num_pairs, self.capacity)
 
 
 # ---- autotuner -----------------------------------------------------------------

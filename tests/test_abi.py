@@ -133,3 +133,53 @@ def test_launch_shape_and_view_entry_points_reject_bad_arguments():
     cams[1].fx = 64.0
     assert L.qb_project_backward_views(10, d, d, d, d, d, 4, cams, 2, d, d, d, d, d, d, d, None) == \
         qb.QB_ERR_INVALID_ARG
+
+
+def test_cameras_need_a_positive_near_plane_and_finite_fields():
+    """Depth keys are the binary32 bits of the view depth, which order
+    correctly only for positive depths: every entry point that takes a camera
+    rejects near_plane <= 0 (or NaN) and any non-finite field."""
+    L = qb.lib()
+    d = C.c_void_p(256)
+
+    def proj(c):
+        return L.qb_project(4, d, d, d, d, d, 0, C.byref(c), 2, d, d, d, None)
+
+    def proj_bwd(c):
+        return L.qb_project_backward(4, d, d, d, d, d, 0, C.byref(c), d, d, d, d, d, d, d, None)
+
+    def views(c):
+        cams = (qb.CCamera * 2)(_cam(), c)
+        return (L.qb_project_views(4, d, d, d, d, d, 0, cams, 2, 2, d, d, d, None),
+                L.qb_project_backward_views(4, d, d, d, d, d, 0, cams, 2, d, d, d, d, d, d, d, None))
+
+    for near in (0.0, -0.5, float("nan")):
+        c = _cam()
+        c.near_plane = near
+        assert proj(c) == qb.QB_ERR_INVALID_ARG
+        assert proj_bwd(c) == qb.QB_ERR_INVALID_ARG
+        assert views(c) == (qb.QB_ERR_INVALID_ARG, qb.QB_ERR_INVALID_ARG)
+    for field, k in (("R", 4), ("t", 2), ("campos", 0)):
+        c = _cam()
+        getattr(c, field)[k] = float("inf")
+        assert proj(c) == qb.QB_ERR_INVALID_ARG and proj_bwd(c) == qb.QB_ERR_INVALID_ARG
+    c = _cam()
+    c.cx = float("nan")
+    assert proj(c) == qb.QB_ERR_INVALID_ARG
+    # a valid camera with n = 0 is accepted without touching the device
+    assert L.qb_project(0, None, None, None, None, None, 0, C.byref(_cam()), 2, None, None, None, None) == qb.QB_OK
+
+
+def test_check_capacity_rejects_bad_arguments():
+    """qb_check_capacity validates everything on the host before it reads
+    the device counts."""
+    L = qb.lib()
+    d = C.c_void_p(256)
+    caps = (C.c_int64 * 65)(*([10] * 65))
+    neg = (C.c_int64 * 2)(10, -1)
+    cp = C.cast(caps, C.c_void_p)
+    assert L.qb_check_capacity(0, d, cp, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_check_capacity(1, None, cp, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_check_capacity(1, d, None, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_check_capacity(2, d, C.cast(neg, C.c_void_p), None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_check_capacity(65, d, cp, None, None) == qb.QB_ERR_INVALID_ARG   # > 64 needs out_counts

@@ -1,6 +1,7 @@
 """Host-side checks of bench.py (no GPU): the lookup of the committed render
-counters that fills roofline.traffic, the design bytes of the HBM-bound
-stages, and the refusal of more than one GPU."""
+counters that fills roofline.traffic, the itemised FLOPs and the roofline
+arithmetic, the design bytes of the HBM-bound stages, and the refusal of
+more than one GPU."""
 import hashlib
 import json
 import os
@@ -24,13 +25,16 @@ def test_render_traffic_lookup():
     current = hashlib.sha256(open(RENDER_SRC, "rb").read()).hexdigest() == meta["render_source_sha256"]
     for name, k in meta["kernels"].items():
         assert k["fetch_bytes_per_launch"] > 0 and k["write_bytes_per_launch"] > 0, name
-        got = bench.render_traffic("clusters", "quadbox", name)
+        got = bench.render_counters("clusters", "quadbox", name)
         want = k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
-        assert got == (want if current else None), name
+        if current:
+            assert got["traffic"] == want and got["valu_insts"] == k.get("valu_insts_per_launch"), name
+        else:
+            assert got is None, name
     # another shape, workload or mode: no figure
-    assert bench.render_traffic("clusters", "quadbox", "k_render<8, false, false>") is None
-    assert bench.render_traffic("aniso", "quadbox", next(iter(meta["kernels"]))) is None
-    assert bench.render_traffic("clusters", "adr", next(iter(meta["kernels"]))) is None
+    assert bench.render_counters("clusters", "quadbox", "k_render<8, false, false>") is None
+    assert bench.render_counters("aniso", "quadbox", next(iter(meta["kernels"]))) is None
+    assert bench.render_counters("clusters", "adr", next(iter(meta["kernels"]))) is None
 
 
 def test_render_traffic_stale_source(tmp_path, monkeypatch):
@@ -44,7 +48,21 @@ def test_render_traffic_stale_source(tmp_path, monkeypatch):
     src.mkdir(parents=True)
     (src / "render.hip").write_bytes(open(RENDER_SRC, "rb").read())
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.render_traffic("clusters", "quadbox", next(iter(meta["kernels"]))) is None
+    assert bench.render_counters("clusters", "quadbox", next(iter(meta["kernels"]))) is None
+
+
+def test_flops_and_roofline_arithmetic():
+    """FLOPs per launch: 9 per examined and 11 more per composited entry in
+    the render, 9 per entry before the last contributor and 30 more per
+    composited entry in the backward; the fraction is FLOP/s over the
+    published 157.3 TFLOP/s."""
+    work = {"examined": 1000, "composited": 400, "contributors": 700}
+    assert bench.render_flops(work) == 9 * 1000 + 11 * 400
+    assert bench.backward_flops(work) == 9 * 700 + 30 * 400
+    r = bench.alu_roofline(1.573e11, 1.0, "k", work)
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
+    assert r["achieved"] == pytest.approx(157.3, rel=1e-6) and r["frac"] == pytest.approx(1.0, rel=1e-4)
+    assert r["examined_per_launch"] == 1000 and r["traffic"] is None
 
 
 def test_stage_bytes():
@@ -59,8 +77,10 @@ def test_stage_bytes():
 
 
 def test_peaks():
-    assert bench.VALU_PEAK_TOPS == pytest.approx(157.3 / 2, rel=1e-3)
-    assert bench.VALU_SINGLE_ISSUE_TOPS == pytest.approx(39.32, rel=1e-3)
+    """Published MI355X peaks: FP32 vector 157.3 TFLOP/s (78.6 T lane-FMAs
+    per second), HBM 8 TB/s."""
+    assert bench.FP32_PEAK_TFLOPS == 157.3
+    assert bench.VALU_LANE_PEAK_T == pytest.approx(157.3 / 2, rel=1e-3)
     assert bench.HBM_PEAK_GBS == 8000.0
 
 

@@ -188,3 +188,24 @@ def test_render_pixels_matches_full_render(oracle):
     for k, (x, y) in enumerate(pix):
         assert np.array_equal(rgb[k], out["image"][:, y, x])
         assert T[k] == out["T"][y, x] and nc[k] == out["n_contrib"][y, x]
+
+
+def test_pairs_chunked_sort_matches_numpy(oracle):
+    """Above 2^17 pairs the oracle sorts chunks in parallel and merges them:
+    the list equals numpy's lexsort by (key, id) of the per-Gaussian tile
+    sets, keys built here from the tile ids and depth bits."""
+    scene, cam = scenes.cluster_scene(seed=9, n=40_000)
+    g = oracle.project(scene, cam, "3sigma")
+    keys, ids = oracle.pairs(g, cam.tiles_x)
+    assert len(keys) > 1 << 19
+    depth_bits = g["depth"].view(np.uint32).astype(np.uint64)
+    tl, il = [], []
+    for i in range(scene.n):
+        t = oracle.tile_set(g, i, cam.tiles_x)
+        tl.append(t.astype(np.uint64))
+        il.append(np.full(len(t), i, np.uint32))
+    u_ids = np.concatenate(il)
+    u_keys = (np.concatenate(tl) << np.uint64(32)) | depth_bits[u_ids]
+    order = np.lexsort((u_ids, u_keys))
+    assert np.array_equal(keys, u_keys[order])
+    assert np.array_equal(ids, u_ids[order])

@@ -8,6 +8,7 @@ per channel outside the oracle's near-threshold mask (pixels whose stopping
 test came within a relative 1e-4 of T = 1e-4, where binary32 and binary64
 transmittances may legitimately stop at different Gaussians); n_contrib exact
 outside that mask."""
+import functools
 import math
 
 import numpy as np
@@ -202,14 +203,6 @@ def test_quadbox_image_equals_adr_image(qb):
     assert np.array_equal(a["image"], q["image"]) and np.array_equal(a["T"], q["T"])
 
 
-def _sampled_tile_check(oracle, gpu, g, cam, tiles, label):
-    for t in tiles:
-        want = oracle.tile_list(g, cam.tiles_x, int(t))
-        s, e = gpu["ranges"][t]
-        got = gpu["ids"][s:e]
-        assert np.array_equal(got, want), f"{label}: tile {t} list differs ({len(got)} vs {len(want)})"
-
-
 def _sampled_render_check(oracle, gpu, g, cam, tiles, label):
     """Oracle render of only the sampled tiles (their lists built by the oracle)."""
     lists = [oracle.tile_list(g, cam.tiles_x, int(t)) for t in tiles]
@@ -227,59 +220,29 @@ def _sampled_render_check(oracle, gpu, g, cam, tiles, label):
     check_image(img, T, nc, near, gpu, label, tiles=mask)
 
 
-@pytest.mark.parametrize("mode", ["quadbox", "3sigma", "quadbox_naive"])
-def test_full_size_clusters(oracle, qb, mode):
-    """The 1M-Gaussian 1280x720 SH3 workload at full size: every projected
-    value and tile count bit-exact, keys globally sorted with consistent depth
-    bits, 160 sampled tile lists and 40 sampled tiles of pixels against the
-    oracle."""
-    scene, cam = scenes.cluster_scene()
-    label = f"clusters-1M {mode}"
-    say("running", label)
-    gpu, _ = gpu_forward(qb, scene, cam, mode)
-    g = oracle.project(scene, cam, mode)
-    check_project(oracle, gpu, g, label)
-    check_counts(oracle, gpu, g, cam.tiles_x, label)
-    keys, ids = gpu["keys"], gpu["ids"]
-    assert np.all(keys[1:] >= keys[:-1])
-    tie = keys[1:] == keys[:-1]
-    assert np.all(ids[1:][tie] > ids[:-1][tie])
-    assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), bits(g["depth"])[ids])
-    want_rt = oracle.ranges(keys, cam.num_tiles)
-    assert np.array_equal(gpu["ranges"], want_rt)
-    rng = np.random.default_rng(5)
-    busy = np.argsort(gpu["ranges"][:, 1] - gpu["ranges"][:, 0])[-20:]
-    tiles = np.unique(np.concatenate([rng.choice(cam.num_tiles, 140, replace=False), busy]))
-    _sampled_tile_check(oracle, gpu, g, cam, tiles, label)
-    _sampled_render_check(oracle, gpu, g, cam, tiles[:40], label)
+@functools.lru_cache(maxsize=None)
+def _full_scene(workload):
+    """The 1M-Gaussian 1280x720 SH3 clustered scene, or the 3M anisotropic
+    1920x1080 scene with its eight zoom cameras (generated once per run)."""
+    return scenes.cluster_scene() if workload == "clusters" else scenes.aniso_scene()
 
 
-@pytest.mark.parametrize("zoom", [1, 4, 8])
-def test_full_size_aniso_zoom(oracle, qb, zoom):
-    """The 3M highly anisotropic Gaussians at 1920x1080 with focal 1920*zoom
-    (the zoom-in sweep), QuadBox boxes: projection and counts bit-exact,
-    keys sorted with consistent depth bits, ranges exact, sampled tile lists
-    and pixels against the oracle."""
-    scene, cams = scenes.aniso_scene()
-    cam = cams[zoom - 1]
-    label = f"aniso-3M x{zoom}"
-    say("running", label)
-    gpu, _ = gpu_forward(qb, scene, cam, "quadbox")
-    g = oracle.project(scene, cam, "quadbox")
-    check_project(oracle, gpu, g, label)
-    check_counts(oracle, gpu, g, cam.tiles_x, label)
-    keys, ids = gpu["keys"], gpu["ids"]
-    assert np.all(keys[1:] >= keys[:-1])
-    tie = keys[1:] == keys[:-1]
-    assert np.all(ids[1:][tie] > ids[:-1][tie])
-    assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), bits(g["depth"])[ids])
-    assert np.array_equal(gpu["ranges"], oracle.ranges(keys, cam.num_tiles))
-    say(label, "pairs", gpu["P"])
-    rng = np.random.default_rng(10 + zoom)
-    busy = np.argsort(gpu["ranges"][:, 1] - gpu["ranges"][:, 0])[-10:]
-    tiles = np.unique(np.concatenate([rng.choice(cam.num_tiles, 60, replace=False), busy]))
-    _sampled_tile_check(oracle, gpu, g, cam, tiles, label)
-    _sampled_render_check(oracle, gpu, g, cam, tiles[:20], label)
+FULL_SIZE = [("clusters", m, 1) for m in ("quadbox", "3sigma", "adr", "quadbox_naive")] + \
+            [("aniso", "quadbox", z) for z in (1, 4, 8)] + [("aniso", "adr", 1)]
+
+
+@pytest.mark.parametrize("workload,mode,zoom", FULL_SIZE)
+def test_full_size_against_oracle(oracle, qb, workload, mode, zoom):
+    """The full-size workloads -- 1M clustered Gaussians at 1280x720 (SH3) in
+    every box mode of the headline comparison, and the 3M anisotropic
+    Gaussians at 1920x1080 with focal 1920*zoom -- against the oracle's whole
+    frame: every projected value and tile count bit-exact, the whole sorted
+    (key, id) list and every range bit-exact, every pixel within 1e-4 and
+    every contributor count exact outside the near-threshold mask."""
+    scene, cams = _full_scene(workload)
+    cam = cams if workload == "clusters" else cams[zoom - 1]
+    gpu, ref = full_check(oracle, qb, scene, cam, mode)
+    say(f"{workload} {mode} x{zoom}: {gpu['P']} pairs, all equal to the oracle's")
 
 
 def test_render_launch_shapes_identical(oracle, qb):
@@ -380,27 +343,28 @@ def test_scan_block_boundary(oracle, qb, n):
 def test_full_size_3sigma_zoom(oracle, qb):
     """The 3M anisotropic Gaussians at 1920x1080, focal x4, with 3-sigma
     boxes: ~2.5e8 pairs, so the tile sort's histogram scans take more than
-    1024 blocks.  Keys globally sorted with consistent depth bits, ranges
-    exact, sampled tile lists against the oracle."""
-    scene, cams = scenes.aniso_scene()
+    1024 blocks.  Projection, counts, the whole sorted (key, id) list and
+    every range bit-exact with the oracle's; pixels of sampled tiles (the
+    oracle renders only those) within 1e-4."""
+    scene, cams = _full_scene("aniso")
     cam = cams[3]
     label = "aniso-3M x4 3sigma"
     say("running", label)
     gpu, _ = gpu_forward(qb, scene, cam, "3sigma")
     assert gpu["P"] > 134_217_728   # more than 1024 scan blocks of 64-digit histograms
     g = oracle.project(scene, cam, "3sigma")
+    check_project(oracle, gpu, g, label)
     check_counts(oracle, gpu, g, cam.tiles_x, label)
-    keys, ids = gpu["keys"], gpu["ids"]
-    assert np.all(keys[1:] >= keys[:-1])
-    tie = keys[1:] == keys[:-1]
-    assert np.all(ids[1:][tie] > ids[:-1][tie])
-    assert np.array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), bits(g["depth"])[ids])
-    assert np.array_equal(gpu["ranges"], oracle.ranges(keys, cam.num_tiles))
+    keys, ids = oracle.pairs(g, cam.tiles_x)
+    assert np.array_equal(gpu["keys"], keys), f"{label}: sorted keys differ"
+    assert np.array_equal(gpu["ids"], ids), f"{label}: sorted ids differ"
+    assert np.array_equal(gpu["ranges"], oracle.ranges(keys, cam.num_tiles)), f"{label}: ranges differ"
+    del keys, ids
     say(label, "pairs", gpu["P"])
     rng = np.random.default_rng(31)
     busy = np.argsort(gpu["ranges"][:, 1] - gpu["ranges"][:, 0])[-5:]
     tiles = np.unique(np.concatenate([rng.choice(cam.num_tiles, 30, replace=False), busy]))
-    _sampled_tile_check(oracle, gpu, g, cam, tiles, label)
+    _sampled_render_check(oracle, gpu, g, cam, tiles, label)
 
 
 def test_clip_3sigma_image_equals_3sigma_on_gpu(oracle, qb):

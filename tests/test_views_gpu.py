@@ -183,9 +183,14 @@ def test_views_graph_replay(qb):
         say(f"replay {rep} matches the eager step")
 
 
-def test_views_full_size_matches_single_view(qb):
+def test_views_full_size_matches_single_view(oracle, qb):
     """The 2M-Gaussian, 32-view workload (640x360 / 1280x720 / 1920x1080):
-    every view's image equals the single-view path's, bit for bit."""
+    every view's image, T and contributor counts equal the single-view
+    path's bit for bit; the batched gradient of the L1 loss summed over the
+    views is within rel-L2 1e-5 of the sum of the 32 single-view gradients
+    (float atomics and the order of the sum over views differ); one
+    1920x1080 view's sorted ids, ranges and pixels equal the oracle's whole
+    frame; every render launch shape gives the same images."""
     scene, cams = scenes.multiview_scene()
     g = qb.Gaussians(scene)
     mv = qb.MultiView(scene.n, cams)
@@ -193,18 +198,50 @@ def test_views_full_size_matches_single_view(qb):
     say("pairs per view (first 6)", counts[:6], "total", sum(counts))
     mv.forward(g)
     torch.cuda.synchronize()
-    assert not mv.overflowed()
-    r = None
-    for v in range(0, mv.V, 5):
+    assert mv.check_capacity() == counts
+    targets = [torch.tensor(scenes.target_image(500 + v, c.width, c.height), device="cuda")
+               for v, c in enumerate(cams)]
+    for v in range(mv.V):
+        mv.dl[v].copy_(l1_grad(mv.images[v], targets[v]))
+    grads = [x.clone() for x in mv.backward(g)]
+    total = [torch.zeros(t.shape, dtype=torch.float64, device="cuda") for t in g.tensors()]
+    grad2d = torch.empty((scene.n, 9), dtype=torch.float32, device="cuda")
+    part = [torch.empty_like(t) for t in g.tensors()]
+    for v in range(mv.V):
         r = qb.Rasterizer(scene.n, cams[v], write_keys=False)
         r.forward(g, "quadbox")
         torch.cuda.synchronize()
         assert torch.equal(r.image, mv.images[v]), v
+        assert torch.equal(r.final_T, mv.final_T[v]), v
         assert torch.equal(r.n_contrib, mv.n_contrib[v]), v
+        dl = l1_grad(r.image, targets[v]).contiguous()
+        assert torch.equal(dl, mv.dl[v]), v
+        qb.render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, (0.0, 0.0, 0.0), r.final_T, r.n_contrib,
+                           dl, scene.n, grad2d, r.backward_variant, r.tile_order())
+        qb.project_backward(g, cams[v], r.splats, grad2d, *part)
+        for t, p in zip(total, part):
+            t.add_(p.double())
+        if v == 2:   # the first 1920x1080 view against the oracle's whole frame
+            ref = oracle.forward(scene, cams[v], "quadbox")
+            P = counts[v]
+            assert P == len(ref["ids"])
+            assert np.array_equal(mv.ids_sorted[v][:P].cpu().numpy().view(np.uint32), ref["ids"])
+            assert np.array_equal(mv.ranges[v].cpu().numpy().view(np.uint32).ravel(), ref["ranges"].ravel())
+            ok = ~ref["near"]
+            err = float(np.abs(mv.images[v].cpu().numpy() - ref["image"]).max(axis=0)[ok].max())
+            assert err <= 1e-4, err
+            assert np.array_equal(mv.n_contrib[v].cpu().numpy().view(np.uint32)[ok], ref["n_contrib"][ok])
+            say(f"view 2 (1920x1080, {P} pairs) equals the oracle's frame, image err {err:.2e}")
+            del ref
         del r
-    say("sampled views equal the single-view path")
-    for v in range(mv.V):
-        mv.dl[v].fill_(1.0 / mv.dl[v].numel())
+    torch.cuda.synchronize()
+    say("all 32 views equal the single-view path")
+    k = scene.sh.shape[0]
+    e = rel_groups(flat_grads([x.double() for x in grads], scene.n, k),
+                   flat_grads(total, scene.n, k))
+    say("batched vs single-view gradient sum, rel-L2", {a: f"{b:.2e}" for a, b in e.items()})
+    for name in GROUPS:
+        assert e[name] <= 1e-5, (name, e[name])
     t_bwd = qb.autotune_backward(mv, reps=1, trials=1)
     say("backward shapes (ms, all views)", {k: round(x, 3) for k, x in t_bwd.items()}, "picked", mv.backward_variant)
     want = [x.clone() for x in mv.images]
@@ -234,6 +271,9 @@ def test_views_capacity_overflow(qb):
     mv.forward(g, bg)
     torch.cuda.synchronize()
     assert mv.overflowed()
+    with pytest.raises(qb.QBError) as e:
+        mv.check_capacity()
+    assert e.value.status == qb.QB_ERR_CAPACITY
     empty = torch.tensor(bg, device="cuda", dtype=torch.float32)[:, None, None].expand_as(mv.images[1])
     assert torch.equal(mv.images[1], empty)
     for v in range(mv.V):
