@@ -43,7 +43,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
     constexpr int NT = 256 / PPL;        // lanes per tile
     constexpr int LX = QB_TILE / PPL;    // lanes per tile row
     __shared__ float4 s_geo[NT];   // u, v, -a/2, -b
-    __shared__ float4 s_opa[NT];   // -c/2, o, -gamma/2, unused
+    __shared__ float4 s_opa[NT];   // -c/2, o, -gamma/2, log2(o)
     __shared__ float4 s_col[NT];   // r, g, b, unused
     __shared__ int s_rows[NT];     // tile rows that can pass the cutoff (entry_rows)
 
@@ -61,6 +61,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
     // -inf, so the cutoff test rejects it by itself (a NaN power, possible
     // only there, is rejected too).
     constexpr float kStopped = __builtin_huge_valf();
+    constexpr float kLog2e = 1.44269504088896341f;
     bool in[PPL];
     float fxp[PPL], T[PPL], c0[PPL], c1[PPL], c2[PPL];
     uint32_t last[PPL], stop[PPL], comp[PPL];
@@ -91,7 +92,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             float4 b = splats[3 * (int64_t)id + 1];   // a, b, c, gamma
             float4 c = splats[3 * (int64_t)id + 2];   // r, g, b, visible
             s_geo[threadIdx.x] = make_float4(a.x, a.y, -0.5f * b.x, -b.y);
-            s_opa[threadIdx.x] = make_float4(-0.5f * b.z, a.w, -0.5f * b.w, 0.0f);
+            s_opa[threadIdx.x] = make_float4(-0.5f * b.z, a.w, -0.5f * b.w, __log2f(a.w));
             s_col[threadIdx.x] = c;
             if (kSkip) s_rows[threadIdx.x] = entry_rows(a.y, b.x, b.y, b.z, b.w, ty);
         }
@@ -100,23 +101,30 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
         uint32_t idx0 = (uint32_t)(base - start);
         // one list entry k of the batch for every pixel of the lane; returns
         // true when the whole wave has stopped
-        // composites one entry (opacity in o.y, colour col, list position
-        // at) into the lane's pixels whose power p passed (act)
+        // composites one entry (log2 of the opacity in o.w, colour col, list
+        // position at) into the lane's pixels whose power p passed (act):
+        //   alpha = min(0.99, o e^p) = min(0.99, 2^(p log2(e) + log2(o))), one
+        //           fma ahead of the exp instead of two multiplies
+        //   T'    = T - alpha T with one rounding (fma)
+        //   w     = T - T', which is alpha T up to the rounding of T' (the
+        //           subtraction is exact while alpha <= 1/2) and 0 where the
+        //           pixel adds nothing, so the weights and the final T sum to 1
         auto composite = [&](const float4& o, const float4& col, const float* p, const bool* act, uint32_t at,
                              bool* stopped) {
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
-                float alpha = fminf(0.99f, o.y * __expf(p[q]));
-                float test_T = T[q] * (1.0f - alpha);
+                float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(p[q], kLog2e, o.w)));
+                float test_T = fmaf(-alpha, T[q], T[q]);
                 // T is never NaN, so !(test_T < 1e-4) is test_T >= 1e-4; one
                 // compare gives both masks
                 bool add = act[q] && test_T >= 1e-4f;
                 bool stp = act[q] && !add;
-                float w = add ? alpha * T[q] : 0.0f;
+                float Tn = add ? test_T : T[q];
+                float w = T[q] - Tn;
                 c0[q] = fmaf(col.x, w, c0[q]);
                 c1[q] = fmaf(col.y, w, c1[q]);
                 c2[q] = fmaf(col.z, w, c2[q]);
-                T[q] = add ? test_T : T[q];
+                T[q] = Tn;
                 last[q] = add ? at : last[q];
                 if (COUNT) stop[q] = stp ? at : stop[q];
                 if (COUNT) comp[q] += add ? 1u : 0u;
