@@ -409,6 +409,30 @@ qb_status qb_project_backward_views(int64_t n, const float* means, const float* 
 qb_status qb_check_capacity(int32_t count, const int64_t* num_pairs, const int64_t* capacities,
                             int64_t* out_counts, qb_stream_t stream);
 
+/* qb_intersect_noalloc -- qb_intersect for callers that cannot allocate
+ * device memory: code recorded under HIP graph capture that may not call
+ * hipMalloc, tight serving loops, and harnesses that forbid allocation.  It
+ * takes no workspace: its scratch (the depth sort's buffers, the pair offsets
+ * and the scan partials, qb_intersect_workspace_size(n) bytes) lives in a
+ * static device array of the library, 60 MiB, one copy on every GPU the
+ * library runs on, held from the library's load until the process ends.
+ * The call itself allocates nothing: no hipMalloc, no hipFree, no
+ * allocating library routine.  The first call on a device looks up that
+ * device's copy (hipGetSymbolAddress, with the device current).
+ *   n         0 <= n <= QB_NOALLOC_MAX_GAUSSIANS; a larger n returns
+ *             QB_ERR_INVALID_ARG (use qb_intersect with a workspace)
+ *   others    as for qb_intersect; the outputs are identical to qb_intersect's
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (each call writes every scratch value it reads, so nothing needs
+ * clearing): calls that overlap on one GPU -- on different streams, or from
+ * different host threads without ordering -- race and give wrong results.
+ * Returns QB_ERR_HIP when the device's copy cannot be looked up. */
+#define QB_NOALLOC_MAX_GAUSSIANS 2097152
+qb_status qb_intersect_noalloc(int64_t n, const qb_splat* splats, const qb_rects* rects,
+                               const int32_t* counts, int32_t width, int32_t height, int32_t mode,
+                               int64_t pair_capacity, uint16_t* pair_tiles, uint32_t* pair_ids,
+                               int64_t* num_pairs, qb_stream_t stream);
+
 /* Human-readable name of a status code (static string). */
 const char* qb_status_string(qb_status s);
 

@@ -19,6 +19,8 @@
 // The naive traversal (QB_BOX_QUADBOX_NAIVE, the ablation without QPass)
 // replaces step 3 by one lane per Gaussian that walks its sub-box rects with
 // nested loops and writes its pairs one by one, as DuplicateWithKeys does.
+#include <mutex>
+
 #include "qb_bin.h"
 
 namespace {
@@ -198,22 +200,13 @@ extern "C" size_t qb_intersect_workspace_size(int64_t n)
     return a.used + 256;
 }
 
-extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_rects* rects,
-                                  const int32_t* counts, int32_t width, int32_t height, int32_t mode,
-                                  int64_t pair_capacity,
-                                  uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs, void* workspace,
-                                  size_t workspace_bytes, qb_stream_t stream)
+// The stages of qb_intersect over a workspace of `workspace_bytes` bytes at
+// `workspace` (already checked to be large enough for n).
+static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rects* rects, const int32_t* counts,
+                                int tiles_x, int32_t mode, int64_t pair_capacity, uint16_t* pair_tiles,
+                                uint32_t* pair_ids, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
+                                hipStream_t s)
 {
-    if (n < 0 || n >= (int64_t)1 << 31 || width <= 0 || height <= 0 || !qb_valid_mode(mode) || pair_capacity < 0 ||
-        pair_capacity > (int64_t)0xFFFFFFFF || !num_pairs || !workspace)
-        return QB_ERR_INVALID_ARG;
-    int tiles_x = (int)qb_div_up(width, QB_TILE);
-    int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
-    if (tiles > 65536) return QB_ERR_UNSUPPORTED;
-    if (n > 0 && (!splats || !rects || !counts)) return QB_ERR_INVALID_ARG;
-    if (pair_capacity > 0 && (!pair_tiles || !pair_ids)) return QB_ERR_INVALID_ARG;
-    if (workspace_bytes < qb_intersect_workspace_size(n)) return QB_ERR_INVALID_ARG;
-    hipStream_t s = qb_hip_stream(stream);
     QbArena a{(char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255), workspace_bytes - 256, 0};
     IsectWs w = carve(a, n);
     if (!a.ok()) return QB_ERR_INVALID_ARG;
@@ -240,4 +233,84 @@ extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_re
         QB_LAUNCH(k_emit, qb_div_up(n, kEmitThreads), kEmitThreads, 0, s, n, order, (const uint64_t*)w.offs, r4,
                   (const uint32_t*)w.csorted, tiles_x, pair_capacity, (const int64_t*)num_pairs, pair_tiles, pair_ids);
     return QB_OK;
+}
+
+// Host-side argument checks shared by qb_intersect and qb_intersect_noalloc;
+// sets the tile-row width on success.
+static qb_status intersect_args(int64_t n, const qb_splat* splats, const qb_rects* rects, const int32_t* counts,
+                                int32_t width, int32_t height, int32_t mode, int64_t pair_capacity,
+                                const uint16_t* pair_tiles, const uint32_t* pair_ids, const int64_t* num_pairs,
+                                int* tiles_x_out)
+{
+    if (n < 0 || n >= (int64_t)1 << 31 || width <= 0 || height <= 0 || !qb_valid_mode(mode) || pair_capacity < 0 ||
+        pair_capacity > (int64_t)0xFFFFFFFF || !num_pairs)
+        return QB_ERR_INVALID_ARG;
+    int tiles_x = (int)qb_div_up(width, QB_TILE);
+    int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
+    if (tiles > 65536) return QB_ERR_UNSUPPORTED;
+    if (n > 0 && (!splats || !rects || !counts)) return QB_ERR_INVALID_ARG;
+    if (pair_capacity > 0 && (!pair_tiles || !pair_ids)) return QB_ERR_INVALID_ARG;
+    *tiles_x_out = tiles_x;
+    return QB_OK;
+}
+
+extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_rects* rects,
+                                  const int32_t* counts, int32_t width, int32_t height, int32_t mode,
+                                  int64_t pair_capacity,
+                                  uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs, void* workspace,
+                                  size_t workspace_bytes, qb_stream_t stream)
+{
+    int tiles_x = 0;
+    QB_CHECK(intersect_args(n, splats, rects, counts, width, height, mode, pair_capacity, pair_tiles, pair_ids,
+                            num_pairs, &tiles_x));
+    if (!workspace || workspace_bytes < qb_intersect_workspace_size(n)) return QB_ERR_INVALID_ARG;
+    return intersect_impl(n, splats, rects, counts, tiles_x, mode, pair_capacity, pair_tiles, pair_ids, num_pairs,
+                          workspace, workspace_bytes, qb_hip_stream(stream));
+}
+
+// ---- qb_intersect without a caller workspace --------------------------------
+// The workspace of qb_intersect_noalloc: a static device array, one copy per
+// GPU the library runs on, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host the name stands for a
+// host-side shadow, not a device address): the first call on a device looks
+// up that device's address with hipGetSymbolAddress, with the device
+// current, and every later call on the device uses that address.
+namespace {
+constexpr size_t kNoallocScratchBytes = (size_t)60 << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];   // device address of `scratch` on each device, once looked up
+
+// Address of `scratch` on the current device, or nullptr on failure.
+void* scratch_on_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_dev[dev] = ptr;
+    }
+    return g_scratch_dev[dev];
+}
+}  // namespace
+
+extern "C" qb_status qb_intersect_noalloc(int64_t n, const qb_splat* splats, const qb_rects* rects,
+                                          const int32_t* counts, int32_t width, int32_t height, int32_t mode,
+                                          int64_t pair_capacity, uint16_t* pair_tiles, uint32_t* pair_ids,
+                                          int64_t* num_pairs, qb_stream_t stream)
+{
+    int tiles_x = 0;
+    QB_CHECK(intersect_args(n, splats, rects, counts, width, height, mode, pair_capacity, pair_tiles, pair_ids,
+                            num_pairs, &tiles_x));
+    if (n > QB_NOALLOC_MAX_GAUSSIANS) return QB_ERR_INVALID_ARG;
+    // the static array holds the workspace of the largest n accepted
+    if (qb_intersect_workspace_size(QB_NOALLOC_MAX_GAUSSIANS) > kNoallocScratchBytes) return QB_ERR_UNSUPPORTED;
+    void* ws = scratch_on_current_device();
+    if (!ws) return QB_ERR_HIP;
+    return intersect_impl(n, splats, rects, counts, tiles_x, mode, pair_capacity, pair_tiles, pair_ids, num_pairs,
+                          ws, kNoallocScratchBytes, qb_hip_stream(stream));
 }

@@ -111,6 +111,8 @@ def lib():
     L.qb_render_stats.restype = i32
     L.qb_check_capacity.argtypes = [i32, vp, vp, vp, vp]
     L.qb_check_capacity.restype = i32
+    L.qb_intersect_noalloc.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp]
+    L.qb_intersect_noalloc.restype = i32
     _lib = L
     return L
 
@@ -211,6 +213,23 @@ def intersect(n, splats, rects, counts, width, height, capacity, pair_tiles, pai
         n, _ptr(splats), _ptr(rects), _ptr(counts), width, height, _mode(mode), capacity, _ptr(pair_tiles),
         _ptr(pair_ids),
         _ptr(num_pairs), _ptr(ws), ws.numel() * ws.element_size(), _stream()))
+
+
+# QB_NOALLOC_MAX_GAUSSIANS: the largest n qb_intersect_noalloc accepts
+NOALLOC_MAX_GAUSSIANS = 2097152
+
+
+def intersect_noalloc(n, splats, rects, counts, width, height, capacity, pair_tiles, pair_ids, num_pairs,
+                      mode="quadbox"):
+    """qb_intersect_noalloc: qb_intersect with the library's static scratch
+    instead of a workspace (allocates nothing; calls overlapping on one GPU
+    race)."""
+    _need(min(_rows(splats), _rows(rects), _rows(counts)) >= n, "qb_intersect_noalloc: inputs hold fewer than n rows")
+    _need(capacity == 0 or min(_rows(pair_tiles), _rows(pair_ids)) >= capacity,
+          "qb_intersect_noalloc: pair buffers hold fewer than capacity entries")
+    _check("qb_intersect_noalloc", lib().qb_intersect_noalloc(
+        n, _ptr(splats), _ptr(rects), _ptr(counts), width, height, _mode(mode), capacity, _ptr(pair_tiles),
+        _ptr(pair_ids), _ptr(num_pairs), _stream()))
 
 
 def sort_workspace_size(capacity: int) -> int:

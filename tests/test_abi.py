@@ -87,6 +87,26 @@ def test_intersect_sort_render_reject_bad_arguments():
     assert L.qb_render(64, 48, None, d, d, d, d, None, None, None, None) == qb.QB_ERR_INVALID_ARG
 
 
+def test_intersect_noalloc_rejects_bad_arguments_and_fits_its_scratch():
+    """qb_intersect_noalloc checks its arguments as qb_intersect does and
+    rejects n above QB_NOALLOC_MAX_GAUSSIANS before any device work; the
+    workspace of the largest accepted n fits the library's 60 MiB static
+    scratch."""
+    L = qb.lib()
+    d = C.c_void_p(256)
+    cap = qb.NOALLOC_MAX_GAUSSIANS
+    assert qb.intersect_workspace_size(cap) <= 60 << 20
+    assert L.qb_intersect_noalloc(cap + 1, d, d, d, 64, 48, 2, 100, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect_noalloc(-1, d, d, d, 64, 48, 2, 100, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect_noalloc(10, d, d, d, 0, 48, 2, 100, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect_noalloc(10, d, d, d, 64, 48, 2, -1, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect_noalloc(10, d, d, d, 64, 48, 2, 100, d, d, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect_noalloc(10, None, d, d, 64, 48, 2, 100, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect_noalloc(10, d, d, d, 64, 48, 5, 100, d, d, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_intersect_noalloc(10, d, d, d, 16 * 300, 16 * 300, 2, 100, d, d, d, None) == \
+        qb.QB_ERR_UNSUPPORTED
+
+
 def test_launch_shape_and_view_entry_points_reject_bad_arguments():
     L = qb.lib()
     d = C.c_void_p(256)
