@@ -126,7 +126,10 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials, extras=True):
     pairs = r.pairs()
     r._alloc_pairs(pairs)
     r.forward(g, mode, sync_count=False)
-    shapes = qb.autotune_render(r, reps=10, trials=5)   # launch shape of the render for this frame
+    # launch shapes of the intersection, the tile sort and the render for this frame
+    isect_shapes = qb.autotune_intersect(r, reps=3, trials=3)
+    sort_shapes = qb.autotune_sort(r, reps=3, trials=3)
+    shapes = qb.autotune_render(r, reps=10, trials=5)
     for _ in range(warmup):
         r.forward(g, mode, sync_count=False)
     torch.cuda.synchronize()
@@ -215,10 +218,16 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials, extras=True):
         torch.cuda.synchronize()
     work = render_work(torch, qb, r)
     names = {v: k for k, v in qb.RENDER_VARIANTS.items()}
+    snames = {v: k for k, v in qb.SORT_VARIANTS.items()}
+    dnames = {v: k for k, v in qb.DEPTH_VARIANTS.items()}
+    enames = {v: k for k, v in qb.EMIT_VARIANTS.items()}
     return dict(ms=min(dev, graph_ms), eager_ms=dev, graph_ms=graph_ms, wall_ms=wall, pairs=pairs, stage_ms=stage,
                 render_launch_ms=render_launch_ms, render_rowmajor_ms=rowmajor_ms, sync_ms=sync_ms,
                 stage_launch_ms=stage_launch, work=work, rast=r,
-                render_shape=names[r.render_variant], shape_ms={k: round(v, 4) for k, v in shapes.items()})
+                render_shape=names[r.render_variant], shape_ms={k: round(v, 4) for k, v in shapes.items()},
+                sort_shape=snames[r.sort_variant], sort_shape_ms={k: round(v, 4) for k, v in sort_shapes.items()},
+                intersect_shape=f"{dnames[r.depth_variant]}/{enames[r.emit_variant]}",
+                intersect_shape_ms={k: round(v, 4) for k, v in isect_shapes.items()})
 
 
 def run_fwd_bwd(torch, qb, g, cam, steps, warmup, trials):
@@ -304,12 +313,19 @@ def run_multiview(torch, qb, steps, warmup, trials):
     for v in range(V):
         torch.sign(mv.images[v] - targets[v], out=mv.dl[v])
         mv.dl[v].mul_(1.0 / mv.images[v].numel())
-    tuned = {"render_ms": qb.autotune_render(mv, reps=3, trials=2),
+    tuned = {"intersect_ms": qb.autotune_intersect(mv, reps=1, trials=2),
+             "sort_ms": qb.autotune_sort(mv, reps=1, trials=2),
+             "render_ms": qb.autotune_render(mv, reps=3, trials=2),
              "render_backward_ms": qb.autotune_backward(mv, reps=2, trials=2)}
     tuned = {k: {s: round(x, 4) for s, x in v.items()} for k, v in tuned.items()}
     names = {v: k for k, v in qb.RENDER_VARIANTS.items()}
     bnames = {v: k for k, v in qb.BACKWARD_VARIANTS.items()}
-    tuned["picked"] = {"render": names[mv.render_variant], "render_backward": bnames[mv.backward_variant]}
+    snames = {v: k for k, v in qb.SORT_VARIANTS.items()}
+    dnames = {v: k for k, v in qb.DEPTH_VARIANTS.items()}
+    enames = {v: k for k, v in qb.EMIT_VARIANTS.items()}
+    tuned["picked"] = {"intersect": f"{dnames[mv.depth_variant]}/{enames[mv.emit_variant]}",
+                       "sort": snames[mv.sort_variant], "render": names[mv.render_variant],
+                       "render_backward": bnames[mv.backward_variant]}
     log("autotune", tuned)
 
     def batched():
@@ -674,6 +690,8 @@ def main():
                                              if r["render_rowmajor_ms"] is not None else None),
                       "ms_with_count_readback": round(r["sync_ms"], 4) if r["sync_ms"] is not None else None,
                       "render_shape": r["render_shape"], "render_shape_ms": r["shape_ms"],
+                      "sort_shape": r["sort_shape"], "sort_shape_ms": r["sort_shape_ms"],
+                      "intersect_shape": r["intersect_shape"], "intersect_shape_ms": r["intersect_shape_ms"],
                       **image_delta(torch, r["rast"].image, q["rast"].image)}
                   for m, r in results.items()},
         "fwd_bwd_ms_per_view": round(fwd_bwd["ms"], 4) if fwd_bwd is not None else None,

@@ -143,6 +143,20 @@ qb_status qb_project(int64_t n, const float* means, const float* log_scales, con
                      const qb_camera* cam, int32_t mode, qb_splat* out_splats,
                      qb_rects* out_rects, int32_t* out_counts, qb_stream_t stream);
 
+/* The three binary32 activations of qb_project (each evaluated in binary64
+ * and rounded once; Eq. (3) for gamma), on arbitrary inputs, so that their
+ * agreement with another implementation can be checked on every binary32
+ * value of a range:
+ *   QB_ACT_SCALE     s = exp(log_scale)
+ *   QB_ACT_OPACITY   o = sigmoid(logit) = 1 / (1 + exp(-logit))
+ *   QB_ACT_GAMMA     gamma = 2 ln(255 o), from an opacity o
+ * qb_project evaluates exactly these device functions. */
+typedef enum { QB_ACT_SCALE = 0, QB_ACT_OPACITY = 1, QB_ACT_GAMMA = 2 } qb_activation;
+
+/* qb_activations -- out[i] = activation `which` of x[i] for i < n (device
+ * arrays of n floats; x and out may alias). */
+qb_status qb_activations(int64_t n, const float* x, int32_t which, float* out, qb_stream_t stream);
+
 /* Workspace bytes qb_intersect needs for n Gaussians. */
 size_t qb_intersect_workspace_size(int64_t n);
 
@@ -173,6 +187,34 @@ qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_rects* rects,
                        uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs, void* workspace,
                        size_t workspace_bytes, qb_stream_t stream);
 
+/* Launch shapes of qb_intersect's stages: the depth sort's radix workgroups
+ * (lanes x keys per lane) and the emission's workgroup size (Gaussians per
+ * workgroup).  Every combination gives the same pairs in the same order. */
+typedef enum {
+    QB_DEPTH_512x4 = 0,   /* 2048 keys per workgroup (qb_intersect's shape) */
+    QB_DEPTH_256x8 = 1,   /* 2048 keys per workgroup                        */
+    QB_DEPTH_512x8 = 2,   /* 4096 keys per workgroup                        */
+    QB_DEPTH_1024x4 = 3,  /* 4096 keys per workgroup                        */
+    QB_DEPTH_VARIANTS = 4
+} qb_depth_variant;
+
+typedef enum {
+    QB_EMIT_256 = 0,      /* 256 Gaussians per workgroup (qb_intersect's)   */
+    QB_EMIT_128 = 1,
+    QB_EMIT_512 = 2,
+    QB_EMIT_VARIANTS = 3
+} qb_emit_variant;
+
+/* qb_intersect_ex -- qb_intersect with explicit launch shapes (a
+ * qb_depth_variant and a qb_emit_variant; the emission shape does not apply
+ * to QB_BOX_QUADBOX_NAIVE); same arguments, workspace size and results as
+ * qb_intersect. */
+qb_status qb_intersect_ex(int64_t n, const qb_splat* splats, const qb_rects* rects,
+                          const int32_t* counts, int32_t width, int32_t height, int32_t mode,
+                          int64_t pair_capacity, uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs,
+                          void* workspace, size_t workspace_bytes, int32_t depth_variant, int32_t emit_variant,
+                          qb_stream_t stream);
+
 /* Workspace bytes qb_sort needs for a pair capacity. */
 size_t qb_sort_workspace_size(int64_t pair_capacity);
 
@@ -194,6 +236,31 @@ qb_status qb_sort(int64_t pair_capacity, const int64_t* num_pairs, int32_t num_t
                   const uint16_t* pair_tiles, const uint32_t* pair_ids, const qb_splat* splats,
                   uint64_t* keys, uint32_t* ids, uint32_t* ranges, void* workspace,
                   size_t workspace_bytes, qb_stream_t stream);
+
+/* Launch shapes of the tile sort: lanes x pairs per lane of one radix
+ * workgroup (larger workgroups write longer runs per digit and launch fewer
+ * workgroups; smaller ones keep more workgroups per compute unit), and the
+ * digit widths of its two passes over more than 8 tile bits (even by default:
+ * 6 + 6 bits at 3600 tiles; the NARROW / WIDE variants give the first pass 2
+ * bits fewer / more, within 1..8 bits per pass).  Every variant gives the
+ * same sorted list and ranges. */
+typedef enum {
+    QB_SORT_512x8 = 0,    /* 4096 pairs per workgroup (qb_sort's shape) */
+    QB_SORT_1024x8 = 1,   /* 8192 pairs per workgroup                   */
+    QB_SORT_512x16 = 2,   /* 8192 pairs per workgroup                   */
+    QB_SORT_256x16 = 3,   /* 4096 pairs per workgroup                   */
+    QB_SORT_512x8_NARROW_FIRST = 4,  /* 512 x 8, first digit 2 bits narrower */
+    QB_SORT_512x8_WIDE_FIRST = 5,    /* 512 x 8, first digit 2 bits wider    */
+    QB_SORT_VARIANTS = 6
+} qb_sort_variant;
+
+/* qb_sort_ex -- qb_sort with an explicit launch shape (a qb_sort_variant,
+ * chosen for example by timing each on the workload); same arguments and
+ * results as qb_sort, the same workspace size. */
+qb_status qb_sort_ex(int64_t pair_capacity, const int64_t* num_pairs, int32_t num_tiles,
+                     const uint16_t* pair_tiles, const uint32_t* pair_ids, const qb_splat* splats,
+                     uint64_t* keys, uint32_t* ids, uint32_t* ranges, void* workspace,
+                     size_t workspace_bytes, int32_t variant, qb_stream_t stream);
 
 /* qb_render -- Eq. (2) per pixel over its tile's sorted list: front to back,
  * skipping a Gaussian where its quadratic form exceeds gamma (alpha < 1/255,

@@ -71,6 +71,7 @@ def lib():
         L.oc_pixel_boxes.argtypes = [vp, i32, vp]
         L.oc_pixel_boxes.restype = i32
         L.oc_project64.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp]
+        L.oc_activations.argtypes = [i64, vp, i32, vp]
         L.oc_set_threads.argtypes = [i32]
         L.oc_threads.restype = i32
         lay = np.zeros(6, np.int64)
@@ -83,6 +84,20 @@ def lib():
 
 def _p(a):
     return a.ctypes.data
+
+
+ACTIVATIONS = {"scale": 0, "opacity": 1, "gamma": 2}
+
+
+def activations(x, which):
+    """Activation `which` ("scale": exp, "opacity": sigmoid, "gamma":
+    2 ln(255 o)) of every binary32 in x, each evaluated in binary64 and
+    rounded once, exactly as the projection evaluates it (Eq. (3) for
+    gamma)."""
+    x = np.ascontiguousarray(x, np.float32)
+    out = np.empty_like(x)
+    lib().oc_activations(x.size, _p(x), ACTIVATIONS[which], _p(out))
+    return out
 
 
 def set_threads(t: int) -> None:

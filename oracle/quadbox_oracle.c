@@ -222,8 +222,23 @@ void oc_build_boxes(oc_gauss* g, int mode, int W, int H)
 }
 
 /* ------------------------------------------------------------------------- */
-/* EWA projection of one Gaussian (Sec. 2, Eq. (1); Eqs. (3), (4) for gamma).  */
+/* The activations, each evaluated in binary64 and rounded once to binary32:
+ * scale s = exp(log_scale), opacity o = sigmoid(logit) = 1 / (1 + exp(-logit)),
+ * and gamma = 2 ln(o / alpha_min) with alpha_min = 1/255 (Eq. (3)). */
+static float oc_act_scale(float l) { return (float)exp((double)l); }
+static float oc_act_opacity(float x) { return (float)(1.0 / (1.0 + exp(-(double)x))); }
+static float oc_act_gamma(float o) { return (float)(2.0 * log(255.0 * (double)o)); }
+
+/* out[i] = activation `which` (0 scale, 1 opacity, 2 gamma) of x[i]. */
+void oc_activations(int64_t n, const float* x, int which, float* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++)
+        out[i] = which == 0 ? oc_act_scale(x[i]) : which == 1 ? oc_act_opacity(x[i]) : oc_act_gamma(x[i]);
+}
+
 /* ------------------------------------------------------------------------- */
+/* EWA projection of one Gaussian (Sec. 2, Eq. (1); Eqs. (3), (4) for gamma).  */
 void oc_project_one(const oc_camera* cam, const float mean[3], const float lscale[3],
                     const float quat[4], float logit, const float* sh, int64_t n, int64_t i,
                     int sh_degree, int mode, oc_gauss* g)
@@ -238,13 +253,12 @@ void oc_project_one(const oc_camera* cam, const float mean[3], const float lscal
     if (!(pz > cam->near_plane) || !isfinite(px) || !isfinite(py) || !isfinite(pz)) return;
 
     /* activations: evaluated in binary64, rounded once */
-    float s0 = (float)exp((double)lscale[0]);
-    float s1 = (float)exp((double)lscale[1]);
-    float s2 = (float)exp((double)lscale[2]);
-    float o = (float)(1.0 / (1.0 + exp(-(double)logit)));
+    float s0 = oc_act_scale(lscale[0]);
+    float s1 = oc_act_scale(lscale[1]);
+    float s2 = oc_act_scale(lscale[2]);
+    float o = oc_act_opacity(logit);
     g->opacity = o;
-    /* gamma = 2 ln(o / alpha_min) with alpha_min = 1/255 (Eq. (3)) */
-    g->gamma = (float)(2.0 * log(255.0 * (double)o));
+    g->gamma = oc_act_gamma(o);
 
     /* unit quaternion (w, x, y, z) -> rotation */
     float n2 = ((quat[0] * quat[0] + quat[1] * quat[1]) + quat[2] * quat[2]) + quat[3] * quat[3];

@@ -91,9 +91,9 @@ __device__ __forceinline__ void render_backward_tile(
     constexpr int NT = 256 / PPL;
     constexpr int LX = QB_TILE / PPL;
     __shared__ float4 s_geo[NT];   // u, v, -a/2, -b
-    __shared__ float4 s_opa[NT];   // -c/2, o, -gamma/2, a
+    __shared__ float4 s_opa[NT];   // -c/2, log2(o), -gamma/2, a
     __shared__ float4 s_col[NT];   // r, g, b, b
-    __shared__ float s_c[NT];      // c
+    __shared__ float2 s_c[NT];     // c, 1/o
     __shared__ uint32_t s_id[NT];
     __shared__ int s_rows[NT];     // tile rows that can pass the cutoff (entry_rows)
     __shared__ uint32_t s_maxlast;
@@ -104,6 +104,7 @@ __device__ __forceinline__ void render_backward_tile(
     int py = ty * QB_TILE + ly;
     int wrow0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64) * kRowsPerWave);
     float fy = (float)py;
+    constexpr float kLog2e = 1.44269504088896341f;
     int lane = threadIdx.x & 63;
     int64_t plane = (int64_t)W * H;
 
@@ -146,9 +147,9 @@ __device__ __forceinline__ void render_backward_tile(
             float4 b = splats[3 * (int64_t)id + 1];
             float4 c = splats[3 * (int64_t)id + 2];
             s_geo[threadIdx.x] = make_float4(a.x, a.y, -0.5f * b.x, -b.y);
-            s_opa[threadIdx.x] = make_float4(-0.5f * b.z, a.w, -0.5f * b.w, b.x);
+            s_opa[threadIdx.x] = make_float4(-0.5f * b.z, __log2f(a.w), -0.5f * b.w, b.x);
             s_col[threadIdx.x] = make_float4(c.x, c.y, c.z, b.y);
-            s_c[threadIdx.x] = b.z;
+            s_c[threadIdx.x] = make_float2(b.z, __builtin_amdgcn_rcpf(a.w));
             s_id[threadIdx.x] = id;
             if (kRowsPerWave < QB_TILE) s_rows[threadIdx.x] = entry_rows(a.y, b.x, b.y, b.z, b.w, ty);
         }
@@ -194,7 +195,8 @@ __device__ __forceinline__ void render_backward_tile(
             }
             if (!__any(any)) continue;
             float4 col = s_col[k];
-            float cc = s_c[k];
+            float2 ci = s_c[k];
+            float cc = ci.x;
             // per pixel: A = dL/dC . rgb of this entry; the geometric shares
             // are summed over the lane's pixels as P = sum dpow,
             // S1 = sum dpow dx and Q = sum dpow dx^2 (the pixels share the
@@ -203,8 +205,9 @@ __device__ __forceinline__ void render_backward_tile(
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
                 if (act[q]) {
-                    float e = __expf(power[q]);
-                    float raw = o.y * e;
+                    // o e^power as the forward evaluates it: one exp2 of
+                    // power log2(e) + log2(o), so alpha matches the forward's
+                    float raw = __builtin_amdgcn_exp2f(fmaf(power[q], kLog2e, o.y));
                     float alpha = fminf(0.99f, raw);
                     // 1 / (1 - alpha) by the hardware reciprocal (1 ulp; 1 - alpha >= 0.01):
                     // the transmittance in front of this Gaussian is T / (1 - alpha)
@@ -220,7 +223,7 @@ __device__ __forceinline__ void render_backward_tile(
                     T[q] = Ti;
                     if (raw <= 0.99f) {
                         float dpow = dalpha * alpha;
-                        go = fmaf(dalpha, e, go);
+                        go = fmaf(dalpha, raw, go);   // times 1/o below: dalpha/do = e^power
                         float t = dpow * dx[q];
                         P += dpow;
                         S1 += t;
@@ -232,7 +235,8 @@ __device__ __forceinline__ void render_backward_tile(
             float a = o.w, b = col.w, dyP = dy * P;
             float gu = -fmaf(a, S1, b * dyP), gv = -fmaf(b, S1, cc * dyP);
             float ga = -0.5f * Q, gb = -(dy * S1), gc = -0.5f * (dy * dyP);
-            float v9[9] = {gu, gv, ga, gb, gc, go, gr, gg, gbl};
+            // an entry some lane composites has gamma >= 0, so o >= 1/255
+            float v9[9] = {gu, gv, ga, gb, gc, go * ci.y, gr, gg, gbl};
             wave_add9(v9, grad2d + 9 * (int64_t)s_id[k], lane);
           }
         }

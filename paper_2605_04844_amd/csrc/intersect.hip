@@ -25,8 +25,12 @@
 
 namespace {
 
-constexpr int kEmitThreads = 256;
-constexpr int kDepthNT = 512, kDepthNI = 4;  // 2048 keys per workgroup: ~500 workgroups at 1M (measured best)
+// Depth-sort workgroup shapes (lanes x keys per lane) and emission workgroup
+// sizes, indexed by qb_depth_variant / qb_emit_variant; the first of each is
+// qb_intersect's (512 x 4: 2048 keys per workgroup, about 500 workgroups at
+// 10^6 Gaussians; 256-lane emission).  The workspace covers the depth-sort
+// shape with the most workgroups.
+constexpr int kDepthMinTile = 2048;
 
 __global__ __launch_bounds__(QB_BLOCK) void k_depth_keys(int64_t n, const float4* __restrict__ splats,
                                                          const int32_t* __restrict__ counts,
@@ -45,6 +49,7 @@ __global__ void k_store_total(const uint64_t* __restrict__ tot, int64_t* __restr
     *num_pairs = tot ? (int64_t)*tot : 0;
 }
 
+template <int kEmitThreads>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     int64_t n, const uint32_t* __restrict__ order, const uint64_t* __restrict__ goff,
     const int4* __restrict__ rects, const uint32_t* __restrict__ sorted_counts, int tiles_x, int64_t cap,
@@ -126,8 +131,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
             uint32_t local = p - s_off[own];
             uint32_t w0 = s_w0[own], w1 = s_w1[own];
             uint32_t len = w1 & 0xFFFFu;
-            // local < 2^16, so the float quotient is off by at most one
-            uint32_t qq = (uint32_t)((float)local * __frcp_rn((float)len));
+            // local < 2^16: with the hardware reciprocal (1 ulp) the float
+            // quotient is within 0.02 of local / len, so its floor is off by
+            // at most one, which the two steps below correct
+            uint32_t qq = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)len));
             int32_t rem = (int32_t)local - (int32_t)(qq * len);
             if (rem < 0) { --qq; rem += (int32_t)len; }
             if (rem >= (int32_t)len) { ++qq; rem -= (int32_t)len; }
@@ -140,7 +147,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
                 out_id[dst] = s_gid[own];
             }
         }
-        cur = __shfl(own, 63, 64);
+        cur = __builtin_amdgcn_readlane(own, 63);
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -186,7 +193,7 @@ IsectWs carve(QbArena& a, int64_t n)
     w.csorted = a.take<uint32_t>(n);
     w.offs = a.take<uint64_t>(n + 1);
     w.scan64 = a.take<uint64_t>(qbr::scan_scratch(n));
-    w.radix = a.take<uint32_t>((int64_t)(qbr::radix_scratch_bytes<kDepthNT, kDepthNI>(n) / sizeof(uint32_t)));
+    w.radix = a.take<uint32_t>((int64_t)(qbr::radix_scratch_bytes<kDepthMinTile, 1>(n) / sizeof(uint32_t)));
     return w;
 }
 
@@ -202,10 +209,31 @@ extern "C" size_t qb_intersect_workspace_size(int64_t n)
 
 // The stages of qb_intersect over a workspace of `workspace_bytes` bytes at
 // `workspace` (already checked to be large enough for n).
+// The depth sort of (keys, ids) in radix workgroups of NT lanes x NI keys;
+// the last pass also gathers the tile counts into the sorted order.
+template <int NT, int NI>
+static qb_status depth_sort(IsectWs& w, int64_t n, const int32_t* counts, hipStream_t s)
+{
+    static_assert(NT * NI >= kDepthMinTile, "the workspace is sized for tiles of at least kDepthMinTile keys");
+    // four 8-bit passes: (dk0, dv0) -> (dk1, dv1) -> (dk0, dv0) -> ...
+    return qbr::radix_sort<uint32_t, NT, NI>(w.dk0, w.dv0, w.dk0, w.dv0, w.dk1, w.dv1, (const int64_t*)nullptr, n, n,
+                                             0, 32, w.radix, s, counts, w.csorted);
+}
+
+template <int NT>
+static qb_status launch_emit(int64_t n, const uint32_t* order, const uint64_t* offs, const int4* r4,
+                             const uint32_t* csorted, int tiles_x, int64_t cap, const int64_t* num_pairs,
+                             uint16_t* pair_tiles, uint32_t* pair_ids, hipStream_t s)
+{
+    QB_LAUNCH(k_emit<NT>, qb_div_up(n, NT), NT, 0, s, n, order, offs, r4, csorted, tiles_x, cap, num_pairs,
+              pair_tiles, pair_ids);
+    return QB_OK;
+}
+
 static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rects* rects, const int32_t* counts,
                                 int tiles_x, int32_t mode, int64_t pair_capacity, uint16_t* pair_tiles,
                                 uint32_t* pair_ids, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
-                                hipStream_t s)
+                                int32_t depth_variant, int32_t emit_variant, hipStream_t s)
 {
     QbArena a{(char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255), workspace_bytes - 256, 0};
     IsectWs w = carve(a, n);
@@ -216,11 +244,12 @@ static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rect
     }
     int64_t grid = qb_div_up(n, QB_BLOCK);
     QB_LAUNCH(k_depth_keys, grid, QB_BLOCK, 0, s, n, reinterpret_cast<const float4*>(splats), counts, w.dk0, w.dv0);
-    // four 8-bit passes: (dk0, dv0) -> (dk1, dv1) -> (dk0, dv0) -> ...
-    // (the last pass also gathers the tile counts in the sorted order)
-    QB_CHECK((qbr::radix_sort<uint32_t, kDepthNT, kDepthNI>(w.dk0, w.dv0, w.dk0, w.dv0, w.dk1, w.dv1,
-                                                            (const int64_t*)nullptr, n, n, 0, 32, w.radix, s,
-                                                            counts, w.csorted)));
+    switch (depth_variant) {
+    case QB_DEPTH_512x4: QB_CHECK((depth_sort<512, 4>(w, n, counts, s))); break;
+    case QB_DEPTH_256x8: QB_CHECK((depth_sort<256, 8>(w, n, counts, s))); break;
+    case QB_DEPTH_512x8: QB_CHECK((depth_sort<512, 8>(w, n, counts, s))); break;
+    default: QB_CHECK((depth_sort<1024, 4>(w, n, counts, s))); break;
+    }
     // pair offsets; the total (a count, below 2^63) lands in *num_pairs
     QB_CHECK((qbr::exclusive_scan<uint32_t, uint64_t>(w.csorted, w.offs, n, w.scan64,
                                                       reinterpret_cast<uint64_t*>(num_pairs), s)));
@@ -229,9 +258,18 @@ static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rect
     if (pair_capacity > 0 && (mode & ~QB_CLIP_3SIGMA) == QB_BOX_QUADBOX_NAIVE)
         QB_LAUNCH(k_emit_naive, grid, QB_BLOCK, 0, s, n, order, (const uint64_t*)w.offs, r4,
                   (const uint32_t*)w.csorted, tiles_x, pair_capacity, (const int64_t*)num_pairs, pair_tiles, pair_ids);
-    else if (pair_capacity > 0)
-        QB_LAUNCH(k_emit, qb_div_up(n, kEmitThreads), kEmitThreads, 0, s, n, order, (const uint64_t*)w.offs, r4,
-                  (const uint32_t*)w.csorted, tiles_x, pair_capacity, (const int64_t*)num_pairs, pair_tiles, pair_ids);
+    else if (pair_capacity > 0) {
+        const uint64_t* offs = w.offs;
+        const uint32_t* cs = w.csorted;
+        switch (emit_variant) {
+        case QB_EMIT_256: QB_CHECK(launch_emit<256>(n, order, offs, r4, cs, tiles_x, pair_capacity, num_pairs,
+                                                    pair_tiles, pair_ids, s)); break;
+        case QB_EMIT_128: QB_CHECK(launch_emit<128>(n, order, offs, r4, cs, tiles_x, pair_capacity, num_pairs,
+                                                    pair_tiles, pair_ids, s)); break;
+        default: QB_CHECK(launch_emit<512>(n, order, offs, r4, cs, tiles_x, pair_capacity, num_pairs, pair_tiles,
+                                           pair_ids, s)); break;
+        }
+    }
     return QB_OK;
 }
 
@@ -260,12 +298,25 @@ extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_re
                                   uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs, void* workspace,
                                   size_t workspace_bytes, qb_stream_t stream)
 {
+    return qb_intersect_ex(n, splats, rects, counts, width, height, mode, pair_capacity, pair_tiles, pair_ids,
+                           num_pairs, workspace, workspace_bytes, QB_DEPTH_512x4, QB_EMIT_256, stream);
+}
+
+extern "C" qb_status qb_intersect_ex(int64_t n, const qb_splat* splats, const qb_rects* rects,
+                                     const int32_t* counts, int32_t width, int32_t height, int32_t mode,
+                                     int64_t pair_capacity, uint16_t* pair_tiles, uint32_t* pair_ids,
+                                     int64_t* num_pairs, void* workspace, size_t workspace_bytes,
+                                     int32_t depth_variant, int32_t emit_variant, qb_stream_t stream)
+{
     int tiles_x = 0;
     QB_CHECK(intersect_args(n, splats, rects, counts, width, height, mode, pair_capacity, pair_tiles, pair_ids,
                             num_pairs, &tiles_x));
+    if (depth_variant < 0 || depth_variant >= QB_DEPTH_VARIANTS || emit_variant < 0 ||
+        emit_variant >= QB_EMIT_VARIANTS)
+        return QB_ERR_INVALID_ARG;
     if (!workspace || workspace_bytes < qb_intersect_workspace_size(n)) return QB_ERR_INVALID_ARG;
     return intersect_impl(n, splats, rects, counts, tiles_x, mode, pair_capacity, pair_tiles, pair_ids, num_pairs,
-                          workspace, workspace_bytes, qb_hip_stream(stream));
+                          workspace, workspace_bytes, depth_variant, emit_variant, qb_hip_stream(stream));
 }
 
 // ---- qb_intersect without a caller workspace --------------------------------
@@ -312,5 +363,5 @@ extern "C" qb_status qb_intersect_noalloc(int64_t n, const qb_splat* splats, con
     void* ws = scratch_on_current_device();
     if (!ws) return QB_ERR_HIP;
     return intersect_impl(n, splats, rects, counts, tiles_x, mode, pair_capacity, pair_tiles, pair_ids, num_pairs,
-                          ws, kNoallocScratchBytes, qb_hip_stream(stream));
+                          ws, kNoallocScratchBytes, QB_DEPTH_512x4, QB_EMIT_256, qb_hip_stream(stream));
 }

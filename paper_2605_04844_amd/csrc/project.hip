@@ -108,8 +108,15 @@ __device__ __forceinline__ void sh_colour(const ShCoef<DEG>& s, float x, float y
     for (int ch = 0; ch < 3; ++ch) rgb[ch] = acc[ch] > 0.0f ? acc[ch] : 0.0f;
 }
 
-// View-independent part of one Gaussian: the activations (binary64, rounded
-// once), the unit quaternion (binary32) and Sigma3D = M M^T with
+// The activations (Eq. (3) for gamma), each evaluated in binary64 and
+// rounded once to binary32: scale s = exp(log_scale), opacity o =
+// sigmoid(logit), gamma = 2 ln(o / (1/255)).
+__device__ __forceinline__ float act_scale(float l) { return (float)exp((double)l); }
+__device__ __forceinline__ float act_opacity(float x) { return (float)(1.0 / (1.0 + exp(-(double)x))); }
+__device__ __forceinline__ float act_gamma(float o) { return (float)(2.0 * log(255.0 * (double)o)); }
+
+// View-independent part of one Gaussian: the activations, the unit
+// quaternion (binary32) and Sigma3D = M M^T with
 // M = R(q) diag(s) in binary64 (6 unique entries: S00 S01 S02 S11 S12 S22).
 struct GaussPre {
     float o, gam;
@@ -121,11 +128,11 @@ __device__ __forceinline__ void gauss_pre(int64_t i, int64_t n, const float* __r
                                           const float* __restrict__ quats, const float* __restrict__ logits,
                                           GaussPre& g)
 {
-    float sx = (float)exp((double)log_scales[i]);
-    float sy = (float)exp((double)log_scales[n + i]);
-    float sz = (float)exp((double)log_scales[2 * n + i]);
-    g.o = (float)(1.0 / (1.0 + exp(-(double)logits[i])));
-    g.gam = (float)(2.0 * log(255.0 * (double)g.o));
+    float sx = act_scale(log_scales[i]);
+    float sy = act_scale(log_scales[n + i]);
+    float sz = act_scale(log_scales[2 * n + i]);
+    g.o = act_opacity(logits[i]);
+    g.gam = act_gamma(g.o);
     float qw = quats[i], qx = quats[n + i], qy = quats[2 * n + i], qz = quats[3 * n + i];
     float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
     g.ok = n2 > 0.0f && isfinite(n2);
@@ -411,6 +418,27 @@ void make_proj_cam(const qb_camera& cam, ProjCam* pc)
 }
 
 }  // namespace
+
+// One activation of qb_project on each input (which: qb_activation).
+__global__ __launch_bounds__(QB_BLOCK) void k_activations(int64_t n, const float* x, int which,
+                                                          float* out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * QB_BLOCK) {
+        float v = x[i];
+        out[i] = which == QB_ACT_SCALE ? act_scale(v) : which == QB_ACT_OPACITY ? act_opacity(v) : act_gamma(v);
+    }
+}
+
+extern "C" qb_status qb_activations(int64_t n, const float* x, int32_t which, float* out, qb_stream_t stream)
+{
+    if (n < 0 || which < QB_ACT_SCALE || which > QB_ACT_GAMMA) return QB_ERR_INVALID_ARG;
+    if (n == 0) return QB_OK;
+    if (!x || !out) return QB_ERR_INVALID_ARG;
+    int64_t grid = qb_div_up(n, QB_BLOCK);
+    if (grid > 16384) grid = 16384;
+    QB_LAUNCH(k_activations, grid, QB_BLOCK, 0, qb_hip_stream(stream), n, x, (int)which, out);
+    return QB_OK;
+}
 
 extern "C" qb_status qb_project(int64_t n, const float* means, const float* log_scales,
                                 const float* quats, const float* opacity_logits, const float* sh,

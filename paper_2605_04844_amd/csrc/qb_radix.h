@@ -8,7 +8,10 @@
 //          blocks; beyond that the totals are scanned recursively first)
 //   radix pass (<= 8 bits):
 //     upsweep   per-block digit histogram in LDS, stored digit-major
-//     scan      exclusive scan of the digit-major histogram (global offsets)
+//     scan      exclusive scan of the digit-major histogram (global offsets);
+//               with at most kFusedBlocks blocks there is no scan launch: the
+//               histograms are stored block-major and every downsweep
+//               workgroup sums the rows itself (16-byte loads, all in flight)
 //     downsweep per-block stable ranks: each wave owns a contiguous run of the
 //               block's items and ranks 64 at a time by matching digits with
 //               one ballot per digit bit; per-wave digit counts are combined
@@ -32,7 +35,7 @@ constexpr int kBigScanTile = kBigScanThreads * kBigScanItems;  // 32768 items, o
 
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kFusedBlocks = 320;
+constexpr int kFusedBlocks = 512;
 
 // DPP lane shift within the wave (update_dpp with `identity` where the
 // source lane falls outside the row or the row is masked off).  Controls:
@@ -320,6 +323,8 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
     }
 }
 
+__device__ __forceinline__ bool b_any(const uint4& v) { return (v.x | v.y | v.z | v.w) != 0u; }
+
 // FUSED: `offs` holds the raw block-major histograms of every block, and the
 // workgroup derives its global digit offsets from them (digit totals scanned
 // over digits, plus the counts of the earlier blocks); otherwise `offs` is the
@@ -338,6 +343,7 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
     __shared__ uint32_t gbase[kRadix];      // global start of each digit for this block
     __shared__ uint32_t lstart[kRadix];     // block-local start of each digit
     __shared__ uint32_t scan_lds[NW];
+    __shared__ uint32_t acc[FUSED ? 2 : 1][kRadix];   // FUSED: digit totals, counts in earlier blocks
     __shared__ K s_key[TILE];
     __shared__ uint32_t s_val[TILE];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -349,26 +355,38 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
     for (int d = threadIdx.x; d < NW * kRadix; d += NT) (&wcnt[0][0])[d] = 0;
     if (FUSED) {
         static_assert(!FUSED || NT >= kRadix, "one lane per digit");
-        uint32_t tot = 0, pre = 0;
-        int d = threadIdx.x;
-        if (d < kRadix) {
-            int b = 0;
-            for (; b + 8 <= (int)nblocks; b += 8) {
-                uint32_t v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = offs[(int64_t)(b + u) * kRadix + d];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    tot += v[u];
-                    pre += (b + u < (int)blockIdx.x) ? v[u] : 0u;
-                }
-            }
-            for (; b < (int)nblocks; ++b) {
-                uint32_t v = offs[(int64_t)b * kRadix + d];
-                tot += v;
-                pre += (b < (int)blockIdx.x) ? v : 0u;
-            }
+        // Every digit's total over all blocks and its count in the blocks
+        // before this one.  Lane c of each wave reads digits 4c..4c+3 of one
+        // block's 1 KB row as one 16-byte load; wave w takes blocks w, w + NW,
+        // ..., so all the loads are independent and in flight together; the
+        // waves' partial sums meet in LDS by atomic adds.
+        for (int d = threadIdx.x; d < 2 * kRadix; d += NT) (&acc[0][0])[d] = 0u;
+        __syncthreads();
+        uint4 tot4 = make_uint4(0u, 0u, 0u, 0u), pre4 = make_uint4(0u, 0u, 0u, 0u);
+        const uint4* rows = reinterpret_cast<const uint4*>(offs);
+#pragma unroll 4
+        for (int b = wave; b < (int)nblocks; b += NW) {
+            uint4 v = rows[(int64_t)b * (kRadix / 4) + lane];
+            bool before = b < (int)blockIdx.x;
+            tot4.x += v.x; tot4.y += v.y; tot4.z += v.z; tot4.w += v.w;
+            pre4.x += before ? v.x : 0u; pre4.y += before ? v.y : 0u;
+            pre4.z += before ? v.z : 0u; pre4.w += before ? v.w : 0u;
         }
+        if (b_any(tot4)) {
+            atomicAdd(&acc[0][4 * lane + 0], tot4.x);
+            atomicAdd(&acc[0][4 * lane + 1], tot4.y);
+            atomicAdd(&acc[0][4 * lane + 2], tot4.z);
+            atomicAdd(&acc[0][4 * lane + 3], tot4.w);
+        }
+        if (b_any(pre4)) {
+            atomicAdd(&acc[1][4 * lane + 0], pre4.x);
+            atomicAdd(&acc[1][4 * lane + 1], pre4.y);
+            atomicAdd(&acc[1][4 * lane + 2], pre4.z);
+            atomicAdd(&acc[1][4 * lane + 3], pre4.w);
+        }
+        __syncthreads();
+        int d = threadIdx.x;
+        uint32_t tot = d < kRadix ? acc[0][d] : 0u, pre = d < kRadix ? acc[1][d] : 0u;
         uint32_t all;
         uint32_t start = block_exclusive_scan<uint32_t, NT>(d < kRadix ? tot : 0u, &all, gbase);
         if (d < kRadix) gbase[d] = start + pre;  // scan scratch reused after its last read
@@ -474,10 +492,15 @@ __global__ __launch_bounds__(QB_BLOCK) void k_copy_items(const K* __restrict__ k
 // alias kout only when the pass count is even.  The item count is *n_dev when
 // n_dev is given (clamped as in sort_count), else n_host; cap sizes the grid.
 // gsrc/gdst (both or neither): the last pass also writes gdst[i] = gsrc[vout[i]].
+// first_bits > 0
+// sets the first pass's digit width (at most 8, leaving at least one bit; the
+// pass count is unchanged, so the later passes must hold the rest: callers
+// keep total - first_bits <= 8 per remaining pass); 0 splits evenly.
 template <typename K, int NT, int NI>
 qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, K* ktmp, uint32_t* vtmp,
                      const int64_t* n_dev, int64_t n_host, int64_t cap, int lo_bit, int hi_bit,
-                     uint32_t* scratch, hipStream_t s, const int32_t* gsrc = nullptr, uint32_t* gdst = nullptr)
+                     uint32_t* scratch, hipStream_t s, const int32_t* gsrc = nullptr, uint32_t* gdst = nullptr,
+                     int first_bits = 0)
 {
     if (cap <= 0) return QB_OK;
     if ((gsrc != nullptr) != (gdst != nullptr) || (gsrc && hi_bit <= lo_bit)) return QB_ERR_INVALID_ARG;
@@ -498,13 +521,15 @@ qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout,
     uint32_t* offs = scratch + hn;
     uint32_t* sscr = scratch + 2 * hn;
     // few blocks: every downsweep workgroup reads all histograms itself
-    // (at most kFusedBlocks * 1 KB), which saves the scan launches
+    // (at most kFusedBlocks KB, from L2), which saves the two scan launches
     bool fused = nb <= kFusedBlocks && NT >= kRadix;
     int shift = lo_bit;
     const K* src_k = kin;
     const uint32_t* src_v = vin;
     for (int p = 0; p < np; ++p) {
         int bits = (total_bits - (shift - lo_bit) + (np - p) - 1) / (np - p);
+        if (p == 0 && np > 1 && first_bits > 0)
+            bits = min(first_bits, min(kRadixBits, total_bits - 1));   // the later passes share the rest
         bool to_out = ((np - 1 - p) & 1) == 0;
         K* dk = to_out ? kout : ktmp;
         uint32_t* dv = to_out ? vout : vtmp;

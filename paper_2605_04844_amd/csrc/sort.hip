@@ -12,7 +12,10 @@
 
 namespace {
 
-constexpr int kSortNT = 512, kSortNI = 8;  // 4096 pairs per workgroup (measured best at 10^7 pairs)
+// Radix workgroup shapes (lanes, pairs per lane), indexed by qb_sort_variant;
+// 512 x 8 (4096 pairs per workgroup) is qb_sort's.  The workspace covers the
+// shape with the most workgroups (the smallest tile).
+constexpr int kSortMinTile = 4096;
 
 // One wave per tile: lanes 0-31 find the first index whose tile is >= t,
 // lanes 32-63 the first whose tile is >= t + 1, each half by a 32-ary
@@ -86,7 +89,7 @@ SortWs carve(QbArena& a, int64_t cap)
     w.tiles_sorted = a.take<uint16_t>(cap);
     w.ktmp = a.take<uint16_t>(cap);
     w.vtmp = a.take<uint32_t>(cap);
-    w.radix = a.take<uint32_t>((int64_t)(qbr::radix_scratch_bytes<kSortNT, kSortNI>(cap) / sizeof(uint32_t)));
+    w.radix = a.take<uint32_t>((int64_t)(qbr::radix_scratch_bytes<kSortMinTile, 1>(cap) / sizeof(uint32_t)));
     return w;
 }
 
@@ -100,13 +103,45 @@ extern "C" size_t qb_sort_workspace_size(int64_t pair_capacity)
     return a.used + 256;
 }
 
+// The tile sort in radix workgroups of NT lanes x NI pairs, the first pass
+// taking first_bits of the tile bits (0: an even split).
+template <int NT, int NI>
+static qb_status tile_sort(const uint16_t* pair_tiles, const uint32_t* pair_ids, uint16_t* tiles_sorted,
+                           uint32_t* ids, uint16_t* ktmp, uint32_t* vtmp, const int64_t* num_pairs,
+                           int64_t cap, int bits, uint32_t* radix, int first_bits, hipStream_t s)
+{
+    static_assert(NT * NI >= kSortMinTile, "the workspace is sized for tiles of at least kSortMinTile pairs");
+    return qbr::radix_sort<uint16_t, NT, NI>(pair_tiles, pair_ids, tiles_sorted, ids, ktmp, vtmp, num_pairs, 0,
+                                             cap, 0, bits, radix, s, nullptr, nullptr, first_bits);
+}
+
+// Digit width of the first pass for a variant: the even split of the two
+// passes (ceil(bits / 2)) for the shape variants, 2 bits narrower or wider
+// for the digit-width variants, kept within 1..8 with at most 8 bits left.
+static int first_pass_bits(int variant, int bits)
+{
+    int even = (bits + 1) / 2;
+    int want = variant == QB_SORT_512x8_NARROW_FIRST ? even - 2 : variant == QB_SORT_512x8_WIDE_FIRST ? even + 2 : even;
+    if (bits <= 8) return 0;   // one pass: no split
+    return max(max(1, bits - 8), min(8, want));
+}
+
 extern "C" qb_status qb_sort(int64_t pair_capacity, const int64_t* num_pairs, int32_t num_tiles,
                              const uint16_t* pair_tiles, const uint32_t* pair_ids, const qb_splat* splats,
                              uint64_t* keys, uint32_t* ids, uint32_t* ranges, void* workspace,
                              size_t workspace_bytes, qb_stream_t stream)
 {
+    return qb_sort_ex(pair_capacity, num_pairs, num_tiles, pair_tiles, pair_ids, splats, keys, ids, ranges,
+                      workspace, workspace_bytes, QB_SORT_512x8, stream);
+}
+
+extern "C" qb_status qb_sort_ex(int64_t pair_capacity, const int64_t* num_pairs, int32_t num_tiles,
+                                const uint16_t* pair_tiles, const uint32_t* pair_ids, const qb_splat* splats,
+                                uint64_t* keys, uint32_t* ids, uint32_t* ranges, void* workspace,
+                                size_t workspace_bytes, int32_t variant, qb_stream_t stream)
+{
     if (pair_capacity < 0 || pair_capacity > (int64_t)0xFFFFFFFF || !num_pairs || num_tiles < 1 ||
-        num_tiles > 65536 || !ranges || !workspace)
+        num_tiles > 65536 || !ranges || !workspace || variant < 0 || variant >= QB_SORT_VARIANTS)
         return QB_ERR_INVALID_ARG;
     if (pair_capacity > 0 && (!pair_tiles || !pair_ids || !ids)) return QB_ERR_INVALID_ARG;
     if (keys && !splats) return QB_ERR_INVALID_ARG;
@@ -117,9 +152,17 @@ extern "C" qb_status qb_sort(int64_t pair_capacity, const int64_t* num_pairs, in
     SortWs w = carve(a, pair_capacity);
     if (!a.ok()) return QB_ERR_INVALID_ARG;
     if (pair_capacity > 0) {
-        QB_CHECK((qbr::radix_sort<uint16_t, kSortNT, kSortNI>(pair_tiles, pair_ids, w.tiles_sorted, ids, w.ktmp,
-                                                              w.vtmp, num_pairs, 0, pair_capacity, 0,
-                                                              tile_bits(num_tiles), w.radix, s)));
+        int bits = tile_bits(num_tiles);
+#define QB_TILE_SORT(NT, NI)                                                                                   \
+    tile_sort<NT, NI>(pair_tiles, pair_ids, w.tiles_sorted, ids, w.ktmp, w.vtmp, num_pairs, pair_capacity, bits, \
+                      w.radix, first_pass_bits(variant, bits), s)
+        switch (variant) {
+        case QB_SORT_1024x8: QB_CHECK(QB_TILE_SORT(1024, 8)); break;
+        case QB_SORT_512x16: QB_CHECK(QB_TILE_SORT(512, 16)); break;
+        case QB_SORT_256x16: QB_CHECK(QB_TILE_SORT(256, 16)); break;
+        default: QB_CHECK(QB_TILE_SORT(512, 8)); break;   // 512x8 and its digit-width variants
+        }
+#undef QB_TILE_SORT
         if (keys) {
             int64_t g = qb_div_up(pair_capacity, QB_BLOCK);
             if (g > 8192) g = 8192;

@@ -14,9 +14,7 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# QB_LIBRARY selects another build of the library (e.g. one built with other
-# tile shapes); the default is the in-tree build
-LIB_PATH = os.environ.get("QB_LIBRARY", os.path.join(HERE, "libquadbox.so"))
+LIB_PATH = os.path.join(HERE, "libquadbox.so")
 
 BOX_MODES = {"3sigma": 0, "adr": 1, "quadbox": 2, "dualbox": 3, "quadbox_naive": 4}
 CLIP_3SIGMA = 16   # QB_CLIP_3SIGMA: added to an opacity-aware mode
@@ -30,6 +28,14 @@ QB_OK, QB_ERR_INVALID_ARG, QB_ERR_CAPACITY, QB_ERR_HIP, QB_ERR_UNSUPPORTED = 0, 
 # (_rows) whether waves drop batch entries whose ellipse misses their rows
 RENDER_VARIANTS = {"2px": 0, "1px": 1, "4px": 2, "2px_rows": 3, "1px_rows": 4}
 BACKWARD_VARIANTS = {"2px": 0, "1px": 1, "4px": 2}
+# tile-sort radix workgroups (qb_sort_variant): lanes x pairs per lane, and
+# two digit-width variants of 512 x 8 (first pass 2 bits narrower / wider)
+SORT_VARIANTS = {"512x8": 0, "1024x8": 1, "512x16": 2, "256x16": 3, "512x8_narrow_first": 4,
+                 "512x8_wide_first": 5}
+# qb_intersect's depth-sort radix workgroups (qb_depth_variant) and emission
+# workgroup sizes (qb_emit_variant)
+DEPTH_VARIANTS = {"512x4": 0, "256x8": 1, "512x8": 2, "1024x4": 3}
+EMIT_VARIANTS = {"256": 0, "128": 1, "512": 2}
 
 
 class QBError(RuntimeError):
@@ -71,6 +77,10 @@ def lib():
     L.qb_intersect_workspace_size.restype = sz
     L.qb_intersect.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz, vp]
     L.qb_intersect.restype = i32
+    L.qb_intersect_ex.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz, i32, i32, vp]
+    L.qb_intersect_ex.restype = i32
+    L.qb_sort_ex.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp]
+    L.qb_sort_ex.restype = i32
     L.qb_sort_workspace_size.argtypes = [i64]
     L.qb_sort_workspace_size.restype = sz
     L.qb_sort.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -205,14 +215,14 @@ def intersect_workspace_size(n: int) -> int:
 
 
 def intersect(n, splats, rects, counts, width, height, capacity, pair_tiles, pair_ids, num_pairs, ws,
-              mode="quadbox"):
+              mode="quadbox", depth_variant=0, emit_variant=0):
     _need(min(_rows(splats), _rows(rects), _rows(counts)) >= n, "qb_intersect: inputs hold fewer than n rows")
     _need(capacity == 0 or min(_rows(pair_tiles), _rows(pair_ids)) >= capacity,
           "qb_intersect: pair buffers hold fewer than capacity entries")
-    _check("qb_intersect", lib().qb_intersect(
+    _check("qb_intersect_ex", lib().qb_intersect_ex(
         n, _ptr(splats), _ptr(rects), _ptr(counts), width, height, _mode(mode), capacity, _ptr(pair_tiles),
-        _ptr(pair_ids),
-        _ptr(num_pairs), _ptr(ws), ws.numel() * ws.element_size(), _stream()))
+        _ptr(pair_ids), _ptr(num_pairs), _ptr(ws), ws.numel() * ws.element_size(), int(depth_variant),
+        int(emit_variant), _stream()))
 
 
 # QB_NOALLOC_MAX_GAUSSIANS: the largest n qb_intersect_noalloc accepts
@@ -236,10 +246,10 @@ def sort_workspace_size(capacity: int) -> int:
     return int(lib().qb_sort_workspace_size(capacity))
 
 
-def sort(capacity, num_pairs, num_tiles, pair_tiles, pair_ids, splats, keys, ids, ranges, ws):
-    _check("qb_sort", lib().qb_sort(
+def sort(capacity, num_pairs, num_tiles, pair_tiles, pair_ids, splats, keys, ids, ranges, ws, variant=0):
+    _check("qb_sort_ex", lib().qb_sort_ex(
         capacity, _ptr(num_pairs), num_tiles, _ptr(pair_tiles), _ptr(pair_ids), _ptr(splats), _ptr(keys),
-        _ptr(ids), _ptr(ranges), _ptr(ws), ws.numel() * ws.element_size(), _stream()))
+        _ptr(ids), _ptr(ranges), _ptr(ws), ws.numel() * ws.element_size(), int(variant), _stream()))
 
 
 def tile_order(width, height, ranges, ids, splats, work, order):
@@ -324,6 +334,9 @@ class Rasterizer:
         self.mode = "quadbox"
         self.render_variant = RENDER_VARIANTS["2px"]
         self.backward_variant = RENDER_VARIANTS["2px"]
+        self.sort_variant = SORT_VARIANTS["512x8"]
+        self.depth_variant = DEPTH_VARIANTS["512x4"]
+        self.emit_variant = EMIT_VARIANTS["256"]
         d = device
         self.splats = torch.empty((max(n, 1), SPLAT_FLOATS), dtype=torch.float32, device=d)
         self.rects = torch.empty((max(n, 1), RECT_SHORTS), dtype=torch.int16, device=d)
@@ -365,11 +378,11 @@ class Rasterizer:
 
     def intersect(self):
         intersect(self.n, self.splats, self.rects, self.counts, self.W, self.H, self.capacity, self.pair_tiles,
-                  self.pair_ids, self.num_pairs, self.ws_isect, self.mode)
+                  self.pair_ids, self.num_pairs, self.ws_isect, self.mode, self.depth_variant, self.emit_variant)
 
     def sort(self):
         sort(self.capacity, self.num_pairs, self.num_tiles, self.pair_tiles, self.pair_ids, self.splats,
-             self.keys_sorted, self.ids_sorted, self.ranges, self.ws_sort)
+             self.keys_sorted, self.ids_sorted, self.ranges, self.ws_sort, self.sort_variant)
 
     def schedule(self):
         """qb_tile_order for the sorted frame (a no-op without balance)."""
@@ -537,6 +550,9 @@ class MultiView:
         self.mode = "quadbox"
         self.render_variant = RENDER_VARIANTS["2px"]
         self.backward_variant = RENDER_VARIANTS["2px"]
+        self.sort_variant = SORT_VARIANTS["512x8"]
+        self.depth_variant = DEPTH_VARIANTS["512x4"]
+        self.emit_variant = EMIT_VARIANTS["256"]
         self.grads = None
         self._table = None
 
@@ -548,7 +564,20 @@ class MultiView:
         w, h = self.sizes[v]
         cap = self.capacity[v]
         intersect(self.n, s, r, c, w, h, cap, self.pair_tiles[v] if cap else None,
-                  self.pair_ids[v] if cap else None, npairs, self.ws_isect[v % self.S], self.mode)
+                  self.pair_ids[v] if cap else None, npairs, self.ws_isect[v % self.S], self.mode,
+                  self.depth_variant, self.emit_variant)
+
+    def _sort(self, v):
+        sort(self.capacity[v], self.num_pairs[v:v + 1], self.num_tiles[v], self.pair_tiles[v], self.pair_ids[v],
+             self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort[v % self.S], self.sort_variant)
+
+    def intersect_all(self):
+        """qb_intersect of every view (side streams, joined back)."""
+        self._per_view(self._intersect)
+
+    def sort_all(self):
+        """qb_sort of every view (side streams, joined back)."""
+        self._per_view(self._sort)
 
     def size_pairs(self, g: Gaussians, mode="quadbox", slack=1.1, pad=1024):
         """Runs the projection and counting once (one host synchronisation)
@@ -618,8 +647,7 @@ class MultiView:
 
         def prep(v):
             self._intersect(v)
-            sort(self.capacity[v], self.num_pairs[v:v + 1], self.num_tiles[v], self.pair_tiles[v], self.pair_ids[v],
-                 self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort[v % self.S])
+            self._sort(v)
 
         self._per_view(prep)
         if self.balance:
@@ -715,4 +743,47 @@ def autotune_render(run, bg=(0.0, 0.0, 0.0), reps=10, trials=3):
     pick = min(times, key=times.get)
     run.render_variant = RENDER_VARIANTS[pick]
     run.render(bg)
+    return times
+
+
+def autotune_sort(run, reps=5, trials=3):
+    """Times every tile-sort launch shape on the pairs `run` (a Rasterizer or
+    a MultiView after a forward) holds, keeps the fastest in run.sort_variant
+    and returns {shape: ms} (per frame: every view's sort for a MultiView).
+    The shapes give identical lists, so the choice only affects speed."""
+    def shape(v):
+        def fn():
+            run.sort_variant = v
+            if isinstance(run, MultiView):
+                run.sort_all()
+            else:
+                run.sort()
+        return fn
+
+    times = _interleaved_best({name: shape(v) for name, v in SORT_VARIANTS.items()}, reps, trials)
+    run.sort_variant = SORT_VARIANTS[min(times, key=times.get)]
+    shape(run.sort_variant)()
+    return times
+
+
+def autotune_intersect(run, reps=5, trials=3):
+    """Times every pair of depth-sort and emission launch shapes of
+    qb_intersect on the frame `run` (a Rasterizer or a MultiView after a
+    forward) holds, keeps the fastest in run.depth_variant /
+    run.emit_variant and returns {"depth/emit": ms}.  Every pair writes the
+    same pairs; the sort and render are left as they were (the frame's
+    pairs are rewritten identically)."""
+    def shape(dv, ev):
+        def fn():
+            run.depth_variant, run.emit_variant = dv, ev
+            if isinstance(run, MultiView):
+                run.intersect_all()
+            else:
+                run.intersect()
+        return fn
+
+    fns = {f"{dn}/{en}": shape(dv, ev) for dn, dv in DEPTH_VARIANTS.items() for en, ev in EMIT_VARIANTS.items()}
+    times = _interleaved_best(fns, reps, trials)
+    dn, en = min(times, key=times.get).split("/")
+    shape(DEPTH_VARIANTS[dn], EMIT_VARIANTS[en])()
     return times

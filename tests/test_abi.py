@@ -107,6 +107,23 @@ def test_intersect_noalloc_rejects_bad_arguments_and_fits_its_scratch():
         qb.QB_ERR_UNSUPPORTED
 
 
+def test_activations_and_shape_entry_points_reject_bad_arguments():
+    L = qb.lib()
+    d = C.c_void_p(256)
+    L.qb_activations.argtypes = [C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+    assert L.qb_activations(-1, d, 0, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_activations(4, d, 3, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_activations(4, d, -1, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_activations(4, None, 0, d, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_activations(0, None, 0, None, None) == qb.QB_OK   # nothing to do, nothing launched
+    ws = qb.intersect_workspace_size(10)
+    for dv, ev in ((4, 0), (-1, 0), (0, 3), (0, -1)):
+        assert L.qb_intersect_ex(10, d, d, d, 64, 48, 2, 100, d, d, d, d, ws, dv, ev, None) == qb.QB_ERR_INVALID_ARG
+    sws = qb.sort_workspace_size(100)
+    for v in (-1, 6):
+        assert L.qb_sort_ex(100, d, 12, d, d, d, None, C.c_void_p(512), d, d, sws, v, None) == qb.QB_ERR_INVALID_ARG
+
+
 def test_launch_shape_and_view_entry_points_reject_bad_arguments():
     L = qb.lib()
     d = C.c_void_p(256)

@@ -133,6 +133,29 @@ def test_activations_and_gamma(oracle):
     assert np.all(np.abs(g["gamma"][ok] - gam[ok]) <= np.spacing(np.abs(gam[ok]).astype(np.float32)))
 
 
+def test_activation_function_against_numpy(oracle):
+    """oracle.activations (the functions the projection evaluates, which the
+    GPU sweep compares with the library on every binary32 of their ranges):
+    exp, scipy's expit and 2 ln(255 o) in binary64 rounded once, equal bit
+    for bit to numpy/scipy's binary64 results rounded once on 3e6 values
+    (spread over the swept ranges, plus their end points)."""
+    rng = np.random.default_rng(23)
+    cases = {"scale": (-20.0, 5.0, lambda x: np.exp(x)),
+             "opacity": (-5.6, 17.0, lambda x: expit(x)),
+             "gamma": (1.0 / 255.0, 1.0, lambda x: 2.0 * np.log(255.0 * x))}
+    for name, (lo, hi, ref) in cases.items():
+        x = np.concatenate([rng.uniform(lo, hi, 1_000_000), [lo, hi]]).astype(np.float32)
+        got = oracle.activations(x, name)
+        want = ref(x.astype(np.float64)).astype(np.float32)
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), name
+    # the projection's own values are these functions of its inputs
+    s = scenes.small_scene(n=2000)[0]
+    g = oracle.project(s, scenes.pinhole(256, 256, 256.0), "3sigma")
+    assert np.array_equal(g["opacity"], oracle.activations(s.logits, "opacity"))
+    ok = g["visible"] == 1
+    assert np.array_equal(g["gamma"][ok], oracle.activations(g["opacity"][ok], "gamma"))
+
+
 def test_culling(oracle):
     """Behind the near plane, degenerate rotation, and (opacity-aware modes
     only) o <= 1/255 are culled."""

@@ -382,3 +382,48 @@ def test_clip_3sigma_image_equals_3sigma_on_gpu(oracle, qb):
     ref = oracle.forward(scene, cam, "quadbox_clip3sigma")
     assert out["quadbox_clip3sigma"]["P"] == len(ref["ids"])
     say("pairs 3sigma / quadbox / clipped:", out["3sigma"]["P"], out["quadbox"]["P"], out["quadbox_clip3sigma"]["P"])
+
+
+def test_intersect_and_sort_launch_shapes(oracle, qb):
+    """Every depth-sort and emission shape of qb_intersect_ex writes the same
+    pairs in the same order, and every tile-sort shape of qb_sort_ex gives
+    the same sorted list and ranges: on the 10k-Gaussian scene against the
+    oracle, on the 1M-Gaussian clustered scene against the default shapes
+    (bit for bit)."""
+    for scene, cam, ref in ((lambda s, c: (s, c, oracle.forward(s, c, "quadbox")))(*scenes.small_scene()),
+                            (*scenes.cluster_scene(), None)):
+        g = qb.Gaussians(scene)
+        r = qb.Rasterizer(scene.n, cam)
+        r.forward(g, "quadbox")
+        torch.cuda.synchronize()
+        P = r.pairs()
+        want_t = r.pair_tiles[:P].clone()
+        want_i = r.pair_ids[:P].clone()
+        want_keys = r.keys_sorted[:P].clone()
+        want_ids = r.ids_sorted[:P].clone()
+        want_ranges = r.ranges.clone()
+        if ref is not None:
+            assert np.array_equal(want_keys.cpu().numpy().view(np.uint64), ref["keys"])
+            assert np.array_equal(want_ids.cpu().numpy().view(np.uint32), ref["ids"])
+            assert np.array_equal(want_ranges.cpu().numpy().view(np.uint32), ref["ranges"])
+        for dn, dv in qb.DEPTH_VARIANTS.items():
+            for en, ev in qb.EMIT_VARIANTS.items():
+                r.pair_tiles.fill_(-1)
+                r.pair_ids.fill_(-1)
+                r.depth_variant, r.emit_variant = dv, ev
+                r.intersect()
+                torch.cuda.synchronize()
+                assert r.pairs() == P
+                assert torch.equal(r.pair_tiles[:P], want_t), (scene.n, dn, en)
+                assert torch.equal(r.pair_ids[:P], want_i), (scene.n, dn, en)
+        for sn, sv in qb.SORT_VARIANTS.items():
+            r.ids_sorted.fill_(-1)
+            r.keys_sorted.fill_(-1)
+            r.ranges.fill_(-1)
+            r.sort_variant = sv
+            r.sort()
+            torch.cuda.synchronize()
+            assert torch.equal(r.keys_sorted[:P], want_keys), (scene.n, sn)
+            assert torch.equal(r.ids_sorted[:P], want_ids), (scene.n, sn)
+            assert torch.equal(r.ranges, want_ranges), (scene.n, sn)
+        say(f"{scene.n} Gaussians, {P} pairs: every intersect and sort shape agrees")

@@ -7,7 +7,8 @@ everywhere, the longest runs of equal digits in the histogram pass), a
 sawtooth over all tiles (every neighbour a different digit), runs of 37
 equal tiles (runs that straddle the 8-pair lane groups and the 4096-pair
 workgroups), and uniform random tiles; counts from 1 to 1M include ragged
-tails that are not whole lane groups or workgroups.  Bit-exact."""
+tails that are not whole lane groups or workgroups.  Every launch shape of
+qb_sort_ex (radix workgroups of 4096 to 8192 pairs) is checked.  Bit-exact."""
 import numpy as np
 import pytest
 
@@ -46,15 +47,17 @@ def test_sort_synthetic_tiles(oracle, qb, n, tiles):
         pt[:n] = torch.from_numpy(t.view(np.int16)).cuda()
         pi = torch.zeros(cap, dtype=torch.int32, device="cuda")
         pi[:n] = torch.from_numpy(ids_in.view(np.int32)).cuda()
-        ids = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
-        ranges = torch.full((tiles * 2,), -1, dtype=torch.int32, device="cuda")
-        qb.sort(cap, num_pairs, tiles, pt, pi, None, None, ids, ranges, ws)
-        torch.cuda.synchronize()
         order = np.argsort(t, kind="stable")
         want_ids = ids_in[order]
         want_ranges = oracle.ranges(t[order].astype(np.uint64) << np.uint64(32), tiles)
-        got_ids = ids.cpu().numpy().view(np.uint32)[:n]
-        assert np.array_equal(got_ids, want_ids), (n, tiles, name)
-        assert np.array_equal(ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), want_ranges), (n, tiles, name)
-        # the input lists are left as they were
-        assert np.array_equal(pt[:n].cpu().numpy().view(np.uint16), t), (n, tiles, name)
+        for shape, variant in qb.SORT_VARIANTS.items():
+            ids = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+            ranges = torch.full((tiles * 2,), -1, dtype=torch.int32, device="cuda")
+            qb.sort(cap, num_pairs, tiles, pt, pi, None, None, ids, ranges, ws, variant)
+            torch.cuda.synchronize()
+            got_ids = ids.cpu().numpy().view(np.uint32)[:n]
+            assert np.array_equal(got_ids, want_ids), (n, tiles, name, shape)
+            assert np.array_equal(ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), want_ranges), \
+                (n, tiles, name, shape)
+            # the input lists are left as they were
+            assert np.array_equal(pt[:n].cpu().numpy().view(np.uint16), t), (n, tiles, name, shape)
