@@ -558,24 +558,45 @@ COUNTERS = os.path.join("profiles", "k_render_clusters_1M_counters.json")
 
 
 def render_counters(workload, mode, kernel):
-    """Counters per launch of the render kernel `kernel` from the committed
-    summary (every launch shape of the frame; the autotuner launches each):
-    HBM bytes (FETCH_SIZE + WRITE_SIZE, copy-calibrated) and VALU
-    instructions (SQ_INSTS_VALU), or None when the summary was taken on
-    another workload or on a different render source (its sha256 is
-    recorded)."""
+    """Counters per launch of the render or render-backward kernel `kernel`
+    from the committed summary (every launch shape of the frame; the
+    autotuners launch each): HBM bytes (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated) and VALU instructions (SQ_INSTS_VALU), or None when the
+    summary was taken on another workload or on a different kernel source
+    (the sha256 of each source is recorded)."""
     path = os.path.join(ROOT, COUNTERS)
     if workload != "clusters" or mode != "quadbox" or not os.path.exists(path):
         return None
     meta = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2605_04844_amd", "csrc", "render.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != meta.get("render_source_sha256"):
-        return None
     k = meta.get("kernels", {}).get(kernel)
     if k is None:
         return None
+    src = k.get("source", "")
+    want = meta.get("source_sha256", {}).get(src)
+    full = os.path.join(ROOT, src)
+    if not want or not os.path.exists(full) or hashlib.sha256(open(full, "rb").read()).hexdigest() != want:
+        return None
     return {"traffic": int(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]),
             "valu_insts": k.get("valu_insts_per_launch")}
+
+
+def counter_fields(roof, ctr, ms, work, per):
+    """Adds the committed counters' traffic and VALU issue rate to a
+    roofline entry (`per`: the work count the lane instructions are divided
+    by)."""
+    if not ctr:
+        return roof
+    roof["traffic"] = ctr["traffic"]
+    roof["traffic_source"] = (f"{COUNTERS}: FETCH_SIZE + WRITE_SIZE per launch of this kernel, copy-calibrated, "
+                              "taken by rocprofv3 on this kernel source (sha256 recorded there), not in this run")
+    if ctr.get("valu_insts"):
+        lane_rate = ctr["valu_insts"] * 64 / (ms * 1e-3) / 1e12
+        roof["valu_issue"] = {"insts_per_launch": int(ctr["valu_insts"]),
+                              f"lane_insts_per_{per}": round(ctr["valu_insts"] * 64 / max(work[per], 1), 2),
+                              "lane_rate_T": round(lane_rate, 2), "peak_T": round(VALU_LANE_PEAK_T, 2),
+                              "frac": round(lane_rate / VALU_LANE_PEAK_T, 4),
+                              "source": f"{COUNTERS}: SQ_INSTS_VALU per launch, not in this run"}
+    return roof
 
 
 def copy_bandwidth(torch, mib=1024, reps=10):
@@ -653,20 +674,19 @@ def main():
     render_ms = q["render_launch_ms"]
     kname = f"k_render<{q['render_shape'][0]}, false, {'true' if q['render_shape'].endswith('rows') else 'false'}>"
     ctr = render_counters(args.workload, modes[0], kname)
-    roof = alu_roofline(render_flops(q["work"]), render_ms, kname, q["work"],
-                        traffic=ctr["traffic"] if ctr else None)
+    roof = alu_roofline(render_flops(q["work"]), render_ms, kname, q["work"])
     roof["flops_per_examined"] = RENDER_FLOPS_EXAMINED
     roof["flops_per_composited"] = RENDER_FLOPS_COMPOSITED
-    if ctr:
-        roof["traffic_source"] = (f"{COUNTERS}: FETCH_SIZE + WRITE_SIZE per launch of this kernel, copy-calibrated, "
-                                  "taken by rocprofv3 on this render source (sha256 recorded there)")
-        if ctr.get("valu_insts"):
-            lane_rate = ctr["valu_insts"] * 64 / (render_ms * 1e-3) / 1e12
-            roof["valu_issue"] = {"insts_per_launch": int(ctr["valu_insts"]),
-                                  "lane_insts_per_examined": round(ctr["valu_insts"] * 64 / q["work"]["examined"], 2),
-                                  "lane_rate_T": round(lane_rate, 2), "peak_T": round(VALU_LANE_PEAK_T, 2),
-                                  "frac": round(lane_rate / VALU_LANE_PEAK_T, 4),
-                                  "source": f"{COUNTERS}: SQ_INSTS_VALU per launch"}
+    counter_fields(roof, ctr, render_ms, q["work"], "examined")
+    bwd_roof = None
+    if fwd_bwd is not None:
+        bname = f"k_render_backward<{fwd_bwd['shape'][0]}>"
+        bwd_roof = alu_roofline(backward_flops(fwd_bwd["work"]), fwd_bwd["render_backward_ms"], bname,
+                                fwd_bwd["work"], note="launch time includes the clear of grad2d (36 B per Gaussian)")
+        bwd_roof["flops_per_contributor_entry"] = BACKWARD_FLOPS_EXAMINED
+        bwd_roof["flops_per_composited"] = BACKWARD_FLOPS_COMPOSITED
+        counter_fields(bwd_roof, render_counters(args.workload, modes[0], bname), fwd_bwd["render_backward_ms"],
+                       fwd_bwd["work"], "contributors")
     out = {
         "metric": METRIC,
         "value": round(1000.0 / q["ms"], 2),
@@ -695,10 +715,7 @@ def main():
                       **image_delta(torch, r["rast"].image, q["rast"].image)}
                   for m, r in results.items()},
         "fwd_bwd_ms_per_view": round(fwd_bwd["ms"], 4) if fwd_bwd is not None else None,
-        "render_backward_roofline": (alu_roofline(backward_flops(fwd_bwd["work"]), fwd_bwd["render_backward_ms"],
-                                                  f"k_render_backward<{fwd_bwd['shape'][0]}>", fwd_bwd["work"],
-                                                  note="launch time includes the clear of grad2d (36 B per Gaussian)")
-                                     if fwd_bwd is not None else None),
+        "render_backward_roofline": bwd_roof,
         "multiview": multiview,
         "zoom_sweep": zoom,
         "quadbox_vs_3sigma": round(results["3sigma"]["ms"] / q["ms"], 3) if "3sigma" in results else None,

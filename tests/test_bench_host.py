@@ -16,18 +16,24 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_render_clusters_1M_counters.json")
-RENDER_SRC = os.path.join(ROOT, "paper_2605_04844_amd", "csrc", "render.hip")
+
+
+def _current(meta, k):
+    src = os.path.join(ROOT, k["source"])
+    return hashlib.sha256(open(src, "rb").read()).hexdigest() == meta["source_sha256"][k["source"]]
 
 
 def test_render_traffic_lookup():
+    """Every render and render-backward launch shape recorded: bytes and VALU
+    instructions per launch, reported while its source is unchanged."""
     meta = json.load(open(COUNTERS))
     assert meta["kernels"], "no render shape recorded"
-    current = hashlib.sha256(open(RENDER_SRC, "rb").read()).hexdigest() == meta["render_source_sha256"]
+    assert any(n.startswith("k_render_backward<") for n in meta["kernels"])
     for name, k in meta["kernels"].items():
         assert k["fetch_bytes_per_launch"] > 0 and k["write_bytes_per_launch"] > 0, name
         got = bench.render_counters("clusters", "quadbox", name)
         want = k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
-        if current:
+        if _current(meta, k):
             assert got["traffic"] == want and got["valu_insts"] == k.get("valu_insts_per_launch"), name
         else:
             assert got is None, name
@@ -38,17 +44,32 @@ def test_render_traffic_lookup():
 
 
 def test_render_traffic_stale_source(tmp_path, monkeypatch):
-    """Counters taken on another render source are not reported."""
+    """Counters taken on another kernel source are not reported."""
     meta = json.load(open(COUNTERS))
-    meta["render_source_sha256"] = "0" * 64
+    for src in meta["source_sha256"]:
+        meta["source_sha256"][src] = "0" * 64
     prof = tmp_path / "profiles"
     prof.mkdir()
     (prof / "k_render_clusters_1M_counters.json").write_text(json.dumps(meta))
     src = tmp_path / "paper_2605_04844_amd" / "csrc"
     src.mkdir(parents=True)
-    (src / "render.hip").write_bytes(open(RENDER_SRC, "rb").read())
+    for f in ("render.hip", "backward.hip"):
+        (src / f).write_bytes(open(os.path.join(ROOT, "paper_2605_04844_amd", "csrc", f), "rb").read())
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.render_counters("clusters", "quadbox", next(iter(meta["kernels"]))) is None
+    for name in meta["kernels"]:
+        assert bench.render_counters("clusters", "quadbox", name) is None
+
+
+def test_counter_fields():
+    """The counters' traffic and the VALU issue rate against 78.6 T
+    lane-instructions per second."""
+    roof = bench.counter_fields({}, {"traffic": 123, "valu_insts": 1_000_000_000}, 1.0,
+                                {"examined": 64_000_000_000}, "examined")
+    assert roof["traffic"] == 123 and "not in this run" in roof["traffic_source"]
+    v = roof["valu_issue"]
+    assert v["lane_insts_per_examined"] == 1.0
+    assert v["lane_rate_T"] == pytest.approx(64.0, rel=1e-3) and v["frac"] == pytest.approx(64.0 / 78.64, rel=1e-3)
+    assert bench.counter_fields({"a": 1}, None, 1.0, {}, "examined") == {"a": 1}
 
 
 def test_flops_and_roofline_arithmetic():
