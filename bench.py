@@ -344,7 +344,7 @@ def run_multiview(torch, qb, steps, warmup, trials):
     fwd_ms = tuned["render_ms"][tuned["picked"]["render"]]
     bwd_ms = tuned["render_backward_ms"][tuned["picked"]["render_backward"]]
     rooflines = {"render_views": alu_roofline(render_flops(work), fwd_ms,
-                                              f"k_render_views<{tuned['picked']['render'][0]}>", work),
+                                              render_kernel_name(tuned["picked"]["render"], views=True), work),
                  "render_backward_views": alu_roofline(backward_flops(work), bwd_ms,
                                                        f"k_render_backward_views<{tuned['picked']['render_backward'][0]}>",
                                                        work, note="launch time includes the clear of every view's grad2d")}
@@ -439,6 +439,16 @@ def render_work(torch, qb, r, view=None):
     torch.cuda.synchronize()
     return {"examined": int(nt.to(torch.int64).sum()), "composited": int(nk.to(torch.int64).sum()),
             "contributors": int(nc.to(torch.int64).sum())}
+
+
+def render_kernel_name(shape, views=False):
+    """The k_render (views: k_render_views) instance a render launch shape
+    (RENDER_VARIANTS key, e.g. "2px", "1px_rows", "2px_xrow1") runs."""
+    rows = "true" if shape.endswith("_rows") else "false"
+    xrow = 2 if shape.endswith("_xrow1") else (1 if shape.endswith("_xrow") else 0)
+    if views:
+        return f"k_render_views<{shape[0]}, {rows}, {xrow}>"
+    return f"k_render<{shape[0]}, false, {rows}, {xrow}>"
 
 
 def render_flops(work):
@@ -672,7 +682,7 @@ def main():
     # roofline of the render kernel (qb_render launches k_render alone, so
     # events around back-to-back calls time that kernel)
     render_ms = q["render_launch_ms"]
-    kname = f"k_render<{q['render_shape'][0]}, false, {'true' if q['render_shape'].endswith('rows') else 'false'}>"
+    kname = render_kernel_name(q["render_shape"])
     ctr = render_counters(args.workload, modes[0], kname)
     roof = alu_roofline(render_flops(q["work"]), render_ms, kname, q["work"])
     roof["flops_per_examined"] = RENDER_FLOPS_EXAMINED

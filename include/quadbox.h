@@ -143,6 +143,18 @@ qb_status qb_project(int64_t n, const float* means, const float* log_scales, con
                      const qb_camera* cam, int32_t mode, qb_splat* out_splats,
                      qb_rects* out_rects, int32_t* out_counts, qb_stream_t stream);
 
+/* qb_project_ex -- qb_project that also writes the keys of qb_intersect's
+ * depth sort, so that qb_intersect_ex need not read the splats back for them:
+ *   out_depth_keys   [n] uint32: float_bits(depth) where out_counts[i] > 0,
+ *                    else 0xFFFFFFFF (the Gaussian emits no pair); may be
+ *                    NULL, which is qb_project
+ * Every other output as qb_project's. */
+qb_status qb_project_ex(int64_t n, const float* means, const float* log_scales, const float* quats,
+                        const float* opacity_logits, const float* sh, int32_t sh_degree,
+                        const qb_camera* cam, int32_t mode, qb_splat* out_splats,
+                        qb_rects* out_rects, int32_t* out_counts, uint32_t* out_depth_keys,
+                        qb_stream_t stream);
+
 /* The three binary32 activations of qb_project (each evaluated in binary64
  * and rounded once; Eq. (3) for gamma), on arbitrary inputs, so that their
  * agreement with another implementation can be checked on every binary32
@@ -202,18 +214,22 @@ typedef enum {
     QB_EMIT_256 = 0,      /* 256 Gaussians per workgroup (qb_intersect's)   */
     QB_EMIT_128 = 1,
     QB_EMIT_512 = 2,
-    QB_EMIT_VARIANTS = 3
+    QB_EMIT_256_2CHAINS = 3,  /* 256, each wave walking two pair ranges at once */
+    QB_EMIT_128_2CHAINS = 4,  /* 128, likewise                                   */
+    QB_EMIT_VARIANTS = 5
 } qb_emit_variant;
 
-/* qb_intersect_ex -- qb_intersect with explicit launch shapes (a
- * qb_depth_variant and a qb_emit_variant; the emission shape does not apply
- * to QB_BOX_QUADBOX_NAIVE); same arguments, workspace size and results as
+/* qb_intersect_ex -- qb_intersect with the depth-sort keys written by
+ * qb_project_ex for the same projection (depth_keys, [n] uint32, read only;
+ * NULL: derived from splats and counts as qb_intersect does) and explicit
+ * launch shapes (a qb_depth_variant and a qb_emit_variant; the emission shape
+ * does not apply to QB_BOX_QUADBOX_NAIVE); same workspace size and results as
  * qb_intersect. */
 qb_status qb_intersect_ex(int64_t n, const qb_splat* splats, const qb_rects* rects,
                           const int32_t* counts, int32_t width, int32_t height, int32_t mode,
                           int64_t pair_capacity, uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs,
-                          void* workspace, size_t workspace_bytes, int32_t depth_variant, int32_t emit_variant,
-                          qb_stream_t stream);
+                          void* workspace, size_t workspace_bytes, const uint32_t* depth_keys,
+                          int32_t depth_variant, int32_t emit_variant, qb_stream_t stream);
 
 /* Workspace bytes qb_sort needs for a pair capacity. */
 size_t qb_sort_workspace_size(int64_t pair_capacity);
@@ -291,7 +307,13 @@ typedef enum {
     QB_RENDER_4PX = 2,        /* 64 lanes, 4 pixels each                       */
     QB_RENDER_2PX_ROWS = 3,   /* 2 pixels each, row-range entry skip           */
     QB_RENDER_1PX_ROWS = 4,   /* 1 pixel each, row-range entry skip            */
-    QB_RENDER_VARIANTS = 5
+    QB_RENDER_2PX_XROW = 5,   /* 2 pixels each; the row terms of the quadratic
+                                 form computed once per tile row and shared
+                                 across the row's lanes                        */
+    QB_RENDER_4PX_XROW = 6,   /* 4 pixels each, row terms shared likewise      */
+    QB_RENDER_2PX_XROW1 = 7,  /* as 2PX_XROW, one branch per entry instead of
+                                 one per pair of entries                       */
+    QB_RENDER_VARIANTS = 8
 } qb_render_variant;
 
 /* qb_tile_order -- the order in which the render's workgroups (one per
@@ -415,6 +437,15 @@ qb_status qb_project_views(int64_t n, const float* means, const float* log_scale
                            const float* opacity_logits, const float* sh, int32_t sh_degree,
                            const qb_camera* cams, int32_t num_views, int32_t mode, qb_splat* out_splats,
                            qb_rects* out_rects, int32_t* out_counts, qb_stream_t stream);
+
+/* qb_project_views_ex -- qb_project_views that also writes each view's
+ * depth-sort keys as qb_project_ex does: out_depth_keys [num_views][n] uint32
+ * (NULL: qb_project_views). */
+qb_status qb_project_views_ex(int64_t n, const float* means, const float* log_scales, const float* quats,
+                              const float* opacity_logits, const float* sh, int32_t sh_degree,
+                              const qb_camera* cams, int32_t num_views, int32_t mode, qb_splat* out_splats,
+                              qb_rects* out_rects, int32_t* out_counts, uint32_t* out_depth_keys,
+                              qb_stream_t stream);
 
 /* qb_render_views -- qb_render of every view in one launch (one workgroup
  * per tile of every view).  views: host array; uses width, height, ranges,

@@ -49,19 +49,24 @@ __global__ void k_store_total(const uint64_t* __restrict__ tot, int64_t* __restr
     *num_pairs = tot ? (int64_t)*tot : 0;
 }
 
-template <int kEmitThreads>
+// kChains: independent cursors per wave.  The block's pairs are cut into
+// (waves x kChains) contiguous ranges; a wave advances its kChains ranges in
+// lockstep, 64 pairs each per step, so the LDS round trips of one range's
+// step (owner table, run lookups) overlap with the other's.
+template <int kEmitThreads, int kChains>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     int64_t n, const uint32_t* __restrict__ order, const uint64_t* __restrict__ goff,
     const int4* __restrict__ rects, const uint32_t* __restrict__ sorted_counts, int tiles_x, int64_t cap,
     const int64_t* __restrict__ num_pairs, uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id)
 {
     constexpr int kRuns = kEmitThreads * QB_MAX_SEG;
+    constexpr int NW = kEmitThreads / 64;
     __shared__ uint32_t s_off[kRuns + 1];  // first pair of each run, block-relative
     __shared__ uint32_t s_w0[kRuns];       // s0 | lo << 16
     __shared__ uint32_t s_w1[kRuns];       // len | axis << 16
     __shared__ uint32_t s_gid[kRuns];      // Gaussian id
-    __shared__ uint32_t s_scan[kEmitThreads / 64];
-    __shared__ int s_tab[kEmitThreads / 64][64];
+    __shared__ uint32_t s_scan[NW];
+    __shared__ int s_tab[NW][kChains][64];
 
     if (*num_pairs > cap) return;  // overflow: the caller re-runs with more capacity
     int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -99,55 +104,80 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     if (t == 0) s_off[nruns] = total;  // sentinel
     int64_t block_start = (int64_t)goff[k0];
     __syncthreads();
-    // each wave takes a contiguous quarter of the block's pairs, 64 per step;
-    // the run holding a step's first pair is the run of the previous step's
-    // last pair, so only the wave's first step searches for it
-    uint32_t per = (total + (kEmitThreads / 64) - 1) / (kEmitThreads / 64);
-    uint32_t w_lo = min(total, (uint32_t)wave * per), w_hi = min(total, w_lo + per);
-    int cur = 0;
-    {
-        int lo = 0, hi = (int)nruns;
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (s_off[mid] <= w_lo) lo = mid; else hi = mid;
+    // each of the block's waves x kChains ranges is a contiguous share of its
+    // pairs, walked 64 per step; the run holding a step's first pair is the
+    // run of the previous step's last pair, so only a range's first step
+    // searches for it
+    uint32_t per = (total + NW * kChains - 1) / (NW * kChains);
+    uint32_t base[kChains], hi[kChains];
+    int cur[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) {
+        uint32_t lo = min(total, (uint32_t)(wave * kChains + c) * per);
+        base[c] = lo;
+        hi[c] = min(total, lo + per);
+        int a = 0, b = (int)nruns;
+        while (b - a > 1) {
+            int mid = (a + b) >> 1;
+            if (s_off[mid] <= lo) a = mid; else b = mid;
         }
-        cur = lo;
+        cur[c] = a;
     }
-    for (uint32_t base = w_lo; base < w_hi; base += 64) {
-        // every later run that starts inside this step marks its first pair;
-        // a running maximum hands the run to the pairs that follow
-        s_tab[wave][lane] = -1;
+    for (;;) {
+        bool left = false;
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) left = left || base[c] < hi[c];
+        if (!left) break;
+        // every later run that starts inside a range's step marks its first
+        // pair; a running maximum hands the run to the pairs that follow
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) s_tab[wave][c][lane] = -1;
         __builtin_amdgcn_wave_barrier();
-        int jj = cur + 1 + lane;
-        if (jj < (int)nruns) {
-            uint32_t st = s_off[jj];
-            if (st >= base && st < base + 64) s_tab[wave][st - base] = jj;
-        }
-        __builtin_amdgcn_wave_barrier();
-        int own = qbr::wave_inclusive_max(s_tab[wave][lane]);
-        if (own < 0) own = cur;
-        uint32_t p = base + lane;
-        if (p < w_hi) {
-            uint32_t local = p - s_off[own];
-            uint32_t w0 = s_w0[own], w1 = s_w1[own];
-            uint32_t len = w1 & 0xFFFFu;
-            // local < 2^16: with the hardware reciprocal (1 ulp) the float
-            // quotient is within 0.02 of local / len, so its floor is off by
-            // at most one, which the two steps below correct
-            uint32_t qq = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)len));
-            int32_t rem = (int32_t)local - (int32_t)(qq * len);
-            if (rem < 0) { --qq; rem += (int32_t)len; }
-            if (rem >= (int32_t)len) { ++qq; rem -= (int32_t)len; }
-            int sl = (int)(w0 & 0xFFFFu) + (int)qq;
-            int ot = (int)(w0 >> 16) + rem;
-            int tile = (w1 >> 16) ? sl * tiles_x + ot : ot * tiles_x + sl;
-            int64_t dst = block_start + p;
-            if (dst < cap) {
-                out_tile[dst] = (uint16_t)tile;
-                out_id[dst] = s_gid[own];
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) {
+            int jj = cur[c] + 1 + lane;
+            if (base[c] < hi[c] && jj < (int)nruns) {
+                uint32_t st = s_off[jj];
+                if (st >= base[c] && st < base[c] + 64) s_tab[wave][c][st - base[c]] = jj;
             }
         }
-        cur = __builtin_amdgcn_readlane(own, 63);
+        __builtin_amdgcn_wave_barrier();
+        int own[kChains];
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) {
+            own[c] = qbr::wave_inclusive_max(s_tab[wave][c][lane]);
+            if (own[c] < 0) own[c] = cur[c];
+        }
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) {
+            uint32_t p = base[c] + lane;
+            if (p < hi[c]) {
+                int o = own[c];
+                uint32_t local = p - s_off[o];
+                uint32_t w0 = s_w0[o], w1 = s_w1[o];
+                uint32_t len = w1 & 0xFFFFu;
+                // local < 2^16: with the hardware reciprocal (1 ulp) the float
+                // quotient is within 0.02 of local / len, so its floor is off
+                // by at most one, which the two steps below correct
+                uint32_t qq = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)len));
+                int32_t rem = (int32_t)local - (int32_t)(qq * len);
+                if (rem < 0) { --qq; rem += (int32_t)len; }
+                if (rem >= (int32_t)len) { ++qq; rem -= (int32_t)len; }
+                int sl = (int)(w0 & 0xFFFFu) + (int)qq;
+                int ot = (int)(w0 >> 16) + rem;
+                int tile = (w1 >> 16) ? sl * tiles_x + ot : ot * tiles_x + sl;
+                int64_t dst = block_start + p;
+                if (dst < cap) {
+                    out_tile[dst] = (uint16_t)tile;
+                    out_id[dst] = s_gid[o];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) {
+            cur[c] = __builtin_amdgcn_readlane(own[c], 63);
+            base[c] += 64;
+        }
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -211,21 +241,25 @@ extern "C" size_t qb_intersect_workspace_size(int64_t n)
 // `workspace` (already checked to be large enough for n).
 // The depth sort of (keys, ids) in radix workgroups of NT lanes x NI keys;
 // the last pass also gathers the tile counts into the sorted order.
+// keys: the depth keys (qb_project_ex's), or w.dk0 after k_depth_keys wrote
+// them there with the identity values in w.dv0.
 template <int NT, int NI>
-static qb_status depth_sort(IsectWs& w, int64_t n, const int32_t* counts, hipStream_t s)
+static qb_status depth_sort(IsectWs& w, const uint32_t* keys, int64_t n, const int32_t* counts, hipStream_t s)
 {
     static_assert(NT * NI >= kDepthMinTile, "the workspace is sized for tiles of at least kDepthMinTile keys");
-    // four 8-bit passes: (dk0, dv0) -> (dk1, dv1) -> (dk0, dv0) -> ...
-    return qbr::radix_sort<uint32_t, NT, NI>(w.dk0, w.dv0, w.dk0, w.dv0, w.dk1, w.dv1, (const int64_t*)nullptr, n, n,
+    // four 8-bit passes: keys -> (dk1, dv1) -> (dk0, dv0) -> ...; the first
+    // pass takes the positions as values when the keys are the caller's
+    const uint32_t* vals = keys == w.dk0 ? w.dv0 : nullptr;
+    return qbr::radix_sort<uint32_t, NT, NI>(keys, vals, w.dk0, w.dv0, w.dk1, w.dv1, (const int64_t*)nullptr, n, n,
                                              0, 32, w.radix, s, counts, w.csorted);
 }
 
-template <int NT>
+template <int NT, int C>
 static qb_status launch_emit(int64_t n, const uint32_t* order, const uint64_t* offs, const int4* r4,
                              const uint32_t* csorted, int tiles_x, int64_t cap, const int64_t* num_pairs,
                              uint16_t* pair_tiles, uint32_t* pair_ids, hipStream_t s)
 {
-    QB_LAUNCH(k_emit<NT>, qb_div_up(n, NT), NT, 0, s, n, order, offs, r4, csorted, tiles_x, cap, num_pairs,
+    QB_LAUNCH((k_emit<NT, C>), qb_div_up(n, NT), NT, 0, s, n, order, offs, r4, csorted, tiles_x, cap, num_pairs,
               pair_tiles, pair_ids);
     return QB_OK;
 }
@@ -233,7 +267,8 @@ static qb_status launch_emit(int64_t n, const uint32_t* order, const uint64_t* o
 static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rects* rects, const int32_t* counts,
                                 int tiles_x, int32_t mode, int64_t pair_capacity, uint16_t* pair_tiles,
                                 uint32_t* pair_ids, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
-                                int32_t depth_variant, int32_t emit_variant, hipStream_t s)
+                                const uint32_t* depth_keys, int32_t depth_variant, int32_t emit_variant,
+                                hipStream_t s)
 {
     QbArena a{(char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255), workspace_bytes - 256, 0};
     IsectWs w = carve(a, n);
@@ -243,12 +278,17 @@ static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rect
         return QB_OK;
     }
     int64_t grid = qb_div_up(n, QB_BLOCK);
-    QB_LAUNCH(k_depth_keys, grid, QB_BLOCK, 0, s, n, reinterpret_cast<const float4*>(splats), counts, w.dk0, w.dv0);
+    const uint32_t* keys = depth_keys;
+    if (!keys) {
+        QB_LAUNCH(k_depth_keys, grid, QB_BLOCK, 0, s, n, reinterpret_cast<const float4*>(splats), counts, w.dk0,
+                  w.dv0);
+        keys = w.dk0;
+    }
     switch (depth_variant) {
-    case QB_DEPTH_512x4: QB_CHECK((depth_sort<512, 4>(w, n, counts, s))); break;
-    case QB_DEPTH_256x8: QB_CHECK((depth_sort<256, 8>(w, n, counts, s))); break;
-    case QB_DEPTH_512x8: QB_CHECK((depth_sort<512, 8>(w, n, counts, s))); break;
-    default: QB_CHECK((depth_sort<1024, 4>(w, n, counts, s))); break;
+    case QB_DEPTH_512x4: QB_CHECK((depth_sort<512, 4>(w, keys, n, counts, s))); break;
+    case QB_DEPTH_256x8: QB_CHECK((depth_sort<256, 8>(w, keys, n, counts, s))); break;
+    case QB_DEPTH_512x8: QB_CHECK((depth_sort<512, 8>(w, keys, n, counts, s))); break;
+    default: QB_CHECK((depth_sort<1024, 4>(w, keys, n, counts, s))); break;
     }
     // pair offsets; the total (a count, below 2^63) lands in *num_pairs
     QB_CHECK((qbr::exclusive_scan<uint32_t, uint64_t>(w.csorted, w.offs, n, w.scan64,
@@ -261,14 +301,16 @@ static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rect
     else if (pair_capacity > 0) {
         const uint64_t* offs = w.offs;
         const uint32_t* cs = w.csorted;
+#define QB_EMIT(NT, C) \
+    QB_CHECK((launch_emit<NT, C>(n, order, offs, r4, cs, tiles_x, pair_capacity, num_pairs, pair_tiles, pair_ids, s)))
         switch (emit_variant) {
-        case QB_EMIT_256: QB_CHECK(launch_emit<256>(n, order, offs, r4, cs, tiles_x, pair_capacity, num_pairs,
-                                                    pair_tiles, pair_ids, s)); break;
-        case QB_EMIT_128: QB_CHECK(launch_emit<128>(n, order, offs, r4, cs, tiles_x, pair_capacity, num_pairs,
-                                                    pair_tiles, pair_ids, s)); break;
-        default: QB_CHECK(launch_emit<512>(n, order, offs, r4, cs, tiles_x, pair_capacity, num_pairs, pair_tiles,
-                                           pair_ids, s)); break;
+        case QB_EMIT_128: QB_EMIT(128, 1); break;
+        case QB_EMIT_512: QB_EMIT(512, 1); break;
+        case QB_EMIT_256_2CHAINS: QB_EMIT(256, 2); break;
+        case QB_EMIT_128_2CHAINS: QB_EMIT(128, 2); break;
+        default: QB_EMIT(256, 1); break;
         }
+#undef QB_EMIT
     }
     return QB_OK;
 }
@@ -299,14 +341,15 @@ extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_re
                                   size_t workspace_bytes, qb_stream_t stream)
 {
     return qb_intersect_ex(n, splats, rects, counts, width, height, mode, pair_capacity, pair_tiles, pair_ids,
-                           num_pairs, workspace, workspace_bytes, QB_DEPTH_512x4, QB_EMIT_256, stream);
+                           num_pairs, workspace, workspace_bytes, nullptr, QB_DEPTH_512x4, QB_EMIT_256, stream);
 }
 
 extern "C" qb_status qb_intersect_ex(int64_t n, const qb_splat* splats, const qb_rects* rects,
                                      const int32_t* counts, int32_t width, int32_t height, int32_t mode,
                                      int64_t pair_capacity, uint16_t* pair_tiles, uint32_t* pair_ids,
                                      int64_t* num_pairs, void* workspace, size_t workspace_bytes,
-                                     int32_t depth_variant, int32_t emit_variant, qb_stream_t stream)
+                                     const uint32_t* depth_keys, int32_t depth_variant, int32_t emit_variant,
+                                     qb_stream_t stream)
 {
     int tiles_x = 0;
     QB_CHECK(intersect_args(n, splats, rects, counts, width, height, mode, pair_capacity, pair_tiles, pair_ids,
@@ -316,7 +359,7 @@ extern "C" qb_status qb_intersect_ex(int64_t n, const qb_splat* splats, const qb
         return QB_ERR_INVALID_ARG;
     if (!workspace || workspace_bytes < qb_intersect_workspace_size(n)) return QB_ERR_INVALID_ARG;
     return intersect_impl(n, splats, rects, counts, tiles_x, mode, pair_capacity, pair_tiles, pair_ids, num_pairs,
-                          workspace, workspace_bytes, depth_variant, emit_variant, qb_hip_stream(stream));
+                          workspace, workspace_bytes, depth_keys, depth_variant, emit_variant, qb_hip_stream(stream));
 }
 
 // ---- qb_intersect without a caller workspace --------------------------------
@@ -363,5 +406,5 @@ extern "C" qb_status qb_intersect_noalloc(int64_t n, const qb_splat* splats, con
     void* ws = scratch_on_current_device();
     if (!ws) return QB_ERR_HIP;
     return intersect_impl(n, splats, rects, counts, tiles_x, mode, pair_capacity, pair_tiles, pair_ids, num_pairs,
-                          ws, kNoallocScratchBytes, QB_DEPTH_512x4, QB_EMIT_256, qb_hip_stream(stream));
+                          ws, kNoallocScratchBytes, nullptr, QB_DEPTH_512x4, QB_EMIT_256, qb_hip_stream(stream));
 }

@@ -185,7 +185,8 @@ template <int DEG>
 __device__ __forceinline__ void project_view(int64_t i, int64_t n, float mx, float my, float mz, const GaussPre& g,
                                              const float* __restrict__ sh, const ShCoef<DEG>* pre,
                                              const ProjCam& cam, int mode_arg, float4* __restrict__ out_splat,
-                                             int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
+                                             int4* __restrict__ out_rects, int32_t* __restrict__ out_count,
+                                             uint32_t* __restrict__ out_key)
 {
     const int mode = mode_arg & ~QB_CLIP_3SIGMA;
     const bool clip = (mode_arg & QB_CLIP_3SIGMA) != 0;
@@ -339,6 +340,9 @@ __device__ __forceinline__ void project_view(int64_t i, int64_t n, float mx, flo
     out_rects[2 * i + 0] = p0;
     out_rects[2 * i + 1] = p1;
     out_count[i] = count;
+    // the depth sort's key: the depth's bits where the Gaussian has tiles,
+    // else the largest key (those Gaussians emit nothing)
+    if (out_key) out_key[i] = count > 0 ? __float_as_uint(s0.z) : 0xFFFFFFFFu;
 }
 
 template <int DEG>
@@ -346,14 +350,15 @@ __global__ __launch_bounds__(QB_BLOCK) void k_project(
     int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, ProjCam cam, int mode,
-    float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
+    float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count,
+    uint32_t* __restrict__ out_key)
 {
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
     GaussPre g;
     gauss_pre(i, n, log_scales, quats, logits, g);
     project_view<DEG>(i, n, means[i], means[n + i], means[2 * n + i], g, sh, (const ShCoef<DEG>*)nullptr, cam, mode,
-                      out_splat, out_rects, out_count);
+                      out_splat, out_rects, out_count, out_key);
 }
 
 // Cameras of a batched call, by value as a kernel argument (3.3 KB at
@@ -371,7 +376,8 @@ __global__ __launch_bounds__(QB_BLOCK) void k_project_views(
     int64_t n, int nv, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, ProjCamTable cams, int mode,
-    float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count)
+    float4* __restrict__ out_splat, int4* __restrict__ out_rects, int32_t* __restrict__ out_count,
+    uint32_t* __restrict__ out_key)
 {
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
@@ -382,7 +388,8 @@ __global__ __launch_bounds__(QB_BLOCK) void k_project_views(
     float mx = means[i], my = means[n + i], mz = means[2 * n + i];
     for (int v = 0; v < nv; ++v)
         project_view<DEG>(i, n, mx, my, mz, g, sh, &c, cams.cam[v], mode, out_splat + 3 * (int64_t)v * n,
-                          out_rects + 2 * (int64_t)v * n, out_count + (int64_t)v * n);
+                          out_rects + 2 * (int64_t)v * n, out_count + (int64_t)v * n,
+                          out_key ? out_key + (int64_t)v * n : nullptr);
 }
 
 // Launches kernel template K for the SH degree (0..3).
@@ -440,11 +447,11 @@ extern "C" qb_status qb_activations(int64_t n, const float* x, int32_t which, fl
     return QB_OK;
 }
 
-extern "C" qb_status qb_project(int64_t n, const float* means, const float* log_scales,
-                                const float* quats, const float* opacity_logits, const float* sh,
-                                int32_t sh_degree, const qb_camera* cam, int32_t mode,
-                                qb_splat* out_splats, qb_rects* out_rects, int32_t* out_counts,
-                                qb_stream_t stream)
+extern "C" qb_status qb_project_ex(int64_t n, const float* means, const float* log_scales,
+                                   const float* quats, const float* opacity_logits, const float* sh,
+                                   int32_t sh_degree, const qb_camera* cam, int32_t mode,
+                                   qb_splat* out_splats, qb_rects* out_rects, int32_t* out_counts,
+                                   uint32_t* out_depth_keys, qb_stream_t stream)
 {
     if (n < 0 || n >= (int64_t)1 << 31 || !cam || sh_degree < 0 || sh_degree > 3) return QB_ERR_INVALID_ARG;
     if (!qb_valid_mode(mode)) return QB_ERR_INVALID_ARG;
@@ -458,15 +465,25 @@ extern "C" qb_status qb_project(int64_t n, const float* means, const float* log_
     int64_t grid = qb_div_up(n, QB_BLOCK);
     QB_LAUNCH_DEG(k_project, sh_degree, grid, qb_hip_stream(stream), n, means, log_scales, quats, opacity_logits, sh,
                   pc, (int)mode, reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects),
-                  out_counts);
+                  out_counts, out_depth_keys);
     return QB_OK;
 }
 
-extern "C" qb_status qb_project_views(int64_t n, const float* means, const float* log_scales,
-                                      const float* quats, const float* opacity_logits, const float* sh,
-                                      int32_t sh_degree, const qb_camera* cams, int32_t num_views, int32_t mode,
-                                      qb_splat* out_splats, qb_rects* out_rects, int32_t* out_counts,
-                                      qb_stream_t stream)
+extern "C" qb_status qb_project(int64_t n, const float* means, const float* log_scales,
+                                const float* quats, const float* opacity_logits, const float* sh,
+                                int32_t sh_degree, const qb_camera* cam, int32_t mode,
+                                qb_splat* out_splats, qb_rects* out_rects, int32_t* out_counts,
+                                qb_stream_t stream)
+{
+    return qb_project_ex(n, means, log_scales, quats, opacity_logits, sh, sh_degree, cam, mode, out_splats,
+                         out_rects, out_counts, nullptr, stream);
+}
+
+extern "C" qb_status qb_project_views_ex(int64_t n, const float* means, const float* log_scales,
+                                         const float* quats, const float* opacity_logits, const float* sh,
+                                         int32_t sh_degree, const qb_camera* cams, int32_t num_views, int32_t mode,
+                                         qb_splat* out_splats, qb_rects* out_rects, int32_t* out_counts,
+                                         uint32_t* out_depth_keys, qb_stream_t stream)
 {
     if (n < 0 || n >= (int64_t)1 << 31 || !cams || sh_degree < 0 || sh_degree > 3 || num_views < 1 ||
         num_views > QB_MAX_VIEWS)
@@ -483,6 +500,17 @@ extern "C" qb_status qb_project_views(int64_t n, const float* means, const float
         return QB_ERR_INVALID_ARG;
     QB_LAUNCH_DEG(k_project_views, sh_degree, qb_div_up(n, QB_BLOCK), qb_hip_stream(stream), n, (int)num_views,
                   means, log_scales, quats, opacity_logits, sh, ct, (int)mode,
-                  reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects), out_counts);
+                  reinterpret_cast<float4*>(out_splats), reinterpret_cast<int4*>(out_rects), out_counts,
+                  out_depth_keys);
     return QB_OK;
+}
+
+extern "C" qb_status qb_project_views(int64_t n, const float* means, const float* log_scales,
+                                      const float* quats, const float* opacity_logits, const float* sh,
+                                      int32_t sh_degree, const qb_camera* cams, int32_t num_views, int32_t mode,
+                                      qb_splat* out_splats, qb_rects* out_rects, int32_t* out_counts,
+                                      qb_stream_t stream)
+{
+    return qb_project_views_ex(n, means, log_scales, quats, opacity_logits, sh, sh_degree, cams, num_views, mode,
+                               out_splats, out_rects, out_counts, nullptr, stream);
 }

@@ -406,7 +406,7 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
         int64_t idx = base + r * 64 + lane;
         bool valid = idx < n;
         kv[r] = valid ? keys_in[idx] : (K)0;
-        vv[r] = valid ? vals_in[idx] : 0u;
+        vv[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
     }
 #pragma unroll
     for (int r = 0; r < NI; ++r) {
@@ -487,7 +487,8 @@ __global__ __launch_bounds__(QB_BLOCK) void k_copy_items(const K* __restrict__ k
 }
 
 // Stable sort of (keys, vals) by key bits [lo_bit, hi_bit) in passes of at
-// most 8 bits (bits spread evenly over the passes).  Reads (kin, vin), ends in
+// most 8 bits (bits spread evenly over the passes).  vin may be null: the
+// values are then the input positions 0, 1, 2, ...  Reads (kin, vin), ends in
 // (kout, vout), and uses (ktmp, vtmp) for the intermediate passes; kin may
 // alias kout only when the pass count is even.  The item count is *n_dev when
 // n_dev is given (clamped as in sort_count), else n_host; cap sizes the grid.

@@ -33,7 +33,40 @@ namespace {
 // wave covers fewer than 16 rows (PPL 1 or 2), each staged batch also gets,
 // per wave, a ballot mask of the entries whose cutoff ellipse can reach the
 // wave's rows (entry_rows), and the wave walks only those entries.
-template <int PPL, bool COUNT, bool SKIP>
+// x of lane (l & AND) | j of each 32-lane half (ds_swizzle, bitmask mode):
+// with AND clearing the low bits of a group of 2^m lanes, lane j of every
+// group broadcast to its group.
+template <int AND, int J>
+__device__ __forceinline__ float bcast_lane_c(float x)
+{
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), AND | (J << 5)));
+}
+
+// the same with j known only after unrolling (0 <= j < 16); the switch folds
+template <int AND>
+__device__ __forceinline__ float bcast_lane(float x, int j)
+{
+    switch (j) {
+    case 0: return bcast_lane_c<AND, 0>(x);
+    case 1: return bcast_lane_c<AND, 1>(x);
+    case 2: return bcast_lane_c<AND, 2>(x);
+    case 3: return bcast_lane_c<AND, 3>(x);
+    case 4: return bcast_lane_c<AND, 4>(x);
+    case 5: return bcast_lane_c<AND, 5>(x);
+    case 6: return bcast_lane_c<AND, 6>(x);
+    case 7: return bcast_lane_c<AND, 7>(x);
+    case 8: return bcast_lane_c<AND, 8>(x);
+    case 9: return bcast_lane_c<AND, 9>(x);
+    case 10: return bcast_lane_c<AND, 10>(x);
+    case 11: return bcast_lane_c<AND, 11>(x);
+    case 12: return bcast_lane_c<AND, 12>(x);
+    case 13: return bcast_lane_c<AND, 13>(x);
+    case 14: return bcast_lane_c<AND, 14>(x);
+    default: return bcast_lane_c<AND, 15>(x);
+    }
+}
+
+template <int PPL, bool COUNT, bool SKIP, int XROW>
 __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x, const uint2* __restrict__ ranges,
                                             const uint32_t* __restrict__ ids, const float4* __restrict__ splats,
                                             float bg0, float bg1, float bg2, float* __restrict__ image,
@@ -56,6 +89,13 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
     int lane = threadIdx.x & 63;
     int wrow0 = (int)(threadIdx.x / 64) * kRowsPerWave;
     float fy = (float)py;
+    // The walk reads the staged batch through bases held in a vector
+    // register: a zero that the compiler cannot prove uniform, so each run of
+    // entries gets its address once and every LDS read an immediate offset
+    // (with the arrays' own uniform bases, the compiler copies a scalar base
+    // into a vector register again before nearly every read).
+    int vzero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
     // A pixel that has stopped (or lies outside the image) has its x set to
     // +inf: dx is then -inf and, the conic's a being positive, its power
     // -inf, so the cutoff test rejects it by itself (a NaN power, possible
@@ -80,6 +120,10 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
         for (int q = 0; q < PPL; ++q) d = d && fxp[q] == kStopped;
         return d;
     };
+
+    const float4* geo = s_geo + vzero;
+    const float4* opa = s_opa + vzero;
+    const float4* col = s_col + vzero;
 
     uint2 rg = ranges[tile];
     int64_t start = rg.x, end = rg.y;
@@ -133,9 +177,9 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             }
         };
         // the cutoff test of entry k for the lane's pixels; returns whether any passed
-        auto test = [&](int k, float4& g, float4& o, float* p, bool* act) -> bool {
-            g = s_geo[k];
-            o = s_opa[k];
+        auto test = [&](int k, float4& o, float* p, bool* act) -> bool {
+            float4 g = geo[k];
+            o = opa[k];
             // the terms of the quadratic form that depend on the row only
             float dy = g.y - fy;
             float nbdy = g.w * dy;
@@ -150,32 +194,71 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             }
             return any;
         };
-        // one list entry k of the batch; returns true when the whole wave has stopped
-        auto entry = [&](int k) -> bool {
-            float4 g, o;
+        // the cutoff test with the row terms (-b) dy and ((-c/2) dy) dy given
+        auto test_rt = [&](int k, float nbdy, float hcdy2, float4& o, float* p, bool* act) -> bool {
+            float4 g = geo[k];
+            o = opa[k];
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                float dx = g.x - fxp[q];
+                p[q] = fmaf(fmaf(g.z, dx, nbdy), dx, hcdy2);
+                act[q] = !(p[q] > 0.0f) && p[q] >= o.z;
+                any = any || act[q];
+            }
+            return any;
+        };
+        // entry k with its row terms given
+        auto entry_rt = [&](int k, float nb, float hc) -> bool {
+            float4 o;
             float p[PPL];
             bool act[PPL];
-            bool any = test(k, g, o, p, act);
+            if (!__any(test_rt(k, nb, hc, o, p, act))) return false;
+            bool stopped[PPL];
+            composite(o, col[k], p, act, idx0 + (uint32_t)k + 1u, stopped);
+            return __all(all_done());
+        };
+        // entries k and k + 1 with their row terms given
+        auto entry2_rt = [&](int k, float nba, float hca, float nbb, float hcb) -> bool {
+            float4 oa, ob;
+            float pa[PPL], pb[PPL];
+            bool acta[PPL], actb[PPL];
+            bool any = test_rt(k, nba, hca, oa, pa, acta);
+            any = test_rt(k + 1, nbb, hcb, ob, pb, actb) || any;
+            if (!__any(any)) return false;
+            bool stopped[PPL];
+            composite(oa, col[k], pa, acta, idx0 + (uint32_t)k + 1u, stopped);
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) actb[q] = actb[q] && !stopped[q];   // a pixel may have stopped at k
+            composite(ob, col[k + 1], pb, actb, idx0 + (uint32_t)k + 2u, stopped);
+            return __all(all_done());
+        };
+        // one list entry k of the batch; returns true when the whole wave has stopped
+        auto entry = [&](int k) -> bool {
+            float4 o;
+            float p[PPL];
+            bool act[PPL];
+            bool any = test(k, o, p, act);
             // branch only when the whole wave agrees; per pixel, select
             if (!__any(any)) return false;
             bool stopped[PPL];
-            composite(o, s_col[k], p, act, idx0 + (uint32_t)k + 1u, stopped);
+            composite(o, col[k], p, act, idx0 + (uint32_t)k + 1u, stopped);
             return __all(all_done());
         };
         // entries k and k + 1: both tests first (independent), one uniform
         // branch for the pair, then the two composites in list order
         auto entry2 = [&](int k) -> bool {
-            float4 ga, oa, gb, ob;
+            float4 oa, ob;
             float pa[PPL], pb[PPL];
             bool acta[PPL], actb[PPL];
-            bool any = test(k, ga, oa, pa, acta);
-            any = test(k + 1, gb, ob, pb, actb) || any;
+            bool any = test(k, oa, pa, acta);
+            any = test(k + 1, ob, pb, actb) || any;
             if (!__any(any)) return false;
             bool stopped[PPL];
-            composite(oa, s_col[k], pa, acta, idx0 + (uint32_t)k + 1u, stopped);
+            composite(oa, col[k], pa, acta, idx0 + (uint32_t)k + 1u, stopped);
 #pragma unroll
             for (int q = 0; q < PPL; ++q) actb[q] = actb[q] && !stopped[q];   // a pixel may have stopped at k
-            composite(ob, s_col[k + 1], pb, actb, idx0 + (uint32_t)k + 2u, stopped);
+            composite(ob, col[k + 1], pb, actb, idx0 + (uint32_t)k + 2u, stopped);
             return __all(all_done());
         };
         if (kSkip) {
@@ -207,7 +290,11 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
                 }
             }
         } else {
-            if (all_done()) continue;
+            // a lane whose pixels have all stopped sits the batch out, except
+            // with shared row terms: there every lane of a row is a source of
+            // the broadcasts, so the wave walks on until all of it has
+            // stopped (a stopped pixel's test rejects every entry by itself)
+            if (XROW ? __all(all_done()) : all_done()) continue;
             // whether the whole wave has stopped is asked once per 8 pairs:
             // after that, entries find no active pixel and only run the
             // tests, which is cheaper than the vote on every pair
@@ -215,9 +302,54 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
             int k = 0;
             constexpr int kPairsPerCheck = 8;
             for (; k + 2 * kPairsPerCheck - 1 < cnt; k += 2 * kPairsPerCheck) {
+                if constexpr (XROW) {
+                    // The row terms of an entry are the same for the LX lanes
+                    // of one tile row: lane lx of the row computes them for
+                    // entries k + c LX + lx, and a swizzle within each group of
+                    // LX lanes hands entry k + c LX + j's terms from lane j to
+                    // the group.  Same values, one lane computing each.
+                    constexpr int kChunks = 2 * kPairsPerCheck / LX;
+                    float tnb[kChunks], thc[kChunks];
 #pragma unroll
-                for (int c = 0; c < kPairsPerCheck - 1; ++c) entry2(k + 2 * c);
-                if (entry2(k + 2 * (kPairsPerCheck - 1))) { finished = true; break; }
+                    for (int c = 0; c < kChunks; ++c) {
+                        int e = k + c * LX + lx;
+                        float4 gg = geo[e];
+                        float ox = opa[e].x;
+                        float dy = gg.y - fy;
+                        tnb[c] = gg.w * dy;
+                        thc[c] = (ox * dy) * dy;
+                    }
+                    constexpr int kAnd = 0x1F & ~(LX - 1);
+                    bool fin = false;
+                    if constexpr (XROW == 1) {
+                        // entries in pairs: both tests, one branch
+#pragma unroll
+                        for (int c = 0; c < kPairsPerCheck; ++c) {
+                            int e0 = 2 * c, e1 = 2 * c + 1;
+                            float nba = bcast_lane<kAnd>(tnb[e0 / LX], e0 % LX);
+                            float hca = bcast_lane<kAnd>(thc[e0 / LX], e0 % LX);
+                            float nbb = bcast_lane<kAnd>(tnb[e1 / LX], e1 % LX);
+                            float hcb = bcast_lane<kAnd>(thc[e1 / LX], e1 % LX);
+                            bool done = entry2_rt(k + e0, nba, hca, nbb, hcb);
+                            if (c == kPairsPerCheck - 1) fin = done;
+                        }
+                    } else {
+                        // one branch per entry: no composite for an entry
+                        // that no pixel of the wave passes
+#pragma unroll
+                        for (int e = 0; e < 2 * kPairsPerCheck; ++e) {
+                            float nb = bcast_lane<kAnd>(tnb[e / LX], e % LX);
+                            float hc = bcast_lane<kAnd>(thc[e / LX], e % LX);
+                            bool done = entry_rt(k + e, nb, hc);
+                            if (e == 2 * kPairsPerCheck - 1) fin = done;
+                        }
+                    }
+                    if (fin) { finished = true; break; }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < kPairsPerCheck - 1; ++c) entry2(k + 2 * c);
+                    if (entry2(k + 2 * (kPairsPerCheck - 1))) { finished = true; break; }
+                }
             }
             for (; !finished && k + 1 < cnt; k += 2)
                 if (entry2(k)) { finished = true; break; }
@@ -245,7 +377,7 @@ __device__ __forceinline__ void render_tile(int tile, int W, int H, int tiles_x,
 // that do not ask for them.  Workgroup i takes tile order[i]
 // (qb_tile_order), or tile i when order is NULL; an entry past the last tile
 // is skipped.
-template <int PPL, bool COUNT, bool SKIP>
+template <int PPL, bool COUNT, bool SKIP, int XROW>
 __global__ __launch_bounds__(256 / PPL) void k_render(
     int W, int H, int tiles_x, const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ splats, float bg0, float bg1, float bg2, float* __restrict__ image,
@@ -254,14 +386,14 @@ __global__ __launch_bounds__(256 / PPL) void k_render(
 {
     uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     if (tile >= gridDim.x) return;
-    render_tile<PPL, COUNT, SKIP>((int)tile, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T,
+    render_tile<PPL, COUNT, SKIP, XROW>((int)tile, W, H, tiles_x, ranges, ids, splats, bg0, bg1, bg2, image, final_T,
                                   n_contrib, n_touched, n_composited);
 }
 
 // Every tile of every view in one launch: workgroup i takes global tile
 // order[i] (or i), whose view is found in the (at most QB_MAX_VIEWS) tile
 // offsets.
-template <int PPL, bool SKIP>
+template <int PPL, bool SKIP, int XROW>
 __global__ __launch_bounds__(256 / PPL) void k_render_views(QbViewTable vt, const uint32_t* __restrict__ order,
                                                             float bg0, float bg1, float bg2)
 {
@@ -270,7 +402,7 @@ __global__ __launch_bounds__(256 / PPL) void k_render_views(QbViewTable vt, cons
     int b = (int)g;
     int v = qb_view_of(vt, b);
     const qb_view& w = vt.view[v];
-    render_tile<PPL, false, SKIP>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
+    render_tile<PPL, false, SKIP, XROW>(b - vt.tile_start[v], w.width, w.height, vt.tiles_x[v], reinterpret_cast<const uint2*>(w.ranges),
                      w.ids, reinterpret_cast<const float4*>(w.splats), bg0, bg1, bg2, w.image, w.final_T, w.n_contrib,
                      nullptr, nullptr);
 }
@@ -284,18 +416,20 @@ static qb_status launch_render(int variant, int64_t tiles, hipStream_t s, int W,
                                float* final_T, uint32_t* n_contrib, uint32_t* n_touched, uint32_t* n_composited,
                                const uint32_t* order)
 {
+#define QB_RENDER_LAUNCH(P, SK, XR)                                                                      \
+    QB_LAUNCH((k_render<P, COUNT, SK, XR>), tiles, 256 / P, 0, s, W, H, tiles_x, rg, ids, sp, bg[0], bg[1], bg[2], \
+              image, final_T, n_contrib, n_touched, n_composited, order)
     switch (variant) {
-    case QB_RENDER_2PX: QB_LAUNCH((k_render<2, COUNT, false>), tiles, 128, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
-                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, n_composited, order); break;
-    case QB_RENDER_1PX: QB_LAUNCH((k_render<1, COUNT, false>), tiles, 256, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
-                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, n_composited, order); break;
-    case QB_RENDER_4PX: QB_LAUNCH((k_render<4, COUNT, false>), tiles, 64, 0, s, W, H, tiles_x, rg, ids, sp, bg[0],
-                                  bg[1], bg[2], image, final_T, n_contrib, n_touched, n_composited, order); break;
-    case QB_RENDER_2PX_ROWS: QB_LAUNCH((k_render<2, COUNT, true>), tiles, 128, 0, s, W, H, tiles_x, rg, ids, sp,
-                                       bg[0], bg[1], bg[2], image, final_T, n_contrib, n_touched, n_composited, order); break;
-    default: QB_LAUNCH((k_render<1, COUNT, true>), tiles, 256, 0, s, W, H, tiles_x, rg, ids, sp, bg[0], bg[1],
-                       bg[2], image, final_T, n_contrib, n_touched, n_composited, order); break;
+    case QB_RENDER_2PX: QB_RENDER_LAUNCH(2, false, 0); break;
+    case QB_RENDER_1PX: QB_RENDER_LAUNCH(1, false, 0); break;
+    case QB_RENDER_4PX: QB_RENDER_LAUNCH(4, false, 0); break;
+    case QB_RENDER_2PX_ROWS: QB_RENDER_LAUNCH(2, true, 0); break;
+    case QB_RENDER_1PX_ROWS: QB_RENDER_LAUNCH(1, true, 0); break;
+    case QB_RENDER_2PX_XROW: QB_RENDER_LAUNCH(2, false, 1); break;
+    case QB_RENDER_4PX_XROW: QB_RENDER_LAUNCH(4, false, 1); break;
+    default: QB_RENDER_LAUNCH(2, false, 2); break;
     }
+#undef QB_RENDER_LAUNCH
     return QB_OK;
 }
 
@@ -354,13 +488,19 @@ extern "C" qb_status qb_render_views_ex(int32_t num_views, const qb_view* views,
     int tiles = vt.tile_start[num_views];
     if (tiles == 0) return QB_OK;
     hipStream_t s = qb_hip_stream(stream);
+#define QB_RENDER_VIEWS(P, SK, XR) \
+    QB_LAUNCH((k_render_views<P, SK, XR>), tiles, 256 / P, 0, s, vt, tile_order, bg[0], bg[1], bg[2])
     switch (variant) {
-    case QB_RENDER_2PX: QB_LAUNCH((k_render_views<2, false>), tiles, 128, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
-    case QB_RENDER_1PX: QB_LAUNCH((k_render_views<1, false>), tiles, 256, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
-    case QB_RENDER_4PX: QB_LAUNCH((k_render_views<4, false>), tiles, 64, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
-    case QB_RENDER_2PX_ROWS: QB_LAUNCH((k_render_views<2, true>), tiles, 128, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
-    default: QB_LAUNCH((k_render_views<1, true>), tiles, 256, 0, s, vt, tile_order, bg[0], bg[1], bg[2]); break;
+    case QB_RENDER_2PX: QB_RENDER_VIEWS(2, false, 0); break;
+    case QB_RENDER_1PX: QB_RENDER_VIEWS(1, false, 0); break;
+    case QB_RENDER_4PX: QB_RENDER_VIEWS(4, false, 0); break;
+    case QB_RENDER_2PX_ROWS: QB_RENDER_VIEWS(2, true, 0); break;
+    case QB_RENDER_1PX_ROWS: QB_RENDER_VIEWS(1, true, 0); break;
+    case QB_RENDER_2PX_XROW: QB_RENDER_VIEWS(2, false, 1); break;
+    case QB_RENDER_4PX_XROW: QB_RENDER_VIEWS(4, false, 1); break;
+    default: QB_RENDER_VIEWS(2, false, 2); break;
     }
+#undef QB_RENDER_VIEWS
     return QB_OK;
 }
 

@@ -25,8 +25,12 @@ RECT_SHORTS = 16    # qb_rects: 4 x (tx0, tx1, ty0, ty1)
 
 QB_OK, QB_ERR_INVALID_ARG, QB_ERR_CAPACITY, QB_ERR_HIP, QB_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 # render launch shapes (qb_render_variant): pixels per lane of a tile row, and
-# (_rows) whether waves drop batch entries whose ellipse misses their rows
-RENDER_VARIANTS = {"2px": 0, "1px": 1, "4px": 2, "2px_rows": 3, "1px_rows": 4}
+# (_rows) whether waves drop batch entries whose ellipse misses their rows,
+# (_xrow) whether the row terms of the quadratic form are computed by one lane
+# per tile row and shared with the row's other lanes, (_xrow1) the same with
+# one branch per entry instead of one per pair of entries
+RENDER_VARIANTS = {"2px": 0, "1px": 1, "4px": 2, "2px_rows": 3, "1px_rows": 4, "2px_xrow": 5, "4px_xrow": 6,
+                   "2px_xrow1": 7}
 BACKWARD_VARIANTS = {"2px": 0, "1px": 1, "4px": 2}
 # tile-sort radix workgroups (qb_sort_variant): lanes x pairs per lane, and
 # two digit-width variants of 512 x 8 (first pass 2 bits narrower / wider)
@@ -35,7 +39,7 @@ SORT_VARIANTS = {"512x8": 0, "1024x8": 1, "512x16": 2, "256x16": 3, "512x8_narro
 # qb_intersect's depth-sort radix workgroups (qb_depth_variant) and emission
 # workgroup sizes (qb_emit_variant)
 DEPTH_VARIANTS = {"512x4": 0, "256x8": 1, "512x8": 2, "1024x4": 3}
-EMIT_VARIANTS = {"256": 0, "128": 1, "512": 2}
+EMIT_VARIANTS = {"256": 0, "128": 1, "512": 2, "256x2": 3, "128x2": 4}
 
 
 class QBError(RuntimeError):
@@ -73,11 +77,13 @@ def lib():
     vp, i64, i32, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
     L.qb_project.argtypes = [i64, vp, vp, vp, vp, vp, i32, C.POINTER(CCamera), i32, vp, vp, vp, vp]
     L.qb_project.restype = i32
+    L.qb_project_ex.argtypes = [i64, vp, vp, vp, vp, vp, i32, C.POINTER(CCamera), i32, vp, vp, vp, vp, vp]
+    L.qb_project_ex.restype = i32
     L.qb_intersect_workspace_size.argtypes = [i64]
     L.qb_intersect_workspace_size.restype = sz
     L.qb_intersect.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz, vp]
     L.qb_intersect.restype = i32
-    L.qb_intersect_ex.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz, i32, i32, vp]
+    L.qb_intersect_ex.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz, vp, i32, i32, vp]
     L.qb_intersect_ex.restype = i32
     L.qb_sort_ex.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp]
     L.qb_sort_ex.restype = i32
@@ -101,6 +107,8 @@ def lib():
     pc = C.POINTER(CCamera)
     L.qb_project_views.argtypes = [i64, vp, vp, vp, vp, vp, i32, pc, i32, i32, vp, vp, vp, vp]
     L.qb_project_views.restype = i32
+    L.qb_project_views_ex.argtypes = [i64, vp, vp, vp, vp, vp, i32, pc, i32, i32, vp, vp, vp, vp, vp]
+    L.qb_project_views_ex.restype = i32
     L.qb_render_views.argtypes = [i32, C.POINTER(CView), vp, vp]
     L.qb_render_views.restype = i32
     L.qb_render_views_ex.argtypes = [i32, C.POINTER(CView), vp, i32, vp, vp]
@@ -203,11 +211,15 @@ class Gaussians:
 
 # ---- one call per ABI entry point --------------------------------------------
 
-def project(g: Gaussians, cam, mode, splats, rects, counts):
+def project(g: Gaussians, cam, mode, splats, rects, counts, depth_keys=None):
+    """qb_project_ex: with depth_keys ([n] int32 tensor) the depth-sort keys
+    are written as well (qb_intersect's depth_keys)."""
     _need(min(_rows(splats), _rows(rects), _rows(counts)) >= g.n, "qb_project: output buffers hold fewer than n rows")
-    _check("qb_project", lib().qb_project(
+    _need(depth_keys is None or _rows(depth_keys) >= g.n, "qb_project_ex: depth_keys holds fewer than n entries")
+    _check("qb_project_ex", lib().qb_project_ex(
         g.n, _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats), _ptr(g.logits), _ptr(g.sh), g.sh_degree,
-        C.byref(camera_struct(cam)), _mode(mode), _ptr(splats), _ptr(rects), _ptr(counts), _stream()))
+        C.byref(camera_struct(cam)), _mode(mode), _ptr(splats), _ptr(rects), _ptr(counts), _ptr(depth_keys),
+        _stream()))
 
 
 def intersect_workspace_size(n: int) -> int:
@@ -215,14 +227,17 @@ def intersect_workspace_size(n: int) -> int:
 
 
 def intersect(n, splats, rects, counts, width, height, capacity, pair_tiles, pair_ids, num_pairs, ws,
-              mode="quadbox", depth_variant=0, emit_variant=0):
+              mode="quadbox", depth_variant=0, emit_variant=0, depth_keys=None):
+    """qb_intersect_ex; depth_keys: the keys qb_project_ex wrote for this
+    projection, or None to derive them from the splats."""
     _need(min(_rows(splats), _rows(rects), _rows(counts)) >= n, "qb_intersect: inputs hold fewer than n rows")
+    _need(depth_keys is None or _rows(depth_keys) >= n, "qb_intersect_ex: depth_keys holds fewer than n entries")
     _need(capacity == 0 or min(_rows(pair_tiles), _rows(pair_ids)) >= capacity,
           "qb_intersect: pair buffers hold fewer than capacity entries")
     _check("qb_intersect_ex", lib().qb_intersect_ex(
         n, _ptr(splats), _ptr(rects), _ptr(counts), width, height, _mode(mode), capacity, _ptr(pair_tiles),
-        _ptr(pair_ids), _ptr(num_pairs), _ptr(ws), ws.numel() * ws.element_size(), int(depth_variant),
-        int(emit_variant), _stream()))
+        _ptr(pair_ids), _ptr(num_pairs), _ptr(ws), ws.numel() * ws.element_size(), _ptr(depth_keys),
+        int(depth_variant), int(emit_variant), _stream()))
 
 
 # QB_NOALLOC_MAX_GAUSSIANS: the largest n qb_intersect_noalloc accepts
@@ -341,6 +356,7 @@ class Rasterizer:
         self.splats = torch.empty((max(n, 1), SPLAT_FLOATS), dtype=torch.float32, device=d)
         self.rects = torch.empty((max(n, 1), RECT_SHORTS), dtype=torch.int16, device=d)
         self.counts = torch.empty(max(n, 1), dtype=torch.int32, device=d)
+        self.depth_keys = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.num_pairs = torch.zeros(1, dtype=torch.int64, device=d)
         self.ws_isect = torch.empty(intersect_workspace_size(n), dtype=torch.uint8, device=d)
         self.ranges = torch.empty((self.num_tiles, 2), dtype=torch.int32, device=d)
@@ -373,12 +389,13 @@ class Rasterizer:
 
     def project(self, g: Gaussians, mode):
         _need(g.n == self.n, f"{g.n} Gaussians given to a rasterizer sized for {self.n}")
-        project(g, self.cam, mode, self.splats, self.rects, self.counts)
+        project(g, self.cam, mode, self.splats, self.rects, self.counts, self.depth_keys)
         self.mode = mode
 
     def intersect(self):
         intersect(self.n, self.splats, self.rects, self.counts, self.W, self.H, self.capacity, self.pair_tiles,
-                  self.pair_ids, self.num_pairs, self.ws_isect, self.mode, self.depth_variant, self.emit_variant)
+                  self.pair_ids, self.num_pairs, self.ws_isect, self.mode, self.depth_variant, self.emit_variant,
+                  self.depth_keys)
 
     def sort(self):
         sort(self.capacity, self.num_pairs, self.num_tiles, self.pair_tiles, self.pair_ids, self.splats,
@@ -474,10 +491,11 @@ def rasterize(means, log_scales, quats, logits, sh, cam, mode="quadbox", bg=(0.0
 
 # ---- several views of one Gaussian set -----------------------------------------
 
-def project_views(g: Gaussians, cam_array, num_views, mode, splats, rects, counts):
-    _check("qb_project_views", lib().qb_project_views(
+def project_views(g: Gaussians, cam_array, num_views, mode, splats, rects, counts, depth_keys=None):
+    """qb_project_views_ex (depth_keys: [num_views][n] int32, or None)."""
+    _check("qb_project_views_ex", lib().qb_project_views_ex(
         g.n, _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats), _ptr(g.logits), _ptr(g.sh), g.sh_degree, cam_array,
-        num_views, _mode(mode), _ptr(splats), _ptr(rects), _ptr(counts), _stream()))
+        num_views, _mode(mode), _ptr(splats), _ptr(rects), _ptr(counts), _ptr(depth_keys), _stream()))
 
 
 def tile_order_views(view_array, num_views, work, order):
@@ -532,6 +550,7 @@ class MultiView:
         self.splats = torch.empty((V, n1, SPLAT_FLOATS), dtype=torch.float32, device=d)
         self.rects = torch.empty((V, n1, RECT_SHORTS), dtype=torch.int16, device=d)
         self.counts = torch.empty((V, n1), dtype=torch.int32, device=d)
+        self.depth_keys = torch.empty((V, n1), dtype=torch.int32, device=d)
         self.num_pairs = torch.zeros(V, dtype=torch.int64, device=d)
         self.ws_isect = [torch.empty(intersect_workspace_size(n), dtype=torch.uint8, device=d) for _ in range(self.S)]
         self.sizes = [(int(c.width), int(c.height)) for c in cams]
@@ -565,7 +584,7 @@ class MultiView:
         cap = self.capacity[v]
         intersect(self.n, s, r, c, w, h, cap, self.pair_tiles[v] if cap else None,
                   self.pair_ids[v] if cap else None, npairs, self.ws_isect[v % self.S], self.mode,
-                  self.depth_variant, self.emit_variant)
+                  self.depth_variant, self.emit_variant, self.depth_keys[v])
 
     def _sort(self, v):
         sort(self.capacity[v], self.num_pairs[v:v + 1], self.num_tiles[v], self.pair_tiles[v], self.pair_ids[v],
@@ -586,7 +605,7 @@ class MultiView:
         _need(g.n == self.n, f"{g.n} Gaussians given to a MultiView sized for {self.n}")
         self.mode = mode
         self.capacity = [0] * self.V
-        project_views(g, self.cam_array, self.V, mode, self.splats, self.rects, self.counts)
+        project_views(g, self.cam_array, self.V, mode, self.splats, self.rects, self.counts, self.depth_keys)
         for v in range(self.V):
             self._intersect(v)
         counts = self.num_pairs.cpu().tolist()
@@ -643,7 +662,7 @@ class MultiView:
         if self._table is None:
             raise RuntimeError("call size_pairs() first")
         _need(g.n == self.n, f"{g.n} Gaussians given to a MultiView sized for {self.n}")
-        project_views(g, self.cam_array, self.V, self.mode, self.splats, self.rects, self.counts)
+        project_views(g, self.cam_array, self.V, self.mode, self.splats, self.rects, self.counts, self.depth_keys)
 
         def prep(v):
             self._intersect(v)

@@ -60,6 +60,11 @@ def test_project_rejects_bad_arguments():
     assert L.qb_project(4, None, dummy, dummy, dummy, dummy, 0, C.byref(cam), 2, dummy, dummy, dummy,
                         None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_project(0, None, None, None, None, None, 0, C.byref(cam), 2, None, None, None, None) == qb.QB_OK
+    # qb_project_ex checks the same arguments (the keys pointer may be NULL)
+    for kw in (dict(n=-1), dict(deg=4), dict(mode=7), dict(c=_cam(w=0))):
+        assert L.qb_project_ex(*args(**kw)[:-1], dummy, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_project_ex(0, None, None, None, None, None, 0, C.byref(cam), 2, None, None, None, None,
+                           None) == qb.QB_OK
 
 
 def test_intersect_sort_render_reject_bad_arguments():
@@ -117,8 +122,11 @@ def test_activations_and_shape_entry_points_reject_bad_arguments():
     assert L.qb_activations(4, None, 0, d, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_activations(0, None, 0, None, None) == qb.QB_OK   # nothing to do, nothing launched
     ws = qb.intersect_workspace_size(10)
-    for dv, ev in ((4, 0), (-1, 0), (0, 3), (0, -1)):
-        assert L.qb_intersect_ex(10, d, d, d, 64, 48, 2, 100, d, d, d, d, ws, dv, ev, None) == qb.QB_ERR_INVALID_ARG
+    for dv, ev in ((4, 0), (-1, 0), (0, 5), (0, -1)):
+        assert L.qb_intersect_ex(10, d, d, d, 64, 48, 2, 100, d, d, d, d, ws, None, dv, ev, None) == \
+            qb.QB_ERR_INVALID_ARG
+        assert L.qb_intersect_ex(10, d, d, d, 64, 48, 2, 100, d, d, d, d, ws, d, dv, ev, None) == \
+            qb.QB_ERR_INVALID_ARG
     sws = qb.sort_workspace_size(100)
     for v in (-1, 6):
         assert L.qb_sort_ex(100, d, 12, d, d, d, None, C.c_void_p(512), d, d, sws, v, None) == qb.QB_ERR_INVALID_ARG
@@ -130,7 +138,8 @@ def test_launch_shape_and_view_entry_points_reject_bad_arguments():
     bg = (C.c_float * 3)(0.0, 0.0, 0.0)
     bgp = C.cast(bg, C.c_void_p)
     # launch shapes out of range
-    assert L.qb_render_ex(64, 48, d, d, d, bgp, d, None, None, None, 5, None, None) == qb.QB_ERR_INVALID_ARG
+    nv = len(qb.RENDER_VARIANTS)   # QB_RENDER_VARIANTS: one past the last launch shape
+    assert L.qb_render_ex(64, 48, d, d, d, bgp, d, None, None, None, nv, None, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_render_ex(64, 48, d, d, d, bgp, d, None, None, None, -1, None, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_render_backward_ex(64, 48, d, d, d, bgp, d, d, d, 10, d, 3, None, None) == qb.QB_ERR_INVALID_ARG
     # view tables: count, null table, bad sizes, missing buffers
@@ -141,7 +150,7 @@ def test_launch_shape_and_view_entry_points_reject_bad_arguments():
     assert L.qb_render_views(0, views, bgp, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_render_views(qb.MAX_VIEWS + 1, views, bgp, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_render_views(1, None, bgp, None) == qb.QB_ERR_INVALID_ARG
-    assert L.qb_render_views_ex(1, views, bgp, 9, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_views_ex(1, views, bgp, nv, None, None) == qb.QB_ERR_INVALID_ARG
     views[1].width = 0
     assert L.qb_render_views(2, views, bgp, None) == qb.QB_ERR_INVALID_ARG
     views[1].width = 64

@@ -386,7 +386,8 @@ def test_clip_3sigma_image_equals_3sigma_on_gpu(oracle, qb):
 
 def test_intersect_and_sort_launch_shapes(oracle, qb):
     """Every depth-sort and emission shape of qb_intersect_ex writes the same
-    pairs in the same order, and every tile-sort shape of qb_sort_ex gives
+    pairs in the same order, with the depth keys of qb_project_ex and with
+    keys derived from the splats, and every tile-sort shape of qb_sort_ex gives
     the same sorted list and ranges: on the 10k-Gaussian scene against the
     oracle, on the 1M-Gaussian clustered scene against the default shapes
     (bit for bit)."""
@@ -406,16 +407,24 @@ def test_intersect_and_sort_launch_shapes(oracle, qb):
             assert np.array_equal(want_keys.cpu().numpy().view(np.uint64), ref["keys"])
             assert np.array_equal(want_ids.cpu().numpy().view(np.uint32), ref["ids"])
             assert np.array_equal(want_ranges.cpu().numpy().view(np.uint32), ref["ranges"])
+        # the projection's depth keys: the depth's bits where the Gaussian
+        # has tiles, else 0xFFFFFFFF
+        depth_bits = r.splats[:scene.n, 2].contiguous().view(torch.int32)
+        assert torch.equal(r.depth_keys[:scene.n],
+                           torch.where(r.counts[:scene.n] > 0, depth_bits, torch.full_like(depth_bits, -1)))
         for dn, dv in qb.DEPTH_VARIANTS.items():
             for en, ev in qb.EMIT_VARIANTS.items():
-                r.pair_tiles.fill_(-1)
-                r.pair_ids.fill_(-1)
-                r.depth_variant, r.emit_variant = dv, ev
-                r.intersect()
-                torch.cuda.synchronize()
-                assert r.pairs() == P
-                assert torch.equal(r.pair_tiles[:P], want_t), (scene.n, dn, en)
-                assert torch.equal(r.pair_ids[:P], want_i), (scene.n, dn, en)
+                for keys in (r.depth_keys, None):
+                    r.pair_tiles.fill_(-1)
+                    r.pair_ids.fill_(-1)
+                    r.num_pairs.fill_(-1)
+                    qb.intersect(scene.n, r.splats, r.rects, r.counts, r.W, r.H, r.capacity, r.pair_tiles,
+                                 r.pair_ids, r.num_pairs, r.ws_isect, "quadbox", dv, ev, keys)
+                    torch.cuda.synchronize()
+                    tag = (scene.n, dn, en, keys is None)
+                    assert r.pairs() == P, tag
+                    assert torch.equal(r.pair_tiles[:P], want_t), tag
+                    assert torch.equal(r.pair_ids[:P], want_i), tag
         for sn, sv in qb.SORT_VARIANTS.items():
             r.ids_sorted.fill_(-1)
             r.keys_sorted.fill_(-1)
