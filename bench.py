@@ -244,6 +244,10 @@ def run_fwd_bwd(torch, qb, g, cam, steps, warmup, trials):
     grads = [torch.empty_like(t) for t in g.tensors()]
     inv = 1.0 / float(target.numel())
     r.forward(g, "quadbox", sync_count=False)
+    qb.autotune_intersect(r, reps=3, trials=2)
+    qb.autotune_sort(r, reps=3, trials=2)
+    qb.autotune_render(r, reps=5, trials=2)
+    r.forward(g, "quadbox", sync_count=False)
     qb.autotune_backward(r, dl=torch.sign(r.image - target) * inv, grad2d=grad2d, reps=3, trials=2)
 
     def step():
@@ -473,15 +477,16 @@ def alu_roofline(flops, ms, kernel, work, traffic=None, note=None):
 def stage_bytes(n, sh_degree, pairs):
     """Bytes each HBM-bound stage moves by its design, per frame:
     project: the SoA inputs (12 + 12 + 16 + 4 + 12 (d+1)^2 B) read, the 48-byte
-      record, 32-byte rects and the count written, per Gaussian;
-    intersect: depth keys (8 B read, 8 written), 4 depth-sort passes (8 B read
-      and written, 4 B upsweep read), the count gather (8 B), the offset scan
-      (4 B read, 8 written), the emission's reads (rects 32 B, order, count,
-      offset 16 B) per Gaussian, and 6 B written per pair;
+      record, 32-byte rects, the count and the 4-byte depth key written, per
+      Gaussian;
+    intersect: 4 depth-sort passes over the projection's keys (8 B read and
+      written, 4 B upsweep read), the count gather (8 B), the offset scan (4 B
+      read, 8 written), the emission's reads (rects 32 B, order, count, offset
+      16 B) per Gaussian, and 6 B written per pair;
     sort: 2 tile passes of 6 B read and written plus a 2-byte upsweep read,
       per pair."""
-    proj = n * (44 + 12 * (sh_degree + 1) ** 2 + 84)
-    isect = n * (16 + 4 * 20 + 8 + 12 + 48) + pairs * 6
+    proj = n * (44 + 12 * (sh_degree + 1) ** 2 + 88)
+    isect = n * (4 * 20 + 8 + 12 + 48) + pairs * 6
     sort = pairs * 28
     return {"project": proj, "intersect": isect, "sort": sort}
 

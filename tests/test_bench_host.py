@@ -87,14 +87,15 @@ def test_flops_and_roofline_arithmetic():
 
 
 def test_stage_bytes():
-    """Design bytes per frame: project 44 + 12 (d+1)^2 B of inputs and 84 B
-    of outputs per Gaussian; intersect 164 B per Gaussian and 6 B per pair;
-    sort 28 B per pair (two passes)."""
+    """Design bytes per frame: project 44 + 12 (d+1)^2 B of inputs and 88 B
+    of outputs (record, rects, count, depth key) per Gaussian; intersect
+    148 B per Gaussian (the depth sort takes the projection's keys) and 6 B
+    per pair; sort 28 B per pair (two passes)."""
     b = bench.stage_bytes(1_000_000, 3, 26_492_435)
-    assert b["project"] == 1_000_000 * (44 + 192 + 84)
-    assert b["intersect"] == 1_000_000 * 164 + 26_492_435 * 6
+    assert b["project"] == 1_000_000 * (44 + 192 + 88)
+    assert b["intersect"] == 1_000_000 * 148 + 26_492_435 * 6
     assert b["sort"] == 26_492_435 * 28
-    assert bench.stage_bytes(10, 0, 0)["project"] == 10 * (44 + 12 + 84)
+    assert bench.stage_bytes(10, 0, 0)["project"] == 10 * (44 + 12 + 88)
 
 
 def test_peaks():
