@@ -1,8 +1,9 @@
 // qb_intersect: DuplicateWithKeys with the QPass traversal (Sec. 2, Sec. 3.2).
 //
 //  1. key every Gaussian by its depth bits (0xFFFFFFFF when it covers no
-//     tile) and stable-radix-sort the ids: the (depth, id) order that orders
-//     the Gaussians within every tile
+//     tile; qb_project_ex writes these keys, else they are derived here from
+//     the splats and counts) and stable-radix-sort the ids: the (depth, id)
+//     order that orders the Gaussians within every tile
 //  2. gather the tile counts in that order (in the sort's last pass) and
 //     scan them: the pair offsets and the total
 //  3. emit: a 256-lane workgroup takes 256 consecutive Gaussians of that

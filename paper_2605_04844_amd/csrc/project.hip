@@ -4,7 +4,8 @@
 //
 // One lane per Gaussian; inputs are structure-of-arrays so every plane is read
 // with coalesced 256-byte wave accesses, outputs are 48-byte records and
-// 32-byte rect sets written as 16-byte vectors.  The work is HBM-bound (236 B
+// 32-byte rect sets written as 16-byte vectors (qb_project_ex also writes
+// each Gaussian's 4-byte depth-sort key).  The work is HBM-bound (236 B
 // read per SH3 Gaussian), so the arithmetic follows the fixed binary32
 // operation order that makes keys reproducible: no contraction (the library is
 // built with -ffp-contract=off), correctly rounded divide/sqrt, and the three
