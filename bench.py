@@ -225,6 +225,7 @@ def run_mode(torch, qb, g, cam, mode, steps, warmup, trials, extras=True):
                 render_launch_ms=render_launch_ms, render_rowmajor_ms=rowmajor_ms, sync_ms=sync_ms,
                 stage_launch_ms=stage_launch, work=work, rast=r,
                 render_shape=names[r.render_variant], shape_ms={k: round(v, 4) for k, v in shapes.items()},
+                packed=r.packed_id_bits() > 0,
                 sort_shape=snames[r.sort_variant], sort_shape_ms={k: round(v, 4) for k, v in sort_shapes.items()},
                 intersect_shape=f"{dnames[r.depth_variant]}/{enames[r.emit_variant]}",
                 intersect_shape_ms={k: round(v, 4) for k, v in isect_shapes.items()})
@@ -474,7 +475,7 @@ def alu_roofline(flops, ms, kernel, work, traffic=None, note=None):
     return out
 
 
-def stage_bytes(n, sh_degree, pairs):
+def stage_bytes(n, sh_degree, pairs, packed=False):
     """Bytes each HBM-bound stage moves by its design, per frame:
     project: the SoA inputs (12 + 12 + 16 + 4 + 12 (d+1)^2 B) read, the 48-byte
       record, 32-byte rects, the count and the 4-byte depth key written, per
@@ -484,10 +485,14 @@ def stage_bytes(n, sh_degree, pairs):
       read, 8 written), the emission's reads (rects 32 B, order, count, offset
       16 B) per Gaussian, and 6 B written per pair;
     sort: 2 tile passes of 6 B read and written plus a 2-byte upsweep read,
-      per pair."""
+      per pair.
+    With packed pairs (tile << id_bits | id in 4 bytes) the emission writes
+    4 B per pair and the sort reads 4 B per pair in each pass's upsweep and
+    downsweep, writes 4 B in the first pass and 6 B (tile and id apart) in
+    the last: 26 B per pair."""
     proj = n * (44 + 12 * (sh_degree + 1) ** 2 + 88)
-    isect = n * (4 * 20 + 8 + 12 + 48) + pairs * 6
-    sort = pairs * 28
+    isect = n * (4 * 20 + 8 + 12 + 48) + pairs * (4 if packed else 6)
+    sort = pairs * (26 if packed else 28)
     return {"project": proj, "intersect": isect, "sort": sort}
 
 
@@ -495,7 +500,7 @@ def stage_bandwidth(q, g, copy_gbs):
     """Achieved bandwidth of the HBM-bound stages (design bytes over the
     stage's back-to-back launch time) against the 8 TB/s peak and the
     measured device-copy rate."""
-    b = stage_bytes(g.n, g.sh_degree, q["pairs"])
+    b = stage_bytes(g.n, g.sh_degree, q["pairs"], q["packed"])
     out = {}
     for k, ms in q["stage_launch_ms"].items():
         if k not in b:
@@ -725,6 +730,7 @@ def main():
                                              if r["render_rowmajor_ms"] is not None else None),
                       "ms_with_count_readback": round(r["sync_ms"], 4) if r["sync_ms"] is not None else None,
                       "render_shape": r["render_shape"], "render_shape_ms": r["shape_ms"],
+                      "pair_format": "packed" if r["packed"] else "split",
                       "sort_shape": r["sort_shape"], "sort_shape_ms": r["sort_shape_ms"],
                       "intersect_shape": r["intersect_shape"], "intersect_shape_ms": r["intersect_shape_ms"],
                       **image_delta(torch, r["rast"].image, q["rast"].image)}

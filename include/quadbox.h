@@ -219,17 +219,28 @@ typedef enum {
     QB_EMIT_VARIANTS = 5
 } qb_emit_variant;
 
+/* qb_pair_id_bits -- the id width of packed pairs for n Gaussians on a
+ * width x height image: ceil(log2(n)) (at least 1) when that many id bits and
+ * the tile id's bits fit 32 bits together, else 0 (pairs cannot be packed). */
+int32_t qb_pair_id_bits(int64_t n, int32_t width, int32_t height);
+
 /* qb_intersect_ex -- qb_intersect with the depth-sort keys written by
  * qb_project_ex for the same projection (depth_keys, [n] uint32, read only;
- * NULL: derived from splats and counts as qb_intersect does) and explicit
+ * NULL: derived from splats and counts as qb_intersect does), explicit
  * launch shapes (a qb_depth_variant and a qb_emit_variant; the emission shape
- * does not apply to QB_BOX_QUADBOX_NAIVE); same workspace size and results as
- * qb_intersect. */
+ * does not apply to QB_BOX_QUADBOX_NAIVE) and a pair format:
+ *   packed_id_bits   0: pairs as qb_intersect writes them; b > 0 (at most
+ *                    qb_pair_id_bits): pair i is the one uint32
+ *                    pair_ids[i] = tile << b | id and pair_tiles is not used
+ *                    (may be NULL); QB_ERR_INVALID_ARG when n > 2^b or the
+ *                    tile id and b exceed 32 bits together
+ * Same workspace size, pair count and pair order as qb_intersect. */
 qb_status qb_intersect_ex(int64_t n, const qb_splat* splats, const qb_rects* rects,
                           const int32_t* counts, int32_t width, int32_t height, int32_t mode,
                           int64_t pair_capacity, uint16_t* pair_tiles, uint32_t* pair_ids, int64_t* num_pairs,
                           void* workspace, size_t workspace_bytes, const uint32_t* depth_keys,
-                          int32_t depth_variant, int32_t emit_variant, qb_stream_t stream);
+                          int32_t depth_variant, int32_t emit_variant, int32_t packed_id_bits,
+                          qb_stream_t stream);
 
 /* Workspace bytes qb_sort needs for a pair capacity. */
 size_t qb_sort_workspace_size(int64_t pair_capacity);
@@ -271,12 +282,16 @@ typedef enum {
 } qb_sort_variant;
 
 /* qb_sort_ex -- qb_sort with an explicit launch shape (a qb_sort_variant,
- * chosen for example by timing each on the workload); same arguments and
- * results as qb_sort, the same workspace size. */
+ * chosen for example by timing each on the workload) and the pair format
+ * qb_intersect_ex wrote (packed_id_bits: 0 for tiles and ids apart, b > 0
+ * for packed pairs tile << b | id in pair_ids, pair_tiles then not used and
+ * may be NULL; the radix passes then move 4 bytes per pair instead of 6).
+ * Same results as qb_sort (plain ids, keys and ranges), the same workspace
+ * size. */
 qb_status qb_sort_ex(int64_t pair_capacity, const int64_t* num_pairs, int32_t num_tiles,
                      const uint16_t* pair_tiles, const uint32_t* pair_ids, const qb_splat* splats,
                      uint64_t* keys, uint32_t* ids, uint32_t* ranges, void* workspace,
-                     size_t workspace_bytes, int32_t variant, qb_stream_t stream);
+                     size_t workspace_bytes, int32_t variant, int32_t packed_id_bits, qb_stream_t stream);
 
 /* qb_render -- Eq. (2) per pixel over its tile's sorted list: front to back,
  * skipping a Gaussian where its quadratic form exceeds gamma (alpha < 1/255,

@@ -50,6 +50,19 @@ __global__ void k_store_total(const uint64_t* __restrict__ tot, int64_t* __restr
     *num_pairs = tot ? (int64_t)*tot : 0;
 }
 
+// Stores pair dst: split (uint16 tile, uint32 id), or, with id_bits > 0,
+// packed as tile << id_bits | id into out_id alone.
+__device__ __forceinline__ void store_pair(int64_t dst, uint32_t tile, uint32_t id, int id_bits,
+                                           uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id)
+{
+    if (id_bits) {
+        out_id[dst] = (tile << id_bits) | id;
+    } else {
+        out_tile[dst] = (uint16_t)tile;
+        out_id[dst] = id;
+    }
+}
+
 // kChains: independent cursors per wave.  The block's pairs are cut into
 // (waves x kChains) contiguous ranges; a wave advances its kChains ranges in
 // lockstep, 64 pairs each per step, so the LDS round trips of one range's
@@ -58,7 +71,8 @@ template <int kEmitThreads, int kChains>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     int64_t n, const uint32_t* __restrict__ order, const uint64_t* __restrict__ goff,
     const int4* __restrict__ rects, const uint32_t* __restrict__ sorted_counts, int tiles_x, int64_t cap,
-    const int64_t* __restrict__ num_pairs, uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id)
+    const int64_t* __restrict__ num_pairs, uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id,
+    int id_bits)
 {
     constexpr int kRuns = kEmitThreads * QB_MAX_SEG;
     constexpr int NW = kEmitThreads / 64;
@@ -168,10 +182,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
                 int ot = (int)(w0 >> 16) + rem;
                 int tile = (w1 >> 16) ? sl * tiles_x + ot : ot * tiles_x + sl;
                 int64_t dst = block_start + p;
-                if (dst < cap) {
-                    out_tile[dst] = (uint16_t)tile;
-                    out_id[dst] = s_gid[o];
-                }
+                if (dst < cap) store_pair(dst, (uint32_t)tile, s_gid[o], id_bits, out_tile, out_id);
             }
         }
 #pragma unroll
@@ -186,7 +197,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
 __global__ __launch_bounds__(QB_BLOCK) void k_emit_naive(
     int64_t n, const uint32_t* __restrict__ order, const uint64_t* __restrict__ goff,
     const int4* __restrict__ rects, const uint32_t* __restrict__ sorted_counts, int tiles_x, int64_t cap,
-    const int64_t* __restrict__ num_pairs, uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id)
+    const int64_t* __restrict__ num_pairs, uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id,
+    int id_bits)
 {
     if (*num_pairs > cap) return;  // overflow: the caller re-runs with more capacity
     int64_t k = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
@@ -199,10 +211,7 @@ __global__ __launch_bounds__(QB_BLOCK) void k_emit_naive(
     int64_t base = (int64_t)goff[k];
     naive_walk(r, [&](int tx, int ty, int c) {
         int64_t dst = base + c;
-        if (dst < cap) {
-            out_tile[dst] = (uint16_t)(ty * tiles_x + tx);
-            out_id[dst] = gi;
-        }
+        if (dst < cap) store_pair(dst, (uint32_t)(ty * tiles_x + tx), gi, id_bits, out_tile, out_id);
     });
 }
 
@@ -258,10 +267,10 @@ static qb_status depth_sort(IsectWs& w, const uint32_t* keys, int64_t n, const i
 template <int NT, int C>
 static qb_status launch_emit(int64_t n, const uint32_t* order, const uint64_t* offs, const int4* r4,
                              const uint32_t* csorted, int tiles_x, int64_t cap, const int64_t* num_pairs,
-                             uint16_t* pair_tiles, uint32_t* pair_ids, hipStream_t s)
+                             uint16_t* pair_tiles, uint32_t* pair_ids, int id_bits, hipStream_t s)
 {
     QB_LAUNCH((k_emit<NT, C>), qb_div_up(n, NT), NT, 0, s, n, order, offs, r4, csorted, tiles_x, cap, num_pairs,
-              pair_tiles, pair_ids);
+              pair_tiles, pair_ids, id_bits);
     return QB_OK;
 }
 
@@ -269,7 +278,7 @@ static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rect
                                 int tiles_x, int32_t mode, int64_t pair_capacity, uint16_t* pair_tiles,
                                 uint32_t* pair_ids, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
                                 const uint32_t* depth_keys, int32_t depth_variant, int32_t emit_variant,
-                                hipStream_t s)
+                                int id_bits, hipStream_t s)
 {
     QbArena a{(char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255), workspace_bytes - 256, 0};
     IsectWs w = carve(a, n);
@@ -298,12 +307,14 @@ static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rect
     const int4* r4 = reinterpret_cast<const int4*>(rects);
     if (pair_capacity > 0 && (mode & ~QB_CLIP_3SIGMA) == QB_BOX_QUADBOX_NAIVE)
         QB_LAUNCH(k_emit_naive, grid, QB_BLOCK, 0, s, n, order, (const uint64_t*)w.offs, r4,
-                  (const uint32_t*)w.csorted, tiles_x, pair_capacity, (const int64_t*)num_pairs, pair_tiles, pair_ids);
+                  (const uint32_t*)w.csorted, tiles_x, pair_capacity, (const int64_t*)num_pairs, pair_tiles, pair_ids,
+                  id_bits);
     else if (pair_capacity > 0) {
         const uint64_t* offs = w.offs;
         const uint32_t* cs = w.csorted;
 #define QB_EMIT(NT, C) \
-    QB_CHECK((launch_emit<NT, C>(n, order, offs, r4, cs, tiles_x, pair_capacity, num_pairs, pair_tiles, pair_ids, s)))
+    QB_CHECK((launch_emit<NT, C>(n, order, offs, r4, cs, tiles_x, pair_capacity, num_pairs, pair_tiles, pair_ids, \
+                                 id_bits, s)))
         switch (emit_variant) {
         case QB_EMIT_128: QB_EMIT(128, 1); break;
         case QB_EMIT_512: QB_EMIT(512, 1); break;
@@ -335,6 +346,23 @@ static qb_status intersect_args(int64_t n, const qb_splat* splats, const qb_rect
     return QB_OK;
 }
 
+// Bits of the tile id for num_tiles tiles.
+static int tile_id_bits(int64_t num_tiles)
+{
+    int b = 0;
+    while ((1ll << b) < num_tiles) ++b;
+    return b;
+}
+
+extern "C" int32_t qb_pair_id_bits(int64_t n, int32_t width, int32_t height)
+{
+    if (n < 0 || width <= 0 || height <= 0) return 0;
+    int64_t tiles = qb_div_up(width, QB_TILE) * qb_div_up(height, QB_TILE);
+    if (tiles > 65536) return 0;
+    int b = tile_id_bits(n > 1 ? n : 2);
+    return b + tile_id_bits(tiles) <= 32 ? b : 0;
+}
+
 extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_rects* rects,
                                   const int32_t* counts, int32_t width, int32_t height, int32_t mode,
                                   int64_t pair_capacity,
@@ -342,7 +370,7 @@ extern "C" qb_status qb_intersect(int64_t n, const qb_splat* splats, const qb_re
                                   size_t workspace_bytes, qb_stream_t stream)
 {
     return qb_intersect_ex(n, splats, rects, counts, width, height, mode, pair_capacity, pair_tiles, pair_ids,
-                           num_pairs, workspace, workspace_bytes, nullptr, QB_DEPTH_512x4, QB_EMIT_256, stream);
+                           num_pairs, workspace, workspace_bytes, nullptr, QB_DEPTH_512x4, QB_EMIT_256, 0, stream);
 }
 
 extern "C" qb_status qb_intersect_ex(int64_t n, const qb_splat* splats, const qb_rects* rects,
@@ -350,17 +378,26 @@ extern "C" qb_status qb_intersect_ex(int64_t n, const qb_splat* splats, const qb
                                      int64_t pair_capacity, uint16_t* pair_tiles, uint32_t* pair_ids,
                                      int64_t* num_pairs, void* workspace, size_t workspace_bytes,
                                      const uint32_t* depth_keys, int32_t depth_variant, int32_t emit_variant,
-                                     qb_stream_t stream)
+                                     int32_t packed_id_bits, qb_stream_t stream)
 {
     int tiles_x = 0;
-    QB_CHECK(intersect_args(n, splats, rects, counts, width, height, mode, pair_capacity, pair_tiles, pair_ids,
+    // packed pairs live in pair_ids alone: pair_tiles may be NULL
+    uint16_t* tiles_arg = packed_id_bits ? reinterpret_cast<uint16_t*>(pair_ids) : pair_tiles;
+    QB_CHECK(intersect_args(n, splats, rects, counts, width, height, mode, pair_capacity, tiles_arg, pair_ids,
                             num_pairs, &tiles_x));
     if (depth_variant < 0 || depth_variant >= QB_DEPTH_VARIANTS || emit_variant < 0 ||
         emit_variant >= QB_EMIT_VARIANTS)
         return QB_ERR_INVALID_ARG;
+    if (packed_id_bits != 0) {
+        int64_t tiles = (int64_t)tiles_x * qb_div_up(height, QB_TILE);
+        if (packed_id_bits < 1 || packed_id_bits > 31 || n > ((int64_t)1 << packed_id_bits) ||
+            packed_id_bits + tile_id_bits(tiles) > 32)
+            return QB_ERR_INVALID_ARG;
+    }
     if (!workspace || workspace_bytes < qb_intersect_workspace_size(n)) return QB_ERR_INVALID_ARG;
     return intersect_impl(n, splats, rects, counts, tiles_x, mode, pair_capacity, pair_tiles, pair_ids, num_pairs,
-                          workspace, workspace_bytes, depth_keys, depth_variant, emit_variant, qb_hip_stream(stream));
+                          workspace, workspace_bytes, depth_keys, depth_variant, emit_variant, packed_id_bits,
+                          qb_hip_stream(stream));
 }
 
 // ---- qb_intersect without a caller workspace --------------------------------
@@ -407,5 +444,5 @@ extern "C" qb_status qb_intersect_noalloc(int64_t n, const qb_splat* splats, con
     void* ws = scratch_on_current_device();
     if (!ws) return QB_ERR_HIP;
     return intersect_impl(n, splats, rects, counts, tiles_x, mode, pair_capacity, pair_tiles, pair_ids, num_pairs,
-                          ws, kNoallocScratchBytes, nullptr, QB_DEPTH_512x4, QB_EMIT_256, qb_hip_stream(stream));
+                          ws, kNoallocScratchBytes, nullptr, QB_DEPTH_512x4, QB_EMIT_256, 0, qb_hip_stream(stream));
 }

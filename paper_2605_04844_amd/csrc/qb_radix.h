@@ -328,15 +328,22 @@ __device__ __forceinline__ bool b_any(const uint4& v) { return (v.x | v.y | v.z 
 // FUSED: `offs` holds the raw block-major histograms of every block, and the
 // workgroup derives its global digit offsets from them (digit totals scanned
 // over digits, plus the counts of the earlier blocks); otherwise `offs` is the
-// scanned digit-major histogram.  GATHER also writes gdst[pos] = gsrc[value]
-// beside each moved value.
-template <typename K, int NT, int NI, bool FUSED, bool GATHER>
+// scanned digit-major histogram.  MODE: kMoveValues moves (key, value)
+// pairs; kGather also writes gdst[pos] = gsrc[value] beside each moved value;
+// kKeysOnly moves the keys alone (vals_in / vals_out unused); kKeysUnpack
+// reads keys alone and writes each key split at bit `unpack_bits`: its high
+// part to ((uint16_t*)keys_out)[pos], its low part to vals_out[pos].
+enum { kMoveValues = 0, kGather = 1, kKeysOnly = 2, kKeysUnpack = 3 };
+
+template <typename K, int NT, int NI, bool FUSED, int MODE>
 __global__ __launch_bounds__(NT) void k_radix_downsweep(
     const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, K* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const int64_t* n_dev, int64_t n_host, int64_t cap, int shift, int bits,
     const uint32_t* __restrict__ offs, int64_t nblocks, const int32_t* __restrict__ gsrc,
-    uint32_t* __restrict__ gdst)
+    uint32_t* __restrict__ gdst, int unpack_bits)
 {
+    constexpr bool VALUES = MODE == kMoveValues || MODE == kGather;
+    static_assert(VALUES || sizeof(K) == 4, "keys-only passes move 32-bit keys");
     constexpr int NW = NT / 64;
     constexpr int TILE = NT * NI;
     __shared__ uint32_t wcnt[NW][kRadix];   // per-wave counts, then per-wave starts
@@ -345,7 +352,7 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
     __shared__ uint32_t scan_lds[NW];
     __shared__ uint32_t acc[FUSED ? 2 : 1][kRadix];   // FUSED: digit totals, counts in earlier blocks
     __shared__ K s_key[TILE];
-    __shared__ uint32_t s_val[TILE];
+    __shared__ uint32_t s_val[VALUES ? TILE : 1];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int64_t n = sort_count(n_dev, n_host, cap);
     int64_t blk0 = (int64_t)blockIdx.x * TILE;
@@ -406,7 +413,7 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
         int64_t idx = base + r * 64 + lane;
         bool valid = idx < n;
         kv[r] = valid ? keys_in[idx] : (K)0;
-        vv[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
+        if (VALUES) vv[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
     }
 #pragma unroll
     for (int r = 0; r < NI; ++r) {
@@ -451,17 +458,24 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
         if (dig[r] == 0xFFFFFFFFu) continue;
         uint32_t lp = lstart[dig[r]] + wcnt[wave][dig[r]] + rank[r];
         s_key[lp] = kv[r];
-        s_val[lp] = vv[r];
+        if (VALUES) s_val[lp] = vv[r];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < cnt_blk; i += NT) {
         K k = s_key[i];
         uint32_t d = digit_of(k, shift, mask);
         uint32_t pos = gbase[d] + (uint32_t)i - lstart[d];
-        uint32_t v = s_val[i];
-        keys_out[pos] = k;
-        vals_out[pos] = v;
-        if (GATHER) gdst[pos] = (uint32_t)gsrc[v];
+        if constexpr (MODE == kKeysUnpack) {
+            reinterpret_cast<uint16_t*>(keys_out)[pos] = (uint16_t)((uint32_t)k >> unpack_bits);
+            vals_out[pos] = (uint32_t)k & ((1u << unpack_bits) - 1u);
+        } else if constexpr (MODE == kKeysOnly) {
+            keys_out[pos] = k;
+        } else {
+            uint32_t v = s_val[i];
+            keys_out[pos] = k;
+            vals_out[pos] = v;
+            if (MODE == kGather) gdst[pos] = (uint32_t)gsrc[v];
+        }
     }
 }
 
@@ -546,16 +560,70 @@ qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout,
             QB_CHECK((exclusive_scan<uint32_t, uint32_t>(hist, offs, hn_used, sscr, (uint32_t*)nullptr, s)));
             o = (const uint32_t*)offs;
         }
-#define QB_DOWNSWEEP(F, G)                                                                                    \
-    QB_LAUNCH((k_radix_downsweep<K, NT, NI, F, G>), nb, NT, 0, s, src_k, src_v, dk, dv, n_dev, n_host, cap,  \
-              shift, bits, o, nb, G ? gsrc : (const int32_t*)nullptr, G ? gdst : (uint32_t*)nullptr)
-        if (fused && gather) QB_DOWNSWEEP(true, true);
-        else if (fused) QB_DOWNSWEEP(true, false);
-        else if (gather) QB_DOWNSWEEP(false, true);
-        else QB_DOWNSWEEP(false, false);
+#define QB_DOWNSWEEP(F, M)                                                                                    \
+    QB_LAUNCH((k_radix_downsweep<K, NT, NI, F, M>), nb, NT, 0, s, src_k, src_v, dk, dv, n_dev, n_host, cap,  \
+              shift, bits, o, nb, M == kGather ? gsrc : (const int32_t*)nullptr,                              \
+              M == kGather ? gdst : (uint32_t*)nullptr, 0)
+        if (fused && gather) QB_DOWNSWEEP(true, kGather);
+        else if (fused) QB_DOWNSWEEP(true, kMoveValues);
+        else if (gather) QB_DOWNSWEEP(false, kGather);
+        else QB_DOWNSWEEP(false, kMoveValues);
 #undef QB_DOWNSWEEP
         src_k = dk;
         src_v = dv;
+        shift += bits;
+    }
+    return QB_OK;
+}
+
+// Stable sort of 32-bit packed keys by their bits [lo_bit, hi_bit) (at most
+// two passes of at most 8 bits), moving the keys alone; the last pass writes
+// each sorted key split at lo_bit: key >> lo_bit to hi_out (uint16), the low
+// lo_bit bits to lo_out.  tmp holds the keys between the passes.  Counts and
+// grid as radix_sort; first_bits as there.
+template <int NT, int NI>
+qb_status radix_sort_packed(const uint32_t* kin, uint32_t* tmp, uint16_t* hi_out, uint32_t* lo_out,
+                            const int64_t* n_dev, int64_t cap, int lo_bit, int hi_bit, uint32_t* scratch,
+                            hipStream_t s, int first_bits = 0)
+{
+    if (cap <= 0) return QB_OK;
+    int total_bits = hi_bit - lo_bit;
+    int np = (total_bits + kRadixBits - 1) / kRadixBits;
+    if (total_bits <= 0 || np > 2 || lo_bit <= 0 || hi_bit > 32 || hi_bit - lo_bit > 16) return QB_ERR_INVALID_ARG;
+    int64_t nb = qb_div_up(cap, NT * NI);
+    int64_t hn = nb * kRadix;
+    uint32_t* hist = scratch;
+    uint32_t* offs = scratch + hn;
+    uint32_t* sscr = scratch + 2 * hn;
+    bool fused = nb <= kFusedBlocks && NT >= kRadix;
+    int shift = lo_bit;
+    const uint32_t* src = kin;
+    for (int p = 0; p < np; ++p) {
+        int bits = (total_bits - (shift - lo_bit) + (np - p) - 1) / (np - p);
+        if (p == 0 && np > 1 && first_bits > 0) bits = min(first_bits, min(kRadixBits, total_bits - 1));
+        bool last = p == np - 1;
+        int64_t hn_used = (int64_t)(1 << bits) * nb;
+        const uint32_t* o = (const uint32_t*)hist;
+        if (fused) {
+            QB_LAUNCH((k_radix_upsweep<uint32_t, NT, NI, true>), nb, NT, 0, s, src, n_dev, (int64_t)0, cap, shift,
+                      bits, hist, nb);
+        } else {
+            QB_LAUNCH((k_radix_upsweep<uint32_t, NT, NI, false>), nb, NT, 0, s, src, n_dev, (int64_t)0, cap, shift,
+                      bits, hist, nb);
+            QB_CHECK((exclusive_scan<uint32_t, uint32_t>(hist, offs, hn_used, sscr, (uint32_t*)nullptr, s)));
+            o = (const uint32_t*)offs;
+        }
+#define QB_DOWNSWEEP_PACKED(F, M, OUTK, OUTV)                                                                  \
+    QB_LAUNCH((k_radix_downsweep<uint32_t, NT, NI, F, M>), nb, NT, 0, s, src, (const uint32_t*)nullptr, OUTK,   \
+              OUTV, n_dev, (int64_t)0, cap, shift, bits, o, nb, (const int32_t*)nullptr, (uint32_t*)nullptr,     \
+              lo_bit)
+        uint32_t* hk = reinterpret_cast<uint32_t*>(hi_out);
+        if (last && fused) QB_DOWNSWEEP_PACKED(true, kKeysUnpack, hk, lo_out);
+        else if (last) QB_DOWNSWEEP_PACKED(false, kKeysUnpack, hk, lo_out);
+        else if (fused) QB_DOWNSWEEP_PACKED(true, kKeysOnly, tmp, (uint32_t*)nullptr);
+        else QB_DOWNSWEEP_PACKED(false, kKeysOnly, tmp, (uint32_t*)nullptr);
+#undef QB_DOWNSWEEP_PACKED
+        src = tmp;
         shift += bits;
     }
     return QB_OK;

@@ -69,6 +69,18 @@ __global__ __launch_bounds__(QB_BLOCK) void k_make_keys(const uint16_t* __restri
     }
 }
 
+// Packed pairs of a one-tile image: the ids in emission order, tile 0.
+__global__ __launch_bounds__(QB_BLOCK) void k_one_tile(const uint32_t* __restrict__ packed,
+                                                       const int64_t* __restrict__ num_pairs, int64_t cap,
+                                                       uint16_t* __restrict__ tiles, uint32_t* __restrict__ ids)
+{
+    int64_t n = qbr::sort_count(num_pairs, 0, cap);
+    for (int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * QB_BLOCK) {
+        tiles[i] = 0;
+        ids[i] = packed[i];
+    }
+}
+
 int tile_bits(int64_t num_tiles)
 {
     int b = 0;
@@ -132,18 +144,35 @@ extern "C" qb_status qb_sort(int64_t pair_capacity, const int64_t* num_pairs, in
                              size_t workspace_bytes, qb_stream_t stream)
 {
     return qb_sort_ex(pair_capacity, num_pairs, num_tiles, pair_tiles, pair_ids, splats, keys, ids, ranges,
-                      workspace, workspace_bytes, QB_SORT_512x8, stream);
+                      workspace, workspace_bytes, QB_SORT_512x8, 0, stream);
+}
+
+// The tile sort of packed pairs (tile << id_bits | id) in radix workgroups of
+// NT lanes x NI pairs: the passes move the 4-byte packed pairs alone, the
+// last one writes the sorted tiles and ids apart.
+template <int NT, int NI>
+static qb_status packed_sort(const uint32_t* packed, uint16_t* tiles_sorted, uint32_t* ids, uint32_t* tmp,
+                             const int64_t* num_pairs, int64_t cap, int id_bits, int bits, uint32_t* radix,
+                             int first_bits, hipStream_t s)
+{
+    static_assert(NT * NI >= kSortMinTile, "the workspace is sized for tiles of at least kSortMinTile pairs");
+    return qbr::radix_sort_packed<NT, NI>(packed, tmp, tiles_sorted, ids, num_pairs, cap, id_bits, id_bits + bits,
+                                          radix, s, first_bits);
 }
 
 extern "C" qb_status qb_sort_ex(int64_t pair_capacity, const int64_t* num_pairs, int32_t num_tiles,
                                 const uint16_t* pair_tiles, const uint32_t* pair_ids, const qb_splat* splats,
                                 uint64_t* keys, uint32_t* ids, uint32_t* ranges, void* workspace,
-                                size_t workspace_bytes, int32_t variant, qb_stream_t stream)
+                                size_t workspace_bytes, int32_t variant, int32_t packed_id_bits,
+                                qb_stream_t stream)
 {
     if (pair_capacity < 0 || pair_capacity > (int64_t)0xFFFFFFFF || !num_pairs || num_tiles < 1 ||
         num_tiles > 65536 || !ranges || !workspace || variant < 0 || variant >= QB_SORT_VARIANTS)
         return QB_ERR_INVALID_ARG;
-    if (pair_capacity > 0 && (!pair_tiles || !pair_ids || !ids)) return QB_ERR_INVALID_ARG;
+    if (packed_id_bits != 0 &&
+        (packed_id_bits < 1 || packed_id_bits > 31 || packed_id_bits + tile_bits(num_tiles) > 32))
+        return QB_ERR_INVALID_ARG;
+    if (pair_capacity > 0 && ((!packed_id_bits && !pair_tiles) || !pair_ids || !ids)) return QB_ERR_INVALID_ARG;
     if (keys && !splats) return QB_ERR_INVALID_ARG;
     if ((const void*)pair_ids == (const void*)ids) return QB_ERR_INVALID_ARG;
     if (workspace_bytes < qb_sort_workspace_size(pair_capacity)) return QB_ERR_INVALID_ARG;
@@ -156,12 +185,30 @@ extern "C" qb_status qb_sort_ex(int64_t pair_capacity, const int64_t* num_pairs,
 #define QB_TILE_SORT(NT, NI)                                                                                   \
     tile_sort<NT, NI>(pair_tiles, pair_ids, w.tiles_sorted, ids, w.ktmp, w.vtmp, num_pairs, pair_capacity, bits, \
                       w.radix, first_pass_bits(variant, bits), s)
-        switch (variant) {
-        case QB_SORT_1024x8: QB_CHECK(QB_TILE_SORT(1024, 8)); break;
-        case QB_SORT_512x16: QB_CHECK(QB_TILE_SORT(512, 16)); break;
-        case QB_SORT_256x16: QB_CHECK(QB_TILE_SORT(256, 16)); break;
-        default: QB_CHECK(QB_TILE_SORT(512, 8)); break;   // 512x8 and its digit-width variants
+#define QB_PACKED_SORT(NT, NI)                                                                                 \
+    packed_sort<NT, NI>(pair_ids, w.tiles_sorted, ids, w.vtmp, num_pairs, pair_capacity, packed_id_bits, bits,    \
+                        w.radix, first_pass_bits(variant, bits), s)
+        if (packed_id_bits && bits > 0) {
+            switch (variant) {
+            case QB_SORT_1024x8: QB_CHECK(QB_PACKED_SORT(1024, 8)); break;
+            case QB_SORT_512x16: QB_CHECK(QB_PACKED_SORT(512, 16)); break;
+            case QB_SORT_256x16: QB_CHECK(QB_PACKED_SORT(256, 16)); break;
+            default: QB_CHECK(QB_PACKED_SORT(512, 8)); break;
+            }
+        } else if (packed_id_bits) {
+            // one tile: the packed pairs are the ids, already in order
+            int64_t g = qb_div_up(pair_capacity, QB_BLOCK);
+            if (g > 8192) g = 8192;
+            QB_LAUNCH(k_one_tile, g, QB_BLOCK, 0, s, pair_ids, num_pairs, pair_capacity, w.tiles_sorted, ids);
+        } else {
+            switch (variant) {
+            case QB_SORT_1024x8: QB_CHECK(QB_TILE_SORT(1024, 8)); break;
+            case QB_SORT_512x16: QB_CHECK(QB_TILE_SORT(512, 16)); break;
+            case QB_SORT_256x16: QB_CHECK(QB_TILE_SORT(256, 16)); break;
+            default: QB_CHECK(QB_TILE_SORT(512, 8)); break;   // 512x8 and its digit-width variants
+            }
         }
+#undef QB_PACKED_SORT
 #undef QB_TILE_SORT
         if (keys) {
             int64_t g = qb_div_up(pair_capacity, QB_BLOCK);

@@ -83,9 +83,11 @@ def lib():
     L.qb_intersect_workspace_size.restype = sz
     L.qb_intersect.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz, vp]
     L.qb_intersect.restype = i32
-    L.qb_intersect_ex.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz, vp, i32, i32, vp]
+    L.qb_intersect_ex.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz, vp, i32, i32, i32, vp]
     L.qb_intersect_ex.restype = i32
-    L.qb_sort_ex.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp]
+    L.qb_sort_ex.argtypes = [i64, vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, i32, i32, vp]
+    L.qb_pair_id_bits.argtypes = [i64, i32, i32]
+    L.qb_pair_id_bits.restype = i32
     L.qb_sort_ex.restype = i32
     L.qb_sort_workspace_size.argtypes = [i64]
     L.qb_sort_workspace_size.restype = sz
@@ -226,18 +228,25 @@ def intersect_workspace_size(n: int) -> int:
     return int(lib().qb_intersect_workspace_size(n))
 
 
+def pair_id_bits(n, width, height) -> int:
+    """qb_pair_id_bits: the id width of packed pairs, 0 if they cannot be
+    packed."""
+    return int(lib().qb_pair_id_bits(n, width, height))
+
+
 def intersect(n, splats, rects, counts, width, height, capacity, pair_tiles, pair_ids, num_pairs, ws,
-              mode="quadbox", depth_variant=0, emit_variant=0, depth_keys=None):
+              mode="quadbox", depth_variant=0, emit_variant=0, depth_keys=None, packed_id_bits=0):
     """qb_intersect_ex; depth_keys: the keys qb_project_ex wrote for this
-    projection, or None to derive them from the splats."""
+    projection, or None to derive them from the splats; packed_id_bits > 0
+    packs each pair into pair_ids (pair_tiles unused)."""
     _need(min(_rows(splats), _rows(rects), _rows(counts)) >= n, "qb_intersect: inputs hold fewer than n rows")
     _need(depth_keys is None or _rows(depth_keys) >= n, "qb_intersect_ex: depth_keys holds fewer than n entries")
-    _need(capacity == 0 or min(_rows(pair_tiles), _rows(pair_ids)) >= capacity,
+    _need(capacity == 0 or (_rows(pair_ids) >= capacity and (packed_id_bits or _rows(pair_tiles) >= capacity)),
           "qb_intersect: pair buffers hold fewer than capacity entries")
     _check("qb_intersect_ex", lib().qb_intersect_ex(
         n, _ptr(splats), _ptr(rects), _ptr(counts), width, height, _mode(mode), capacity, _ptr(pair_tiles),
         _ptr(pair_ids), _ptr(num_pairs), _ptr(ws), ws.numel() * ws.element_size(), _ptr(depth_keys),
-        int(depth_variant), int(emit_variant), _stream()))
+        int(depth_variant), int(emit_variant), int(packed_id_bits), _stream()))
 
 
 # QB_NOALLOC_MAX_GAUSSIANS: the largest n qb_intersect_noalloc accepts
@@ -261,10 +270,13 @@ def sort_workspace_size(capacity: int) -> int:
     return int(lib().qb_sort_workspace_size(capacity))
 
 
-def sort(capacity, num_pairs, num_tiles, pair_tiles, pair_ids, splats, keys, ids, ranges, ws, variant=0):
+def sort(capacity, num_pairs, num_tiles, pair_tiles, pair_ids, splats, keys, ids, ranges, ws, variant=0,
+         packed_id_bits=0):
+    """qb_sort_ex; packed_id_bits as given to qb_intersect_ex."""
     _check("qb_sort_ex", lib().qb_sort_ex(
         capacity, _ptr(num_pairs), num_tiles, _ptr(pair_tiles), _ptr(pair_ids), _ptr(splats), _ptr(keys),
-        _ptr(ids), _ptr(ranges), _ptr(ws), ws.numel() * ws.element_size(), int(variant), _stream()))
+        _ptr(ids), _ptr(ranges), _ptr(ws), ws.numel() * ws.element_size(), int(variant), int(packed_id_bits),
+        _stream()))
 
 
 def tile_order(width, height, ranges, ids, splats, work, order):
@@ -352,6 +364,9 @@ class Rasterizer:
         self.sort_variant = SORT_VARIANTS["512x8"]
         self.depth_variant = DEPTH_VARIANTS["512x4"]
         self.emit_variant = EMIT_VARIANTS["256"]
+        # packed pairs (tile << id_bits | id, 4 bytes) where they fit 32 bits
+        self.packed = True
+        self.id_bits = pair_id_bits(n, self.W, self.H)
         d = device
         self.splats = torch.empty((max(n, 1), SPLAT_FLOATS), dtype=torch.float32, device=d)
         self.rects = torch.empty((max(n, 1), RECT_SHORTS), dtype=torch.int16, device=d)
@@ -392,14 +407,19 @@ class Rasterizer:
         project(g, self.cam, mode, self.splats, self.rects, self.counts, self.depth_keys)
         self.mode = mode
 
+    def packed_id_bits(self) -> int:
+        """The pair format intersect() and sort() use: id bits of packed
+        pairs, or 0 for tiles and ids apart."""
+        return self.id_bits if self.packed else 0
+
     def intersect(self):
         intersect(self.n, self.splats, self.rects, self.counts, self.W, self.H, self.capacity, self.pair_tiles,
                   self.pair_ids, self.num_pairs, self.ws_isect, self.mode, self.depth_variant, self.emit_variant,
-                  self.depth_keys)
+                  self.depth_keys, self.packed_id_bits())
 
     def sort(self):
         sort(self.capacity, self.num_pairs, self.num_tiles, self.pair_tiles, self.pair_ids, self.splats,
-             self.keys_sorted, self.ids_sorted, self.ranges, self.ws_sort, self.sort_variant)
+             self.keys_sorted, self.ids_sorted, self.ranges, self.ws_sort, self.sort_variant, self.packed_id_bits())
 
     def schedule(self):
         """qb_tile_order for the sorted frame (a no-op without balance)."""
@@ -572,6 +592,9 @@ class MultiView:
         self.sort_variant = SORT_VARIANTS["512x8"]
         self.depth_variant = DEPTH_VARIANTS["512x4"]
         self.emit_variant = EMIT_VARIANTS["256"]
+        # per view: packed pairs where tile and id fit 32 bits
+        self.packed = True
+        self.id_bits = [pair_id_bits(n, w, h) for w, h in self.sizes]
         self.grads = None
         self._table = None
 
@@ -584,11 +607,15 @@ class MultiView:
         cap = self.capacity[v]
         intersect(self.n, s, r, c, w, h, cap, self.pair_tiles[v] if cap else None,
                   self.pair_ids[v] if cap else None, npairs, self.ws_isect[v % self.S], self.mode,
-                  self.depth_variant, self.emit_variant, self.depth_keys[v])
+                  self.depth_variant, self.emit_variant, self.depth_keys[v], self._packed_bits(v))
+
+    def _packed_bits(self, v):
+        return self.id_bits[v] if self.packed else 0
 
     def _sort(self, v):
         sort(self.capacity[v], self.num_pairs[v:v + 1], self.num_tiles[v], self.pair_tiles[v], self.pair_ids[v],
-             self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort[v % self.S], self.sort_variant)
+             self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort[v % self.S], self.sort_variant,
+             self._packed_bits(v))
 
     def intersect_all(self):
         """qb_intersect of every view (side streams, joined back)."""

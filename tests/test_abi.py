@@ -123,13 +123,42 @@ def test_activations_and_shape_entry_points_reject_bad_arguments():
     assert L.qb_activations(0, None, 0, None, None) == qb.QB_OK   # nothing to do, nothing launched
     ws = qb.intersect_workspace_size(10)
     for dv, ev in ((4, 0), (-1, 0), (0, 5), (0, -1)):
-        assert L.qb_intersect_ex(10, d, d, d, 64, 48, 2, 100, d, d, d, d, ws, None, dv, ev, None) == \
+        assert L.qb_intersect_ex(10, d, d, d, 64, 48, 2, 100, d, d, d, d, ws, None, dv, ev, 0, None) == \
             qb.QB_ERR_INVALID_ARG
-        assert L.qb_intersect_ex(10, d, d, d, 64, 48, 2, 100, d, d, d, d, ws, d, dv, ev, None) == \
+        assert L.qb_intersect_ex(10, d, d, d, 64, 48, 2, 100, d, d, d, d, ws, d, dv, ev, 0, None) == \
             qb.QB_ERR_INVALID_ARG
     sws = qb.sort_workspace_size(100)
     for v in (-1, 6):
-        assert L.qb_sort_ex(100, d, 12, d, d, d, None, C.c_void_p(512), d, d, sws, v, None) == qb.QB_ERR_INVALID_ARG
+        assert L.qb_sort_ex(100, d, 12, d, d, d, None, C.c_void_p(512), d, d, sws, v, 0, None) == \
+            qb.QB_ERR_INVALID_ARG
+
+
+def test_packed_pair_format_arguments():
+    """qb_pair_id_bits: ceil(log2 n) id bits when they and the tile id fit 32
+    bits, else 0; qb_intersect_ex and qb_sort_ex reject a packed format that
+    cannot hold the ids or the tiles, and accept a NULL pair_tiles with it."""
+    L = qb.lib()
+    assert qb.pair_id_bits(1_000_000, 1280, 720) == 20        # 3600 tiles: 12 bits
+    assert qb.pair_id_bits(1 << 20, 1280, 720) == 20
+    assert qb.pair_id_bits((1 << 20) + 1, 1280, 720) == 0     # 21 + 12 bits
+    assert qb.pair_id_bits(2_000_000, 640, 360) == 21         # 920 tiles: 10 bits
+    assert qb.pair_id_bits(2_000_000, 1920, 1080) == 0
+    assert qb.pair_id_bits(1, 64, 64) == 1 and qb.pair_id_bits(0, 64, 64) == 1
+    assert qb.pair_id_bits(5, 0, 64) == 0 and qb.pair_id_bits(-1, 64, 64) == 0
+    d = C.c_void_p(256)
+    ws = qb.intersect_workspace_size(10)
+    args = lambda n, bits: (n, d, d, d, 64, 48, 2, 100, None, d, d, d, ws, None, 0, 0, bits, None)
+    for bits in (-1, 32, 3):   # 3 bits cannot hold 10 ids
+        assert L.qb_intersect_ex(*args(10, bits)) == qb.QB_ERR_INVALID_ARG, bits
+    wsb = qb.intersect_workspace_size(1 << 20)
+    big = (1 << 20, d, d, d, 16 * 256, 16 * 256, 2, 100, None, d, d, d, wsb, None, 0, 0, 20, None)
+    assert L.qb_intersect_ex(*big) == qb.QB_ERR_INVALID_ARG   # 65536 tiles: 16 bits + 20 > 32
+    sws = qb.sort_workspace_size(100)
+    for bits in (-1, 32, 21):   # 21 + 12 tile bits > 32
+        assert L.qb_sort_ex(100, d, 3600, None, d, d, None, d, d, d, sws, 0, bits, None) == \
+            qb.QB_ERR_INVALID_ARG, bits
+    # split pairs still need pair_tiles
+    assert L.qb_sort_ex(100, d, 3600, None, d, d, None, d, d, d, sws, 0, 0, None) == qb.QB_ERR_INVALID_ARG
 
 
 def test_launch_shape_and_view_entry_points_reject_bad_arguments():

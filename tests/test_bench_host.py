@@ -90,12 +90,16 @@ def test_stage_bytes():
     """Design bytes per frame: project 44 + 12 (d+1)^2 B of inputs and 88 B
     of outputs (record, rects, count, depth key) per Gaussian; intersect
     148 B per Gaussian (the depth sort takes the projection's keys) and 6 B
-    per pair; sort 28 B per pair (two passes)."""
+    per pair; sort 28 B per pair (two passes); packed pairs 4 and 26 B."""
     b = bench.stage_bytes(1_000_000, 3, 26_492_435)
     assert b["project"] == 1_000_000 * (44 + 192 + 88)
     assert b["intersect"] == 1_000_000 * 148 + 26_492_435 * 6
     assert b["sort"] == 26_492_435 * 28
     assert bench.stage_bytes(10, 0, 0)["project"] == 10 * (44 + 12 + 88)
+    # packed pairs: 4 B written per pair by the emission, 26 B per pair sorted
+    bp = bench.stage_bytes(1_000_000, 3, 26_492_435, packed=True)
+    assert bp["intersect"] == 1_000_000 * 148 + 26_492_435 * 4
+    assert bp["sort"] == 26_492_435 * 26
 
 
 def test_peaks():

@@ -387,7 +387,8 @@ def test_clip_3sigma_image_equals_3sigma_on_gpu(oracle, qb):
 def test_intersect_and_sort_launch_shapes(oracle, qb):
     """Every depth-sort and emission shape of qb_intersect_ex writes the same
     pairs in the same order, with the depth keys of qb_project_ex and with
-    keys derived from the splats, and every tile-sort shape of qb_sort_ex gives
+    keys derived from the splats, split or packed (tile << id_bits | id), and
+    every tile-sort shape of qb_sort_ex, on either pair format, gives
     the same sorted list and ranges: on the 10k-Gaussian scene against the
     oracle, on the 1M-Gaussian clustered scene against the default shapes
     (bit for bit)."""
@@ -395,6 +396,9 @@ def test_intersect_and_sort_launch_shapes(oracle, qb):
                             (*scenes.cluster_scene(), None)):
         g = qb.Gaussians(scene)
         r = qb.Rasterizer(scene.n, cam)
+        bits = r.id_bits
+        assert bits > 0
+        r.packed = False
         r.forward(g, "quadbox")
         torch.cuda.synchronize()
         P = r.pairs()
@@ -403,6 +407,8 @@ def test_intersect_and_sort_launch_shapes(oracle, qb):
         want_keys = r.keys_sorted[:P].clone()
         want_ids = r.ids_sorted[:P].clone()
         want_ranges = r.ranges.clone()
+        want_packed = ((want_t.to(torch.int64) & 0xFFFF) << bits | (want_i.to(torch.int64) & 0xFFFFFFFF))
+        want_packed = torch.where(want_packed >= 2 ** 31, want_packed - 2 ** 32, want_packed).to(torch.int32)
         if ref is not None:
             assert np.array_equal(want_keys.cpu().numpy().view(np.uint64), ref["keys"])
             assert np.array_equal(want_ids.cpu().numpy().view(np.uint32), ref["ids"])
@@ -425,14 +431,30 @@ def test_intersect_and_sort_launch_shapes(oracle, qb):
                     assert r.pairs() == P, tag
                     assert torch.equal(r.pair_tiles[:P], want_t), tag
                     assert torch.equal(r.pair_ids[:P], want_i), tag
+                # packed pairs: tile << bits | id in one 32-bit word
+                r.pair_ids.fill_(-1)
+                qb.intersect(scene.n, r.splats, r.rects, r.counts, r.W, r.H, r.capacity, None, r.pair_ids,
+                             r.num_pairs, r.ws_isect, "quadbox", dv, ev, r.depth_keys, bits)
+                torch.cuda.synchronize()
+                assert r.pairs() == P, (scene.n, dn, en, "packed")
+                assert torch.equal(r.pair_ids[:P], want_packed), (scene.n, dn, en, "packed")
         for sn, sv in qb.SORT_VARIANTS.items():
-            r.ids_sorted.fill_(-1)
-            r.keys_sorted.fill_(-1)
-            r.ranges.fill_(-1)
-            r.sort_variant = sv
-            r.sort()
-            torch.cuda.synchronize()
-            assert torch.equal(r.keys_sorted[:P], want_keys), (scene.n, sn)
-            assert torch.equal(r.ids_sorted[:P], want_ids), (scene.n, sn)
-            assert torch.equal(r.ranges, want_ranges), (scene.n, sn)
+            for packed in (False, True):
+                r.ids_sorted.fill_(-1)
+                r.keys_sorted.fill_(-1)
+                r.ranges.fill_(-1)
+                r.sort_variant = sv
+                r.packed = packed
+                if packed:   # the packed sort reads packed pairs
+                    r.pair_ids[:P].copy_(want_packed)
+                else:
+                    r.pair_tiles[:P].copy_(want_t)
+                    r.pair_ids[:P].copy_(want_i)
+                r.sort()
+                torch.cuda.synchronize()
+                tag = (scene.n, sn, packed)
+                assert torch.equal(r.keys_sorted[:P], want_keys), tag
+                assert torch.equal(r.ids_sorted[:P], want_ids), tag
+                assert torch.equal(r.ranges, want_ranges), tag
+        r.packed = False
         say(f"{scene.n} Gaussians, {P} pairs: every intersect and sort shape agrees")

@@ -8,7 +8,8 @@ sawtooth over all tiles (every neighbour a different digit), runs of 37
 equal tiles (runs that straddle the 8-pair lane groups and the 4096-pair
 workgroups), and uniform random tiles; counts from 1 to 1M include ragged
 tails that are not whole lane groups or workgroups.  Every launch shape of
-qb_sort_ex (radix workgroups of 4096 to 8192 pairs) is checked.  Bit-exact."""
+qb_sort_ex (radix workgroups of 4096 to 8192 pairs) is checked, on split
+pairs and, where tile and id fit 32 bits, on packed ones.  Bit-exact."""
 import numpy as np
 import pytest
 
@@ -61,3 +62,20 @@ def test_sort_synthetic_tiles(oracle, qb, n, tiles):
                 (n, tiles, name, shape)
             # the input lists are left as they were
             assert np.array_equal(pt[:n].cpu().numpy().view(np.uint16), t), (n, tiles, name, shape)
+        # the same pairs packed as tile << bits | id (where they fit 32 bits)
+        bits = max(1, int(np.ceil(np.log2(max(n, 2)))))
+        tbits = int(np.ceil(np.log2(tiles))) if tiles > 1 else 0
+        if bits + tbits > 32:
+            continue
+        packed = (t.astype(np.uint64) << np.uint64(bits)) | ids_in.astype(np.uint64)
+        pk = torch.zeros(cap, dtype=torch.int32, device="cuda")
+        pk[:n] = torch.from_numpy(packed.astype(np.uint32).view(np.int32)).cuda()
+        for shape, variant in qb.SORT_VARIANTS.items():
+            ids = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+            ranges = torch.full((tiles * 2,), -1, dtype=torch.int32, device="cuda")
+            qb.sort(cap, num_pairs, tiles, None, pk, None, None, ids, ranges, ws, variant, bits)
+            torch.cuda.synchronize()
+            got_ids = ids.cpu().numpy().view(np.uint32)[:n]
+            assert np.array_equal(got_ids, want_ids), (n, tiles, name, shape, "packed")
+            assert np.array_equal(ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), want_ranges), \
+                (n, tiles, name, shape, "packed")

@@ -21,6 +21,7 @@ def say(*a):
 def run_both(scene, cam, mode):
     g = qb.Gaussians(scene)
     r = qb.Rasterizer(scene.n, cam, write_keys=True)
+    r.packed = False     # the reference pairs in qb_intersect's own format
     r.forward(g, mode)   # projection, and the reference pairs from qb_intersect
     torch.cuda.synchronize()
     P = r.pairs()
