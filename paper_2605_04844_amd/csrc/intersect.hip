@@ -12,9 +12,10 @@
 //     LDS with the block-relative index of their first pair.  The workgroup
 //     then walks its pairs pair-parallel, 64 consecutive pairs per wave per
 //     step.  The run of each pair comes from a per-step owner table (every run
-//     that starts inside the step marks its first pair; a wave-wide running
-//     maximum carries it to the following pairs), its tile from one division
-//     of the pair's offset in the run; the stores of a wave are contiguous.
+//     that starts inside the step marks its first pair; a ballot and a prefix
+//     bit count give each pair the number of runs started up to it), its tile
+//     from a reciprocal multiply and two 24-bit multiply-adds on the pair's
+//     offset in the run; the stores of a wave are contiguous.
 // A pair is stored compactly as (uint16 tile, uint32 Gaussian id); its key
 // tile << 32 | bits(depth) is implied by the id.
 // The naive traversal (QB_BOX_QUADBOX_NAIVE, the ablation without QPass)
@@ -67,6 +68,17 @@ __device__ __forceinline__ void store_pair(int64_t dst, uint32_t tile, uint32_t 
 // (waves x kChains) contiguous ranges; a wave advances its kChains ranges in
 // lockstep, 64 pairs each per step, so the LDS round trips of one range's
 // step (owner table, run lookups) overlap with the other's.
+//
+// A run of n scanlines x len tiles holds its pairs scanline-major, so pair
+// `local` of the run is on scanline q = local / len at offset local - q * len.
+// Its tile is affine in (local, q): tbase + local * A + q * B, with
+//   rows    (axis 1): tbase = s0 * tiles_x + lo, A = 1,       B = tiles_x - len
+//   columns (axis 0): tbase = lo * tiles_x + s0, A = tiles_x, B = 1 - len * tiles_x
+// (|A|, |B| < 2^17 and local, q < 2^16 with at most 65536 tiles, so 24-bit
+// multiplies suffice).  q comes from the run's reciprocal r ~ 1/len (1 ulp):
+// (local + 1/2) r is (local + 1/2) / len within a relative 2^-22, i.e. within
+// 0.02 / len for local < 2^16, and the exact quotient sits at least 1/(2 len)
+// from an integer, so truncation gives the exact q.
 template <int kEmitThreads, int kChains>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     int64_t n, const uint32_t* __restrict__ order, const uint64_t* __restrict__ goff,
@@ -77,14 +89,14 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     constexpr int kRuns = kEmitThreads * QB_MAX_SEG;
     constexpr int NW = kEmitThreads / 64;
     __shared__ uint32_t s_off[kRuns + 1];  // first pair of each run, block-relative
-    __shared__ uint32_t s_w0[kRuns];       // s0 | lo << 16
-    __shared__ uint32_t s_w1[kRuns];       // len | axis << 16
-    __shared__ uint32_t s_gid[kRuns];      // Gaussian id
+    __shared__ uint4 s_run[kRuns];         // Gaussian id, bits(r), tbase | A << 16, B
     __shared__ uint32_t s_scan[NW];
-    __shared__ int s_tab[NW][kChains][64];
+    __shared__ uint32_t s_tab[NW][kChains][64];
 
     if (*num_pairs > cap) return;  // overflow: the caller re-runs with more capacity
-    int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    int t = threadIdx.x;
+    uint32_t lane = (uint32_t)t & 63u;
+    int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     int64_t k0 = (int64_t)blockIdx.x * kEmitThreads;
     int64_t k = k0 + t;
     uint32_t gi = 0;
@@ -104,20 +116,38 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     uint32_t total, nruns;
     uint32_t off = qbr::block_exclusive_scan<uint32_t, kEmitThreads>(cnt, &total, s_scan);
     uint32_t slot = qbr::block_exclusive_scan<uint32_t, kEmitThreads>(nr, &nruns, s_scan);
+    total = __builtin_amdgcn_readfirstlane(total);
+    nruns = __builtin_amdgcn_readfirstlane(nruns);
 #pragma unroll
     for (int i = 0; i < QB_MAX_SEG; ++i) {
-        uint32_t sz = (uint32_t)(q.n[i] * q.len[i]);
+        uint32_t len = (uint32_t)q.len[i];
+        uint32_t sz = (uint32_t)q.n[i] * len;
         if (sz > 0) {
+            uint32_t tb, a;
+            int32_t b;
+            if (q.axis) {
+                tb = (uint32_t)(q.s0[i] * tiles_x + q.lo[i]);
+                a = 1;
+                b = tiles_x - (int)len;
+            } else {
+                tb = (uint32_t)(q.lo[i] * tiles_x + q.s0[i]);
+                a = (uint32_t)tiles_x;
+                b = 1 - (int)len * tiles_x;
+            }
             s_off[slot] = off;
-            s_w0[slot] = (uint32_t)q.s0[i] | ((uint32_t)q.lo[i] << 16);
-            s_w1[slot] = (uint32_t)q.len[i] | ((uint32_t)q.axis << 16);
-            s_gid[slot] = gi;
+            s_run[slot] = make_uint4(gi, __float_as_uint(__builtin_amdgcn_rcpf((float)len)), tb | a << 16,
+                                     (uint32_t)b);
             ++slot;
             off += sz;
         }
     }
     if (t == 0) s_off[nruns] = total;  // sentinel
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) s_tab[wave][c][lane] = 0xFFFFFFFFu;
     int64_t block_start = (int64_t)goff[k0];
+    // the pairs of the block fill [block_start, block_start + total) <= num_pairs
+    // <= cap; the bound below only keeps a stale offset table inside the buffer
+    if (block_start + (int64_t)total > cap) total = cap > block_start ? (uint32_t)(cap - block_start) : 0u;
     __syncthreads();
     // each of the block's waves x kChains ranges is a contiguous share of its
     // pairs, walked 64 per step; the run holding a step's first pair is the
@@ -134,7 +164,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
         int a = 0, b = (int)nruns;
         while (b - a > 1) {
             int mid = (a + b) >> 1;
-            if (s_off[mid] <= lo) a = mid; else b = mid;
+            if (__builtin_amdgcn_readfirstlane(s_off[mid]) <= lo) a = mid; else b = mid;
         }
         cur[c] = a;
     }
@@ -143,52 +173,44 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
 #pragma unroll
         for (int c = 0; c < kChains; ++c) left = left || base[c] < hi[c];
         if (!left) break;
-        // every later run that starts inside a range's step marks its first
-        // pair; a running maximum hands the run to the pairs that follow
-#pragma unroll
-        for (int c = 0; c < kChains; ++c) s_tab[wave][c][lane] = -1;
-        __builtin_amdgcn_wave_barrier();
+        // every later run that starts inside a range's step writes its start
+        // into the owner table slot of its first pair.  Starts only grow, so a
+        // slot holds the current step's pair exactly when that pair starts a
+        // run; the run of a pair is cur + the run starts at or before it.
 #pragma unroll
         for (int c = 0; c < kChains; ++c) {
-            int jj = cur[c] + 1 + lane;
-            if (base[c] < hi[c] && jj < (int)nruns) {
-                uint32_t st = s_off[jj];
-                if (st >= base[c] && st < base[c] + 64) s_tab[wave][c][st - base[c]] = jj;
+            uint32_t jj = (uint32_t)cur[c] + 1u + lane;
+            if (base[c] < hi[c] && jj < nruns) {
+                uint32_t d = s_off[jj] - base[c];
+                if (d < 64u) s_tab[wave][c][d] = base[c] + d;
             }
         }
         __builtin_amdgcn_wave_barrier();
-        int own[kChains];
 #pragma unroll
         for (int c = 0; c < kChains; ++c) {
-            own[c] = qbr::wave_inclusive_max(s_tab[wave][c][lane]);
-            if (own[c] < 0) own[c] = cur[c];
-        }
-#pragma unroll
-        for (int c = 0; c < kChains; ++c) {
-            uint32_t p = base[c] + lane;
-            if (p < hi[c]) {
-                int o = own[c];
-                uint32_t local = p - s_off[o];
-                uint32_t w0 = s_w0[o], w1 = s_w1[o];
-                uint32_t len = w1 & 0xFFFFu;
-                // local < 2^16: with the hardware reciprocal (1 ulp) the float
-                // quotient is within 0.02 of local / len, so its floor is off
-                // by at most one, which the two steps below correct
-                uint32_t qq = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)len));
-                int32_t rem = (int32_t)local - (int32_t)(qq * len);
-                if (rem < 0) { --qq; rem += (int32_t)len; }
-                if (rem >= (int32_t)len) { ++qq; rem -= (int32_t)len; }
-                int sl = (int)(w0 & 0xFFFFu) + (int)qq;
-                int ot = (int)(w0 >> 16) + rem;
-                int tile = (w1 >> 16) ? sl * tiles_x + ot : ot * tiles_x + sl;
-                int64_t dst = block_start + p;
-                if (dst < cap) store_pair(dst, (uint32_t)tile, s_gid[o], id_bits, out_tile, out_id);
+            if (base[c] < hi[c]) {
+                uint32_t p = base[c] + lane;
+                uint64_t m = __builtin_amdgcn_ballot_w64(s_tab[wave][c][lane] == p);
+                uint32_t c0 = (uint32_t)cur[c] + (uint32_t)(m & 1u);
+                m >>= 1;
+                uint32_t o = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, c0));
+                if (p < hi[c]) {
+                    uint32_t local = p - s_off[o];
+                    uint4 rr = s_run[o];
+                    float r = __uint_as_float(rr.y);
+                    uint32_t qq = (uint32_t)__builtin_fmaf((float)local, r, 0.5f * r);
+                    uint32_t tile = (rr.z & 0xFFFFu) + __umul24(local, rr.z >> 16) + (uint32_t)__mul24((int)qq, (int)rr.w);
+                    int64_t wbase = block_start + base[c];
+                    if (id_bits) {
+                        out_id[wbase + lane] = (tile << id_bits) | rr.x;
+                    } else {
+                        out_tile[wbase + lane] = (uint16_t)tile;
+                        out_id[wbase + lane] = rr.x;
+                    }
+                }
+                cur[c] = __builtin_amdgcn_readlane((int)o, 63);
+                base[c] += 64;
             }
-        }
-#pragma unroll
-        for (int c = 0; c < kChains; ++c) {
-            cur[c] = __builtin_amdgcn_readlane(own[c], 63);
-            base[c] += 64;
         }
         __builtin_amdgcn_wave_barrier();
     }
