@@ -3,7 +3,8 @@
 //  1. key every Gaussian by its depth bits (0xFFFFFFFF when it covers no
 //     tile; qb_project_ex writes these keys, else they are derived here from
 //     the splats and counts) and stable-radix-sort the ids: the (depth, id)
-//     order that orders the Gaussians within every tile
+//     order that orders the Gaussians within every tile (those that cover no
+//     tile emit nothing and may fall anywhere in it)
 //  2. gather the tile counts in that order (in the sort's last pass) and
 //     scan them: the pair offsets and the total
 //  3. emit: a 256-lane workgroup takes 256 consecutive Gaussians of that
@@ -36,14 +37,12 @@ constexpr int kDepthMinTile = 2048;
 
 __global__ __launch_bounds__(QB_BLOCK) void k_depth_keys(int64_t n, const float4* __restrict__ splats,
                                                          const int32_t* __restrict__ counts,
-                                                         uint32_t* __restrict__ keys,
-                                                         uint32_t* __restrict__ vals)
+                                                         uint32_t* __restrict__ keys)
 {
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
     float d = splats[3 * i].z;
     keys[i] = counts[i] > 0 ? __float_as_uint(d) : 0xFFFFFFFFu;
-    vals[i] = (uint32_t)i;
 }
 
 __global__ void k_store_total(const uint64_t* __restrict__ tot, int64_t* __restrict__ num_pairs)
@@ -269,21 +268,26 @@ extern "C" size_t qb_intersect_workspace_size(int64_t n)
     return a.used + 256;
 }
 
-// The stages of qb_intersect over a workspace of `workspace_bytes` bytes at
-// `workspace` (already checked to be large enough for n).
 // The depth sort of (keys, ids) in radix workgroups of NT lanes x NI keys;
-// the last pass also gathers the tile counts into the sorted order.
-// keys: the depth keys (qb_project_ex's), or w.dk0 after k_depth_keys wrote
-// them there with the identity values in w.dv0.
+// the last pass also gathers the tile counts into the sorted order, which
+// ends in w.dv0.  keys: the depth keys (qb_project_ex's, or w.dk0 after
+// k_depth_keys wrote them there); the ids are the positions.  With at most
+// kFusedBlocks workgroups the passes cover only the span of the keys of the
+// Gaussians that cover a tile (the others, 0xFFFFFFFF, emit nothing, so
+// their place in the order is free): the positive binary32 depths of one
+// view seldom span more than 2^24 key values, and the fourth pass then
+// returns at once.  The pair offsets' array, written after the sort, holds
+// values between passes.
 template <int NT, int NI>
 static qb_status depth_sort(IsectWs& w, const uint32_t* keys, int64_t n, const int32_t* counts, hipStream_t s)
 {
     static_assert(NT * NI >= kDepthMinTile, "the workspace is sized for tiles of at least kDepthMinTile keys");
-    // four 8-bit passes: keys -> (dk1, dv1) -> (dk0, dv0) -> ...; the first
-    // pass takes the positions as values when the keys are the caller's
-    const uint32_t* vals = keys == w.dk0 ? w.dv0 : nullptr;
-    return qbr::radix_sort<uint32_t, NT, NI>(keys, vals, w.dk0, w.dv0, w.dk1, w.dv1, (const int64_t*)nullptr, n, n,
-                                             0, 32, w.radix, s, counts, w.csorted);
+    if (qb_div_up(n, NT * NI) <= qbr::kFusedBlocks)
+        return qbr::radix_sort_span<NT, NI>(keys, w.dk1, w.dv1, w.dk0, reinterpret_cast<uint32_t*>(w.offs), w.dv0,
+                                            n, w.radix, s, counts, w.csorted);
+    // four 8-bit passes over the whole key: keys -> (dk1, dv1) -> (dk0, dv0) -> ...
+    return qbr::radix_sort<uint32_t, NT, NI>(keys, nullptr, w.dk0, w.dv0, w.dk1, w.dv1, (const int64_t*)nullptr, n,
+                                             n, 0, 32, w.radix, s, counts, w.csorted);
 }
 
 template <int NT, int C>
@@ -296,6 +300,8 @@ static qb_status launch_emit(int64_t n, const uint32_t* order, const uint64_t* o
     return QB_OK;
 }
 
+// The stages of qb_intersect over a workspace of `workspace_bytes` bytes at
+// `workspace` (already checked to be large enough for n).
 static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rects* rects, const int32_t* counts,
                                 int tiles_x, int32_t mode, int64_t pair_capacity, uint16_t* pair_tiles,
                                 uint32_t* pair_ids, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
@@ -312,8 +318,7 @@ static qb_status intersect_impl(int64_t n, const qb_splat* splats, const qb_rect
     int64_t grid = qb_div_up(n, QB_BLOCK);
     const uint32_t* keys = depth_keys;
     if (!keys) {
-        QB_LAUNCH(k_depth_keys, grid, QB_BLOCK, 0, s, n, reinterpret_cast<const float4*>(splats), counts, w.dk0,
-                  w.dv0);
+        QB_LAUNCH(k_depth_keys, grid, QB_BLOCK, 0, s, n, reinterpret_cast<const float4*>(splats), counts, w.dk0);
         keys = w.dk0;
     }
     switch (depth_variant) {

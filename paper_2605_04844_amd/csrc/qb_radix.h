@@ -76,18 +76,6 @@ __device__ __forceinline__ T wave_inclusive_scan(T v)
     }
 }
 
-// Inclusive running maximum across one wave64 (DPP, as above).
-__device__ __forceinline__ int wave_inclusive_max(int v)
-{
-    v = max(v, dpp_shift<0x111, 0xF>(v, INT_MIN));
-    v = max(v, dpp_shift<0x112, 0xF>(v, INT_MIN));
-    v = max(v, dpp_shift<0x114, 0xF>(v, INT_MIN));
-    v = max(v, dpp_shift<0x118, 0xF>(v, INT_MIN));
-    v = max(v, dpp_shift<0x142, 0xA>(v, INT_MIN));
-    v = max(v, dpp_shift<0x143, 0xC>(v, INT_MIN));
-    return v;
-}
-
 // Exclusive scan over a block of NT threads; returns the block total too.
 // lds must hold NT/64 elements.
 template <typename T, int NT>
@@ -249,14 +237,53 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask)
     return (uint32_t)(key >> shift) & mask;
 }
 
+// Pass control of a 32-bit key sort whose pass count is settled on the device
+// (radix_sort_span).  Keys equal to kNoKey are placed anywhere: they order
+// nothing.  Pass 0's upsweep stores each block's (min, max) over the other
+// keys in range[]; every pass-0 downsweep workgroup reduces them to the
+// span's base b (the minimum rounded down to a multiple of 256), stores the
+// other keys as key - b (kNoKey as 0: bits 0..7 of every other key are kept,
+// so pass 0's own digits are those of the raw keys), and takes
+// np = max(1, ceil(bits(max - b) / 8)) passes, which block 0 stores in *np.
+// A later pass returns at once when pass >= *np.  The last pass writes to
+// fin_keys (skipped when null) / fin_vals and gathers; the others write to
+// their own outputs and do not gather.  pass < 0: an ordinary sort.
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+
+struct PassCtl {
+    uint2* range;
+    int32_t* np;
+    int pass;
+    uint32_t* fin_keys;
+    uint32_t* fin_vals;
+};
+
+inline PassCtl no_pass_ctl() { return PassCtl{nullptr, nullptr, -1, nullptr, nullptr}; }
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
+}
+
 // Per-block digit histogram.  Digit-major layout (hist[d * nblocks + b]) feeds
 // the flat scan; block-major (hist[b * 256 + d], every digit written) feeds a
 // downsweep that derives its own offsets.
-template <typename K, int NT, int NI, bool BLOCK_MAJOR>
+template <typename K, int NT, int NI, bool BLOCK_MAJOR, bool RANGE = false>
 __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys, const int64_t* n_dev,
                                                       int64_t n_host, int64_t cap, int shift, int bits,
-                                                      uint32_t* __restrict__ hist, int64_t nblocks)
+                                                      uint32_t* __restrict__ hist, int64_t nblocks, PassCtl ctl)
 {
+    static_assert(!RANGE || sizeof(K) == 4, "key spans are taken over 32-bit keys");
+    if (ctl.pass > 0 && ctl.pass >= *ctl.np) return;  // a pass past the key span
     constexpr int NW = NT / 64;
     // kSub histograms per wave, a lane adding into copy lane % kSub; rows
     // padded by one word so that one digit lies in a different bank in each
@@ -283,6 +310,7 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
     constexpr int kPerVec = 16 / sizeof(K);
     const K* wk = keys + base;
     bool vec = (NI * sizeof(K)) % 16 == 0 && base + 64 * NI <= n && ((uintptr_t)wk & 15u) == 0;
+    uint32_t klo = kNoKey, khi = 0u;  // RANGE: span of the keys other than kNoKey
     if (vec) {
         const uint4* src = reinterpret_cast<const uint4*>(wk + (int64_t)lane * NI);
         uint32_t cur = 0u, run = 0u;
@@ -292,6 +320,10 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
             const K* e = reinterpret_cast<const K*>(&x);
 #pragma unroll
             for (int u = 0; u < kPerVec; ++u) {
+                if (RANGE && (uint32_t)e[u] != kNoKey) {
+                    klo = min(klo, (uint32_t)e[u]);
+                    khi = max(khi, (uint32_t)e[u]);
+                }
                 uint32_t d = digit_of(e[u], shift, mask);
                 if (run != 0u && d != cur) {
                     atomicAdd(&hw[cur], run);
@@ -306,7 +338,32 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
 #pragma unroll 4
         for (int r = 0; r < NI; ++r) {
             int64_t idx = base + r * 64 + lane;
-            if (idx < n) atomicAdd(&hw[digit_of(keys[idx], shift, mask)], 1u);
+            if (idx < n) {
+                K key = keys[idx];
+                if (RANGE && (uint32_t)key != kNoKey) {
+                    klo = min(klo, (uint32_t)key);
+                    khi = max(khi, (uint32_t)key);
+                }
+                atomicAdd(&hw[digit_of(key, shift, mask)], 1u);
+            }
+        }
+    }
+    if (RANGE) {
+        __shared__ uint32_t s_lo[NW], s_hi[NW];
+        klo = wave_min_u32(klo);
+        khi = wave_max_u32(khi);
+        if (lane == 0) {
+            s_lo[wave] = klo;
+            s_hi[wave] = khi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int w = 1; w < NW; ++w) {
+                klo = min(klo, s_lo[w]);
+                khi = max(khi, s_hi[w]);
+            }
+            ctl.range[blockIdx.x] = make_uint2(klo, khi);
         }
     }
     __syncthreads();
@@ -340,10 +397,17 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
     const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, K* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const int64_t* n_dev, int64_t n_host, int64_t cap, int shift, int bits,
     const uint32_t* __restrict__ offs, int64_t nblocks, const int32_t* __restrict__ gsrc,
-    uint32_t* __restrict__ gdst, int unpack_bits)
+    uint32_t* __restrict__ gdst, int unpack_bits, PassCtl ctl)
 {
     constexpr bool VALUES = MODE == kMoveValues || MODE == kGather;
     static_assert(VALUES || sizeof(K) == 4, "keys-only passes move 32-bit keys");
+    // pass control (PassCtl): last = write the final outputs and gather
+    bool last = ctl.pass < 0;
+    if (ctl.pass > 0) {
+        int np = *ctl.np;
+        if (ctl.pass >= np) return;
+        last = ctl.pass == np - 1;
+    }
     constexpr int NW = NT / 64;
     constexpr int TILE = NT * NI;
     __shared__ uint32_t wcnt[NW][kRadix];   // per-wave counts, then per-wave starts
@@ -399,6 +463,38 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
         if (d < kRadix) gbase[d] = start + pre;  // scan scratch reused after its last read
     } else {
         for (int d = threadIdx.x; d <= (int)mask; d += NT) gbase[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+    }
+    uint32_t span_base = 0u;
+    if (ctl.pass == 0) {
+        // the span of the keys other than kNoKey over every block
+        __shared__ uint32_t s_lo[NW], s_hi[NW];
+        uint32_t lo = kNoKey, hi = 0u;
+        for (int b = threadIdx.x; b < (int)nblocks; b += NT) {
+            uint2 r = ctl.range[b];
+            lo = min(lo, r.x);
+            hi = max(hi, r.y);
+        }
+        lo = wave_min_u32(lo);
+        hi = wave_max_u32(hi);
+        if (lane == 0) {
+            s_lo[wave] = lo;
+            s_hi[wave] = hi;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            lo = min(lo, s_lo[w]);
+            hi = max(hi, s_hi[w]);
+        }
+        int np = 1;
+        if (lo <= hi) {
+            span_base = lo & ~0xFFu;
+            uint32_t span = hi - span_base;
+            int sb = span ? 32 - __clz((int)span) : 0;
+            np = max(1, (sb + 7) >> 3);
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) *ctl.np = np;
+        last = np == 1;
     }
     __syncthreads();
 
@@ -461,6 +557,13 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
         if (VALUES) s_val[lp] = vv[r];
     }
     __syncthreads();
+    K* ko = keys_out;
+    uint32_t* vo = vals_out;
+    if (ctl.pass >= 0 && last) {
+        ko = reinterpret_cast<K*>(ctl.fin_keys);
+        vo = ctl.fin_vals;
+    }
+    bool gather = MODE == kGather && last;
     for (int i = threadIdx.x; i < cnt_blk; i += NT) {
         K k = s_key[i];
         uint32_t d = digit_of(k, shift, mask);
@@ -472,9 +575,10 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
             keys_out[pos] = k;
         } else {
             uint32_t v = s_val[i];
-            keys_out[pos] = k;
-            vals_out[pos] = v;
-            if (MODE == kGather) gdst[pos] = (uint32_t)gsrc[v];
+            if (ctl.pass == 0) k = (uint32_t)k == kNoKey ? (K)0 : (K)((uint32_t)k - span_base);
+            if (ko) ko[pos] = k;
+            vo[pos] = v;
+            if (gather) gdst[pos] = (uint32_t)gsrc[v];
         }
     }
 }
@@ -553,17 +657,17 @@ qb_status radix_sort(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout,
         const uint32_t* o = (const uint32_t*)hist;
         if (fused) {
             QB_LAUNCH((k_radix_upsweep<K, NT, NI, true>), nb, NT, 0, s, src_k, n_dev, n_host, cap, shift, bits,
-                      hist, nb);
+                      hist, nb, no_pass_ctl());
         } else {
             QB_LAUNCH((k_radix_upsweep<K, NT, NI, false>), nb, NT, 0, s, src_k, n_dev, n_host, cap, shift, bits,
-                      hist, nb);
+                      hist, nb, no_pass_ctl());
             QB_CHECK((exclusive_scan<uint32_t, uint32_t>(hist, offs, hn_used, sscr, (uint32_t*)nullptr, s)));
             o = (const uint32_t*)offs;
         }
 #define QB_DOWNSWEEP(F, M)                                                                                    \
     QB_LAUNCH((k_radix_downsweep<K, NT, NI, F, M>), nb, NT, 0, s, src_k, src_v, dk, dv, n_dev, n_host, cap,  \
               shift, bits, o, nb, M == kGather ? gsrc : (const int32_t*)nullptr,                              \
-              M == kGather ? gdst : (uint32_t*)nullptr, 0)
+              M == kGather ? gdst : (uint32_t*)nullptr, 0, no_pass_ctl())
         if (fused && gather) QB_DOWNSWEEP(true, kGather);
         else if (fused) QB_DOWNSWEEP(true, kMoveValues);
         else if (gather) QB_DOWNSWEEP(false, kGather);
@@ -606,17 +710,17 @@ qb_status radix_sort_packed(const uint32_t* kin, uint32_t* tmp, uint16_t* hi_out
         const uint32_t* o = (const uint32_t*)hist;
         if (fused) {
             QB_LAUNCH((k_radix_upsweep<uint32_t, NT, NI, true>), nb, NT, 0, s, src, n_dev, (int64_t)0, cap, shift,
-                      bits, hist, nb);
+                      bits, hist, nb, no_pass_ctl());
         } else {
             QB_LAUNCH((k_radix_upsweep<uint32_t, NT, NI, false>), nb, NT, 0, s, src, n_dev, (int64_t)0, cap, shift,
-                      bits, hist, nb);
+                      bits, hist, nb, no_pass_ctl());
             QB_CHECK((exclusive_scan<uint32_t, uint32_t>(hist, offs, hn_used, sscr, (uint32_t*)nullptr, s)));
             o = (const uint32_t*)offs;
         }
 #define QB_DOWNSWEEP_PACKED(F, M, OUTK, OUTV)                                                                  \
     QB_LAUNCH((k_radix_downsweep<uint32_t, NT, NI, F, M>), nb, NT, 0, s, src, (const uint32_t*)nullptr, OUTK,   \
               OUTV, n_dev, (int64_t)0, cap, shift, bits, o, nb, (const int32_t*)nullptr, (uint32_t*)nullptr,     \
-              lo_bit)
+              lo_bit, no_pass_ctl())
         uint32_t* hk = reinterpret_cast<uint32_t*>(hi_out);
         if (last && fused) QB_DOWNSWEEP_PACKED(true, kKeysUnpack, hk, lo_out);
         else if (last) QB_DOWNSWEEP_PACKED(false, kKeysUnpack, hk, lo_out);
@@ -625,6 +729,51 @@ qb_status radix_sort_packed(const uint32_t* kin, uint32_t* tmp, uint16_t* hi_out
 #undef QB_DOWNSWEEP_PACKED
         src = tmp;
         shift += bits;
+    }
+    return QB_OK;
+}
+
+// Stable sort of n 32-bit keys (kNoKey: placed anywhere) with their
+// positions as values, in 8-bit passes over the span of the other keys only
+// (PassCtl): the pass count is settled on the device by the first pass, and
+// the passes beyond it return at once.  Reads kin; (ka, va) and (kb, vb) hold
+// the items between passes (pass p writes to a when p is even, b when odd;
+// kb may be kin's buffer, which only pass 0 reads); the last pass writes the
+// sorted positions to fin_vals and gdst[i] = gsrc[fin_vals[i]], but no keys.
+// n items (host count) in at most kFusedBlocks blocks of NT*NI; scratch as
+// radix_scratch_bytes.
+template <int NT, int NI>
+qb_status radix_sort_span(const uint32_t* kin, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
+                          uint32_t* fin_vals, int64_t n, uint32_t* scratch, hipStream_t s, const int32_t* gsrc,
+                          uint32_t* gdst)
+{
+    static_assert(NT >= kRadix, "one lane per digit");
+    if (n <= 0) return QB_OK;
+    int64_t nb = qb_div_up(n, NT * NI);
+    if (nb > kFusedBlocks || !gsrc || !gdst) return QB_ERR_INVALID_ARG;
+    int64_t hn = nb * kRadix;
+    uint32_t* hist = scratch;
+    // block key ranges and the pass count in the scan-offset area, which a
+    // fused sort does not use (2 * nb + 1 <= 256 * nb words)
+    uint2* range = reinterpret_cast<uint2*>(scratch + hn);
+    int32_t* np = reinterpret_cast<int32_t*>(scratch + hn + 2 * nb);
+    const uint32_t* src_k = kin;
+    const uint32_t* src_v = nullptr;
+    for (int p = 0; p < 32 / kRadixBits; ++p) {
+        uint32_t* dk = (p & 1) ? kb : ka;
+        uint32_t* dv = (p & 1) ? vb : va;
+        PassCtl ctl{range, np, p, nullptr, fin_vals};
+        int shift = p * kRadixBits;
+        if (p == 0)
+            QB_LAUNCH((k_radix_upsweep<uint32_t, NT, NI, true, true>), nb, NT, 0, s, src_k, (const int64_t*)nullptr,
+                      n, n, shift, kRadixBits, hist, nb, ctl);
+        else
+            QB_LAUNCH((k_radix_upsweep<uint32_t, NT, NI, true, false>), nb, NT, 0, s, src_k, (const int64_t*)nullptr,
+                      n, n, shift, kRadixBits, hist, nb, ctl);
+        QB_LAUNCH((k_radix_downsweep<uint32_t, NT, NI, true, kGather>), nb, NT, 0, s, src_k, src_v, dk, dv,
+                  (const int64_t*)nullptr, n, n, shift, kRadixBits, (const uint32_t*)hist, nb, gsrc, gdst, 0, ctl);
+        src_k = dk;
+        src_v = dv;
     }
     return QB_OK;
 }

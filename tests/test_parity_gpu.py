@@ -384,6 +384,76 @@ def test_clip_3sigma_image_equals_3sigma_on_gpu(oracle, qb):
     say("pairs 3sigma / quadbox / clipped:", out["3sigma"]["P"], out["quadbox"]["P"], out["quadbox_clip3sigma"]["P"])
 
 
+def _pairs_by_gaussian(tiles, ids, n):
+    """Each Gaussian's tiles in the order the emission wrote them: (tiles
+    grouped by Gaussian, first index of each Gaussian's group)."""
+    srt = np.argsort(ids, kind="stable")
+    return tiles[srt], np.searchsorted(ids[srt], np.arange(n, dtype=np.int64))
+
+
+def _expected_pairs(keys, counts, grouped, start):
+    """The pairs of a stable sort of the covering Gaussians by their keys:
+    each Gaussian's group of tiles, Gaussians in (key, id) order."""
+    vis = np.nonzero(counts > 0)[0]
+    order = vis[np.argsort(keys[vis], kind="stable")]
+    lens = counts[order].astype(np.int64)
+    first = np.cumsum(lens) - lens
+    idx = np.repeat(start[order] - first, lens) + np.arange(int(lens.sum()), dtype=np.int64)
+    return grouped[idx], np.repeat(order.astype(np.uint32), lens)
+
+
+def test_depth_key_spans(qb):
+    """The depth sort covers only the span of the keys of the Gaussians that
+    cover a tile (the others' key is 0xFFFFFFFF and orders nothing), in one to
+    four 8-bit passes settled on the device.  For caller keys of every span
+    (all equal, ties within a byte, 2^12 across a binary32 exponent step,
+    2^20, 2^26, the whole range with 0 and 0xFFFFFFFE) and every depth-sort
+    shape, the emission writes each covering Gaussian's pairs, Gaussians in
+    the order of a stable sort of those keys, exactly as the reference run
+    wrote them per Gaussian: on the 10k-Gaussian scene (several blocks) and,
+    at the default shape, on the 1M-Gaussian clustered scene."""
+    rng = np.random.default_rng(7)
+    for scene, cam, shapes in ((*scenes.small_scene(), list(qb.DEPTH_VARIANTS.items())),
+                               (*scenes.cluster_scene(), [("512x4", qb.DEPTH_VARIANTS["512x4"])])):
+        n = scene.n
+        g = qb.Gaussians(scene)
+        r = qb.Rasterizer(n, cam)
+        r.packed = False
+        r.forward(g, "quadbox")
+        torch.cuda.synchronize()
+        P = r.pairs()
+        counts = r.counts[:n].cpu().numpy()
+        grouped, start = _pairs_by_gaussian(r.pair_tiles[:P].cpu().numpy().view(np.uint16),
+                                            r.pair_ids[:P].cpu().numpy().view(np.uint32), n)
+        spans = {
+            "equal": np.full(n, 0x3F800000, np.uint64),
+            "ties": 0x3F800000 + rng.integers(0, 8, n, dtype=np.uint64),
+            "2^12 across 2.0": 0x40000000 - 2000 + rng.integers(0, 4096, n, dtype=np.uint64),
+            "2^20": 0x3FF00000 + rng.integers(0, 1 << 20, n, dtype=np.uint64),
+            "2^26": rng.integers(0x3E000000, 0x42000000, n, dtype=np.uint64),
+            "whole range": rng.integers(0, 0xFFFFFFFF, n, dtype=np.uint64),
+        }
+        vis = np.nonzero(counts > 0)[0]
+        spans["whole range"][vis[:2]] = [0, 0xFFFFFFFE]
+        if n > 100_000:
+            spans = {k: spans[k] for k in ("2^12 across 2.0", "whole range")}
+        for name, k64 in spans.items():
+            keys = np.where(counts > 0, k64, 0xFFFFFFFF).astype(np.uint32)
+            want_t, want_i = _expected_pairs(keys, counts, grouped, start)
+            kdev = torch.from_numpy(keys.view(np.int32)).to(r.splats.device)
+            for dn, dv in shapes:
+                r.pair_tiles.fill_(-1)
+                r.pair_ids.fill_(-1)
+                qb.intersect(n, r.splats, r.rects, r.counts, r.W, r.H, r.capacity, r.pair_tiles, r.pair_ids,
+                             r.num_pairs, r.ws_isect, "quadbox", dv, 0, kdev)
+                torch.cuda.synchronize()
+                tag = (n, name, dn)
+                assert r.pairs() == P, tag
+                assert np.array_equal(r.pair_tiles[:P].cpu().numpy().view(np.uint16), want_t), tag
+                assert np.array_equal(r.pair_ids[:P].cpu().numpy().view(np.uint32), want_i), tag
+        say(f"{n} Gaussians: every key span and depth-sort shape emits the stable key order")
+
+
 def test_intersect_and_sort_launch_shapes(oracle, qb):
     """Every depth-sort and emission shape of qb_intersect_ex writes the same
     pairs in the same order, with the depth keys of qb_project_ex and with
