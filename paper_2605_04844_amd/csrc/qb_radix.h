@@ -294,29 +294,39 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
     __shared__ uint32_t h[NW * kSub][kRow];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t mask = (1u << bits) - 1u;
+    int64_t base = (int64_t)blockIdx.x * (NT * NI) + (int64_t)wave * 64 * NI;
+    // the wave's keys as 16-byte vectors, loaded first and bounded by the
+    // capacity (which the buffer holds), so that their latency overlaps the
+    // count's read; used when all 64*NI keys turn out to be below the count
+    constexpr int kPerVec = 16 / sizeof(K);
+    constexpr int kVecs = (int)(NI * sizeof(K) / 16);
+    const K* wk = keys + base;
+    bool vec_ok = (NI * sizeof(K)) % 16 == 0 && base + 64 * NI <= cap && ((uintptr_t)wk & 15u) == 0;
+    uint4 xv[kVecs > 0 ? kVecs : 1];
+    if (vec_ok) {
+        const uint4* src = reinterpret_cast<const uint4*>(wk + (int64_t)lane * NI);
+#pragma unroll
+        for (int q = 0; q < kVecs; ++q) xv[q] = src[q];
+    }
     // only the digits this pass can produce (0..mask) are cleared and summed
     for (int r = wave; r < NW * kSub; r += NW)
         for (int c = lane; c <= (int)mask; c += 64) h[r][c] = 0;
     __syncthreads();
     int64_t n = sort_count(n_dev, n_host, cap);
-    int64_t base = (int64_t)blockIdx.x * (NT * NI) + (int64_t)wave * 64 * NI;
     uint32_t* hw = h[wave * kSub + (lane & (kSub - 1))];
     // the histogram ignores order: when the wave's 64*NI keys are all valid
-    // and 16-byte aligned, each lane reads NI consecutive keys as 16-byte
-    // vectors and adds each run of equal digits among them with one atomic
+    // and 16-byte aligned, each lane takes NI consecutive keys (the vectors
+    // above) and adds each run of equal digits among them with one atomic
     // (runs are common where neighbouring keys share their high bits, and
     // same-address LDS atomics from many lanes serialise); otherwise one key
     // per lane per step
-    constexpr int kPerVec = 16 / sizeof(K);
-    const K* wk = keys + base;
-    bool vec = (NI * sizeof(K)) % 16 == 0 && base + 64 * NI <= n && ((uintptr_t)wk & 15u) == 0;
+    bool vec = vec_ok && base + 64 * NI <= n;
     uint32_t klo = kNoKey, khi = 0u;  // RANGE: span of the keys other than kNoKey
     if (vec) {
-        const uint4* src = reinterpret_cast<const uint4*>(wk + (int64_t)lane * NI);
         uint32_t cur = 0u, run = 0u;
 #pragma unroll
-        for (int q = 0; q < (int)(NI * sizeof(K) / 16); ++q) {
-            uint4 x = src[q];
+        for (int q = 0; q < kVecs; ++q) {
+            uint4 x = xv[q];
             const K* e = reinterpret_cast<const K*>(&x);
 #pragma unroll
             for (int u = 0; u < kPerVec; ++u) {
@@ -418,11 +428,27 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
     __shared__ K s_key[TILE];
     __shared__ uint32_t s_val[VALUES ? TILE : 1];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int64_t n = sort_count(n_dev, n_host, cap);
     int64_t blk0 = (int64_t)blockIdx.x * TILE;
+    int64_t base = blk0 + (int64_t)wave * 64 * NI;
+    // the block's items are loaded first, bounded by the capacity (which the
+    // buffers hold) rather than the count, so that their latency overlaps
+    // the reads of the count and of the digit offsets
+    K kv[NI];
+    uint32_t vv[NI];
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        int64_t idx = base + r * 64 + lane;
+        bool inb = idx < cap;
+        kv[r] = inb ? keys_in[idx] : (K)0;
+        if (VALUES) vv[r] = inb ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
+    }
+    uint32_t mask = (1u << bits) - 1u;
+    // without the fused prologue, this block's digit offsets are read early too
+    uint32_t gb_own = 0u;
+    if (!FUSED && threadIdx.x <= mask) gb_own = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    int64_t n = sort_count(n_dev, n_host, cap);
     if (blk0 >= n) return;
     int cnt_blk = (int)min((int64_t)TILE, n - blk0);
-    uint32_t mask = (1u << bits) - 1u;
     for (int d = threadIdx.x; d < NW * kRadix; d += NT) (&wcnt[0][0])[d] = 0;
     if (FUSED) {
         static_assert(!FUSED || NT >= kRadix, "one lane per digit");
@@ -462,7 +488,7 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
         uint32_t start = block_exclusive_scan<uint32_t, NT>(d < kRadix ? tot : 0u, &all, gbase);
         if (d < kRadix) gbase[d] = start + pre;  // scan scratch reused after its last read
     } else {
-        for (int d = threadIdx.x; d <= (int)mask; d += NT) gbase[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+        if (threadIdx.x <= mask) gbase[threadIdx.x] = gb_own;  // NT >= 256 > mask
     }
     uint32_t span_base = 0u;
     if (ctl.pass == 0) {
@@ -499,18 +525,8 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
     __syncthreads();
 
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    int64_t base = blk0 + (int64_t)wave * 64 * NI;
-    K kv[NI];
-    uint32_t vv[NI];
     uint32_t rank[NI];
     uint32_t dig[NI];
-#pragma unroll
-    for (int r = 0; r < NI; ++r) {
-        int64_t idx = base + r * 64 + lane;
-        bool valid = idx < n;
-        kv[r] = valid ? keys_in[idx] : (K)0;
-        if (VALUES) vv[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
-    }
 #pragma unroll
     for (int r = 0; r < NI; ++r) {
         int64_t idx = base + r * 64 + lane;
