@@ -85,9 +85,17 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     const int64_t* __restrict__ num_pairs, uint16_t* __restrict__ out_tile, uint32_t* __restrict__ out_id,
     int id_bits)
 {
-    constexpr int kRuns = kEmitThreads * QB_MAX_SEG;
+    // the run list holds kRunsPerLane runs per Gaussian on average (QuadBox
+    // Gaussians have at most 5 runs, 2.3-3.4 on average, and no 128-Gaussian
+    // block of the clustered, anisotropic or random test scenes averages
+    // above 3.7); a block with more runs walks its two halves one after the
+    // other (at most QB_MAX_SEG <= 2 * kRunsPerLane runs per Gaussian each).
+    // The smaller list doubles the blocks that LDS lets a CU hold.
+    constexpr int kRunsPerLane = 4;
+    static_assert(QB_MAX_SEG <= 2 * kRunsPerLane, "a half block's runs fit the list");
+    constexpr int kRuns = kEmitThreads * kRunsPerLane;
     constexpr int NW = kEmitThreads / 64;
-    __shared__ uint32_t s_off[kRuns + 1];  // first pair of each run, block-relative
+    __shared__ uint32_t s_off[kRuns + 1];  // first pair of each run, relative to the walk's first pair
     __shared__ uint4 s_run[kRuns];         // Gaussian id, bits(r), tbase | A << 16, B
     __shared__ uint32_t s_scan[NW];
     __shared__ uint32_t s_tab[NW][kChains][64];
@@ -117,101 +125,124 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     uint32_t slot = qbr::block_exclusive_scan<uint32_t, kEmitThreads>(nr, &nruns, s_scan);
     total = __builtin_amdgcn_readfirstlane(total);
     nruns = __builtin_amdgcn_readfirstlane(nruns);
-#pragma unroll
-    for (int i = 0; i < QB_MAX_SEG; ++i) {
-        uint32_t len = (uint32_t)q.len[i];
-        uint32_t sz = (uint32_t)q.n[i] * len;
-        if (sz > 0) {
-            uint32_t tb, a;
-            int32_t b;
-            if (q.axis) {
-                tb = (uint32_t)(q.s0[i] * tiles_x + q.lo[i]);
-                a = 1;
-                b = tiles_x - (int)len;
-            } else {
-                tb = (uint32_t)(q.lo[i] * tiles_x + q.s0[i]);
-                a = (uint32_t)tiles_x;
-                b = 1 - (int)len * tiles_x;
-            }
-            s_off[slot] = off;
-            s_run[slot] = make_uint4(gi, __float_as_uint(__builtin_amdgcn_rcpf((float)len)), tb | a << 16,
-                                     (uint32_t)b);
-            ++slot;
-            off += sz;
-        }
-    }
-    if (t == 0) s_off[nruns] = total;  // sentinel
-#pragma unroll
-    for (int c = 0; c < kChains; ++c) s_tab[wave][c][lane] = 0xFFFFFFFFu;
     int64_t block_start = (int64_t)goff[k0];
-    // the pairs of the block fill [block_start, block_start + total) <= num_pairs
-    // <= cap; the bound below only keeps a stale offset table inside the buffer
-    if (block_start + (int64_t)total > cap) total = cap > block_start ? (uint32_t)(cap - block_start) : 0u;
-    __syncthreads();
-    // each of the block's waves x kChains ranges is a contiguous share of its
-    // pairs, walked 64 per step; the run holding a step's first pair is the
-    // run of the previous step's last pair, so only a range's first step
-    // searches for it
-    uint32_t per = (total + NW * kChains - 1) / (NW * kChains);
-    uint32_t base[kChains], hi[kChains];
-    int cur[kChains];
+    // One walk: the runs of the lanes that take part (mine) go to the run
+    // list at their slots, and the walk's `total` pairs are written from
+    // pair `start` on.  Ends with a barrier, so that a second walk may reuse
+    // the list.
+    auto walk = [&](bool mine, uint32_t off, uint32_t slot, uint32_t total, uint32_t nruns, int64_t start) {
 #pragma unroll
-    for (int c = 0; c < kChains; ++c) {
-        uint32_t lo = min(total, (uint32_t)(wave * kChains + c) * per);
-        base[c] = lo;
-        hi[c] = min(total, lo + per);
-        int a = 0, b = (int)nruns;
-        while (b - a > 1) {
-            int mid = (a + b) >> 1;
-            if (__builtin_amdgcn_readfirstlane(s_off[mid]) <= lo) a = mid; else b = mid;
-        }
-        cur[c] = a;
-    }
-    for (;;) {
-        bool left = false;
-#pragma unroll
-        for (int c = 0; c < kChains; ++c) left = left || base[c] < hi[c];
-        if (!left) break;
-        // every later run that starts inside a range's step writes its start
-        // into the owner table slot of its first pair.  Starts only grow, so a
-        // slot holds the current step's pair exactly when that pair starts a
-        // run; the run of a pair is cur + the run starts at or before it.
-#pragma unroll
-        for (int c = 0; c < kChains; ++c) {
-            uint32_t jj = (uint32_t)cur[c] + 1u + lane;
-            if (base[c] < hi[c] && jj < nruns) {
-                uint32_t d = s_off[jj] - base[c];
-                if (d < 64u) s_tab[wave][c][d] = base[c] + d;
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int c = 0; c < kChains; ++c) {
-            if (base[c] < hi[c]) {
-                uint32_t p = base[c] + lane;
-                uint64_t m = __builtin_amdgcn_ballot_w64(s_tab[wave][c][lane] == p);
-                uint32_t c0 = (uint32_t)cur[c] + (uint32_t)(m & 1u);
-                m >>= 1;
-                uint32_t o = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, c0));
-                if (p < hi[c]) {
-                    uint32_t local = p - s_off[o];
-                    uint4 rr = s_run[o];
-                    float r = __uint_as_float(rr.y);
-                    uint32_t qq = (uint32_t)__builtin_fmaf((float)local, r, 0.5f * r);
-                    uint32_t tile = (rr.z & 0xFFFFu) + __umul24(local, rr.z >> 16) + (uint32_t)__mul24((int)qq, (int)rr.w);
-                    int64_t wbase = block_start + base[c];
-                    if (id_bits) {
-                        out_id[wbase + lane] = (tile << id_bits) | rr.x;
-                    } else {
-                        out_tile[wbase + lane] = (uint16_t)tile;
-                        out_id[wbase + lane] = rr.x;
-                    }
+        for (int i = 0; i < QB_MAX_SEG; ++i) {
+            uint32_t len = (uint32_t)q.len[i];
+            uint32_t sz = (uint32_t)q.n[i] * len;
+            if (mine && sz > 0) {
+                uint32_t tb, a;
+                int32_t b;
+                if (q.axis) {
+                    tb = (uint32_t)(q.s0[i] * tiles_x + q.lo[i]);
+                    a = 1;
+                    b = tiles_x - (int)len;
+                } else {
+                    tb = (uint32_t)(q.lo[i] * tiles_x + q.s0[i]);
+                    a = (uint32_t)tiles_x;
+                    b = 1 - (int)len * tiles_x;
                 }
-                cur[c] = __builtin_amdgcn_readlane((int)o, 63);
-                base[c] += 64;
+                s_off[slot] = off;
+                s_run[slot] = make_uint4(gi, __float_as_uint(__builtin_amdgcn_rcpf((float)len)), tb | a << 16,
+                                         (uint32_t)b);
+                ++slot;
+                off += sz;
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        if (t == 0) s_off[nruns] = total;  // sentinel
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) s_tab[wave][c][lane] = 0xFFFFFFFFu;
+        // the pairs of the walk fill [start, start + total) <= num_pairs <= cap;
+        // the bound below only keeps a stale offset table inside the buffer
+        if (start + (int64_t)total > cap) total = cap > start ? (uint32_t)(cap - start) : 0u;
+        __syncthreads();
+        // each of the block's waves x kChains ranges is a contiguous share of its
+        // pairs, walked 64 per step; the run holding a step's first pair is the
+        // run of the previous step's last pair, so only a range's first step
+        // searches for it
+        uint32_t per = (total + NW * kChains - 1) / (NW * kChains);
+        uint32_t base[kChains], hi[kChains];
+        int cur[kChains];
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) {
+            uint32_t lo = min(total, (uint32_t)(wave * kChains + c) * per);
+            base[c] = lo;
+            hi[c] = min(total, lo + per);
+            int a = 0, b = (int)nruns;
+            while (b - a > 1) {
+                int mid = (a + b) >> 1;
+                if (__builtin_amdgcn_readfirstlane(s_off[mid]) <= lo) a = mid; else b = mid;
+            }
+            cur[c] = a;
+        }
+        for (;;) {
+            bool left = false;
+#pragma unroll
+            for (int c = 0; c < kChains; ++c) left = left || base[c] < hi[c];
+            if (!left) break;
+            // every later run that starts inside a range's step writes its start
+            // into the owner table slot of its first pair.  Starts only grow, so a
+            // slot holds the current step's pair exactly when that pair starts a
+            // run; the run of a pair is cur + the run starts at or before it.
+#pragma unroll
+            for (int c = 0; c < kChains; ++c) {
+                uint32_t jj = (uint32_t)cur[c] + 1u + lane;
+                if (base[c] < hi[c] && jj < nruns) {
+                    uint32_t d = s_off[jj] - base[c];
+                    if (d < 64u) s_tab[wave][c][d] = base[c] + d;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = 0; c < kChains; ++c) {
+                if (base[c] < hi[c]) {
+                    uint32_t p = base[c] + lane;
+                    uint64_t m = __builtin_amdgcn_ballot_w64(s_tab[wave][c][lane] == p);
+                    uint32_t c0 = (uint32_t)cur[c] + (uint32_t)(m & 1u);
+                    m >>= 1;
+                    uint32_t o = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, c0));
+                    if (p < hi[c]) {
+                        uint32_t local = p - s_off[o];
+                        uint4 rr = s_run[o];
+                        float r = __uint_as_float(rr.y);
+                        uint32_t qq = (uint32_t)__builtin_fmaf((float)local, r, 0.5f * r);
+                        uint32_t tile = (rr.z & 0xFFFFu) + __umul24(local, rr.z >> 16) + (uint32_t)__mul24((int)qq, (int)rr.w);
+                        int64_t wbase = start + base[c];
+                        if (id_bits) {
+                            out_id[wbase + lane] = (tile << id_bits) | rr.x;
+                        } else {
+                            out_tile[wbase + lane] = (uint16_t)tile;
+                            out_id[wbase + lane] = rr.x;
+                        }
+                    }
+                    cur[c] = __builtin_amdgcn_readlane((int)o, 63);
+                    base[c] += 64;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+    };
+    if (nruns <= (uint32_t)kRuns) {
+        walk(true, off, slot, total, nruns, block_start);
+    } else {
+        // two walks: the first half of the lanes' Gaussians, then the second
+        int64_t start = block_start;
+        for (int part = 0; part < 2; ++part) {
+            bool mine = (t >= part * (kEmitThreads / 2)) && (t < (part + 1) * (kEmitThreads / 2));
+            uint32_t pt, pr;
+            uint32_t po = qbr::block_exclusive_scan<uint32_t, kEmitThreads>(mine ? cnt : 0u, &pt, s_scan);
+            uint32_t ps = qbr::block_exclusive_scan<uint32_t, kEmitThreads>(mine ? nr : 0u, &pr, s_scan);
+            pt = __builtin_amdgcn_readfirstlane(pt);
+            pr = __builtin_amdgcn_readfirstlane(pr);
+            walk(mine, po, ps, pt, pr, start);
+            start += pt;
+        }
     }
 }
 

@@ -454,6 +454,119 @@ def test_depth_key_spans(qb):
         say(f"{n} Gaussians: every key span and depth-sort shape emits the stable key order")
 
 
+def _qpass_run_counts(r):
+    """Runs per Gaussian of QPass (Sec. 3.2) over rects [n, 4, (x0, x1, y0,
+    y1)]: scanlines along the shorter axis of the union's extent, split at
+    every sub-box start and end + 1; only used to check that a test's blocks
+    exceed the emission's run list."""
+    big = 1 << 30
+    x0, x1, y0, y1 = (r[..., i].astype(np.int64) for i in range(4))
+    act = (x0 <= x1) & (y0 <= y1)
+    wide = (np.where(act, x1, -big).max(1) - np.where(act, x0, big).min(1)
+            > np.where(act, y1, -big).max(1) - np.where(act, y0, big).min(1))
+    a = np.where(act, np.where(wide[:, None], y0, x0), big)
+    b = np.where(act, np.where(wide[:, None], y1, x1), big - 1)
+    oa, ob = np.where(wide[:, None], x0, y0), np.where(wide[:, None], x1, y1)
+    e = np.sort(np.concatenate([a, b + 1], 1), 1)
+    runs = np.zeros(len(r), np.int64)
+    for i in range(7):
+        s0, s1 = e[:, i], e[:, i + 1]
+        cover = (a <= s0[:, None]) & (b >= s0[:, None])
+        lo, hi = np.where(cover, oa, big).min(1), np.where(cover, ob, -big).max(1)
+        runs += (s1 > s0) & (s0 < big) & (hi >= lo)
+    return runs
+
+
+def test_emission_blocks_with_many_runs(qb):
+    """Synthetic sub-boxes that all hold one centre tile (as QuadBox's do)
+    with 5 to 7 QPass runs per Gaussian, so that every emission workgroup
+    holds more runs than its run list and walks its two halves one after the
+    other: for every emission shape, on both pair formats, the sorted ids and
+    ranges equal a stable sort by tile of each Gaussian's tile set (the union
+    of its sub-boxes), Gaussians in (depth key, id) order; a few Gaussians
+    cover no tile (key 0xFFFFFFFF)."""
+    rng = np.random.default_rng(11)
+    W, H = 1280, 720
+    tx, ty = (W + 15) // 16, (H + 15) // 16
+    rects, got = [], 0
+    while got < 4096:
+        m = 20000
+        c = np.stack([rng.integers(6, tx - 6, m), rng.integers(6, ty - 6, m)], 1)
+        ext = rng.integers(0, 6, (m, 4, 4))
+        r = np.empty((m, 4, 4), np.int64)
+        r[..., 0] = c[:, None, 0] - ext[..., 0]
+        r[..., 1] = c[:, None, 0] + ext[..., 1]
+        r[..., 2] = c[:, None, 1] - ext[..., 2]
+        r[..., 3] = c[:, None, 1] + ext[..., 3]
+        keep = r[_qpass_run_counts(r) >= 5]
+        rects.append(keep)
+        got += len(keep)
+    r = np.concatenate(rects)[:4096]
+    n = len(r)
+    cover = np.ones(n, bool)
+    cover[rng.choice(n, 40, replace=False)] = False
+    r[~cover, :, 0] = 1   # empty sub-boxes: x0 > x1
+    r[~cover, :, 1] = 0
+    tiles_of = []
+    for i in range(n):
+        t = set()
+        if cover[i]:
+            for k in range(4):
+                for yy in range(r[i, k, 2], r[i, k, 3] + 1):
+                    t.update(range(yy * tx + r[i, k, 0], yy * tx + r[i, k, 1] + 1))
+        tiles_of.append(np.array(sorted(t), np.int64))
+    counts = np.array([len(t) for t in tiles_of], np.int32)
+    depth = rng.uniform(1.0, 9.0, n).astype(np.float32)
+    depth[:300] = depth[300:600]   # ties, ordered by id
+    keys = np.where(cover, depth.view(np.uint32), np.uint32(0xFFFFFFFF)).astype(np.uint32)
+    # reference: Gaussians in (key, id) order, each with its tile set, then a
+    # stable sort by tile
+    order = np.nonzero(cover)[0][np.argsort(keys[cover], kind="stable")]
+    pt = np.concatenate([tiles_of[i] for i in order])
+    pi = np.concatenate([np.full(len(tiles_of[i]), i, np.int64) for i in order])
+    srt = np.argsort(pt, kind="stable")
+    want_ids = pi[srt].astype(np.uint32)
+    want_ranges = np.stack([np.searchsorted(pt[srt], np.arange(tx * ty), "left"),
+                            np.searchsorted(pt[srt], np.arange(tx * ty), "right")], 1).astype(np.uint32)
+    P = int(counts.sum())
+    assert P == len(want_ids)
+    # every emission block size sees blocks with more runs than its list
+    runs = np.where(cover, _qpass_run_counts(r), 0)[order]
+    for nt in (128, 256, 512):
+        full = len(runs) // nt * nt
+        assert (runs[:full].reshape(-1, nt).sum(1) > 4 * nt).any(), nt
+    dev = torch.device("cuda")
+    rects_dev = torch.from_numpy(r.astype(np.int16).reshape(n, 16)).to(dev)
+    counts_dev = torch.from_numpy(counts).to(dev)
+    keys_dev = torch.from_numpy(keys.view(np.int32)).to(dev)
+    splats = torch.zeros((n, 12), dtype=torch.float32, device=dev)
+    cap = P + 1000
+    pair_tiles = torch.empty(cap, dtype=torch.int16, device=dev)
+    pair_ids = torch.empty(cap, dtype=torch.int32, device=dev)
+    num_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws_i = torch.empty(qb.intersect_workspace_size(n), dtype=torch.uint8, device=dev)
+    ws_s = torch.empty(qb.sort_workspace_size(cap), dtype=torch.uint8, device=dev)
+    ids = torch.empty(cap, dtype=torch.int32, device=dev)
+    ranges = torch.empty((tx * ty, 2), dtype=torch.int32, device=dev)
+    bits = qb.pair_id_bits(n, W, H)
+    assert bits > 0
+    for en, ev in qb.EMIT_VARIANTS.items():
+        for packed in (0, bits):
+            pair_ids.fill_(-1)
+            ids.fill_(-1)
+            ranges.fill_(-1)
+            qb.intersect(n, splats, rects_dev, counts_dev, W, H, cap, None if packed else pair_tiles, pair_ids,
+                         num_pairs, ws_i, "quadbox", 0, ev, keys_dev, packed)
+            qb.sort(cap, num_pairs, tx * ty, None if packed else pair_tiles, pair_ids, splats, None, ids, ranges,
+                    ws_s, 0, packed)
+            torch.cuda.synchronize()
+            tag = (en, packed)
+            assert int(num_pairs.item()) == P, tag
+            assert np.array_equal(ids[:P].cpu().numpy().view(np.uint32), want_ids), tag
+            assert np.array_equal(ranges.cpu().numpy().view(np.uint32), want_ranges), tag
+    say(f"{n} Gaussians with 5-7 runs each, {P} pairs: every emission shape walks its blocks in two halves")
+
+
 def test_intersect_and_sort_launch_shapes(oracle, qb):
     """Every depth-sort and emission shape of qb_intersect_ex writes the same
     pairs in the same order, with the depth keys of qb_project_ex and with
