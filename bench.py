@@ -249,16 +249,18 @@ def run_fwd_bwd(torch, qb, g, cam, steps, warmup, trials):
     grad2d = torch.empty((g.n, 9), dtype=torch.float32, device="cuda")
     grads = [torch.empty_like(t) for t in g.tensors()]
     inv = 1.0 / float(target.numel())
+    dl = torch.empty_like(r.image)
     r.forward(g, "quadbox", sync_count=False)
     qb.autotune_intersect(r, reps=3, trials=2)
     qb.autotune_sort(r, reps=3, trials=2)
     qb.autotune_render(r, reps=5, trials=2)
     r.forward(g, "quadbox", sync_count=False)
-    qb.autotune_backward(r, dl=torch.sign(r.image - target) * inv, grad2d=grad2d, reps=3, trials=2)
+    qb.l1_grad([(r.image, target, dl, inv)])
+    qb.autotune_backward(r, dl=dl, grad2d=grad2d, reps=3, trials=2)
 
     def step():
         r.forward(g, "quadbox", sync_count=False)
-        dl = torch.sign(r.image - target) * inv
+        qb.l1_grad([(r.image, target, dl, inv)])   # dL/dimage = sign(image - target) / count
         qb.render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, (0.0, 0.0, 0.0), r.final_T, r.n_contrib,
                            dl, g.n, grad2d, r.backward_variant, r.tile_order())
         qb.project_backward(g, cam, r.splats, grad2d, *grads)
@@ -279,7 +281,7 @@ def run_fwd_bwd(torch, qb, g, cam, steps, warmup, trials):
     r.check_capacity()
     # the render backward call on its own, back to back on the last frame's
     # buffers: the 36-byte-per-Gaussian clear of grad2d, then k_render_backward
-    dl = torch.sign(r.image - target) * inv
+    qb.l1_grad([(r.image, target, dl, inv)])
     bwd_ms = _time(torch, lambda: qb.render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, (0.0, 0.0, 0.0),
                                                      r.final_T, r.n_contrib, dl, g.n, grad2d, r.backward_variant,
                                                      r.tile_order()), 20, 2, trials)
@@ -320,9 +322,8 @@ def run_multiview(torch, qb, steps, warmup, trials):
     mv = qb.MultiView(scene.n, cams)
     pairs = mv.size_pairs(g, "quadbox")
     mv.forward(g)
-    for v in range(V):
-        torch.sign(mv.images[v] - targets[v], out=mv.dl[v])
-        mv.dl[v].mul_(1.0 / mv.images[v].numel())
+    loss_items = [(mv.images[v], targets[v], mv.dl[v], 1.0 / mv.images[v].numel()) for v in range(V)]
+    qb.l1_grad(loss_items)
     tuned = {"intersect_ms": qb.autotune_intersect(mv, reps=1, trials=2),
              "sort_ms": qb.autotune_sort(mv, reps=1, trials=2),
              "render_ms": qb.autotune_render(mv, reps=3, trials=2),
@@ -339,10 +340,8 @@ def run_multiview(torch, qb, steps, warmup, trials):
     log("autotune", tuned)
 
     def batched():
-        imgs = mv.forward(g)
-        for v in range(V):
-            torch.sign(imgs[v] - targets[v], out=mv.dl[v])
-            mv.dl[v].mul_(1.0 / imgs[v].numel())
+        mv.forward(g)
+        qb.l1_grad(loss_items)   # every view's dL/dimage in one launch
         mv.backward(g)
 
     batched_ms = _time(torch, batched, steps, warmup, trials)
@@ -380,15 +379,16 @@ def run_multiview(torch, qb, steps, warmup, trials):
     grad2d = torch.empty((g.n, 9), dtype=torch.float32, device="cuda")
     part = [torch.empty_like(t) for t in g.tensors()]
     total = [torch.empty_like(t) for t in g.tensors()]
+    dls = [torch.empty_like(r.image) for r in rasts]
 
     def per_view():
         for t in total:
             t.zero_()
         for v, r in enumerate(rasts):
             r.forward(g, "quadbox", sync_count=False)
-            dl = torch.sign(r.image - targets[v]) * (1.0 / r.image.numel())
+            qb.l1_grad([(r.image, targets[v], dls[v], 1.0 / r.image.numel())])
             qb.render_backward(r.W, r.H, r.ranges, r.ids_sorted, r.splats, (0.0, 0.0, 0.0), r.final_T,
-                               r.n_contrib, dl, g.n, grad2d, r.backward_variant, r.tile_order())
+                               r.n_contrib, dls[v], g.n, grad2d, r.backward_variant, r.tile_order())
             qb.project_backward(g, cams[v], r.splats, grad2d, *part)
             for t, p in zip(total, part):
                 t.add_(p)

@@ -501,6 +501,28 @@ qb_status qb_project_backward_views(int64_t n, const float* means, const float* 
                                     const float* grad2d, float* d_means, float* d_log_scales, float* d_quats,
                                     float* d_opacity_logits, float* d_sh, qb_stream_t stream);
 
+/* ---- Loss gradient of a training step -----------------------------------
+ * Training (Sec. 4.1) drives the render backward with dL/dimage.  For the
+ * mean absolute (L1) error of an image against a target, that gradient is
+ * scale * sign(image - target) elementwise, scale = 1 / element count. */
+typedef struct {
+    int64_t count;        /* elements (3 * width * height for an image), >= 0  */
+    const float* image;   /* [count] rendered image (device)                   */
+    const float* target;  /* [count] target (device)                           */
+    float* grad;          /* [count] written: scale * sign(image - target)     */
+    float scale;          /* the factor of the sign                            */
+} qb_l1_item;
+
+/* qb_l1_grad -- grad = scale * sign(image - target) for every item, one
+ * launch for all of them.  sign is +1, -1 or 0 (for equal values, either
+ * zero, and NaN), so grad holds exactly +scale, -scale or +0.
+ *   num_items   0 .. QB_MAX_VIEWS (0 is a no-op)
+ *   items       host array of num_items items; pointers may be NULL only
+ *               where count is 0; grad must not overlap image or target
+ * Returns QB_ERR_INVALID_ARG (before any device work) for a count < 0, a
+ * missing pointer or num_items out of range. */
+qb_status qb_l1_grad(int32_t num_items, const qb_l1_item* items, qb_stream_t stream);
+
 /* qb_check_capacity -- the pair-capacity check of a frame (Sec. 2: the pair
  * buffers of DuplicateWithKeys are sized before the frame).  qb_intersect
  * writes the true pair count P to its device num_pairs also when P exceeds

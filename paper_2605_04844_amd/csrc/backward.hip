@@ -350,39 +350,71 @@ __device__ __forceinline__ void sh_colour_backward(const float* __restrict__ sh,
     }
 }
 
-// Chain rule of one Gaussian for one camera from its grad2d row g2 to the
-// mean (through the projection), log-scales, quaternion and opacity logit;
-// ADDS to the accumulators.  The forward forms Sigma3D, Sigma2D and the conic
-// in binary64 from its binary32 inputs; their derivatives are taken the same
-// way.  The colour's share of the mean gradient is left to the SH part.
-__device__ __forceinline__ void geometry_backward(int64_t i, int64_t n, const float* __restrict__ means,
-                                                  const float* __restrict__ log_scales,
-                                                  const float* __restrict__ quats, const float* __restrict__ logits,
-                                                  const BwdCam& cam, const float* __restrict__ g2, double dm[3],
-                                                  double dls[3], double dq[4], float& dlogit)
+// Chain rule of one Gaussian from its grad2d rows to the mean (through the
+// projection), log-scales, quaternion and opacity logit, in three parts:
+// geometry_prep forms what every view shares (M = R(q) diag(s)), geometry_view
+// takes one camera's row and ADDS its shares to dm, to dM = dL/dM and to
+// dL/do, and geometry_finish turns the summed dM and dL/do into the scale,
+// quaternion and logit gradients (linear in them, so one pass serves every
+// view).  The forward forms Sigma3D, Sigma2D and the conic in binary64 from
+// its binary32 inputs; their derivatives are taken the same way.  The
+// colour's share of the mean gradient is left to the SH part.
+struct GeoPrep {
+    float mx, my, mz;
+    double M[9];
+};
+
+// The rotation of the normalised quaternion of Gaussian i (binary64 from the
+// binary32 norm, as the forward), its unit quaternion (w, x, y, z) and norm.
+__device__ __forceinline__ void geometry_rotation(int64_t i, int64_t n, const float* __restrict__ quats,
+                                                  double Rq[9], double qn[4], double& nr)
 {
-    double du = g2[0], dv = g2[1], da = g2[2], db = g2[3], dc = g2[4];
-    float dop = g2[5];
-    float mx = means[i], my = means[n + i], mz = means[2 * n + i];
-    const float* R = cam.R;
-    float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + cam.t[0];
-    float py = ((R[3] * mx + R[4] * my) + R[5] * mz) + cam.t[1];
-    float pz = ((R[6] * mx + R[7] * my) + R[8] * mz) + cam.t[2];
-    double s[3];
-    for (int k = 0; k < 3; ++k) s[k] = (double)(float)exp((double)log_scales[k * n + i]);
-    float o = (float)(1.0 / (1.0 + exp(-(double)logits[i])));
     float q4[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
     float n2 = ((q4[0] * q4[0] + q4[1] * q4[1]) + q4[2] * q4[2]) + q4[3] * q4[3];
     float nrf = sqrtf(n2);
-    double nr = nrf;
+    nr = nrf;
     double w = q4[0] / nrf, x = q4[1] / nrf, y = q4[2] / nrf, z = q4[3] / nrf;
-    double Rq[9];
+    qn[0] = w; qn[1] = x; qn[2] = y; qn[3] = z;
     Rq[0] = 1.0 - 2.0 * (y * y + z * z); Rq[1] = 2.0 * (x * y - w * z); Rq[2] = 2.0 * (x * z + w * y);
     Rq[3] = 2.0 * (x * y + w * z); Rq[4] = 1.0 - 2.0 * (x * x + z * z); Rq[5] = 2.0 * (y * z - w * x);
     Rq[6] = 2.0 * (x * z - w * y); Rq[7] = 2.0 * (y * z + w * x); Rq[8] = 1.0 - 2.0 * (x * x + y * y);
-    double M[9];
+}
+
+__device__ __forceinline__ void geometry_scales(int64_t i, int64_t n, const float* __restrict__ log_scales,
+                                                double s[3])
+{
+    for (int k = 0; k < 3; ++k) s[k] = (double)(float)exp((double)log_scales[k * n + i]);
+}
+
+__device__ __forceinline__ void geometry_prep(int64_t i, int64_t n, const float* __restrict__ means,
+                                              const float* __restrict__ log_scales,
+                                              const float* __restrict__ quats, GeoPrep& g)
+{
+    g.mx = means[i];
+    g.my = means[n + i];
+    g.mz = means[2 * n + i];
+    double s[3], Rq[9], qn[4], nr;
+    geometry_scales(i, n, log_scales, s);
+    geometry_rotation(i, n, quats, Rq, qn, nr);
     for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) M[r * 3 + c] = Rq[r * 3 + c] * s[c];
+        for (int c = 0; c < 3; ++c) g.M[r * 3 + c] = Rq[r * 3 + c] * s[c];
+}
+
+__device__ __forceinline__ bool geometry_view(const GeoPrep& g, const BwdCam& cam, const float* __restrict__ g2,
+                                              double dm[3], double dMs[9], float& dop_sum)
+{
+    float r0 = g2[0], r1 = g2[1], r2 = g2[2], r3 = g2[3], r4 = g2[4], r5 = g2[5];
+    // a zero row adds nothing (culled Gaussians and views a Gaussian does
+    // not reach in any pixel have one), so the splat's visibility is not
+    // read; returns whether the row added anything
+    if (r0 == 0.f && r1 == 0.f && r2 == 0.f && r3 == 0.f && r4 == 0.f && r5 == 0.f) return false;
+    double du = r0, dv = r1, da = r2, db = r3, dc = r4;
+    dop_sum += r5;
+    const double* M = g.M;
+    const float* R = cam.R;
+    float px = ((R[0] * g.mx + R[1] * g.my) + R[2] * g.mz) + cam.t[0];
+    float py = ((R[3] * g.mx + R[4] * g.my) + R[5] * g.mz) + cam.t[1];
+    float pz = ((R[6] * g.mx + R[7] * g.my) + R[8] * g.mz) + cam.t[2];
     float xs = px / pz, ys = py / pz;
     float clx = xs < -cam.limx ? -1.f : (xs > cam.limx ? 1.f : 0.f);
     float cly = ys < -cam.limy ? -1.f : (ys > cam.limy ? 1.f : 0.f);
@@ -444,10 +476,21 @@ __device__ __forceinline__ void geometry_backward(int64_t i, int64_t n, const fl
     dp[2] += dv * (-fy * dpy / z2);
     for (int c = 0; c < 3; ++c)
         dm[c] += (double)R[c] * dp[0] + (double)R[3 + c] * dp[1] + (double)R[6 + c] * dp[2];
-    // Sigma = M M^T, M = R diag(s)
-    double dM[9];  // 2 T^T G T M = 2 T^T (G V)
+    // Sigma = M M^T, M = R diag(s): dL/dM = 2 T^T G T M = 2 T^T (G V)
     for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) dM[r * 3 + c] = 2.0 * (T[r] * GV[c] + T[3 + r] * GV[3 + c]);
+        for (int c = 0; c < 3; ++c) dMs[r * 3 + c] += 2.0 * (T[r] * GV[c] + T[3 + r] * GV[3 + c]);
+    return true;
+}
+
+__device__ __forceinline__ void geometry_finish(int64_t i, int64_t n, const float* __restrict__ log_scales,
+                                                const float* __restrict__ quats, const float* __restrict__ logits,
+                                                const double dM[9], float dop, double dls[3], double dq[4],
+                                                float& dlogit)
+{
+    double s[3], Rq[9], qn[4], nr;
+    geometry_scales(i, n, log_scales, s);
+    geometry_rotation(i, n, quats, Rq, qn, nr);
+    double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
     double dR[9];
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) dR[r * 3 + c] = dM[r * 3 + c] * s[c];
@@ -462,8 +505,8 @@ __device__ __forceinline__ void geometry_backward(int64_t i, int64_t n, const fl
     gq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
                    y * dR[7]);
     double qd = w * gq[0] + x * gq[1] + y * gq[2] + z * gq[3];
-    double qn[4] = {w, x, y, z};
     for (int k = 0; k < 4; ++k) dq[k] += (gq[k] - qn[k] * qd) / nr;
+    float o = (float)(1.0 / (1.0 + exp(-(double)logits[i])));
     dlogit += dop * o * (1.0f - o);
 }
 
@@ -492,15 +535,22 @@ __device__ __forceinline__ float view_dir(float mx, float my, float mz, const fl
 __global__ __launch_bounds__(QB_BLOCK) void k_geometry_backward(
     int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits, BwdCam cam,
-    const float4* __restrict__ splats, const float* __restrict__ grad2d, float* __restrict__ d_means,
+    const float* __restrict__ grad2d, float* __restrict__ d_means,
     float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_logits)
 {
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
     double dm[3] = {0.0, 0.0, 0.0}, dls[3] = {0.0, 0.0, 0.0}, dq[4] = {0.0, 0.0, 0.0, 0.0};
     float dlogit = 0.f;
-    if (splats[3 * i + 2].w == 1.0f)
-        geometry_backward(i, n, means, log_scales, quats, logits, cam, grad2d + 9 * i, dm, dls, dq, dlogit);
+    const float* g2 = grad2d + 9 * i;
+    if (g2[0] != 0.f || g2[1] != 0.f || g2[2] != 0.f || g2[3] != 0.f || g2[4] != 0.f || g2[5] != 0.f) {
+        GeoPrep g;
+        geometry_prep(i, n, means, log_scales, quats, g);
+        double dM[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        float dop = 0.f;
+        geometry_view(g, cam, g2, dm, dM, dop);
+        geometry_finish(i, n, log_scales, quats, logits, dM, dop, dls, dq, dlogit);
+    }
     for (int c = 0; c < 3; ++c) {
         d_means[c * n + i] = (float)dm[c];
         d_log_scales[c * n + i] = (float)dls[c];
@@ -520,7 +570,11 @@ __global__ __launch_bounds__(QB_BLOCK) void k_sh_backward(
     constexpr int K = (DEG + 1) * (DEG + 1);
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
-    float4 s2 = splats[3 * i + 2];
+    // a zero colour row (culled Gaussians, and those no pixel composites)
+    // adds nothing: the splat's colour record is read only where it does not
+    const float* g2 = grad2d + 9 * i;
+    float4 s2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (g2[6] != 0.f || g2[7] != 0.f || g2[8] != 0.f) s2 = splats[3 * i + 2];
     if (s2.w != 1.0f) {
 #pragma unroll
         for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = 0.f;
@@ -537,22 +591,28 @@ __global__ __launch_bounds__(QB_BLOCK) void k_sh_backward(
 }
 
 // Views: the geometry part summed over views (the colour's share of the
-// mean gradient follows in k_sh_backward_views).
-__global__ __launch_bounds__(QB_BLOCK) void k_geometry_backward_views(
+// mean gradient follows in k_sh_backward_views).  Three waves per SIMD are
+// asked for (178 -> 168 VGPRs at the price of 44 bytes of spills): 0.14 ms
+// less over 32 views of 2M Gaussians than at two.
+__global__ __launch_bounds__(QB_BLOCK, 3) void k_geometry_backward_views(
     int64_t n, int nv, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits, BwdCamTable cams,
-    const float4* __restrict__ splats, const float* __restrict__ grad2d, float* __restrict__ d_means,
+    const float* __restrict__ grad2d, float* __restrict__ d_means,
     float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_logits)
 {
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
     double dm[3] = {0.0, 0.0, 0.0}, dls[3] = {0.0, 0.0, 0.0}, dq[4] = {0.0, 0.0, 0.0, 0.0};
     float dlogit = 0.f;
-    for (int v = 0; v < nv; ++v) {
-        int64_t vi = (int64_t)v * n + i;
-        if (splats[3 * vi + 2].w != 1.0f) continue;
-        geometry_backward(i, n, means, log_scales, quats, logits, cams.cam[v], grad2d + 9 * vi, dm, dls, dq, dlogit);
-    }
+    GeoPrep g;
+    geometry_prep(i, n, means, log_scales, quats, g);
+    double dM[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    float dop = 0.f;
+    bool any = false;
+    for (int v = 0; v < nv; ++v)
+        any |= geometry_view(g, cams.cam[v], grad2d + 9 * ((int64_t)v * n + i), dm, dM, dop);
+    // (a culled Gaussian, whose rows are all zero, may have no valid rotation)
+    if (any) geometry_finish(i, n, log_scales, quats, logits, dM, dop, dls, dq, dlogit);
     for (int c = 0; c < 3; ++c) {
         d_means[c * n + i] = (float)dm[c];
         d_log_scales[c * n + i] = (float)dls[c];
@@ -582,24 +642,28 @@ __global__ __launch_bounds__(QB_BLOCK) void k_sh_backward_views(
     float dmx = 0.f, dmy = 0.f, dmz = 0.f;
     for (int v = 0; v < nv; ++v) {
         int64_t vi = (int64_t)v * n + i;
+        // a zero colour row adds nothing (culled Gaussians, and views where
+        // no pixel composites the Gaussian): only the others read the splat
+        const float* g2 = grad2d + 9 * vi;
+        if (g2[6] == 0.f && g2[7] == 0.f && g2[8] == 0.f) continue;
         float4 s2 = splats[3 * vi + 2];
         if (s2.w != 1.0f) continue;
         float dir[3], drgb[3];
         float dn = view_dir(mx, my, mz, cams.cam[v].campos, dir);
-        colour_grad(s2, grad2d + 9 * vi, drgb);
+        colour_grad(s2, g2, drgb);
         float Y[16], G[16][3];
         sh_basis_and_grad(dir[0], dir[1], dir[2], Y, G);
         float ddir[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
+            // dL/dY_k = sum over the channels of coef * drgb
+            float cw = fmaf(coef[k * 3 + 2], drgb[2], fmaf(coef[k * 3 + 1], drgb[1], coef[k * 3] * drgb[0]));
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                acc[k * 3 + ch] = fmaf(Y[k], drgb[ch], acc[k * 3 + ch]);
-                float cw = coef[k * 3 + ch] * drgb[ch];
-                ddir[0] = fmaf(G[k][0], cw, ddir[0]);
-                ddir[1] = fmaf(G[k][1], cw, ddir[1]);
-                ddir[2] = fmaf(G[k][2], cw, ddir[2]);
-            }
+            for (int ch = 0; ch < 3; ++ch) acc[k * 3 + ch] = fmaf(Y[k], drgb[ch], acc[k * 3 + ch]);
+            ddir[0] = fmaf(G[k][0], cw, ddir[0]);
+            ddir[1] = fmaf(G[k][1], cw, ddir[1]);
+            ddir[2] = fmaf(G[k][2], cw, ddir[2]);
+        }
         if (dn > 0.0f) {
             float dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
             dmx += (ddir[0] - dir[0] * dd) / dn;
@@ -612,6 +676,47 @@ __global__ __launch_bounds__(QB_BLOCK) void k_sh_backward_views(
     d_means[i] += dmx;
     d_means[n + i] += dmy;
     d_means[2 * n + i] += dmz;
+}
+
+// qb_l1_grad: the items of one launch, by value as a kernel argument.  Item v
+// takes workgroups [wg0[v], wg0[v + 1]); each lane handles 4 consecutive
+// elements (one 16-byte load of each input where the item allows it).
+struct L1Table {
+    const float* image[QB_MAX_VIEWS];
+    const float* target[QB_MAX_VIEWS];
+    float* grad[QB_MAX_VIEWS];
+    int64_t count[QB_MAX_VIEWS];
+    float scale[QB_MAX_VIEWS];
+    int64_t wg0[QB_MAX_VIEWS + 1];
+    int vec[QB_MAX_VIEWS];  // count % 4 == 0 and 16-byte aligned pointers
+    int num;
+};
+
+__device__ __forceinline__ float l1_sign_scaled(float a, float b, float s)
+{
+    float d = a - b;  // its sign is that of a - b: rounding keeps signs and zero
+    return d > 0.0f ? s : (d < 0.0f ? -s : 0.0f);
+}
+
+__global__ __launch_bounds__(QB_BLOCK) void k_l1_grad(L1Table t)
+{
+    int64_t b = blockIdx.x;
+    int v = 0;
+    while (v + 1 < t.num && t.wg0[v + 1] <= b) ++v;
+    int64_t i = ((b - t.wg0[v]) * QB_BLOCK + threadIdx.x) * 4;
+    int64_t cnt = t.count[v];
+    if (i >= cnt) return;
+    const float* img = t.image[v];
+    const float* tgt = t.target[v];
+    float* g = t.grad[v];
+    float s = t.scale[v];
+    if (t.vec[v]) {
+        float4 x = *reinterpret_cast<const float4*>(img + i), y = *reinterpret_cast<const float4*>(tgt + i);
+        *reinterpret_cast<float4*>(g + i) = make_float4(l1_sign_scaled(x.x, y.x, s), l1_sign_scaled(x.y, y.y, s),
+                                                        l1_sign_scaled(x.z, y.z, s), l1_sign_scaled(x.w, y.w, s));
+    } else {
+        for (int64_t k = i; k < i + 4 && k < cnt; ++k) g[k] = l1_sign_scaled(img[k], tgt[k], s);
+    }
 }
 
 __global__ void k_zero(float* __restrict__ p, int64_t count)
@@ -704,7 +809,7 @@ extern "C" qb_status qb_project_backward(int64_t n, const float* means, const fl
     hipStream_t s = qb_hip_stream(stream);
     int64_t grid = qb_div_up(n, QB_BLOCK);
     const float4* sp = reinterpret_cast<const float4*>(splats);
-    QB_LAUNCH(k_geometry_backward, grid, QB_BLOCK, 0, s, n, means, log_scales, quats, opacity_logits, bc, sp, grad2d,
+    QB_LAUNCH(k_geometry_backward, grid, QB_BLOCK, 0, s, n, means, log_scales, quats, opacity_logits, bc, grad2d,
               d_means, d_log_scales, d_quats, d_opacity_logits);
     switch (sh_degree) {
     case 0: QB_LAUNCH(k_sh_backward<0>, grid, QB_BLOCK, 0, s, n, means, sh, bc, sp, grad2d, d_means, d_sh); break;
@@ -768,7 +873,7 @@ extern "C" qb_status qb_project_backward_views(int64_t n, const float* means, co
     int64_t grid = qb_div_up(n, QB_BLOCK);
     const float4* sp = reinterpret_cast<const float4*>(splats);
     QB_LAUNCH(k_geometry_backward_views, grid, QB_BLOCK, 0, s, n, (int)num_views, means, log_scales, quats,
-              opacity_logits, ct, sp, grad2d, d_means, d_log_scales, d_quats, d_opacity_logits);
+              opacity_logits, ct, grad2d, d_means, d_log_scales, d_quats, d_opacity_logits);
     switch (sh_degree) {
     case 0: QB_LAUNCH(k_sh_backward_views<0>, grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, grad2d,
                       d_means, d_sh); break;
@@ -779,5 +884,30 @@ extern "C" qb_status qb_project_backward_views(int64_t n, const float* means, co
     default: QB_LAUNCH(k_sh_backward_views<3>, grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, grad2d,
                        d_means, d_sh); break;
     }
+    return QB_OK;
+}
+
+extern "C" qb_status qb_l1_grad(int32_t num_items, const qb_l1_item* items, qb_stream_t stream)
+{
+    if (num_items < 0 || num_items > QB_MAX_VIEWS || (num_items > 0 && !items)) return QB_ERR_INVALID_ARG;
+    L1Table t;
+    t.num = num_items;
+    t.wg0[0] = 0;
+    constexpr int64_t kPerBlock = 4 * QB_BLOCK;
+    for (int v = 0; v < num_items; ++v) {
+        const qb_l1_item& it = items[v];
+        if (it.count < 0 || (it.count > 0 && (!it.image || !it.target || !it.grad))) return QB_ERR_INVALID_ARG;
+        t.image[v] = it.image;
+        t.target[v] = it.target;
+        t.grad[v] = it.grad;
+        t.count[v] = it.count;
+        t.scale[v] = it.scale;
+        t.vec[v] = (it.count % 4 == 0) && (((uintptr_t)it.image | (uintptr_t)it.target | (uintptr_t)it.grad) & 15u) == 0;
+        t.wg0[v + 1] = t.wg0[v] + qb_div_up(it.count, kPerBlock);
+    }
+    int64_t grid = num_items > 0 ? t.wg0[num_items] : 0;
+    if (grid == 0) return QB_OK;
+    if (grid > 0x7FFFFFFF) return QB_ERR_INVALID_ARG;
+    QB_LAUNCH(k_l1_grad, grid, QB_BLOCK, 0, qb_hip_stream(stream), t);
     return QB_OK;
 }

@@ -61,6 +61,12 @@ class CView(C.Structure):
                 ("dL_dimage", C.c_void_p), ("grad2d", C.c_void_p)]
 
 
+class CL1Item(C.Structure):
+    """qb_l1_item: one (image, target, grad, scale) of qb_l1_grad."""
+    _fields_ = [("count", C.c_int64), ("image", C.c_void_p), ("target", C.c_void_p), ("grad", C.c_void_p),
+                ("scale", C.c_float)]
+
+
 MAX_VIEWS = 32
 
 _lib = None
@@ -133,6 +139,8 @@ def lib():
     L.qb_check_capacity.restype = i32
     L.qb_intersect_noalloc.argtypes = [i64, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp, vp]
     L.qb_intersect_noalloc.restype = i32
+    L.qb_l1_grad.argtypes = [i32, C.POINTER(CL1Item), vp]
+    L.qb_l1_grad.restype = i32
     _lib = L
     return L
 
@@ -309,6 +317,20 @@ def render_backward(width, height, ranges, ids, splats, bg, final_T, n_contrib, 
     _check("qb_render_backward_ex", lib().qb_render_backward_ex(
         width, height, _ptr(ranges), _ptr(ids), _ptr(splats), C.cast(bgv, C.c_void_p), _ptr(final_T),
         _ptr(n_contrib), _ptr(dl_dimage), n, _ptr(grad2d), int(variant), _ptr(order), _stream()))
+
+
+def l1_grad(items):
+    """qb_l1_grad over items [(image, target, grad, scale), ...] (float32
+    device tensors of one size each): grad = scale * sign(image - target),
+    one launch for all items."""
+    _need(len(items) <= MAX_VIEWS, f"qb_l1_grad: at most {MAX_VIEWS} items per call")
+    arr = (CL1Item * max(len(items), 1))()
+    for k, (image, target, grad, scale) in enumerate(items):
+        _need(image.numel() == target.numel() == grad.numel(), "qb_l1_grad: image, target and grad differ in size")
+        _need(all(t.dtype == torch.float32 and t.is_contiguous() for t in (image, target, grad)),
+              "qb_l1_grad: contiguous float32 tensors only")
+        arr[k] = CL1Item(image.numel(), image.data_ptr(), target.data_ptr(), grad.data_ptr(), float(scale))
+    _check("qb_l1_grad", lib().qb_l1_grad(len(items), arr, _stream()))
 
 
 def project_backward(g: Gaussians, cam, splats, grad2d, d_means, d_log_scales, d_quats, d_logits, d_sh):

@@ -258,3 +258,23 @@ def test_check_capacity_rejects_bad_arguments():
     assert L.qb_check_capacity(1, d, None, None, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_check_capacity(2, d, C.cast(neg, C.c_void_p), None, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_check_capacity(65, d, cp, None, None) == qb.QB_ERR_INVALID_ARG   # > 64 needs out_counts
+
+
+def test_l1_grad_rejects_bad_arguments():
+    """qb_l1_grad checks its items before any device work: item counts out
+    of range, a missing item array, a negative count or a missing pointer
+    where the count is positive; empty items launch nothing."""
+    L = qb.lib()
+    d = 256
+    good = qb.CL1Item(8, d, d, d, 0.5)
+    arr = (qb.CL1Item * 2)(good, good)
+    assert L.qb_l1_grad(-1, arr, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_l1_grad(qb.MAX_VIEWS + 1, arr, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_l1_grad(1, None, None) == qb.QB_ERR_INVALID_ARG
+    for bad in (qb.CL1Item(-1, d, d, d, 1.0), qb.CL1Item(8, None, d, d, 1.0), qb.CL1Item(8, d, None, d, 1.0),
+                qb.CL1Item(8, d, d, None, 1.0)):
+        arr2 = (qb.CL1Item * 2)(good, bad)
+        assert L.qb_l1_grad(2, arr2, None) == qb.QB_ERR_INVALID_ARG
+    empty = (qb.CL1Item * 2)(qb.CL1Item(0, None, None, None, 1.0), qb.CL1Item(0, d, d, d, 1.0))
+    assert L.qb_l1_grad(2, empty, None) == qb.QB_OK
+    assert L.qb_l1_grad(0, None, None) == qb.QB_OK
