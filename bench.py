@@ -356,7 +356,7 @@ def run_multiview(torch, qb, steps, warmup, trials):
                                               render_kernel_name(tuned["picked"]["render"], views=True), work),
                  "render_backward_views": alu_roofline(backward_flops(work), bwd_ms,
                                                        f"k_render_backward_views<{tuned['picked']['render_backward'][0]}>",
-                                                       work, note="launch time includes the clear of every view's grad2d")}
+                                                       work)}
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):

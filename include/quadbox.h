@@ -501,6 +501,34 @@ qb_status qb_project_backward_views(int64_t n, const float* means, const float* 
                                     const float* grad2d, float* d_means, float* d_log_scales, float* d_quats,
                                     float* d_opacity_logits, float* d_sh, qb_stream_t stream);
 
+/* A batched training step without the clear of grad2d (32 views of 2M
+ * Gaussians hold 2.3 GB of it).  For callers that run the backward step
+ * after step on the same grad2d buffers: the projection backward already
+ * reads every row, so it can leave the rows at zero behind it, and the next
+ * render backward then adds into them without clearing.  The caller keeps
+ * the invariant "grad2d is all zero between steps": allocate it zeroed, and
+ * after anything else wrote it (qb_render_backward_views_ex without
+ * qb_project_backward_views_ex's clear) use the clearing entry points once. */
+
+/* qb_render_backward_views_acc -- qb_render_backward_views_ex that adds to
+ * each view's grad2d instead of clearing it first.  With grad2d all zero on
+ * entry the result is bit-identical to qb_render_backward_views_ex. */
+qb_status qb_render_backward_views_acc(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
+                                       int32_t variant, const uint32_t* tile_order, qb_stream_t stream);
+
+/* qb_project_backward_views_ex -- qb_project_backward_views; clear_grad2d 1:
+ * also sets every grad2d row to zero once read (grad2d is then written, hence
+ * not const), with the same d_* bit for bit; 0: exactly
+ * qb_project_backward_views.  INVALID_ARG for other clear_grad2d values and
+ * wherever qb_project_backward_views returns it.  A row that is zero apart
+ * from the sign of its zeros is left as it is. */
+qb_status qb_project_backward_views_ex(int64_t n, const float* means, const float* log_scales, const float* quats,
+                                       const float* opacity_logits, const float* sh, int32_t sh_degree,
+                                       const qb_camera* cams, int32_t num_views, const qb_splat* splats,
+                                       float* grad2d, float* d_means, float* d_log_scales, float* d_quats,
+                                       float* d_opacity_logits, float* d_sh, int32_t clear_grad2d,
+                                       qb_stream_t stream);
+
 /* ---- Loss gradient of a training step -----------------------------------
  * Training (Sec. 4.1) drives the render backward with dL/dimage.  For the
  * mean absolute (L1) error of an image against a target, that gradient is

@@ -570,11 +570,7 @@ __global__ __launch_bounds__(QB_BLOCK) void k_sh_backward(
     constexpr int K = (DEG + 1) * (DEG + 1);
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
     if (i >= n) return;
-    // a zero colour row (culled Gaussians, and those no pixel composites)
-    // adds nothing: the splat's colour record is read only where it does not
-    const float* g2 = grad2d + 9 * i;
-    float4 s2 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (g2[6] != 0.f || g2[7] != 0.f || g2[8] != 0.f) s2 = splats[3 * i + 2];
+    float4 s2 = splats[3 * i + 2];
     if (s2.w != 1.0f) {
 #pragma unroll
         for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = 0.f;
@@ -594,10 +590,14 @@ __global__ __launch_bounds__(QB_BLOCK) void k_sh_backward(
 // mean gradient follows in k_sh_backward_views).  Three waves per SIMD are
 // asked for (178 -> 168 VGPRs at the price of 44 bytes of spills): 0.14 ms
 // less over 32 views of 2M Gaussians than at two.
+// CLEAR: the SH kernel ran first (it stored d_means), this one adds to
+// d_means and then zeroes every nonzero grad2d row it read, so that the next
+// step's render backward can add into grad2d without clearing it.
+template <bool CLEAR>
 __global__ __launch_bounds__(QB_BLOCK, 3) void k_geometry_backward_views(
     int64_t n, int nv, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits, BwdCamTable cams,
-    const float* __restrict__ grad2d, float* __restrict__ d_means,
+    float* __restrict__ grad2d, float* __restrict__ d_means,
     float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_logits)
 {
     int64_t i = (int64_t)blockIdx.x * QB_BLOCK + threadIdx.x;
@@ -609,12 +609,19 @@ __global__ __launch_bounds__(QB_BLOCK, 3) void k_geometry_backward_views(
     double dM[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     float dop = 0.f;
     bool any = false;
-    for (int v = 0; v < nv; ++v)
-        any |= geometry_view(g, cams.cam[v], grad2d + 9 * ((int64_t)v * n + i), dm, dM, dop);
+    for (int v = 0; v < nv; ++v) {
+        float* g2 = grad2d + 9 * ((int64_t)v * n + i);
+        bool used = geometry_view(g, cams.cam[v], g2, dm, dM, dop);
+        any |= used;
+        if (CLEAR && (used || g2[6] != 0.f || g2[7] != 0.f || g2[8] != 0.f))
+#pragma unroll
+            for (int k = 0; k < 9; ++k) g2[k] = 0.f;
+    }
     // (a culled Gaussian, whose rows are all zero, may have no valid rotation)
     if (any) geometry_finish(i, n, log_scales, quats, logits, dM, dop, dls, dq, dlogit);
     for (int c = 0; c < 3; ++c) {
-        d_means[c * n + i] = (float)dm[c];
+        if (CLEAR) d_means[c * n + i] += (float)dm[c];
+        else d_means[c * n + i] = (float)dm[c];
         d_log_scales[c * n + i] = (float)dls[c];
     }
     for (int c = 0; c < 4; ++c) d_quats[c * n + i] = (float)dq[c];
@@ -622,8 +629,10 @@ __global__ __launch_bounds__(QB_BLOCK, 3) void k_geometry_backward_views(
 }
 
 // Views: SH coefficients and the colour's share of the mean gradient, summed
-// over views in registers; adds to d_means (after k_geometry_backward_views).
-template <int DEG>
+// over views in registers.  FIRST: runs before k_geometry_backward_views and
+// stores its share of d_means, which that kernel then adds to; otherwise it
+// runs after it and adds its share.
+template <int DEG, bool FIRST>
 __global__ __launch_bounds__(QB_BLOCK) void k_sh_backward_views(
     int64_t n, int nv, const float* __restrict__ means, const float* __restrict__ sh, BwdCamTable cams,
     const float4* __restrict__ splats, const float* __restrict__ grad2d, float* __restrict__ d_means,
@@ -673,9 +682,15 @@ __global__ __launch_bounds__(QB_BLOCK) void k_sh_backward_views(
     }
 #pragma unroll
     for (int k = 0; k < K * 3; ++k) d_sh[(int64_t)k * n + i] = acc[k];
-    d_means[i] += dmx;
-    d_means[n + i] += dmy;
-    d_means[2 * n + i] += dmz;
+    if (FIRST) {
+        d_means[i] = dmx;
+        d_means[n + i] = dmy;
+        d_means[2 * n + i] = dmz;
+    } else {
+        d_means[i] += dmx;
+        d_means[n + i] += dmy;
+        d_means[2 * n + i] += dmz;
+    }
 }
 
 // qb_l1_grad: the items of one launch, by value as a kernel argument.  Item v
@@ -820,16 +835,17 @@ extern "C" qb_status qb_project_backward(int64_t n, const float* means, const fl
     return QB_OK;
 }
 
-extern "C" qb_status qb_render_backward_views_ex(int32_t num_views, const qb_view* views, const float* bg,
-                                                 int64_t n, int32_t variant, const uint32_t* tile_order,
-                                                 qb_stream_t stream)
+// The batched render backward; clear: zero every view's grad2d first, else
+// add to what it holds.
+static qb_status render_backward_views(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
+                                       int32_t variant, const uint32_t* tile_order, bool clear, qb_stream_t stream)
 {
     if (!bg || n < 0 || variant < 0 || variant > QB_RENDER_4PX) return QB_ERR_INVALID_ARG;
     QbViewTable vt;
     qb_status st = qb_make_view_table(num_views, views, true, &vt);
     if (st != QB_OK) return st;
     hipStream_t s = qb_hip_stream(stream);
-    if (n > 0) {
+    if (n > 0 && clear) {
         int64_t g = qb_div_up(9 * n, QB_BLOCK);
         QB_LAUNCH(k_zero_views, dim3(g > 1024 ? 1024 : (unsigned)g, num_views), QB_BLOCK, 0, s, vt, 9 * n);
     }
@@ -843,18 +859,33 @@ extern "C" qb_status qb_render_backward_views_ex(int32_t num_views, const qb_vie
     return QB_OK;
 }
 
+extern "C" qb_status qb_render_backward_views_ex(int32_t num_views, const qb_view* views, const float* bg,
+                                                 int64_t n, int32_t variant, const uint32_t* tile_order,
+                                                 qb_stream_t stream)
+{
+    return render_backward_views(num_views, views, bg, n, variant, tile_order, true, stream);
+}
+
+extern "C" qb_status qb_render_backward_views_acc(int32_t num_views, const qb_view* views, const float* bg,
+                                                  int64_t n, int32_t variant, const uint32_t* tile_order,
+                                                  qb_stream_t stream)
+{
+    return render_backward_views(num_views, views, bg, n, variant, tile_order, false, stream);
+}
+
 extern "C" qb_status qb_render_backward_views(int32_t num_views, const qb_view* views, const float* bg, int64_t n,
                                               qb_stream_t stream)
 {
     return qb_render_backward_views_ex(num_views, views, bg, n, QB_RENDER_2PX, nullptr, stream);
 }
 
-extern "C" qb_status qb_project_backward_views(int64_t n, const float* means, const float* log_scales,
-                                               const float* quats, const float* opacity_logits, const float* sh,
-                                               int32_t sh_degree, const qb_camera* cams, int32_t num_views,
-                                               const qb_splat* splats, const float* grad2d, float* d_means,
-                                               float* d_log_scales, float* d_quats, float* d_opacity_logits,
-                                               float* d_sh, qb_stream_t stream)
+// The batched projection backward; clear: the SH kernel first, then the
+// geometry kernel, which zeroes the grad2d rows it has read.
+static qb_status project_backward_views(int64_t n, const float* means, const float* log_scales, const float* quats,
+                                        const float* opacity_logits, const float* sh, int32_t sh_degree,
+                                        const qb_camera* cams, int32_t num_views, const qb_splat* splats,
+                                        float* grad2d, float* d_means, float* d_log_scales, float* d_quats,
+                                        float* d_opacity_logits, float* d_sh, bool clear, qb_stream_t stream)
 {
     if (n < 0 || n >= (int64_t)1 << 31 || !cams || sh_degree < 0 || sh_degree > 3 || num_views < 1 ||
         num_views > QB_MAX_VIEWS)
@@ -872,19 +903,54 @@ extern "C" qb_status qb_project_backward_views(int64_t n, const float* means, co
     hipStream_t s = qb_hip_stream(stream);
     int64_t grid = qb_div_up(n, QB_BLOCK);
     const float4* sp = reinterpret_cast<const float4*>(splats);
-    QB_LAUNCH(k_geometry_backward_views, grid, QB_BLOCK, 0, s, n, (int)num_views, means, log_scales, quats,
-              opacity_logits, ct, grad2d, d_means, d_log_scales, d_quats, d_opacity_logits);
-    switch (sh_degree) {
-    case 0: QB_LAUNCH(k_sh_backward_views<0>, grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, grad2d,
-                      d_means, d_sh); break;
-    case 1: QB_LAUNCH(k_sh_backward_views<1>, grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, grad2d,
-                      d_means, d_sh); break;
-    case 2: QB_LAUNCH(k_sh_backward_views<2>, grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, grad2d,
-                      d_means, d_sh); break;
-    default: QB_LAUNCH(k_sh_backward_views<3>, grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, grad2d,
-                       d_means, d_sh); break;
+#define QB_SH_VIEWS(FIRST)                                                                                     \
+    switch (sh_degree) {                                                                                       \
+    case 0: QB_LAUNCH((k_sh_backward_views<0, FIRST>), grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, \
+                      grad2d, d_means, d_sh); break;                                                           \
+    case 1: QB_LAUNCH((k_sh_backward_views<1, FIRST>), grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, \
+                      grad2d, d_means, d_sh); break;                                                           \
+    case 2: QB_LAUNCH((k_sh_backward_views<2, FIRST>), grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct, sp, \
+                      grad2d, d_means, d_sh); break;                                                           \
+    default: QB_LAUNCH((k_sh_backward_views<3, FIRST>), grid, QB_BLOCK, 0, s, n, (int)num_views, means, sh, ct,   \
+                       sp, grad2d, d_means, d_sh); break;                                                      \
     }
+    if (clear) {
+        QB_SH_VIEWS(true);
+        QB_LAUNCH((k_geometry_backward_views<true>), grid, QB_BLOCK, 0, s, n, (int)num_views, means, log_scales, quats,
+                  opacity_logits, ct, grad2d, d_means, d_log_scales, d_quats, d_opacity_logits);
+    } else {
+        QB_LAUNCH((k_geometry_backward_views<false>), grid, QB_BLOCK, 0, s, n, (int)num_views, means, log_scales,
+                  quats, opacity_logits, ct, grad2d, d_means, d_log_scales, d_quats, d_opacity_logits);
+        QB_SH_VIEWS(false);
+    }
+#undef QB_SH_VIEWS
     return QB_OK;
+}
+
+extern "C" qb_status qb_project_backward_views(int64_t n, const float* means, const float* log_scales,
+                                               const float* quats, const float* opacity_logits, const float* sh,
+                                               int32_t sh_degree, const qb_camera* cams, int32_t num_views,
+                                               const qb_splat* splats, const float* grad2d, float* d_means,
+                                               float* d_log_scales, float* d_quats, float* d_opacity_logits,
+                                               float* d_sh, qb_stream_t stream)
+{
+    // without clearing, grad2d is only read
+    return project_backward_views(n, means, log_scales, quats, opacity_logits, sh, sh_degree, cams, num_views,
+                                  splats, const_cast<float*>(grad2d), d_means, d_log_scales, d_quats,
+                                  d_opacity_logits, d_sh, false, stream);
+}
+
+extern "C" qb_status qb_project_backward_views_ex(int64_t n, const float* means, const float* log_scales,
+                                                  const float* quats, const float* opacity_logits, const float* sh,
+                                                  int32_t sh_degree, const qb_camera* cams, int32_t num_views,
+                                                  const qb_splat* splats, float* grad2d, float* d_means,
+                                                  float* d_log_scales, float* d_quats, float* d_opacity_logits,
+                                                  float* d_sh, int32_t clear_grad2d, qb_stream_t stream)
+{
+    if (clear_grad2d != 0 && clear_grad2d != 1) return QB_ERR_INVALID_ARG;
+    return project_backward_views(n, means, log_scales, quats, opacity_logits, sh, sh_degree, cams, num_views,
+                                  splats, grad2d, d_means, d_log_scales, d_quats, d_opacity_logits, d_sh,
+                                  clear_grad2d != 0, stream);
 }
 
 extern "C" qb_status qb_l1_grad(int32_t num_items, const qb_l1_item* items, qb_stream_t stream)

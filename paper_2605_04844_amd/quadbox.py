@@ -129,6 +129,11 @@ def lib():
     L.qb_render_backward_views_ex.restype = i32
     L.qb_project_backward_views.argtypes = [i64, vp, vp, vp, vp, vp, i32, pc, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.qb_project_backward_views.restype = i32
+    L.qb_render_backward_views_acc.argtypes = [i32, C.POINTER(CView), vp, i64, i32, vp, vp]
+    L.qb_render_backward_views_acc.restype = i32
+    L.qb_project_backward_views_ex.argtypes = [i64, vp, vp, vp, vp, vp, i32, pc, i32, vp, vp, vp, vp, vp, vp, vp,
+                                               i32, vp]
+    L.qb_project_backward_views_ex.restype = i32
     L.qb_status_string.argtypes = [i32]
     L.qb_status_string.restype = C.c_char_p
     L.qb_version.argtypes = []
@@ -551,18 +556,26 @@ def render_views(view_array, num_views, bg, variant=0, order=None):
                                                           int(variant), _ptr(order), _stream()))
 
 
-def render_backward_views(view_array, num_views, bg, n, variant=0, order=None):
+def render_backward_views(view_array, num_views, bg, n, variant=0, order=None, accumulate=False):
+    """qb_render_backward_views_ex, or with ``accumulate``
+    qb_render_backward_views_acc (adds to grad2d, which must hold zeros)."""
     bgv = (C.c_float * 3)(*[float(x) for x in bg])
-    _check("qb_render_backward_views_ex", lib().qb_render_backward_views_ex(
-        num_views, view_array, C.cast(bgv, C.c_void_p), n, int(variant), _ptr(order), _stream()))
+    name = "qb_render_backward_views_acc" if accumulate else "qb_render_backward_views_ex"
+    _check(name, getattr(lib(), name)(num_views, view_array, C.cast(bgv, C.c_void_p), n, int(variant), _ptr(order),
+                                      _stream()))
 
 
 def project_backward_views(g: Gaussians, cam_array, num_views, splats, grad2d, d_means, d_log_scales, d_quats,
-                           d_logits, d_sh):
-    _check("qb_project_backward_views", lib().qb_project_backward_views(
-        g.n, _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats), _ptr(g.logits), _ptr(g.sh), g.sh_degree, cam_array,
-        num_views, _ptr(splats), _ptr(grad2d), _ptr(d_means), _ptr(d_log_scales), _ptr(d_quats), _ptr(d_logits),
-        _ptr(d_sh), _stream()))
+                           d_logits, d_sh, clear_grad2d=False):
+    """qb_project_backward_views, or with ``clear_grad2d``
+    qb_project_backward_views_ex leaving every grad2d row at zero."""
+    args = (g.n, _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats), _ptr(g.logits), _ptr(g.sh), g.sh_degree,
+            cam_array, num_views, _ptr(splats), _ptr(grad2d), _ptr(d_means), _ptr(d_log_scales), _ptr(d_quats),
+            _ptr(d_logits), _ptr(d_sh))
+    if clear_grad2d:
+        _check("qb_project_backward_views_ex", lib().qb_project_backward_views_ex(*args, 1, _stream()))
+    else:
+        _check("qb_project_backward_views", lib().qb_project_backward_views(*args, _stream()))
 
 
 class MultiView:
@@ -575,7 +588,10 @@ class MultiView:
     buffers are sized (size_pairs); a frame whose pair count exceeds its
     view's capacity renders that view empty (check overflowed()).  With
     ``balance`` (the default) qb_tile_order_views orders every view's tiles
-    in one list, heaviest first, for the render and its backward."""
+    in one list, heaviest first, for the render and its backward.  grad2d
+    stays all zero between backward calls (the projection backward clears
+    the rows it reads), so the render backward adds into it without a
+    separate clear."""
 
     def __init__(self, n: int, cams, device="cuda", streams: int = 4, balance: bool = True):
         self.V = len(cams)
@@ -602,7 +618,8 @@ class MultiView:
         self.final_T = [torch.zeros((h, w), dtype=torch.float32, device=d) for w, h in self.sizes]
         self.n_contrib = [torch.zeros((h, w), dtype=torch.int32, device=d) for w, h in self.sizes]
         self.dl = [torch.zeros((3, h, w), dtype=torch.float32, device=d) for w, h in self.sizes]
-        self.grad2d = torch.empty((V, n1, 9), dtype=torch.float32, device=d)
+        self.grad2d = torch.zeros((V, n1, 9), dtype=torch.float32, device=d)
+        self.grad2d_zero = True  # whether grad2d holds only zeros
         self.balance = balance
         total_tiles = sum(self.num_tiles)
         self.work = torch.zeros(total_tiles, dtype=torch.int32, device=d)
@@ -735,8 +752,10 @@ class MultiView:
         first); returns (d_means, d_log_scales, d_quats, d_logits, d_sh)."""
         if self.grads is None:
             self.grads = [torch.empty_like(t) for t in g.tensors()]
-        render_backward_views(self._table, self.V, bg, self.n, self.backward_variant, self.tile_order())
-        project_backward_views(g, self.cam_array, self.V, self.splats, self.grad2d, *self.grads)
+        render_backward_views(self._table, self.V, bg, self.n, self.backward_variant, self.tile_order(),
+                              accumulate=self.grad2d_zero)
+        project_backward_views(g, self.cam_array, self.V, self.splats, self.grad2d, *self.grads, clear_grad2d=True)
+        self.grad2d_zero = True
         return self.grads
 
     def overflowed(self) -> bool:
@@ -785,7 +804,11 @@ def autotune_backward(run, bg=(0.0, 0.0, 0.0), dl=None, grad2d=None, reps=5, tri
     fns = {}
     for name, v in BACKWARD_VARIANTS.items():
         if isinstance(run, MultiView):
-            fns[name] = (lambda v=v: render_backward_views(run._table, run.V, bg, run.n, v, run.tile_order()))
+            # timed without the clear; the sums these calls leave in grad2d
+            # make the next backward clear it
+            run.grad2d_zero = False
+            fns[name] = (lambda v=v: render_backward_views(run._table, run.V, bg, run.n, v, run.tile_order(),
+                                                           accumulate=True))
         else:
             fns[name] = (lambda v=v: render_backward(run.W, run.H, run.ranges, run.ids_sorted, run.splats, bg,
                                                      run.final_T, run.n_contrib, dl, run.n, grad2d, v,

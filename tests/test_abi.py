@@ -205,9 +205,18 @@ def test_launch_shape_and_view_entry_points_reject_bad_arguments():
     assert L.qb_project_views(10, d, d, d, d, d, 0, cams, 2, 2, d, d, d, None) == qb.QB_ERR_INVALID_ARG
     assert L.qb_project_backward_views(10, d, d, d, d, d, 0, cams, 2, d, d, d, d, d, d, d, None) == \
         qb.QB_ERR_INVALID_ARG
+    assert L.qb_project_backward_views_ex(10, d, d, d, d, d, 0, cams, 2, d, d, d, d, d, d, d, 1, None) == \
+        qb.QB_ERR_INVALID_ARG
     cams[1].fx = 64.0
     assert L.qb_project_backward_views(10, d, d, d, d, d, 4, cams, 2, d, d, d, d, d, d, d, None) == \
         qb.QB_ERR_INVALID_ARG
+    # the clear flag is 0 or 1; the adding render backward checks like the clearing one
+    for flag in (-1, 2):
+        assert L.qb_project_backward_views_ex(10, d, d, d, d, d, 0, cams, 2, d, d, d, d, d, d, d, flag, None) == \
+            qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_backward_views_acc(2, views, bgp, 10, 0, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_backward_views_acc(1, views, bgp, 10, 4, None, None) == qb.QB_ERR_INVALID_ARG
+    assert L.qb_render_backward_views_acc(1, views, None, 10, 0, None, None) == qb.QB_ERR_INVALID_ARG
 
 
 def test_cameras_need_a_positive_near_plane_and_finite_fields():

@@ -296,3 +296,67 @@ def test_views_capacity_overflow(qb):
         if v != 1:
             assert torch.equal(mv.images[v], want[v]), v
     say("overflowed view renders the background; the others are unchanged")
+
+
+def _close(a, b, rel=1e-5):
+    den = float(b.norm())
+    return float((a - b).norm()) <= rel * max(den, 1e-30)
+
+
+def test_views_backward_without_clear(qb):
+    """The projection backward with clear_grad2d gives the same gradients bit
+    for bit and leaves every grad2d row at zero; the render backward that adds
+    into that zeroed grad2d equals the clearing one (up to the order of its
+    float atomics); MultiView.backward twice in a row, the second on twice
+    the loss gradient, and again after the autotuner left sums in grad2d."""
+    scene, cams = small_views()
+    bg = (0.1, 0.2, 0.3)
+    g = qb.Gaussians(scene)
+    mv = qb.MultiView(scene.n, cams)
+    mv.size_pairs(g, "quadbox")
+    imgs = mv.forward(g, bg)
+    targets = [torch.tensor(scenes.target_image(90 + v, w, h), device="cuda") for v, (w, h) in enumerate(mv.sizes)]
+    for v in range(mv.V):
+        mv.dl[v].copy_(l1_grad(imgs[v], targets[v]))
+    # the clearing path, as qb_project_backward_views alone computes it
+    qb.render_backward_views(mv._table, mv.V, bg, mv.n, mv.backward_variant, mv.tile_order())
+    g2_ref = mv.grad2d.clone()
+    ref = [torch.empty_like(t) for t in g.tensors()]
+    qb.project_backward_views(g, mv.cam_array, mv.V, mv.splats, mv.grad2d, *ref)
+    torch.cuda.synchronize()
+    assert torch.equal(mv.grad2d, g2_ref)   # read only
+    assert int((g2_ref != 0).any(dim=2).sum()) > 0
+    got = [torch.full_like(t, 123.0) for t in g.tensors()]
+    qb.project_backward_views(g, mv.cam_array, mv.V, mv.splats, mv.grad2d, *got, clear_grad2d=True)
+    torch.cuda.synchronize()
+    for a, b in zip(got, ref):
+        assert torch.equal(a, b)
+    assert not bool((mv.grad2d != 0).any())
+    say("clear_grad2d: identical gradients, grad2d left at zero")
+    qb.render_backward_views(mv._table, mv.V, bg, mv.n, mv.backward_variant, mv.tile_order(), accumulate=True)
+    torch.cuda.synchronize()
+    assert _close(mv.grad2d, g2_ref)
+    assert torch.equal(mv.grad2d != 0, g2_ref != 0)
+    # MultiView.backward: grad2d is zero again here, so it adds without a clear
+    qb.project_backward_views(g, mv.cam_array, mv.V, mv.splats, mv.grad2d, *got, clear_grad2d=True)
+    mv.grad2d_zero = True
+    for scale in (1.0, 2.0):
+        for v in range(mv.V):
+            mv.dl[v].copy_(l1_grad(imgs[v], targets[v]) * scale)
+        grads = mv.backward(g, bg)
+        torch.cuda.synchronize()
+        for a, b in zip(grads, ref):
+            assert _close(a, b * scale), scale
+        assert not bool((mv.grad2d != 0).any())
+    # the autotuner's timing calls add into grad2d: the next backward clears
+    qb.autotune_backward(mv, bg, reps=1, trials=1)
+    assert not mv.grad2d_zero
+    assert bool((mv.grad2d != 0).any())
+    for v in range(mv.V):
+        mv.dl[v].copy_(l1_grad(imgs[v], targets[v]))
+    grads = mv.backward(g, bg)
+    torch.cuda.synchronize()
+    for a, b in zip(grads, ref):
+        assert _close(a, b)
+    assert mv.grad2d_zero and not bool((mv.grad2d != 0).any())
+    say("backward twice in a row and after the autotuner: same gradients")
