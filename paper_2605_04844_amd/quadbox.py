@@ -640,20 +640,23 @@ class MultiView:
     def _slice(self, v):
         return self.splats[v], self.rects[v], self.counts[v], self.num_pairs[v:v + 1]
 
-    def _intersect(self, v):
+    # slot: the side stream the call is issued on, whose workspaces it uses
+    # (calls on different streams may run at once; each stream's calls run
+    # one after another, so they can share that stream's workspaces)
+    def _intersect(self, v, slot=0):
         s, r, c, npairs = self._slice(v)
         w, h = self.sizes[v]
         cap = self.capacity[v]
         intersect(self.n, s, r, c, w, h, cap, self.pair_tiles[v] if cap else None,
-                  self.pair_ids[v] if cap else None, npairs, self.ws_isect[v % self.S], self.mode,
+                  self.pair_ids[v] if cap else None, npairs, self.ws_isect[slot], self.mode,
                   self.depth_variant, self.emit_variant, self.depth_keys[v], self._packed_bits(v))
 
     def _packed_bits(self, v):
         return self.id_bits[v] if self.packed else 0
 
-    def _sort(self, v):
+    def _sort(self, v, slot=0):
         sort(self.capacity[v], self.num_pairs[v:v + 1], self.num_tiles[v], self.pair_tiles[v], self.pair_ids[v],
-             self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort[v % self.S], self.sort_variant,
+             self.splats[v], None, self.ids_sorted[v], self.ranges[v], self.ws_sort[slot], self.sort_variant,
              self._packed_bits(v))
 
     def intersect_all(self):
@@ -709,18 +712,22 @@ class MultiView:
         return counts
 
     def _per_view(self, fn):
-        """Runs fn(v) for every view, round-robin over the side streams
-        (forked from and joined back into the current stream)."""
+        """Runs fn(v, slot) for every view, round-robin over the side streams
+        (view v on stream slot v % S, forked from and joined back into the
+        current stream).  Placing the views longest first on the least loaded
+        stream evened the streams' pair counts (within 5 %, against 17 %) but
+        made the 32-view step 0.1-0.3 ms slower."""
         if not self.streams:
             for v in range(self.V):
-                fn(v)
+                fn(v, 0)
             return
         main = torch.cuda.current_stream()
         for st in self.streams:
             st.wait_stream(main)
         for v in range(self.V):
-            with torch.cuda.stream(self.streams[v % self.S]):
-                fn(v)
+            st = v % self.S
+            with torch.cuda.stream(self.streams[st]):
+                fn(v, st)
         for st in self.streams:
             main.wait_stream(st)
 
@@ -730,9 +737,9 @@ class MultiView:
         _need(g.n == self.n, f"{g.n} Gaussians given to a MultiView sized for {self.n}")
         project_views(g, self.cam_array, self.V, self.mode, self.splats, self.rects, self.counts, self.depth_keys)
 
-        def prep(v):
-            self._intersect(v)
-            self._sort(v)
+        def prep(v, slot):
+            self._intersect(v, slot)
+            self._sort(v, slot)
 
         self._per_view(prep)
         if self.balance:
