@@ -9,7 +9,9 @@ equal tiles (runs that straddle the 8-pair lane groups and the 4096-pair
 workgroups), and uniform random tiles; counts from 1 to 1M include ragged
 tails that are not whole lane groups or workgroups.  Every launch shape of
 qb_sort_ex (radix workgroups of 4096 to 8192 pairs) is checked, on split
-pairs and, where tile and id fit 32 bits, on packed ones.  Bit-exact."""
+pairs and, where tile and id fit 32 bits, on packed ones; 3M packed pairs
+over 1000 tiles take more radix workgroups than one workgroup's prologue
+scans itself (the scan launches).  Bit-exact."""
 import numpy as np
 import pytest
 
@@ -36,7 +38,7 @@ def patterns(seed, n, tiles):
 
 
 @pytest.mark.parametrize("n,tiles", [(1, 1), (5, 1), (4095, 3600), (4096 * 3 + 17, 3600), (200_003, 65536),
-                                     (1_000_000, 3600), (1_000_000, 64)])
+                                     (1_000_000, 3600), (1_000_000, 64), (3_000_017, 1000)])
 def test_sort_synthetic_tiles(oracle, qb, n, tiles):
     cap = n + 100
     ws = torch.empty(qb.sort_workspace_size(cap), dtype=torch.uint8, device="cuda")
