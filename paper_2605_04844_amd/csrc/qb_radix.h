@@ -274,6 +274,22 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
     return v;
 }
 
+// Data tile of radix workgroup w where the histograms are digit-major (the
+// scan launches).  Workgroups go to the 8 XCDs round-robin (w % 8), so within
+// each group of 256 workgroups, workgroup 8j + x takes tile 32x + j: 32
+// consecutive tiles run on one XCD.  Their 32 histogram words of a digit (one
+// 128-byte line), their 32 digit offsets, and the output lines where one
+// tile's run of a digit meets the next tile's, then pass through one XCD's L2
+// as whole lines instead of partial lines from up to eight.  A tail of fewer
+// than 256 workgroups keeps its order.  A bijection on [0, nblocks).
+__device__ __forceinline__ int64_t xcd_tile(int64_t w, int64_t nblocks)
+{
+    constexpr int64_t kGroup = 256;
+    if (w >= (nblocks / kGroup) * kGroup) return w;
+    int64_t r = w & (kGroup - 1);
+    return (w - r) + (r & 7) * 32 + (r >> 3);
+}
+
 // Per-block digit histogram.  Digit-major layout (hist[d * nblocks + b]) feeds
 // the flat scan; block-major (hist[b * 256 + d], every digit written) feeds a
 // downsweep that derives its own offsets.
@@ -294,7 +310,8 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
     __shared__ uint32_t h[NW * kSub][kRow];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t mask = (1u << bits) - 1u;
-    int64_t base = (int64_t)blockIdx.x * (NT * NI) + (int64_t)wave * 64 * NI;
+    const int64_t tile = BLOCK_MAJOR ? (int64_t)blockIdx.x : xcd_tile(blockIdx.x, nblocks);
+    int64_t base = tile * (NT * NI) + (int64_t)wave * 64 * NI;
     // the wave's keys as 16-byte vectors, loaded first and bounded by the
     // capacity (which the buffer holds), so that their latency overlaps the
     // count's read; used when all 64*NI keys turn out to be below the count
@@ -373,7 +390,7 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
                 klo = min(klo, s_lo[w]);
                 khi = max(khi, s_hi[w]);
             }
-            ctl.range[blockIdx.x] = make_uint2(klo, khi);
+            ctl.range[tile] = make_uint2(klo, khi);
         }
     }
     __syncthreads();
@@ -384,9 +401,9 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
             for (int w = 0; w < NW * kSub; ++w) t += h[w][d];
         }
         if (BLOCK_MAJOR)
-            hist[(int64_t)blockIdx.x * kRadix + d] = t;
+            hist[tile * kRadix + d] = t;
         else if (d <= (int)mask)
-            hist[(int64_t)d * nblocks + blockIdx.x] = t;
+            hist[(int64_t)d * nblocks + tile] = t;
     }
 }
 
@@ -428,7 +445,9 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
     __shared__ K s_key[TILE];
     __shared__ uint32_t s_val[VALUES ? TILE : 1];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int64_t blk0 = (int64_t)blockIdx.x * TILE;
+    // the data tile (xcd_tile where the offsets come from the scan launches)
+    const int64_t tile = FUSED ? (int64_t)blockIdx.x : xcd_tile(blockIdx.x, nblocks);
+    int64_t blk0 = tile * TILE;
     int64_t base = blk0 + (int64_t)wave * 64 * NI;
     // the block's items are loaded first, bounded by the capacity (which the
     // buffers hold) rather than the count, so that their latency overlaps
@@ -445,7 +464,7 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
     uint32_t mask = (1u << bits) - 1u;
     // without the fused prologue, this block's digit offsets are read early too
     uint32_t gb_own = 0u;
-    if (!FUSED && threadIdx.x <= mask) gb_own = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    if (!FUSED && threadIdx.x <= mask) gb_own = offs[(int64_t)threadIdx.x * nblocks + tile];
     int64_t n = sort_count(n_dev, n_host, cap);
     if (blk0 >= n) return;
     int cnt_blk = (int)min((int64_t)TILE, n - blk0);
