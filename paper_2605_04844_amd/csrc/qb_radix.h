@@ -274,10 +274,9 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
     return v;
 }
 
-// Data tile of radix workgroup w where the histograms are digit-major (the
-// scan launches).  Workgroups go to the 8 XCDs round-robin (w % 8), so within
-// each group of 256 workgroups, workgroup 8j + x takes tile 32x + j: 32
-// consecutive tiles run on one XCD.  Their 32 histogram words of a digit (one
+// Data tile of radix workgroup w.  Workgroups go to the 8 XCDs round-robin
+// (w % 8), so within each group of 256 workgroups, workgroup 8j + x takes
+// tile 32x + j: 32 consecutive tiles run on one XCD.  Their 32 histogram words of a digit (one
 // 128-byte line), their 32 digit offsets, and the output lines where one
 // tile's run of a digit meets the next tile's, then pass through one XCD's L2
 // as whole lines instead of partial lines from up to eight.  A tail of fewer
@@ -310,7 +309,7 @@ __global__ __launch_bounds__(NT) void k_radix_upsweep(const K* __restrict__ keys
     __shared__ uint32_t h[NW * kSub][kRow];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t mask = (1u << bits) - 1u;
-    const int64_t tile = BLOCK_MAJOR ? (int64_t)blockIdx.x : xcd_tile(blockIdx.x, nblocks);
+    const int64_t tile = xcd_tile(blockIdx.x, nblocks);
     int64_t base = tile * (NT * NI) + (int64_t)wave * 64 * NI;
     // the wave's keys as 16-byte vectors, loaded first and bounded by the
     // capacity (which the buffer holds), so that their latency overlaps the
@@ -445,8 +444,7 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
     __shared__ K s_key[TILE];
     __shared__ uint32_t s_val[VALUES ? TILE : 1];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // the data tile (xcd_tile where the offsets come from the scan launches)
-    const int64_t tile = FUSED ? (int64_t)blockIdx.x : xcd_tile(blockIdx.x, nblocks);
+    const int64_t tile = xcd_tile(blockIdx.x, nblocks);   // the data tile
     int64_t blk0 = tile * TILE;
     int64_t base = blk0 + (int64_t)wave * 64 * NI;
     // the block's items are loaded first, bounded by the capacity (which the
@@ -483,7 +481,7 @@ __global__ __launch_bounds__(NT) void k_radix_downsweep(
 #pragma unroll 4
         for (int b = wave; b < (int)nblocks; b += NW) {
             uint4 v = rows[(int64_t)b * (kRadix / 4) + lane];
-            bool before = b < (int)blockIdx.x;
+            bool before = b < (int)tile;
             tot4.x += v.x; tot4.y += v.y; tot4.z += v.z; tot4.w += v.w;
             pre4.x += before ? v.x : 0u; pre4.y += before ? v.y : 0u;
             pre4.z += before ? v.z : 0u; pre4.w += before ? v.w : 0u;
