@@ -309,10 +309,12 @@ def _time(torch, fn, steps, warmup, trials):
 
 def run_multiview(torch, qb, steps, warmup, trials):
     """Forward + backward of an L1 loss over 32 views of 2M Gaussians
-    (640x360 / 1280x720 / 1920x1080 by view index), three ways: the
+    (640x360 / 1280x720 / 1920x1080 by view index), four ways: the
     single-view entry points view after view (gradients summed by torch),
-    the batched entry points (quadbox.MultiView), and the batched step
-    captured once in a HIP graph and replayed.  Returns ms per view."""
+    the batched entry points (quadbox.MultiView forward, l1_grad, backward),
+    MultiView.step (each side stream renders and back-propagates its views
+    behind their sorts), the last two also captured once in a HIP graph and
+    replayed.  Returns ms per view."""
     from paper_2605_04844_amd import scenes
     scene, cams = scenes.multiview_scene()
     g = qb.Gaussians(scene)
@@ -369,6 +371,23 @@ def run_multiview(torch, qb, steps, warmup, trials):
     mv.check_capacity()
     del graph
 
+    # the same step from MultiView.step: each side stream renders, takes the
+    # loss gradient of and back-propagates its views behind their sorts
+    def stepped():
+        mv.step(g, targets)
+
+    step_ms = _time(torch, stepped, steps, warmup, trials)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        stepped()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        stepped()
+    step_graph_ms = _time(torch, graph.replay, steps, warmup, trials)
+    mv.check_capacity()
+    del graph
+
     rasts = []
     for c in cams:
         r = qb.Rasterizer(g.n, c, write_keys=False)
@@ -401,6 +420,8 @@ def run_multiview(torch, qb, steps, warmup, trials):
             "per_view_path_ms_per_view": round(per_view_ms / V, 4),
             "batched_ms_per_view": round(batched_ms / V, 4),
             "batched_graph_ms_per_view": round(graph_ms / V, 4),
+            "step_ms_per_view": round(step_ms / V, 4),
+            "step_graph_ms_per_view": round(step_graph_ms / V, 4),
             "graph_speedup_vs_per_view": round(per_view_ms / graph_ms, 3),
             "autotune": tuned, "rooflines": rooflines}
 

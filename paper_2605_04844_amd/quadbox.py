@@ -625,6 +625,7 @@ class MultiView:
         self.work = torch.zeros(total_tiles, dtype=torch.int32, device=d)
         self.order = torch.arange(total_tiles, dtype=torch.int32, device=d)
         self.capacity = [0] * V
+        self._groups = []
         self.mode = "quadbox"
         self.render_variant = RENDER_VARIANTS["2px"]
         self.backward_variant = RENDER_VARIANTS["2px"]
@@ -709,6 +710,7 @@ class MultiView:
             views[v].dL_dimage = self.dl[v].data_ptr()
             views[v].grad2d = self.grad2d[v].data_ptr()
         self._table = views
+        self._make_groups()
         return counts
 
     def _per_view(self, fn):
@@ -761,6 +763,67 @@ class MultiView:
             self.grads = [torch.empty_like(t) for t in g.tensors()]
         render_backward_views(self._table, self.V, bg, self.n, self.backward_variant, self.tile_order(),
                               accumulate=self.grad2d_zero)
+        project_backward_views(g, self.cam_array, self.V, self.splats, self.grad2d, *self.grads, clear_grad2d=True)
+        self.grad2d_zero = True
+        return self.grads
+
+    def _make_groups(self):
+        """step()'s groups: per side stream, its views (v % S == slot), their
+        view table and the work / order buffers of their tiles."""
+        self._groups = []
+        for slot in range(self.S if self.streams else 0):
+            vs = [v for v in range(self.V) if v % self.S == slot]
+            tiles = sum(self.num_tiles[v] for v in vs)
+            self._groups.append((vs, (CView * len(vs))(*[self._table[v] for v in vs]),
+                                 torch.zeros(tiles, dtype=torch.int32, device=self.device),
+                                 torch.arange(tiles, dtype=torch.int32, device=self.device)))
+
+    def step(self, g: Gaussians, targets, bg=(0.0, 0.0, 0.0)):
+        """One training step over every view: forward, dL/dimage of the mean
+        absolute error against targets[v] (qb_l1_grad, scale 1 / element
+        count, into dl[v]) and backward; returns the gradients as backward()
+        does.  Each side stream renders, takes the loss gradient of and runs
+        the render backward of its own views (v % S == slot) right behind
+        their intersections and sorts, so the streams that finish their sorts
+        first start on this work while the others still sort; the projection
+        backward then sums every view on the current stream.  Images, dl and
+        gradients are those of forward(), l1_grad() and backward() in turn,
+        the rounding of the render backward's float atomics aside (tiles are
+        ordered within each stream's views rather than over all views).
+        Without side streams: forward(), l1_grad() and backward()."""
+        if self._table is None:
+            raise RuntimeError("call size_pairs() first")
+        _need(len(targets) == self.V, f"{len(targets)} targets for {self.V} views")
+        if not self.streams:
+            self.forward(g, bg)
+            l1_grad([(self.images[v], targets[v], self.dl[v], 1.0 / self.images[v].numel()) for v in range(self.V)])
+            return self.backward(g, bg)
+        _need(g.n == self.n, f"{g.n} Gaussians given to a MultiView sized for {self.n}")
+        if self.grads is None:
+            self.grads = [torch.empty_like(t) for t in g.tensors()]
+        project_views(g, self.cam_array, self.V, self.mode, self.splats, self.rects, self.counts, self.depth_keys)
+        main = torch.cuda.current_stream()
+        for st in self.streams:
+            st.wait_stream(main)
+        # every view's intersection and sort first, round-robin, then each
+        # stream's render chain behind its own sorts
+        for v in range(self.V):
+            slot = v % self.S
+            with torch.cuda.stream(self.streams[slot]):
+                self._intersect(v, slot)
+                self._sort(v, slot)
+        accumulate = self.grad2d_zero
+        for slot, (vs, table, work, order) in enumerate(self._groups):
+            with torch.cuda.stream(self.streams[slot]):
+                o = None
+                if self.balance:
+                    tile_order_views(table, len(vs), work, order)
+                    o = order
+                render_views(table, len(vs), bg, self.render_variant, o)
+                l1_grad([(self.images[v], targets[v], self.dl[v], 1.0 / self.images[v].numel()) for v in vs])
+                render_backward_views(table, len(vs), bg, self.n, self.backward_variant, o, accumulate=accumulate)
+        for st in self.streams:
+            main.wait_stream(st)
         project_backward_views(g, self.cam_array, self.V, self.splats, self.grad2d, *self.grads, clear_grad2d=True)
         self.grad2d_zero = True
         return self.grads

@@ -360,3 +360,64 @@ def test_views_backward_without_clear(qb):
         assert _close(a, b)
     assert mv.grad2d_zero and not bool((mv.grad2d != 0).any())
     say("backward twice in a row and after the autotuner: same gradients")
+
+
+def test_views_pipelined_step(qb):
+    """MultiView.step (each side stream renders, takes the L1 loss gradient
+    of and back-propagates its own views behind their sorts) against
+    forward, l1_grad and backward in turn: identical images and dL/dimage,
+    the same gradients (float atomics aside); then the step captured in a
+    HIP graph and replayed twice with eager work in between, and a step
+    after the autotuner left sums in grad2d."""
+    scene, cams = small_views()
+    bg = (0.2, 0.1, 0.3)
+    g = qb.Gaussians(scene)
+    mv = qb.MultiView(scene.n, cams)
+    mv.size_pairs(g, "quadbox")
+    assert mv.S == 4 and [c[0] for c in mv._groups] == [[0, 4], [1], [2], [3]]
+    targets = [torch.tensor(scenes.target_image(110 + v, w, h), device="cuda") for v, (w, h) in enumerate(mv.sizes)]
+    mv.forward(g, bg)
+    qb.l1_grad([(mv.images[v], targets[v], mv.dl[v], 1.0 / mv.images[v].numel()) for v in range(mv.V)])
+    ref = [x.clone() for x in mv.backward(g, bg)]
+    torch.cuda.synchronize()
+    want_img = [x.clone() for x in mv.images]
+    want_dl = [x.clone() for x in mv.dl]
+    assert sum(int((d != 0).sum()) for d in want_dl) > 0
+
+    def check(label):
+        torch.cuda.synchronize()
+        for v in range(mv.V):
+            assert torch.equal(mv.images[v], want_img[v]), (label, v)
+            assert torch.equal(mv.dl[v], want_dl[v]), (label, v)
+        for a, b in zip(mv.grads, ref):
+            assert _close(a, b), label
+        assert not bool((mv.grad2d != 0).any()), label
+        say(label, "matches forward + l1_grad + backward")
+
+    for x in mv.images + mv.dl:
+        x.fill_(-3.0)
+    mv.step(g, targets, bg)
+    check("eager step")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        mv.step(g, targets, bg)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        mv.step(g, targets, bg)
+    for rep in range(2):
+        for x in mv.images + mv.dl:
+            x.fill_(-3.0)
+        for x in mv.grads:
+            x.fill_(123.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        check(f"replay {rep}")
+        mv.forward(g, bg)   # eager work between the replays
+        torch.cuda.synchronize()
+    del graph
+    qb.autotune_backward(mv, bg, reps=1, trials=1)
+    assert not mv.grad2d_zero
+    mv.step(g, targets, bg)
+    check("step after the autotuner")
