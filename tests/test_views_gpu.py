@@ -421,3 +421,33 @@ def test_views_pipelined_step(qb):
     assert not mv.grad2d_zero
     mv.step(g, targets, bg)
     check("step after the autotuner")
+
+
+@pytest.mark.parametrize("streams,balance", [(1, True), (2, False)])
+def test_views_step_without_side_streams_or_order(qb, streams, balance):
+    """MultiView.step with one stream (forward, l1_grad and backward in turn)
+    and with two side streams in row-major tile order: the images and dL/dimage
+    of forward + l1_grad, the gradients of backward (float atomics aside)."""
+    scene, cams = small_views()
+    bg = (0.0, 0.3, 0.1)
+    g = qb.Gaussians(scene)
+    mv = qb.MultiView(scene.n, cams, streams=streams, balance=balance)
+    mv.size_pairs(g, "quadbox")
+    assert len(mv._groups) == (0 if streams == 1 else 2)
+    targets = [torch.tensor(scenes.target_image(130 + v, w, h), device="cuda") for v, (w, h) in enumerate(mv.sizes)]
+    mv.forward(g, bg)
+    qb.l1_grad([(mv.images[v], targets[v], mv.dl[v], 1.0 / mv.images[v].numel()) for v in range(mv.V)])
+    ref = [x.clone() for x in mv.backward(g, bg)]
+    torch.cuda.synchronize()
+    want_img = [x.clone() for x in mv.images]
+    want_dl = [x.clone() for x in mv.dl]
+    for x in mv.images + mv.dl:
+        x.fill_(-3.0)
+    grads = mv.step(g, targets, bg)
+    torch.cuda.synchronize()
+    for v in range(mv.V):
+        assert torch.equal(mv.images[v], want_img[v]), v
+        assert torch.equal(mv.dl[v], want_dl[v]), v
+    for a, b in zip(grads, ref):
+        assert _close(a, b)
+    say(f"step with {streams} stream(s), balance {balance}: matches")
