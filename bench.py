@@ -359,6 +359,10 @@ def run_multiview(torch, qb, steps, warmup, trials):
                  "render_backward_views": alu_roofline(backward_flops(work), bwd_ms,
                                                        f"k_render_backward_views<{tuned['picked']['render_backward'][0]}>",
                                                        work)}
+    # the committed counters of the picked shapes' 32-view launches
+    for key, ms, per in (("render_views", fwd_ms, "examined"), ("render_backward_views", bwd_ms, "contributors")):
+        counter_fields(rooflines[key], _counters(VIEWS_COUNTERS, rooflines[key]["kernel"]), ms, work, per,
+                       source=VIEWS_COUNTERS)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -601,6 +605,7 @@ def cpu_baseline(scene, cam, exact_stride=10, trials=3):
 
 
 COUNTERS = os.path.join("profiles", "k_render_clusters_1M_counters.json")
+VIEWS_COUNTERS = os.path.join("profiles", "k_render_views_multiview_2M_counters.json")
 
 
 def render_counters(workload, mode, kernel):
@@ -610,8 +615,16 @@ def render_counters(workload, mode, kernel):
     copy-calibrated) and VALU instructions (SQ_INSTS_VALU), or None when the
     summary was taken on another workload or on a different kernel source
     (the sha256 of each source is recorded)."""
-    path = os.path.join(ROOT, COUNTERS)
-    if workload != "clusters" or mode != "quadbox" or not os.path.exists(path):
+    if workload != "clusters" or mode != "quadbox":
+        return None
+    return _counters(COUNTERS, kernel)
+
+
+def _counters(rel, kernel):
+    """The entry of `kernel` in the committed counters summary `rel`, or
+    None (no summary, no entry, or a different kernel source)."""
+    path = os.path.join(ROOT, rel)
+    if not os.path.exists(path):
         return None
     meta = json.load(open(path))
     k = meta.get("kernels", {}).get(kernel)
@@ -626,14 +639,14 @@ def render_counters(workload, mode, kernel):
             "valu_insts": k.get("valu_insts_per_launch")}
 
 
-def counter_fields(roof, ctr, ms, work, per):
+def counter_fields(roof, ctr, ms, work, per, source=COUNTERS):
     """Adds the committed counters' traffic and VALU issue rate to a
     roofline entry (`per`: the work count the lane instructions are divided
-    by)."""
+    by; `source`: the summary they come from)."""
     if not ctr:
         return roof
     roof["traffic"] = ctr["traffic"]
-    roof["traffic_source"] = (f"{COUNTERS}: FETCH_SIZE + WRITE_SIZE per launch of this kernel, copy-calibrated, "
+    roof["traffic_source"] = (f"{source}: FETCH_SIZE + WRITE_SIZE per launch of this kernel, copy-calibrated, "
                               "taken by rocprofv3 on this kernel source (sha256 recorded there), not in this run")
     if ctr.get("valu_insts"):
         lane_rate = ctr["valu_insts"] * 64 / (ms * 1e-3) / 1e12
@@ -643,7 +656,7 @@ def counter_fields(roof, ctr, ms, work, per):
                               "frac": round(lane_rate / VALU_LANE_PEAK_T, 4),
                               "single_issue_T": round(VALU_SINGLE_ISSUE_T, 2),
                               "frac_of_single_issue": round(lane_rate / VALU_SINGLE_ISSUE_T, 4),
-                              "source": f"{COUNTERS}: SQ_INSTS_VALU per launch, not in this run"}
+                              "source": f"{source}: SQ_INSTS_VALU per launch, not in this run"}
     return roof
 
 

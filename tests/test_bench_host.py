@@ -43,6 +43,30 @@ def test_render_traffic_lookup():
     assert bench.render_counters("clusters", "adr", next(iter(meta["kernels"]))) is None
 
 
+def test_views_traffic_lookup():
+    """The 32-view step's render and render-backward launches recorded
+    (every shape, the launch over all views): bytes and VALU instructions
+    per launch, reported while the source is unchanged; the multi-view
+    rooflines take them by kernel name."""
+    path = os.path.join(ROOT, bench.VIEWS_COUNTERS)
+    meta = json.load(open(path))
+    names = set(meta["kernels"])
+    assert any(n.startswith("k_render_views<") for n in names)
+    assert any(n.startswith("k_render_backward_views<") for n in names)
+    from paper_2605_04844_amd import quadbox as qb
+    for shape in qb.RENDER_VARIANTS:
+        assert bench.render_kernel_name(shape, views=True) in names, shape
+    for name, k in meta["kernels"].items():
+        assert k["fetch_bytes_per_launch"] > 0 and k["write_bytes_per_launch"] > 0, name
+        got = bench._counters(bench.VIEWS_COUNTERS, name)
+        if _current(meta, k):
+            assert got["traffic"] == k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"], name
+            assert got["valu_insts"] == k["valu_insts_per_launch"], name
+        else:
+            assert got is None, name
+    assert bench._counters(bench.VIEWS_COUNTERS, "k_render_views<8, false, 0>") is None
+
+
 def test_render_traffic_stale_source(tmp_path, monkeypatch):
     """Counters taken on another kernel source are not reported."""
     meta = json.load(open(COUNTERS))
