@@ -53,14 +53,11 @@ BACKWARD_FLOPS_EXAMINED, BACKWARD_FLOPS_COMPOSITED = 9, 30
 # Published MI355X FP32 vector peak, 157.3 TFLOP/s (256 CUs x 2.4 GHz x 256
 # FLOP per clock per CU: 128 lane-FMAs).  In lane operations per second
 # that is 78.6 T, the ceiling the measured VALU instruction rate
-# (SQ_INSTS_VALU x 64) is read against.  Reaching it takes two FP32
-# operations per lane per instruction (packed FP32, which this library does
-# not emit); one 64-lane VALU instruction per SIMD every four clocks (4
-# SIMDs of 16 lanes per CU) is 39.3 T lane operations per second, the
-# ceiling of single FP32 operations, reported beside it.
+# (SQ_INSTS_VALU x 64) is read against.  (A quarter-rate reading, one
+# 64-lane instruction per SIMD every four clocks, 39.3 T, is no ceiling on
+# this chip: the 32-view render issues 46-48 T.)
 FP32_PEAK_TFLOPS = 157.3
 VALU_LANE_PEAK_T = 256 * 2.4e9 * 128 / 1e12
-VALU_SINGLE_ISSUE_T = 256 * 2.4e9 * 4 * 16 / 1e12
 
 
 def log(*a):
@@ -654,8 +651,6 @@ def counter_fields(roof, ctr, ms, work, per, source=COUNTERS):
                               f"lane_insts_per_{per}": round(ctr["valu_insts"] * 64 / max(work[per], 1), 2),
                               "lane_rate_T": round(lane_rate, 2), "peak_T": round(VALU_LANE_PEAK_T, 2),
                               "frac": round(lane_rate / VALU_LANE_PEAK_T, 4),
-                              "single_issue_T": round(VALU_SINGLE_ISSUE_T, 2),
-                              "frac_of_single_issue": round(lane_rate / VALU_SINGLE_ISSUE_T, 4),
                               "source": f"{source}: SQ_INSTS_VALU per launch, not in this run"}
     return roof
 
